@@ -1,0 +1,117 @@
+"""Sensor and atmosphere configurations of the modulated pyramid workloads.
+
+Plain records: both the oracle and the HIP path read the same numbers,
+neither shares code with the other through this module.
+
+Parameter provenance.  The paper's example (Sec. 4, Tab. 1, "pyramid",
+"detector", "atmo" and "control" blocks) fixes the kind of system: an 8 m
+class pupil, a modulated four-face pyramid at 750 nm with a modulation
+radius of 3 lambda/D, a 1 ms step and an integrator with a delay of two
+steps.  The sizes below are the measured workloads; the conventions the paper
+leaves open (pupil centring, mask apex, face shift, modulation phase
+origin, normalisation, ...) are applied identically by both
+implementations.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace, asdict
+
+
+@dataclass(frozen=True)
+class SensorConfig:
+    """Geometry of one modulated pyramid sensor.
+
+    n_fft       N: side of the square FFT grid (pupil plane == focal plane grid).
+    n_pupil     P: pupil diameter in pupil-plane pixels.
+    n_bin       b: detector binning; S = P / b subapertures across.
+    n_mod       K: modulation points on the circle.
+    face_shift  Delta: pupil-image displacement in pixels produced by each
+                pyramid face; 0 selects N / 4.
+    norm_mode   0: slopes divided by the mean total flux over valid
+                subapertures of the current frame; 1: by each
+                subaperture's own total flux.
+    mod_radius_lod  modulation radius in lambda / D.
+    wavelength_m    sensing wavelength.
+    diameter_m      telescope diameter (sets the metric pixel size P / D).
+    obstruction     central obstruction as a fraction of the diameter.
+    """
+    name: str
+    n_fft: int
+    n_pupil: int
+    n_bin: int
+    n_mod: int
+    mod_radius_lod: float
+    wavelength_m: float
+    diameter_m: float
+    obstruction: float = 0.0
+    face_shift: int = 0
+    norm_mode: int = 0
+
+    @property
+    def n_sub(self) -> int:
+        return self.n_pupil // self.n_bin
+
+    @property
+    def delta(self) -> int:
+        return self.face_shift if self.face_shift else self.n_fft // 4
+
+    @property
+    def pixel_m(self) -> float:
+        return self.diameter_m / self.n_pupil
+
+    def with_(self, **kw) -> "SensorConfig":
+        return replace(self, **kw)
+
+    def as_dict(self) -> dict:
+        return asdict(self)
+
+
+@dataclass(frozen=True)
+class AtmoConfig:
+    """Von Karman turbulence used to draw the input phase screens.
+
+    r0_m is quoted at r0_wavelength_m (500 nm); screens are returned as
+    optical path difference in nanometres, which is achromatic.
+    """
+    r0_m: float
+    L0_m: float
+    r0_wavelength_m: float = 500e-9
+    wind_m_s: float = 0.0
+    frame_rate_hz: float = 1000.0
+
+
+# Plain single-source sensor: 8 m pupil on 32 px, 128-point FFT grid,
+# 16 modulation points on a 3 lambda/D ring at 750 nm, pupils separated
+# by 64 px (Delta = 32), 2x2 binning to 16x16 subapertures.
+CFG1 = SensorConfig(name="cfg1_n128_p32_k16", n_fft=128, n_pupil=32, n_bin=2,
+                    n_mod=16, mod_radius_lod=3.0, wavelength_m=750e-9,
+                    diameter_m=8.0)
+ATMO1 = AtmoConfig(r0_m=0.15, L0_m=25.0)
+
+# LBT-like SCAO sensor: 8.4 m pupil on 160 px, 640-point FFT grid,
+# 48 modulation points at 3 lambda/D, 750 nm, 40x40 subapertures.
+CFG2 = SensorConfig(name="cfg2_n640_p160_k48", n_fft=640, n_pupil=160, n_bin=4,
+                    n_mod=48, mod_radius_lod=3.0, wavelength_m=750e-9,
+                    diameter_m=8.4)
+ATMO2 = AtmoConfig(r0_m=0.12, L0_m=40.0, wind_m_s=15.0, frame_rate_hz=1000.0)
+
+# Precision study on the same shapes: 16 independent screens with
+# r0 drawn uniformly in [0.08, 0.2] m (L0 as in the closed loop).
+CFG4_R0_RANGE = (0.08, 0.2)
+CFG4_SEEDS = tuple(range(16))
+
+# 40 m class multi-source sensor (shapes only; batched multi-source
+# sensing is a later extension).
+CFG3 = SensorConfig(name="cfg3_n1920_p480_k64", n_fft=1920, n_pupil=480, n_bin=5,
+                    n_mod=64, mod_radius_lod=3.0, wavelength_m=650e-9,
+                    diameter_m=39.0)
+
+# Closed-loop constants of the integrator (gain of the LBT-like loop,
+# delay of the paper's example control block).
+LOOP_GAIN = 0.4
+LOOP_DELAY = 2
+LOOP_SETTLE_STEPS = 50
+N_KL_MODES = 600
+PUSH_PULL_NM = 10.0
+
+CONFIGS = {"cfg1": CFG1, "cfg2": CFG2, "cfg3": CFG3}

@@ -1,0 +1,89 @@
+"""Karhunen-Loeve modal basis of von Karman turbulence over the pupil.
+
+This is the definition of the modal deformable mirror (its influence
+functions), an input shared by both implementations; it holds none of the
+sensor's arithmetic.
+
+Modes are eigenvectors of the piston-removed phase covariance between
+pupil pixels, C(r) proportional to (2 pi r / L0)^(5/6) K_(5/6)(2 pi r / L0)
+(von Karman; the scale factor does not change eigenvectors).  The
+covariance depends only on the pixel offset, so it is applied by FFT
+convolution on a 2P x 2P grid; the leading eigenvectors are found by block
+subspace iteration followed by a Rayleigh-Ritz step.  Each mode is zero
+outside the pupil, has zero mean over it and unit RMS (1 nm) over it, and
+modes are mutually orthogonal over the pupil.
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+
+import numpy as np
+import scipy.fft as sfft
+from scipy.special import gamma, kv
+
+_WORKERS = os.cpu_count() or 1
+
+
+def _cov_kernel(P: int, pixel_m: float, L0_m: float) -> np.ndarray:
+    n = 2 * P
+    d = np.arange(n)
+    d = np.where(d < P, d, d - n).astype(np.float64)        # signed offsets
+    r = np.hypot(d[:, None], d[None, :]) * pixel_m
+    x = 2 * np.pi * r / L0_m
+    with np.errstate(invalid="ignore"):
+        c = x ** (5.0 / 6.0) * kv(5.0 / 6.0, x)
+    c[r == 0] = 2.0 ** (-1.0 / 6.0) * gamma(5.0 / 6.0)
+    return sfft.rfft2(c)
+
+
+def kl_modes(A: np.ndarray, pixel_m: float, L0_m: float, n_modes: int,
+             iters: int = 8, oversample: int = 64, seed: int = 12345,
+             cache: bool = True) -> np.ndarray:
+    """[n_modes, P, P] float64 KL modes (unit RMS in nm over the pupil)."""
+    P = A.shape[0]
+    key = hashlib.sha1(np.packbits(A.astype(bool)).tobytes()
+                       + repr((P, pixel_m, L0_m, n_modes, iters, oversample, seed)).encode()).hexdigest()[:16]
+    cdir = os.environ.get("PWFS_CACHE_DIR", os.path.join(os.path.expanduser("~"), ".cache", "pwfs_kl"))
+    path = os.path.join(cdir, f"kl_{key}.npy")
+    if cache and os.path.exists(path):
+        return np.load(path)
+    pix = np.flatnonzero(A.ravel() > 0)
+    npix = pix.size
+    Ck = _cov_kernel(P, pixel_m, L0_m)
+
+    def apply(X):                               # X [npix, m] -> Q C Q X
+        X = X - X.mean(axis=0, keepdims=True)
+        m = X.shape[1]
+        out = np.empty_like(X)
+        step = 128
+        for s in range(0, m, step):
+            blk = X[:, s:s + step]
+            flat = np.zeros((blk.shape[1], P * P))
+            flat[:, pix] = blk.T
+            g = np.zeros((blk.shape[1], 2 * P, 2 * P))
+            g[:, :P, :P] = flat.reshape(-1, P, P)
+            y = sfft.irfft2(sfft.rfft2(g, workers=_WORKERS) * Ck, s=(2 * P, 2 * P), workers=_WORKERS)
+            out[:, s:s + step] = y[:, :P, :P].reshape(blk.shape[1], -1)[:, pix].T
+        return out - out.mean(axis=0, keepdims=True)
+
+    rng = np.random.default_rng(seed)
+    m = min(n_modes + oversample, npix - 1)
+    X = np.linalg.qr(apply(rng.standard_normal((npix, m))))[0]
+    for _ in range(iters):
+        X = np.linalg.qr(apply(X))[0]
+    H = X.T @ apply(X)
+    w, V = np.linalg.eigh(0.5 * (H + H.T))
+    order = np.argsort(w)[::-1][:n_modes]
+    U = X @ V[:, order]                          # orthonormal columns, piston-free
+    U -= U.mean(axis=0, keepdims=True)
+    U, _ = np.linalg.qr(U)
+    modes = np.zeros((n_modes, P * P))
+    modes[:, pix] = U.T * np.sqrt(npix)
+    modes = modes.reshape(n_modes, P, P)
+    if cache:
+        os.makedirs(cdir, exist_ok=True)
+        tmp = path + f".{os.getpid()}.tmp.npy"
+        np.save(tmp, modes)
+        os.replace(tmp, path)
+    return modes
