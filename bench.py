@@ -1,0 +1,267 @@
+"""Benchmark of the modulated pyramid sensor path on one MI355X.
+
+A step is one pass of the whole path over a batch of 16 independent seeded
+von Karman screens at the LBT-like geometry (P = 160 pupil pixels, 640-point
+FFT grid, 48 modulation points, 40 x 40 subapertures, 600 KL modes):
+pwfs_measure (row pass, column pass, slopes) followed by recon_apply with
+the calibrated 600 x 2544 reconstructor.  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+
+Besides throughput the line carries
+  roofline      the column-pass kernel (the dominant one) against the FP32
+                vector peak, from its algorithmic flop count and its event-
+                timed average duration inside the timed region;
+  cpu_baseline  the FP64 oracle timed on the host's cores on a small sample
+                of the same frames;
+  loop          the 1000-step frozen-flow closed loop (integrator gain 0.4,
+                delay 2) run on the GPU: residual nm RMS and steps/s.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np
+
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# --- algorithmic flop count of the HIP line operator -----------------------
+_RADIX_FLOPS = {1: 0, 2: 4, 3: 16, 4: 16, 5: 48}
+
+
+def _first_radix(n):
+    if n % 4 == 0 and n != 8:
+        return 4
+    for r in (2, 3, 5):
+        if n % r == 0:
+            return r
+    return n
+
+
+def dft_flops(E: int) -> int:
+    """Real flops of the in-register mixed-radix DFT of length E (trivial twiddles free)."""
+    R = _first_radix(E)
+    Q = E // R
+    if Q == 1:
+        return _RADIX_FLOPS[R]
+    tw = sum(6 for r in range(R) for k in range(Q) if ((r * k) % E) * 4 % E != 0)
+    return R * dft_flops(Q) + Q * _RADIX_FLOPS[R] + tw
+
+
+def line_flops(P: int, intensity: bool) -> int:
+    """Flops of one 1-D pyramid line operator (two half-band projections of
+    length P in four-step form, input twist, output twiddles, y_L = f - y_H,
+    plus |E|^2 accumulation in the column pass)."""
+    E = P // 4
+    projection = 4 * (2 * dft_flops(E) + 20 * E)     # 4 lanes: DFT_E, twiddle + 3-tap mix + conj twiddle, IDFT_E
+    f = 6 * P                                         # tilt ramp times input
+    twist = 2 * 6 * P
+    out = 2 * 6 * P + 2 * P + 2 * P                   # output twiddles, sum of the two halves, f - y_H
+    acc = 2 * 2 * P * 2 if intensity else 0           # |.|^2 + accumulate, both windows
+    return 2 * projection + f + twist + out + acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--cpu-frames", type=int, default=6)
+    ap.add_argument("--loop-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-loop", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by independent frames with no exchange, see the design notes)",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_1607_07624_amd as pw
+    from synth.configs import CFG2, ATMO2, CFG4_R0_RANGE, N_KL_MODES, PUSH_PULL_NM, LOOP_GAIN, \
+        LOOP_DELAY, LOOP_SETTLE_STEPS
+    from synth.screens import open_loop_batch, frozen_flow_sequence
+    from synth.kl import kl_modes
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg, B = CFG2, args.batch
+    P = cfg.n_pupil
+
+    log("inputs")
+    opd_host, r0 = open_loop_batch(cfg, ATMO2, list(range(B)), r0_range=CFG4_R0_RANGE)
+    opd = torch.from_numpy(opd_host).to(dev)
+    plan = pw.Plan(cfg, batch_max=B)
+    nv = plan.n_valid
+    ns = 2 * nv
+
+    # Calibration: KL modal DM, push-pull interaction matrix measured on the
+    # GPU, full-SVD pseudo-inverse on the host (FP64).
+    log("calibration")
+    t0 = time.time()
+    amp = plan.pupil.astype(np.float64)
+    modes = kl_modes(amp, cfg.pixel_m, ATMO2.L0_m, N_KL_MODES)
+    M = modes.shape[0]
+    modes_dev = torch.from_numpy(modes.astype(np.float32)).to(dev)
+    IM = np.empty((ns, M))
+    s_buf = torch.empty((B, ns), device=dev)
+    for i0 in range(0, M, B // 2):
+        idx = list(range(i0, min(M, i0 + B // 2)))
+        push = torch.cat([PUSH_PULL_NM * modes_dev[idx], -PUSH_PULL_NM * modes_dev[idx]]).contiguous()
+        sl = torch.empty((push.shape[0], ns), device=dev)
+        plan.measure_into(push, None, sl)
+        sl = sl.cpu().numpy().astype(np.float64)
+        n = len(idx)
+        IM[:, idx] = ((sl[:n] - sl[n:]) / (2.0 * PUSH_PULL_NM)).T
+    U, sig, Vt = np.linalg.svd(IM, full_matrices=False)
+    R_host = (Vt.T / sig) @ U.T
+    R = torch.from_numpy(R_host.astype(np.float32)).to(dev).contiguous()
+    log(f"calibration {time.time() - t0:.1f}s, cond {sig[0] / sig[-1]:.1f}")
+
+    modes_out = torch.empty((B, M), device=dev)
+
+    def step():
+        plan.measure_into(opd, None, s_buf)
+        pw.recon_apply(R, s_buf, 1.0, 0.0, modes_out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.timing_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms_total = ev0.elapsed_time(ev1)
+    kt = plan.timing_read()
+    plan.timing_enable(False)
+    ms_step = ms_total / args.steps
+    fps = B * args.steps / (ms_total / 1e3)
+    log(f"{fps:.0f} frames/s, {ms_step:.3f} ms/step (wall {wall:.2f}s) kernels {kt}")
+
+    # Roofline of the column pass (dominant kernel).
+    n_launch = kt["slices"]
+    col_ms = kt["col_ms"] / n_launch
+    row_ms = kt["row_ms"] / n_launch
+    lines_col = B * cfg.n_mod * 2 * P
+    lines_row = B * (cfg.n_mod // 2 + 1) * P
+    fl_col = lines_col * line_flops(P, True)
+    fl_row = lines_row * line_flops(P, False)
+    achieved = fl_col / (col_ms * 1e-3) / 1e12
+    conv = lines_col * 2 * 5 * cfg.n_fft * np.log2(cfg.n_fft)     # 5 N log2 N convention, N = 640
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "col_pass_kernel<40>", "kernel_ms": round(col_ms, 4),
+                "flop_per_launch": int(fl_col),
+                "convention_5NlogN_tflops": round(conv / (col_ms * 1e-3) / 1e12, 2)}
+    extra = {"row_pass_ms": round(row_ms, 4), "row_pass_tflops": round(fl_row / (row_ms * 1e-3) / 1e12, 2),
+             "slopes_ms": round(kt["slopes_ms"] / n_launch, 4),
+             "recon_ms": round(ms_step - (kt["row_ms"] + kt["col_ms"] + kt["slopes_ms"]) / n_launch, 4)}
+
+    # B = 1 latency (one frame per call, same path).
+    plan1 = pw.Plan(cfg, batch_max=1)
+    s1 = torch.empty((1, ns), device=dev)
+    m1 = torch.empty((1, M), device=dev)
+    o1 = opd[:1].contiguous()
+    for _ in range(20):
+        plan1.measure_into(o1, None, s1)
+        pw.recon_apply(R, s1, 1.0, 0.0, m1)
+    torch.cuda.synchronize()
+    ev0.record()
+    n1 = 200
+    for _ in range(n1):
+        plan1.measure_into(o1, None, s1)
+        pw.recon_apply(R, s1, 1.0, 0.0, m1)
+    ev1.record()
+    torch.cuda.synchronize()
+    extra["b1_frames_per_s"] = round(n1 / (ev0.elapsed_time(ev1) / 1e3), 1)
+
+    # Closed loop on the GPU (frozen flow, 1 kHz, 15 m/s).
+    loop = None
+    if not args.no_loop:
+        log("closed loop")
+        T = args.loop_steps
+        seq = torch.from_numpy(frozen_flow_sequence(cfg, ATMO2, T, seed=2024)).to(dev)
+        BKL = modes_dev.reshape(M, P * P).t().contiguous()          # [P*P, M]
+        c_hist = torch.zeros((T + LOOP_DELAY, M), device=dev)      # c(t) at row t + delay
+        res = torch.empty((T, P * P), device=dev)
+        sl = torch.empty((1, ns), device=dev)
+        torch.cuda.synchronize()
+        ev0.record()
+        for t in range(T):
+            r_t = res[t:t + 1]
+            r_t.copy_(seq[t].reshape(1, -1))
+            pw.recon_apply(BKL, c_hist[t:t + 1], -1.0, 1.0, r_t)    # u(t) = c(t - delay)
+            plan1.measure_into(r_t.view(1, P, P), None, sl)
+            c_next = c_hist[t + LOOP_DELAY:t + LOOP_DELAY + 1]
+            c_next.copy_(c_hist[t + LOOP_DELAY - 1:t + LOOP_DELAY] if t > 0 else torch.zeros_like(c_next))
+            pw.recon_apply(R, sl, LOOP_GAIN, 1.0, c_next)
+        ev1.record()
+        torch.cuda.synchronize()
+        loop_ms = ev0.elapsed_time(ev1)
+        rr = res.cpu().numpy().astype(np.float64)[:, amp.ravel() > 0]
+        rr -= rr.mean(axis=1, keepdims=True)
+        per_step = np.sqrt((rr ** 2).mean(axis=1))
+        ol = seq.cpu().numpy().astype(np.float64).reshape(T, -1)[:, amp.ravel() > 0]
+        ol -= ol.mean(axis=1, keepdims=True)
+        loop = {"steps": T, "residual_nm_rms": round(float(np.sqrt(np.mean(per_step[LOOP_SETTLE_STEPS:] ** 2))), 2),
+                "open_loop_nm_rms": round(float(np.sqrt(np.mean(ol ** 2))), 2),
+                "steps_per_s": round(T / (loop_ms / 1e3), 1), "gain": LOOP_GAIN, "delay": LOOP_DELAY,
+                "reconstructor": "linear (KL 600, push-pull IM, full-SVD pinv)"}
+        log(f"loop {loop}")
+
+    # CPU baseline: the FP64 oracle on the host cores, small sample.
+    cpu = None
+    if not args.no_cpu:
+        cores = len(os.sched_getaffinity(0))
+        os.environ["ORACLE_FFT_WORKERS"] = str(cores)
+        import oracle
+        orc = oracle.Oracle(cfg)
+        n = min(args.cpu_frames, B)
+        t0 = time.perf_counter()
+        for i in range(n):
+            orc.measure(opd_host[i].astype(np.float64))
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(n / dt, 4), "unit": "frames/s", "cores": cores, "kind": "oracle",
+               "sample": f"{n} of the {B} benchmark frames, FP64 literal 2-D route, scipy.fft workers={cores}"}
+        log(f"cpu {cpu}")
+
+    out = {
+        "metric": "PWFS frames/s at 640^2 FFT, 48 mod pts",
+        "value": round(fps, 1), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "lbt_like_pwfs_n640_p160_k48_s40_b16", "frames_per_step": B,
+                   "n_fft": cfg.n_fft, "n_pupil": P, "n_mod": cfg.n_mod, "n_sub": cfg.n_sub,
+                   "n_valid": nv, "n_modes": M, "screens": "von Karman r0~U[0.08,0.2] m, L0=40 m",
+                   "step": "pwfs_measure + recon_apply"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "loop": loop,
+        "kernels": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

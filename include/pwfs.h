@@ -1,0 +1,154 @@
+/*
+ * pwfs.h -- C ABI of the modulated pyramid wavefront-sensor library.
+ *
+ * The operations follow the sensor chain of the paper's SCAO example
+ * (Sec. 4, main file, Tab. 2): the pyramid turns the pupil electric field
+ * into pupil-plane intensity with circular modulation (pyr.in_ef ->
+ * pyr.out_i), the detector integrates it into pixels (ccd.in_i ->
+ * out_pixels), the slope computer turns pixels into slopes using the
+ * sub-aperture indices and a slope reference vector (sc.in_pixels ->
+ * out_slopes; Tab. 1 "slopec"), and the modal reconstructor multiplies the
+ * slopes by the reconstruction matrix (rec.in_slopes -> out_modes;
+ * Tab. 1 "modalrec"), whose output feeds the integrator (Tab. 1
+ * "control").  Pyramid parameters: Tab. 1 "pyramid" (modulation radius in
+ * lambda/D, wavelength).
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - FFT grid N x N, pupil P x P embedded at offset (N-P)/2, circular pupil
+ *     of diameter P centred at (P-1)/2 (pixel inside iff r^2 <= (P/2)^2,
+ *     optional central obstruction removing r < eps P / 2);
+ *   - phase = 2 pi opd[nm] 1e-9 / lambda;
+ *   - K modulation points at angles 2 pi k / K, radius r_mod N / P focal
+ *     pixels; intensity is the mean over the K points;
+ *   - pyramid mask exp(-2 pi i Delta (|u| + |v|) / N) on signed frequency
+ *     indices, apex on frequency bin 0, Delta = N / 4;
+ *   - pupil q = (x side +) + 2 (y side +), each binned b x b to S x S,
+ *     S = P / b, stored [q][iy][ix] row-major;
+ *   - valid subapertures: pupil fill fraction of the b x b block >= 0.5,
+ *     listed as j = iy * S + ix in ascending order;
+ *   - slopes: sx = [(I1 + I3) - (I0 + I2)] / n, sy = [(I2 + I3) - (I0 + I1)] / n
+ *     with n the mean total flux over valid subapertures of the same frame
+ *     (norm_mode 0) or each subaperture's own total flux (norm_mode 1);
+ *     layout [sx over valid ; sy over valid] minus the reference slopes
+ *     (slopes of a flat wavefront, measured when the plan is made).
+ *
+ * Memory: every pointer documented as "device" is a device allocation on
+ * the device that was current when the plan was made, owned by the
+ * caller; "host" pointers are ordinary host memory.  Streams are
+ * hipStream_t passed as void* (NULL = default stream).  All calls return
+ * PWFS_OK or a negative status; argument checks run on the host before
+ * anything is launched.  There is no CPU fallback: without a usable
+ * device the plan call fails with PWFS_ERR_NO_DEVICE.
+ */
+#ifndef PWFS_H
+#define PWFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pwfs_plan_s* pwfs_plan_t;
+
+enum {
+  PWFS_OK = 0,
+  PWFS_ERR_INVALID_ARG = -1,   /* NULL pointer, non-positive size, inconsistent geometry */
+  PWFS_ERR_UNSUPPORTED = -2,   /* geometry outside what the kernels implement            */
+  PWFS_ERR_NO_DEVICE = -3,     /* no HIP device visible                                  */
+  PWFS_ERR_OUT_OF_MEMORY = -4, /* device allocation failed                               */
+  PWFS_ERR_HIP = -5            /* a HIP runtime call or kernel launch failed             */
+};
+
+typedef struct {
+  int32_t n_fft;      /* N: FFT grid side.  Must equal 4 * n_pupil.                        */
+  int32_t n_pupil;    /* P: pupil diameter in pixels: 32, 64 or 160.                       */
+  int32_t n_bin;      /* b: detector binning, P % b == 0, b in {1, 2, 4, 8}.              */
+  int32_t n_mod;      /* K: modulation points, 1 <= K <= 1024.                            */
+  int32_t face_shift; /* Delta in pixels; 0 selects N / 4 (the only supported value).     */
+  int32_t norm_mode;  /* 0: global mean flux over valid subapertures; 1: per subaperture. */
+  int32_t batch_max;  /* largest batch the workspace is sized for (larger batches are     */
+                      /* processed in slices of batch_max frames).                         */
+  int32_t reserved;   /* must be 0                                                         */
+  double diameter_m;      /* D (informational: the sensor works in pixels)                */
+  double wavelength_m;    /* lambda                                                       */
+  double mod_radius_lod;  /* r_mod in lambda / D, >= 0                                    */
+  double obstruction;     /* central obstruction, fraction of D, 0 <= eps < 1              */
+} pwfs_config_t;
+
+/* Build a plan: validates cfg, generates the FP64 tables (tilt ramps,
+ * pyramid twiddles), uploads them as FP32, allocates the workspace for
+ * batch_max frames and measures the reference slopes of a flat wavefront
+ * (synchronises the default stream once).  pupil_amp_host: P * P floats,
+ * row-major [y][x], or NULL for the circular pupil described above.
+ * On success *out owns every device buffer until pwfs_destroy. */
+int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t* out);
+
+/* Sizes of a plan: number of valid subapertures, S = P / b and the bytes
+ * of device workspace held.  Any output pointer may be NULL. */
+int pwfs_plan_info(pwfs_plan_t plan, int32_t* n_valid, int32_t* n_sub, size_t* workspace_bytes);
+
+/* Copy the valid-subaperture list (n_valid int32, ascending j = iy*S+ix)
+ * into host memory. */
+int pwfs_get_valid(pwfs_plan_t plan, int32_t* idx_host);
+
+/* Copy the current reference slopes (2 * n_valid floats) into host memory. */
+int pwfs_get_reference(pwfs_plan_t plan, float* sref_host);
+
+/* Replace the reference slopes with 2 * n_valid floats from device memory
+ * (stream-ordered copy), or with zeros when d_sref is NULL. */
+int pwfs_set_reference(pwfs_plan_t plan, const float* d_sref, void* stream);
+
+/* Modulated pyramid measurement of B frames.
+ *   d_opd_nm  device, B * P * P float, [frame][y][x], optical path in nm.
+ *   d_pupils  device, B * 4 * S * S float, binned pupil images (mean over
+ *             modulation points of |E|^2, pupil-plane pixels summed b x b,
+ *             unit input amplitude), or NULL to skip writing them.
+ *   d_slopes  device, B * 2 * n_valid float, reference-subtracted slopes,
+ *             or NULL to skip them.
+ * Asynchronous on `stream`.  A plan holds one workspace: calls on the same
+ * plan must not overlap on different streams. */
+int pwfs_measure(pwfs_plan_t plan, const float* d_opd_nm, int32_t B,
+                 float* d_pupils, float* d_slopes, void* stream);
+
+/* Copy the pupil amplitude used by the plan (P * P floats, [y][x]) into
+ * host memory. */
+int pwfs_get_pupil(pwfs_plan_t plan, float* amp_host);
+
+/* Per-kernel timing of pwfs_measure.  With enable != 0 every later
+ * pwfs_measure on this plan records HIP events around its row-pass,
+ * column-pass and slopes kernels on the caller's stream (the previous
+ * record is discarded); enable == 0 stops recording.  pwfs_timing_read
+ * waits for the recorded events and returns the summed kernel durations
+ * in milliseconds and the number of pwfs_measure batch slices recorded.
+ * Any output pointer may be NULL. */
+int pwfs_timing_enable(pwfs_plan_t plan, int enable);
+int pwfs_timing_read(pwfs_plan_t plan, double* ms_row, double* ms_col, double* ms_slopes,
+                     int64_t* n_slices);
+
+/* Modal reconstruction and integration, m = alpha * R s + beta * m for each
+ * of B vectors (an integrator step is alpha = gain, beta = 1; the DM
+ * projection opd -= B_KL u is alpha = -1, beta = 1 with R = B_KL).
+ *   d_R  device, M * n_s float, row-major [mode][slope].
+ *   d_s  device, B * n_s float.
+ *   d_m  device, B * M float, read (when beta != 0) and written.
+ * FP32 with FP32 accumulation in a fixed order (bitwise reproducible).
+ * Asynchronous on `stream`. */
+int recon_apply(const float* d_R, int32_t M, int32_t n_s, const float* d_s, int32_t B,
+                float alpha, float beta, float* d_m, void* stream);
+
+/* Release every device buffer of the plan (synchronises its device). */
+void pwfs_destroy(pwfs_plan_t plan);
+
+/* Static description of a status code. */
+const char* pwfs_strerror(int status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* pwfs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWFS_H */

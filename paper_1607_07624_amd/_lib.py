@@ -1,0 +1,212 @@
+"""ctypes binding of libpwfs.so: same names as the C ABI, marshalling only.
+
+Device buffers are torch tensors on the current HIP device; the HIP stream
+is torch's current stream.  torch is used for memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+STATUS_NAMES = {0: "PWFS_OK", -1: "PWFS_ERR_INVALID_ARG", -2: "PWFS_ERR_UNSUPPORTED",
+                -3: "PWFS_ERR_NO_DEVICE", -4: "PWFS_ERR_OUT_OF_MEMORY", -5: "PWFS_ERR_HIP"}
+
+
+class PwfsError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({detail})")
+
+
+class config_struct(ctypes.Structure):
+    _fields_ = [("n_fft", ctypes.c_int32), ("n_pupil", ctypes.c_int32), ("n_bin", ctypes.c_int32),
+                ("n_mod", ctypes.c_int32), ("face_shift", ctypes.c_int32), ("norm_mode", ctypes.c_int32),
+                ("batch_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("diameter_m", ctypes.c_double), ("wavelength_m", ctypes.c_double),
+                ("mod_radius_lod", ctypes.c_double), ("obstruction", ctypes.c_double)]
+
+
+def library_path() -> str:
+    return os.path.join(_PKG, "libpwfs.so")
+
+
+def load_library():
+    """Load libpwfs.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1607_07624_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, i32, f32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_size_t
+    lib.pwfs_plan.argtypes = [ctypes.POINTER(config_struct), vp, ctypes.POINTER(vp)]
+    lib.pwfs_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz)]
+    lib.pwfs_get_valid.argtypes = [vp, vp]
+    lib.pwfs_get_reference.argtypes = [vp, vp]
+    lib.pwfs_set_reference.argtypes = [vp, vp, vp]
+    lib.pwfs_measure.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.recon_apply.argtypes = [vp, i32, i32, vp, i32, f32, f32, vp, vp]
+    lib.pwfs_get_pupil.argtypes = [vp, vp]
+    lib.pwfs_timing_enable.argtypes = [vp, ctypes.c_int]
+    lib.pwfs_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.pwfs_destroy.argtypes = [vp]
+    lib.pwfs_destroy.restype = None
+    lib.pwfs_strerror.argtypes = [ctypes.c_int]
+    lib.pwfs_strerror.restype = ctypes.c_char_p
+    lib.pwfs_last_error.argtypes = []
+    lib.pwfs_last_error.restype = ctypes.c_char_p
+    for name in ("pwfs_plan", "pwfs_plan_info", "pwfs_get_valid", "pwfs_get_reference",
+                 "pwfs_set_reference", "pwfs_measure", "recon_apply", "pwfs_get_pupil",
+                 "pwfs_timing_enable", "pwfs_timing_read"):
+        getattr(lib, name).restype = ctypes.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        detail = load_library().pwfs_last_error().decode(errors="replace")
+        raise PwfsError(status, where, detail)
+
+
+def _stream_handle(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _need(t, torch, dtype, numel, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == numel):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor with {numel} elements")
+
+
+def make_config(cfg, batch_max: int) -> config_struct:
+    """Lower a sensor configuration record (attributes as in synth.configs.SensorConfig)."""
+    return config_struct(n_fft=cfg.n_fft, n_pupil=cfg.n_pupil, n_bin=cfg.n_bin, n_mod=cfg.n_mod,
+                         face_shift=cfg.face_shift, norm_mode=cfg.norm_mode, batch_max=batch_max,
+                         reserved=0, diameter_m=cfg.diameter_m, wavelength_m=cfg.wavelength_m,
+                         mod_radius_lod=cfg.mod_radius_lod, obstruction=cfg.obstruction)
+
+
+class Plan:
+    """pwfs_plan / pwfs_measure / pwfs_destroy for one sensor geometry."""
+
+    def __init__(self, cfg, batch_max: int = 16, pupil_amp: np.ndarray | None = None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.cfg = cfg
+        self.device = torch.cuda.current_device()
+        c = make_config(cfg, batch_max)
+        amp = None
+        if pupil_amp is not None:
+            amp = np.ascontiguousarray(pupil_amp, dtype=np.float32)
+            if amp.shape != (cfg.n_pupil, cfg.n_pupil):
+                raise ValueError("pupil_amp must be P x P")
+        h = ctypes.c_void_p()
+        _check(self.lib.pwfs_plan(ctypes.byref(c), amp.ctypes.data if amp is not None else None,
+                                  ctypes.byref(h)), "pwfs_plan")
+        self.handle = h
+        nv, ns, ws = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(self.lib.pwfs_plan_info(h, ctypes.byref(nv), ctypes.byref(ns), ctypes.byref(ws)),
+               "pwfs_plan_info")
+        self.n_valid, self.n_sub, self.workspace_bytes = nv.value, ns.value, ws.value
+        self.batch_max = batch_max
+
+    @property
+    def valid(self) -> np.ndarray:
+        out = np.empty(self.n_valid, np.int32)
+        _check(self.lib.pwfs_get_valid(self.handle, out.ctypes.data), "pwfs_get_valid")
+        return out
+
+    @property
+    def s_ref(self) -> np.ndarray:
+        out = np.empty(2 * self.n_valid, np.float32)
+        _check(self.lib.pwfs_get_reference(self.handle, out.ctypes.data), "pwfs_get_reference")
+        return out
+
+    @property
+    def pupil(self) -> np.ndarray:
+        P = self.cfg.n_pupil
+        out = np.empty((P, P), np.float32)
+        _check(self.lib.pwfs_get_pupil(self.handle, out.ctypes.data), "pwfs_get_pupil")
+        return out
+
+    def timing_enable(self, enable: bool = True):
+        _check(self.lib.pwfs_timing_enable(self.handle, int(enable)), "pwfs_timing_enable")
+
+    def timing_read(self) -> dict:
+        r, c, s, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(self.lib.pwfs_timing_read(self.handle, ctypes.byref(r), ctypes.byref(c), ctypes.byref(s),
+                                         ctypes.byref(n)), "pwfs_timing_read")
+        return {"row_ms": r.value, "col_ms": c.value, "slopes_ms": s.value, "slices": n.value}
+
+    def set_reference(self, sref=None):
+        t = self._torch
+        if sref is not None:
+            _need(sref, t, t.float32, 2 * self.n_valid, "sref")
+        _check(self.lib.pwfs_set_reference(self.handle, _ptr(sref), _stream_handle(t, self.device)),
+               "pwfs_set_reference")
+
+    def measure_into(self, opd, pupils=None, slopes=None):
+        """pwfs_measure on caller-owned tensors (asynchronous on torch's current stream)."""
+        t = self._torch
+        P, S = self.cfg.n_pupil, self.n_sub
+        B = opd.shape[0] if opd.dim() == 3 else 1
+        _need(opd, t, t.float32, B * P * P, "opd")
+        if pupils is not None:
+            _need(pupils, t, t.float32, B * 4 * S * S, "pupils")
+        if slopes is not None:
+            _need(slopes, t, t.float32, B * 2 * self.n_valid, "slopes")
+        _check(self.lib.pwfs_measure(self.handle, _ptr(opd), B, _ptr(pupils), _ptr(slopes),
+                                     _stream_handle(t, self.device)), "pwfs_measure")
+        return pupils, slopes
+
+    def measure(self, opd, want_pupils: bool = True):
+        """(pupils [B,4,S,S] or None, slopes [B, 2 n_valid]) for opd [B,P,P] float32 nm."""
+        t = self._torch
+        opd = opd.contiguous()
+        B = opd.shape[0] if opd.dim() == 3 else 1
+        S = self.n_sub
+        pupils = t.empty((B, 4, S, S), dtype=t.float32, device=opd.device) if want_pupils else None
+        slopes = t.empty((B, 2 * self.n_valid), dtype=t.float32, device=opd.device)
+        return self.measure_into(opd, pupils, slopes)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pwfs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def recon_apply(R, s, alpha: float = 1.0, beta: float = 0.0, m=None):
+    """m = alpha R s + beta m for each row of s ([B, n_s]); returns m [B, M]."""
+    import torch
+    lib = load_library()
+    M, ns = R.shape
+    s2 = s.reshape(-1, ns)
+    B = s2.shape[0]
+    _need(R, torch, torch.float32, M * ns, "R")
+    _need(s2, torch, torch.float32, B * ns, "s")
+    if m is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs an existing m")
+        m = torch.empty((B, M), dtype=torch.float32, device=R.device)
+    _need(m, torch, torch.float32, B * M, "m")
+    _check(lib.recon_apply(_ptr(R), M, ns, _ptr(s2), B, float(alpha), float(beta), _ptr(m),
+                           _stream_handle(torch, R.device)), "recon_apply")
+    return m

@@ -1,0 +1,505 @@
+// pwfs_api.cpp -- C ABI of the modulated pyramid sensor: validation, FP64 table
+// generation, workspace management and launch sequencing.
+#include "../../include/pwfs.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pwfs_launch.h"
+
+namespace pwfs {
+struct cpx {
+  float re, im;
+};
+}  // namespace pwfs
+
+using pwfs::cpx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PWFS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool fault_inject_oom() {
+  const char* v = std::getenv("PWFS_FAULT_INJECT");
+  return v && std::strcmp(v, "oom") == 0;
+}
+
+int dev_alloc(void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (bytes == 0) return PWFS_OK;
+  if (fault_inject_oom()) return fail(PWFS_ERR_OUT_OF_MEMORY, std::string("injected OOM: ") + what);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(PWFS_ERR_OUT_OF_MEMORY, std::string("hipMalloc(") + what + ", " +
+                                            std::to_string(bytes) + " B): " + hipGetErrorString(e));
+  }
+  return PWFS_OK;
+}
+
+// exp(-2 pi i n / d) with the integer ratio reduced first (FP64).
+cpx unit_frac(long n, long d, int sign) {
+  n %= d;
+  if (n < 0) n += d;
+  const double ang = 2.0 * M_PI * (double)n / (double)d;
+  return {(float)std::cos(ang), (float)(-sign * std::sin(ang))};
+}
+
+// exp(+2 pi i t) for a real number of turns t (FP64, fractional part first).
+cpx unit_turns(double t) {
+  const double f = t - std::floor(t);
+  const double ang = 2.0 * M_PI * f;
+  return {(float)std::cos(ang), (float)std::sin(ang)};
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct pwfs_plan_s {
+  pwfs_config_t cfg{};
+  int device = 0;
+  int N = 0, P = 0, E = 0, S = 0, b = 0, K = 0, n_a = 0, nv = 0, batch_max = 0;
+  double kphase = 0.0;
+  std::vector<int> valid;
+  // device tables
+  float* amp = nullptr;
+  cpx* ramp_a = nullptr;
+  cpx* ramp_b = nullptr;
+  cpx* twist = nullptr;
+  cpx* mid = nullptr;
+  cpx* outw = nullptr;
+  int* k_order = nullptr;
+  int* k_ia = nullptr;
+  int* d_valid = nullptr;
+  float* sref = nullptr;
+  // workspace
+  cpx* Rw = nullptr;
+  float* partial = nullptr;
+  float* zero_opd = nullptr;
+  float* tmp_slopes = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<float> amp_host;
+  // per-kernel timing
+  bool timing = false;
+  std::vector<std::array<hipEvent_t, 4>> ev_used, ev_free;
+};
+
+namespace {
+
+void split_work(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk, int* n_chunks) {
+  const long target = 2048;  // waves per pass: several per SIMD of the 256-CU chip
+  const long row_waves = (long)(p->P / 8) * p->n_a * B;
+  int ac = (int)std::max<long>(1, row_waves / target);
+  *a_chunk = std::min(ac, p->n_a);
+  const long col_tiles = (long)(2 * p->P / 8) * B;
+  long nc = (target + col_tiles - 1) / col_tiles;
+  nc = std::max<long>(1, std::min<long>(nc, p->K));
+  int kc = (int)((p->K + nc - 1) / nc);
+  *k_chunk = kc;
+  *n_chunks = (p->K + kc - 1) / kc;
+}
+
+int validate(const pwfs_config_t* c) {
+  if (!c) return fail(PWFS_ERR_INVALID_ARG, "cfg is NULL");
+  if (c->reserved != 0) return fail(PWFS_ERR_INVALID_ARG, "reserved field must be 0");
+  if (c->n_pupil <= 0 || c->n_fft <= 0 || c->n_bin <= 0 || c->n_mod <= 0 || c->batch_max <= 0)
+    return fail(PWFS_ERR_INVALID_ARG, "sizes must be positive");
+  if (c->n_pupil % c->n_bin != 0) return fail(PWFS_ERR_INVALID_ARG, "n_pupil must be a multiple of n_bin");
+  if (!(c->wavelength_m > 0.0) || !(c->mod_radius_lod >= 0.0) || !(c->obstruction >= 0.0) ||
+      !(c->obstruction < 1.0) || !std::isfinite(c->wavelength_m) || !std::isfinite(c->mod_radius_lod))
+    return fail(PWFS_ERR_INVALID_ARG, "wavelength, modulation radius or obstruction out of range");
+  if (c->norm_mode != 0 && c->norm_mode != 1) return fail(PWFS_ERR_INVALID_ARG, "norm_mode must be 0 or 1");
+  if (c->face_shift < 0) return fail(PWFS_ERR_INVALID_ARG, "face_shift must be >= 0");
+  if (c->n_mod > 1024) return fail(PWFS_ERR_UNSUPPORTED, "n_mod > 1024");
+  if (c->n_fft != 4 * c->n_pupil) return fail(PWFS_ERR_UNSUPPORTED, "n_fft must equal 4 * n_pupil");
+  if (c->face_shift != 0 && c->face_shift != c->n_fft / 4)
+    return fail(PWFS_ERR_UNSUPPORTED, "face_shift must be n_fft / 4");
+  const int E = c->n_pupil / 4;
+  if (c->n_pupil % 8 != 0 || !(E == 8 || E == 16 || E == 40))
+    return fail(PWFS_ERR_UNSUPPORTED, "n_pupil must be 32, 64 or 160");
+  if (!(c->n_bin == 1 || c->n_bin == 2 || c->n_bin == 4 || c->n_bin == 8))
+    return fail(PWFS_ERR_UNSUPPORTED, "n_bin must be 1, 2, 4 or 8");
+  if (c->batch_max > 65535) return fail(PWFS_ERR_UNSUPPORTED, "batch_max > 65535");
+  return PWFS_OK;
+}
+
+void free_plan(pwfs_plan_s* p) {
+  if (!p) return;
+  DeviceGuard g(p->device);
+  void* ptrs[] = {p->amp, p->ramp_a, p->ramp_b, p->twist, p->mid, p->outw, p->k_order, p->k_ia,
+                  p->d_valid, p->sref, p->Rw, p->partial, p->zero_opd, p->tmp_slopes};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (auto* pool : {&p->ev_used, &p->ev_free})
+    for (auto& a : *pool)
+      for (hipEvent_t ev : a) (void)hipEventDestroy(ev);
+  delete p;
+}
+
+int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* slopes,
+                const float* sref, hipStream_t st) {
+  for (int b0 = 0; b0 < B; b0 += p->batch_max) {
+    const int Bs = std::min(p->batch_max, B - b0);
+    pwfs::MeasureArgs a{};
+    a.P = p->P;
+    a.n_bin = p->b;
+    a.K = p->K;
+    a.n_a = p->n_a;
+    a.nv = p->nv;
+    a.norm_mode = p->cfg.norm_mode;
+    a.B = Bs;
+    split_work(p, Bs, &a.a_chunk, &a.k_chunk, &a.n_chunks);
+    a.kphase = p->kphase;
+    a.opd = opd + (size_t)b0 * p->P * p->P;
+    a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : nullptr;
+    a.slopes = slopes ? slopes + (size_t)b0 * 2 * p->nv : nullptr;
+    a.amp = p->amp;
+    a.ramp_a = p->ramp_a;
+    a.ramp_b = p->ramp_b;
+    a.twist = p->twist;
+    a.mid = p->mid;
+    a.outw = p->outw;
+    a.k_order = p->k_order;
+    a.k_ia = p->k_ia;
+    a.valid = p->d_valid;
+    a.sref = sref;
+    a.Rw = p->Rw;
+    a.partial = p->partial;
+    hipEvent_t* ev = nullptr;
+    if (p->timing) {
+      std::array<hipEvent_t, 4> evs{};
+      if (!p->ev_free.empty()) {
+        evs = p->ev_free.back();
+        p->ev_free.pop_back();
+      } else {
+        for (auto& x : evs) {
+          hipError_t ce = hipEventCreate(&x);
+          if (ce != hipSuccess) return hip_fail(ce, "hipEventCreate");
+        }
+      }
+      p->ev_used.push_back(evs);
+      ev = p->ev_used.back().data();
+    }
+    hipError_t e = pwfs::launch_measure(a, st, ev);
+    if (e != hipSuccess) return hip_fail(e, "pwfs_measure launch");
+  }
+  return PWFS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pwfs_strerror(int status) {
+  switch (status) {
+    case PWFS_OK: return "ok";
+    case PWFS_ERR_INVALID_ARG: return "invalid argument";
+    case PWFS_ERR_UNSUPPORTED: return "unsupported geometry";
+    case PWFS_ERR_NO_DEVICE: return "no HIP device";
+    case PWFS_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case PWFS_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* pwfs_last_error(void) { return g_last_error.c_str(); }
+
+int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t* out) {
+  g_last_error.clear();
+  if (!out) return fail(PWFS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int st = validate(cfg);
+  if (st != PWFS_OK) return st;
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(PWFS_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  auto* p = new pwfs_plan_s();
+  p->cfg = *cfg;
+  if ((e = hipGetDevice(&p->device)) != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  const int N = cfg->n_fft, P = cfg->n_pupil, K = cfg->n_mod, b = cfg->n_bin;
+  p->N = N;
+  p->P = P;
+  p->E = P / 4;
+  p->b = b;
+  p->S = P / b;
+  p->K = K;
+  p->batch_max = cfg->batch_max;
+  p->kphase = 2.0 * M_PI * 1e-9 / cfg->wavelength_m;
+
+  // Pupil amplitude.
+  std::vector<float> amp((size_t)P * P);
+  if (pupil_amp_host) {
+    for (size_t i = 0; i < amp.size(); ++i) {
+      if (!std::isfinite(pupil_amp_host[i])) {
+        delete p;
+        return fail(PWFS_ERR_INVALID_ARG, "pupil amplitude has non-finite values");
+      }
+      amp[i] = pupil_amp_host[i];
+    }
+  } else {
+    const double c = 0.5 * (P - 1), r2o = 0.25 * P * P;
+    const double r2i = 0.25 * cfg->obstruction * cfg->obstruction * P * P;
+    for (int y = 0; y < P; ++y)
+      for (int x = 0; x < P; ++x) {
+        const double r2 = (x - c) * (x - c) + (y - c) * (y - c);
+        const bool in = r2 <= r2o && (cfg->obstruction <= 0.0 || r2 >= r2i);
+        amp[(size_t)y * P + x] = in ? 1.0f : 0.0f;
+      }
+  }
+  // Valid subapertures: block fill fraction >= 0.5.
+  const int S = p->S;
+  for (int iy = 0; iy < S; ++iy)
+    for (int ix = 0; ix < S; ++ix) {
+      double s = 0.0;
+      for (int dy = 0; dy < b; ++dy)
+        for (int dx = 0; dx < b; ++dx) s += amp[(size_t)(iy * b + dy) * P + ix * b + dx];
+      if (s >= 0.5 * b * b) p->valid.push_back(iy * S + ix);
+    }
+  p->nv = (int)p->valid.size();
+  p->amp_host = amp;
+  if (p->nv == 0) {
+    delete p;
+    return fail(PWFS_ERR_INVALID_ARG, "pupil has no valid subaperture");
+  }
+
+  // Modulation: k and K-k share the x tilt a_k = rho cos(2 pi k / K).
+  const double rho = cfg->mod_radius_lod * (double)N / (double)P;
+  p->n_a = K / 2 + 1;
+  std::vector<int> k_ia(K), k_order;
+  for (int k = 0; k < K; ++k) k_ia[k] = std::min(k, K - k);
+  for (int ia = 0; ia < p->n_a; ++ia) {
+    k_order.push_back(ia);
+    if (ia != 0 && K - ia != ia && K - ia < K) k_order.push_back(K - ia);
+  }
+  if ((int)k_order.size() != K) {
+    delete p;
+    return fail(PWFS_ERR_INVALID_ARG, "internal: modulation ordering");
+  }
+  const double xc = 0.5 * (P - 1);
+  std::vector<cpx> ramp_a((size_t)p->n_a * P), ramp_b((size_t)K * P);
+  for (int ia = 0; ia < p->n_a; ++ia) {
+    const double a = rho * std::cos(2.0 * M_PI * (double)ia / (double)K);
+    for (int x = 0; x < P; ++x) ramp_a[(size_t)ia * P + x] = unit_turns(a * ((double)x - xc) / (double)N);
+  }
+  for (int k = 0; k < K; ++k) {
+    const double bk = rho * std::sin(2.0 * M_PI * (double)k / (double)K);
+    for (int y = 0; y < P; ++y) ramp_b[(size_t)k * P + y] = unit_turns(bk * ((double)y - xc) / (double)N);
+  }
+  // Pyramid line-operator tables.
+  std::vector<cpx> twist(2 * (size_t)P), outw(2 * (size_t)P), mid(4 * (size_t)p->E);
+  for (int q = 0; q < 2; ++q)
+    for (int x = 0; x < P; ++x) {
+      twist[(size_t)q * P + x] = unit_frac((long)(2 * q + 1) * x, N, +1);
+      cpx w = unit_frac((long)(2 * q + 1) * x, N, -1);
+      const float sc = (float)(2.0 / (double)N);
+      outw[(size_t)q * P + x] = {w.re * sc, w.im * sc};
+    }
+  for (int l = 0; l < 4; ++l)
+    for (int k = 0; k < p->E; ++k) mid[(size_t)l * p->E + k] = unit_frac((long)l * k, P, +1);
+
+  // Device buffers.
+  int bm = cfg->batch_max;
+  int ac, kc, nc;
+  size_t partial_elems = 0;
+  for (int B = 1; B <= bm; ++B) {
+    split_work(p, B, &ac, &kc, &nc);
+    partial_elems = std::max(partial_elems, (size_t)B * nc * 4 * S * S);
+  }
+  const size_t rw_elems = (size_t)bm * p->n_a * 2 * P * P;
+  struct A { void** ptr; size_t bytes; const char* what; } allocs[] = {
+      {(void**)&p->amp, amp.size() * sizeof(float), "amp"},
+      {(void**)&p->ramp_a, ramp_a.size() * sizeof(cpx), "ramp_a"},
+      {(void**)&p->ramp_b, ramp_b.size() * sizeof(cpx), "ramp_b"},
+      {(void**)&p->twist, twist.size() * sizeof(cpx), "twist"},
+      {(void**)&p->mid, mid.size() * sizeof(cpx), "mid"},
+      {(void**)&p->outw, outw.size() * sizeof(cpx), "outw"},
+      {(void**)&p->k_order, (size_t)K * sizeof(int), "k_order"},
+      {(void**)&p->k_ia, (size_t)K * sizeof(int), "k_ia"},
+      {(void**)&p->d_valid, (size_t)p->nv * sizeof(int), "valid"},
+      {(void**)&p->sref, (size_t)2 * p->nv * sizeof(float), "sref"},
+      {(void**)&p->Rw, rw_elems * sizeof(cpx), "row-pass workspace"},
+      {(void**)&p->partial, partial_elems * sizeof(float), "pupil partials"},
+      {(void**)&p->zero_opd, (size_t)P * P * sizeof(float), "zero opd"},
+      {(void**)&p->tmp_slopes, (size_t)2 * p->nv * sizeof(float), "reference scratch"},
+  };
+  for (auto& a : allocs) {
+    st = dev_alloc(a.ptr, a.bytes, a.what);
+    if (st != PWFS_OK) {
+      free_plan(p);
+      return st;
+    }
+    p->ws_bytes += a.bytes;
+  }
+  struct C { void* dst; const void* src; size_t bytes; } copies[] = {
+      {p->amp, amp.data(), amp.size() * sizeof(float)},
+      {p->ramp_a, ramp_a.data(), ramp_a.size() * sizeof(cpx)},
+      {p->ramp_b, ramp_b.data(), ramp_b.size() * sizeof(cpx)},
+      {p->twist, twist.data(), twist.size() * sizeof(cpx)},
+      {p->mid, mid.data(), mid.size() * sizeof(cpx)},
+      {p->outw, outw.data(), outw.size() * sizeof(cpx)},
+      {p->k_order, k_order.data(), (size_t)K * sizeof(int)},
+      {p->k_ia, k_ia.data(), (size_t)K * sizeof(int)},
+      {p->d_valid, p->valid.data(), (size_t)p->nv * sizeof(int)},
+  };
+  for (auto& c : copies) {
+    if ((e = hipMemcpy(c.dst, c.src, c.bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "table upload");
+    }
+  }
+  if ((e = hipMemset(p->zero_opd, 0, (size_t)P * P * sizeof(float))) != hipSuccess ||
+      (e = hipMemset(p->sref, 0, (size_t)2 * p->nv * sizeof(float))) != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "workspace clear");
+  }
+  // Reference slopes: a flat wavefront measured with a zero reference.
+  st = run_measure(p, p->zero_opd, 1, nullptr, p->tmp_slopes, p->sref, nullptr);
+  if (st != PWFS_OK) {
+    free_plan(p);
+    return st;
+  }
+  if ((e = hipMemcpy(p->sref, p->tmp_slopes, (size_t)2 * p->nv * sizeof(float), hipMemcpyDeviceToDevice)) !=
+          hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "reference slopes");
+  }
+  *out = p;
+  return PWFS_OK;
+}
+
+int pwfs_get_pupil(pwfs_plan_t p, float* amp_host) {
+  if (!p || !amp_host) return fail(PWFS_ERR_INVALID_ARG, "plan or amp_host is NULL");
+  std::memcpy(amp_host, p->amp_host.data(), p->amp_host.size() * sizeof(float));
+  return PWFS_OK;
+}
+
+int pwfs_timing_enable(pwfs_plan_t p, int enable) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  DeviceGuard g(p->device);
+  for (auto& a : p->ev_used) p->ev_free.push_back(a);
+  p->ev_used.clear();
+  p->timing = enable != 0;
+  return PWFS_OK;
+}
+
+int pwfs_timing_read(pwfs_plan_t p, double* ms_row, double* ms_col, double* ms_slopes, int64_t* n_slices) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  DeviceGuard g(p->device);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (auto& a : p->ev_used) {
+    hipError_t e = hipEventSynchronize(a[3]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    for (int i = 0; i < 3; ++i) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, a[i], a[i + 1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      acc[i] += ms;
+    }
+  }
+  if (ms_row) *ms_row = acc[0];
+  if (ms_col) *ms_col = acc[1];
+  if (ms_slopes) *ms_slopes = acc[2];
+  if (n_slices) *n_slices = (int64_t)p->ev_used.size();
+  return PWFS_OK;
+}
+
+int pwfs_plan_info(pwfs_plan_t p, int32_t* n_valid, int32_t* n_sub, size_t* workspace_bytes) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (n_valid) *n_valid = p->nv;
+  if (n_sub) *n_sub = p->S;
+  if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+  return PWFS_OK;
+}
+
+int pwfs_get_valid(pwfs_plan_t p, int32_t* idx_host) {
+  if (!p || !idx_host) return fail(PWFS_ERR_INVALID_ARG, "plan or idx_host is NULL");
+  std::memcpy(idx_host, p->valid.data(), p->valid.size() * sizeof(int32_t));
+  return PWFS_OK;
+}
+
+int pwfs_get_reference(pwfs_plan_t p, float* sref_host) {
+  if (!p || !sref_host) return fail(PWFS_ERR_INVALID_ARG, "plan or sref_host is NULL");
+  DeviceGuard g(p->device);
+  hipError_t e = hipMemcpy(sref_host, p->sref, (size_t)2 * p->nv * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "pwfs_get_reference");
+  return PWFS_OK;
+}
+
+int pwfs_set_reference(pwfs_plan_t p, const float* d_sref, void* stream) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  DeviceGuard g(p->device);
+  const size_t bytes = (size_t)2 * p->nv * sizeof(float);
+  hipError_t e = d_sref ? hipMemcpyAsync(p->sref, d_sref, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream)
+                        : pwfs::launch_fill(p->sref, (size_t)2 * p->nv, 0.0f, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pwfs_set_reference");
+  return PWFS_OK;
+}
+
+int pwfs_measure(pwfs_plan_t p, const float* d_opd_nm, int32_t B, float* d_pupils, float* d_slopes,
+                 void* stream) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (B < 0) return fail(PWFS_ERR_INVALID_ARG, "B must be >= 0");
+  if (B == 0 || (!d_pupils && !d_slopes)) return PWFS_OK;
+  if (!d_opd_nm) return fail(PWFS_ERR_INVALID_ARG, "d_opd_nm is NULL");
+  DeviceGuard g(p->device);
+  return run_measure(p, d_opd_nm, B, d_pupils, d_slopes, p->sref, (hipStream_t)stream);
+}
+
+int recon_apply(const float* d_R, int32_t M, int32_t n_s, const float* d_s, int32_t B, float alpha,
+                float beta, float* d_m, void* stream) {
+  if (M <= 0 || n_s <= 0 || B < 0) return fail(PWFS_ERR_INVALID_ARG, "M, n_s must be > 0 and B >= 0");
+  if (B == 0) return PWFS_OK;
+  if (!d_R || !d_s || !d_m) return fail(PWFS_ERR_INVALID_ARG, "NULL matrix or vector");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PWFS_ERR_INVALID_ARG, "alpha/beta not finite");
+  if (B > 65535 * 8) return fail(PWFS_ERR_UNSUPPORTED, "B too large");
+  hipError_t e = pwfs::launch_recon(d_R, M, n_s, d_s, B, alpha, beta, d_m, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "recon_apply launch");
+  return PWFS_OK;
+}
+
+void pwfs_destroy(pwfs_plan_t p) {
+  if (!p) return;
+  {
+    DeviceGuard g(p->device);
+    (void)hipDeviceSynchronize();
+  }
+  free_plan(p);
+}
+
+}  // extern "C"

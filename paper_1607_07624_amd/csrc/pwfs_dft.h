@@ -1,0 +1,250 @@
+// pwfs_dft.h -- in-register mixed-radix DFTs and quad-lane helpers for gfx950.
+//
+// Every transform here is fully unrolled at compile time: the data live in
+// registers of one lane, all twiddles are compile-time FP64 values rounded
+// to FP32, and trivial twiddles (1, -1, +-i) are never multiplied.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+namespace pwfs {
+
+struct cpx {
+  float re, im;
+};
+
+__device__ __forceinline__ cpx cadd(cpx a, cpx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cpx csub(cpx a, cpx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cpx cmul(cpx a, cpx b) {
+  return {fmaf(a.re, b.re, -a.im * b.im), fmaf(a.re, b.im, a.im * b.re)};
+}
+// a * conj(b)
+__device__ __forceinline__ cpx cmulc(cpx a, cpx b) {
+  return {fmaf(a.re, b.re, a.im * b.im), fmaf(a.im, b.re, -a.re * b.im)};
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time sin / cos of the rational angle 2 pi n / d in double precision.
+// The angle is reduced exactly with integers to |r| <= pi / 4 before a Taylor
+// series, so every constant is correctly rounded to well below FP32 ulp.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double taylor_sin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / double((2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / double((2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
+}
+// cos and sin of 2 pi n / d.
+constexpr double cos_frac(long n, long d) {
+  n %= d;
+  if (n < 0) n += d;
+  long q = (8 * n + d) / (2 * d);  // nearest quarter turn
+  double r = 2.0 * kPi * double(4 * n - q * d) / double(4 * d);
+  double c = taylor_cos(r), s = taylor_sin(r);
+  switch (q & 3) {
+    case 0: return c;
+    case 1: return -s;
+    case 2: return -c;
+    default: return s;
+  }
+}
+constexpr double sin_frac(long n, long d) {
+  n %= d;
+  if (n < 0) n += d;
+  long q = (8 * n + d) / (2 * d);
+  double r = 2.0 * kPi * double(4 * n - q * d) / double(4 * d);
+  double c = taylor_cos(r), s = taylor_sin(r);
+  switch (q & 3) {
+    case 0: return s;
+    case 1: return c;
+    case 2: return -s;
+    default: return -c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Unrolling helper: f(std::integral_constant<int, I>{}) for I in [0, N).
+template <int Base, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, Base + I>{}), ...);
+}
+template <int Begin, int End, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<Begin>(f, std::make_integer_sequence<int, End - Begin>{});
+}
+
+// v * w with w = exp(-2 pi i DIR n / d): trivial angles are exact.
+template <long n, long d, int DIR>
+__device__ __forceinline__ cpx twiddle(cpx v) {
+  constexpr long nn = ((n % d) + d) % d;
+  if constexpr (nn == 0) {
+    return v;
+  } else if constexpr (4 * nn == d) {         // -i DIR
+    return DIR > 0 ? cpx{v.im, -v.re} : cpx{-v.im, v.re};
+  } else if constexpr (2 * nn == d) {
+    return cpx{-v.re, -v.im};
+  } else if constexpr (4 * nn == 3 * d) {     // +i DIR
+    return DIR > 0 ? cpx{-v.im, v.re} : cpx{v.im, -v.re};
+  } else {
+    constexpr float c = float(cos_frac(nn, d));
+    constexpr float s = float(-DIR * sin_frac(nn, d));
+    return {fmaf(v.re, c, -v.im * s), fmaf(v.re, s, v.im * c)};
+  }
+}
+
+// Small radices -------------------------------------------------------------
+// All compute X[k] = sum_m x[m] exp(-2 pi i DIR m k / R), natural order.
+template <int R, int DIR>
+struct Radix;
+
+template <int DIR>
+struct Radix<1, DIR> {
+  __device__ __forceinline__ static void run(cpx*) {}
+};
+
+template <int DIR>
+struct Radix<2, DIR> {
+  __device__ __forceinline__ static void run(cpx* x) {
+    cpx a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  }
+};
+
+template <int DIR>
+struct Radix<3, DIR> {
+  __device__ __forceinline__ static void run(cpx* x) {
+    constexpr float s3 = float(0.86602540378443864676372317075294);  // sin(2 pi / 3)
+    cpx s = cadd(x[1], x[2]), d = csub(x[1], x[2]);
+    cpx a = {x[0].re - 0.5f * s.re, x[0].im - 0.5f * s.im};
+    cpx b = {s3 * d.re, s3 * d.im};
+    x[0] = cadd(x[0], s);
+    // X1 = a - i DIR b, X2 = a + i DIR b
+    x[1] = DIR > 0 ? cpx{a.re + b.im, a.im - b.re} : cpx{a.re - b.im, a.im + b.re};
+    x[2] = DIR > 0 ? cpx{a.re - b.im, a.im + b.re} : cpx{a.re + b.im, a.im - b.re};
+  }
+};
+
+template <int DIR>
+struct Radix<4, DIR> {
+  __device__ __forceinline__ static void run(cpx* x) {
+    cpx t0 = cadd(x[0], x[2]), t1 = cadd(x[1], x[3]);
+    cpx t2 = csub(x[0], x[2]), t3 = csub(x[1], x[3]);
+    // t3 * (-i DIR)
+    cpx t3r = DIR > 0 ? cpx{t3.im, -t3.re} : cpx{-t3.im, t3.re};
+    x[0] = cadd(t0, t1);
+    x[2] = csub(t0, t1);
+    x[1] = cadd(t2, t3r);
+    x[3] = csub(t2, t3r);
+  }
+};
+
+template <int DIR>
+struct Radix<5, DIR> {
+  __device__ __forceinline__ static void run(cpx* x) {
+    constexpr float c1 = float(0.30901699437494742410229341718282);   // cos(2 pi / 5)
+    constexpr float c2 = float(-0.80901699437494742410229341718282);  // cos(4 pi / 5)
+    constexpr float s1 = float(0.95105651629515357211643933337938);   // sin(2 pi / 5)
+    constexpr float s2 = float(0.58778525229247312916870595463907);   // sin(4 pi / 5)
+    cpx sA = cadd(x[1], x[4]), dA = csub(x[1], x[4]);
+    cpx sB = cadd(x[2], x[3]), dB = csub(x[2], x[3]);
+    cpx x0 = x[0];
+    cpx a1 = {fmaf(c2, sB.re, fmaf(c1, sA.re, x0.re)), fmaf(c2, sB.im, fmaf(c1, sA.im, x0.im))};
+    cpx a2 = {fmaf(c1, sB.re, fmaf(c2, sA.re, x0.re)), fmaf(c1, sB.im, fmaf(c2, sA.im, x0.im))};
+    cpx b1 = {fmaf(s2, dB.re, s1 * dA.re), fmaf(s2, dB.im, s1 * dA.im)};
+    cpx b2 = {fmaf(-s1, dB.re, s2 * dA.re), fmaf(-s1, dB.im, s2 * dA.im)};
+    x[0] = {x0.re + sA.re + sB.re, x0.im + sA.im + sB.im};
+    // X_k = a_k - i DIR b_k, X_{5-k} = a_k + i DIR b_k
+    if constexpr (DIR > 0) {
+      x[1] = {a1.re + b1.im, a1.im - b1.re};
+      x[4] = {a1.re - b1.im, a1.im + b1.re};
+      x[2] = {a2.re + b2.im, a2.im - b2.re};
+      x[3] = {a2.re - b2.im, a2.im + b2.re};
+    } else {
+      x[1] = {a1.re - b1.im, a1.im + b1.re};
+      x[4] = {a1.re + b1.im, a1.im - b1.re};
+      x[2] = {a2.re - b2.im, a2.im + b2.re};
+      x[3] = {a2.re + b2.im, a2.im - b2.re};
+    }
+  }
+};
+
+constexpr int first_radix(int n) {
+  if (n % 4 == 0 && n != 8) return 4;
+  if (n % 2 == 0) return 2;
+  if (n % 3 == 0) return 3;
+  if (n % 5 == 0) return 5;
+  return n;
+}
+
+// Composite length: decimation in time, E = R * Q.
+//   X[k1 + Q k2] = sum_r w_E^{r k1} w_R^{r k2} DFT_Q(x[R q + r])[k1]
+template <int E, int DIR>
+struct Dft {
+  static constexpr int R = first_radix(E);
+  static constexpr int Q = E / R;
+  __device__ __forceinline__ static void run(cpx (&x)[E]) {
+    if constexpr (Q == 1) {
+      Radix<R, DIR>::run(x);
+    } else {
+      cpx t[R][Q];
+      static_for<0, R>([&](auto r_) {
+        constexpr int r = decltype(r_)::value;
+        static_for<0, Q>([&](auto q_) {
+          constexpr int q = decltype(q_)::value;
+          t[r][q] = x[R * q + r];
+        });
+        Dft<Q, DIR>::run(t[r]);
+        static_for<0, Q>([&](auto k_) {
+          constexpr int k1 = decltype(k_)::value;
+          t[r][k1] = twiddle<long(r) * k1, E, DIR>(t[r][k1]);
+        });
+      });
+      static_for<0, Q>([&](auto k_) {
+        constexpr int k1 = decltype(k_)::value;
+        cpx u[R];
+        static_for<0, R>([&](auto r_) {
+          constexpr int r = decltype(r_)::value;
+          u[r] = t[r][k1];
+        });
+        Radix<R, DIR>::run(u);
+        static_for<0, R>([&](auto k2_) {
+          constexpr int k2 = decltype(k2_)::value;
+          x[k1 + Q * k2] = u[k2];
+        });
+      });
+    }
+  }
+};
+
+template <int DIR>
+struct Dft<1, DIR> {
+  __device__ __forceinline__ static void run(cpx (&)[1]) {}
+};
+
+// ---------------------------------------------------------------------------
+// Cross-lane moves.  DPP quad_perm: lane i of each quad reads lane perm[i].
+template <int CTRL>
+__device__ __forceinline__ float quad_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+// Lane i reads lane i ^ 4 (partner quad of an 8-lane team), ds_swizzle bit mode.
+__device__ __forceinline__ float swap_quads(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
+}
+
+}  // namespace pwfs

@@ -1,0 +1,45 @@
+// pwfs_launch.h -- argument bundle between the C ABI and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace pwfs {
+
+struct cpx;
+
+struct MeasureArgs {
+  // geometry
+  int P, n_bin, K, n_a, nv, norm_mode;
+  // batch slice and work split
+  int B, a_chunk, k_chunk, n_chunks;
+  double kphase;  // 2 pi 1e-9 / lambda
+  // inputs / outputs
+  const float* opd;
+  float* pupils;
+  float* slopes;
+  // plan tables
+  const float* amp;
+  const cpx* ramp_a;   // [n_a][P]
+  const cpx* ramp_b;   // [K][P]
+  const cpx* twist;    // [2][P]
+  const cpx* mid;      // [4][P/4]
+  const cpx* outw;     // [2][P]
+  const int* k_order;  // [K]
+  const int* k_ia;     // [K]
+  const int* valid;    // [nv]
+  const float* sref;   // [2 nv]
+  // workspace
+  cpx* Rw;             // [B][n_a][2P][P]
+  float* partial;      // [B][n_chunks][4][S][S]
+};
+
+// ev: NULL, or four events recorded before the row pass, between the passes
+// and after the slopes kernel.
+hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
+hipError_t launch_fill(float* p, size_t n, float v, hipStream_t stream);
+hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, float alpha, float beta,
+                        float* m, hipStream_t stream);
+
+}  // namespace pwfs

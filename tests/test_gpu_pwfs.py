@@ -1,0 +1,138 @@
+"""Parity of the HIP pyramid sensor (through the C ABI) with the FP64 oracle.
+
+Gate: relative slope error ||s_gpu - s_orc|| / ||s_orc|| <= 1e-5 per frame on
+reference-subtracted slopes; binned pupils within 2e-6 relative (FP32
+accumulation over the modulation points and bins).
+"""
+import numpy as np
+import pytest
+
+from synth.configs import CFG1, CFG2, ATMO1, ATMO2, CFG4_R0_RANGE, SensorConfig
+from synth.screens import open_loop_batch, tilt_opd_nm
+import oracle
+from tests.gpu_common import torch_cuda, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+SLOPE_TOL = 1e-5
+PUPIL_TOL = 2e-6
+
+CFG_P64 = SensorConfig(name="p64_k12_b8", n_fft=256, n_pupil=64, n_bin=8, n_mod=12,
+                       mod_radius_lod=2.0, wavelength_m=850e-9, diameter_m=4.0, obstruction=0.2)
+CFG_P64N = SensorConfig(name="p64_k9_b1_norm1", n_fft=256, n_pupil=64, n_bin=1, n_mod=9,
+                        mod_radius_lod=1.5, wavelength_m=650e-9, diameter_m=4.0, norm_mode=1)
+
+_ORC = {}
+
+
+def orc_for(cfg):
+    if cfg.name not in _ORC:
+        _ORC[cfg.name] = oracle.Oracle(cfg)
+    return _ORC[cfg.name]
+
+
+def _check_batch(cfg, opd, batch_max, check_frames=None):
+    import paper_1607_07624_amd as pw
+    torch = torch_cuda()
+    say(f"[gpu] {cfg.name}: B={len(opd)} batch_max={batch_max}")
+    plan = pw.Plan(cfg, batch_max=batch_max)
+    orc = orc_for(cfg)
+    assert plan.n_valid == orc.n_valid
+    assert np.array_equal(plan.valid, orc.valid)
+    d = torch.from_numpy(np.ascontiguousarray(opd)).cuda()
+    pup, s = plan.measure(d)
+    torch.cuda.synchronize()
+    pup, s = pup.cpu().numpy(), s.cpu().numpy()
+    frames = range(len(opd)) if check_frames is None else check_frames
+    worst = 0.0
+    for i in frames:
+        p_o, s_o = orc.measure(opd[i].astype(np.float64))
+        e_s = rel_l2(s[i], s_o)
+        e_p = rel_l2(pup[i], p_o)
+        say(f"[gpu]   frame {i}: slope rel err {e_s:.3e}  pupil rel err {e_p:.3e}")
+        assert e_s <= SLOPE_TOL, (i, e_s)
+        assert e_p <= PUPIL_TOL, (i, e_p)
+        worst = max(worst, e_s)
+    plan.close()
+    return worst
+
+
+def test_reference_slopes_match_oracle():
+    """Flat-wavefront slopes vanish exactly in exact arithmetic (phase
+    conjugation symmetry with Delta = N/4), so the check is absolute: FP32
+    rounding of O(1) intensities only."""
+    import paper_1607_07624_amd as pw
+    torch_cuda()
+    for cfg in (CFG1, CFG2, CFG_P64):
+        plan = pw.Plan(cfg, batch_max=2)
+        orc = orc_for(cfg)
+        e = float(np.abs(plan.s_ref.astype(np.float64) - orc.s_ref).max())
+        say(f"[gpu] {cfg.name}: reference slope max abs err {e:.3e}")
+        assert e <= 1e-6
+        plan.close()
+
+
+def test_cfg1_open_loop_four_seeds():
+    opd, _ = open_loop_batch(CFG1, ATMO1, [0, 1, 2, 3], screen_n=64)
+    _check_batch(CFG1, opd, batch_max=4)
+
+
+def test_cfg1_batch_slicing_ragged_tail():
+    opd, _ = open_loop_batch(CFG1, ATMO1, list(range(10, 17)), screen_n=64)
+    _check_batch(CFG1, opd, batch_max=3)
+
+
+def test_cfg2_open_loop_random_r0():
+    opd, r0 = open_loop_batch(CFG2, ATMO2, [0, 1, 2], r0_range=CFG4_R0_RANGE)
+    _check_batch(CFG2, opd, batch_max=3)
+
+
+def test_cfg2_full_batch_sampled_frames():
+    """The timed launch shape (16 frames in one call); frames 0 and 15 checked."""
+    opd, _ = open_loop_batch(CFG2, ATMO2, list(range(100, 116)), r0_range=CFG4_R0_RANGE)
+    _check_batch(CFG2, opd, batch_max=16, check_frames=[0, 15])
+
+
+@pytest.mark.parametrize("cfg", [CFG_P64, CFG_P64N], ids=lambda c: c.name)
+def test_other_geometries(cfg):
+    from synth.configs import AtmoConfig
+    opd, _ = open_loop_batch(cfg, AtmoConfig(r0_m=0.1, L0_m=20.0), [5, 6])
+    _check_batch(cfg, opd, batch_max=2)
+
+
+def test_flat_wavefront_gives_zero_and_tilt_sign():
+    import paper_1607_07624_amd as pw
+    torch = torch_cuda()
+    plan = pw.Plan(CFG1, batch_max=4)
+    P = CFG1.n_pupil
+    opd = np.stack([np.zeros((P, P)), tilt_opd_nm(P, 0.3, CFG1.wavelength_m),
+                    tilt_opd_nm(P, -0.3, CFG1.wavelength_m),
+                    tilt_opd_nm(P, 0.3, CFG1.wavelength_m, "y")]).astype(np.float32)
+    _, s = plan.measure(torch.from_numpy(opd).cuda())
+    s = s.cpu().numpy()
+    nv = plan.n_valid
+    assert np.all(s[0] == 0.0)
+    assert s[1, :nv].mean() > 0 and s[2, :nv].mean() < 0 and s[3, nv:].mean() > 0
+    orc = orc_for(CFG1)
+    for i in (1, 2, 3):
+        assert rel_l2(s[i], orc.measure(opd[i].astype(np.float64))[1]) <= SLOPE_TOL
+
+
+def test_bitwise_reproducible_and_empty_batch():
+    import paper_1607_07624_amd as pw
+    torch = torch_cuda()
+    plan = pw.Plan(CFG2, batch_max=4)
+    opd, _ = open_loop_batch(CFG2, ATMO2, [7, 8, 9, 10])
+    d = torch.from_numpy(opd).cuda()
+    p1, s1 = plan.measure(d)
+    p2, s2 = plan.measure(d)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p2) and torch.equal(s1, s2)
+    empty = torch.empty((0, CFG2.n_pupil, CFG2.n_pupil), device="cuda")
+    pe, se = plan.measure(empty)
+    assert se.shape == (0, 2 * plan.n_valid)
+    # Pupils only (slopes pointer NULL) gives the same pupils.
+    pupils = torch.empty_like(p1)
+    plan.measure_into(d, pupils, None)
+    torch.cuda.synchronize()
+    assert torch.equal(pupils, p1)

@@ -286,3 +286,24 @@ def test_random_screen_slopes_reference_subtracted():
     _, s0 = orc.measure(np.zeros_like(opd[0]))
     assert np.abs(s0).max() < 1e-15
     assert np.isfinite(s).all() and np.abs(s).max() > 1e-3
+
+
+@pytest.mark.parametrize("cfg", [TINY24, SMALL, CFG1])
+def test_response_is_odd_in_phase(cfg):
+    """With Delta = N/4 the conjugate mask equals the mask times (-1)^u, a
+    shift by N/2 = 2 Delta, so conj(T g) is T conj(g) moved from one window
+    to the other.  For a real pupil and a modulation ring symmetric in the
+    x tilt this makes every subaperture's slopes exactly odd in the phase,
+    s(-phi) = -s(phi), and the flat-wavefront reference exactly zero."""
+    orc = oracle.Oracle(cfg)
+    rng = np.random.default_rng(11)
+    opd = rng.normal(0, 300.0, (cfg.n_pupil, cfg.n_pupil))
+    _, sp = orc.measure(opd)
+    _, sm = orc.measure(-opd)
+    assert np.abs(sp + sm).max() <= 1e-12 * np.abs(sp).max()
+    assert np.abs(orc.s_ref).max() < 1e-13
+    pp = orc.pupils(opd)
+    pm = orc.pupils(-opd)
+    # Pupil-level statement: I_q(phi) = I_(q xor 1 xor 2)(-phi)
+    for q in range(4):
+        assert np.abs(pp[q] - pm[q ^ 3]).max() <= 1e-12 * pp.max()
