@@ -73,6 +73,24 @@ def line_flops(P: int, intensity: bool) -> int:
     return 2 * projection + f + twist + out + acc
 
 
+def calibrate(plan, modes_dev, B, ns, eps_nm, torch, dev):
+    """Push-pull interaction matrix measured on the GPU, full-SVD pseudo-inverse (FP64, host)."""
+    M = modes_dev.shape[0]
+    IM = np.empty((ns, M))
+    h = max(1, B // 2)
+    for i0 in range(0, M, h):
+        idx = list(range(i0, min(M, i0 + h)))
+        push = torch.cat([eps_nm * modes_dev[idx], -eps_nm * modes_dev[idx]]).contiguous()
+        sl = torch.empty((push.shape[0], ns), device=dev)
+        plan.measure_into(push, None, sl)
+        sl = sl.cpu().numpy().astype(np.float64)
+        n = len(idx)
+        IM[:, idx] = ((sl[:n] - sl[n:]) / (2.0 * eps_nm)).T
+    U, sig, Vt = np.linalg.svd(IM, full_matrices=False)
+    log(f"IM condition number {sig[0] / sig[-1]:.1f}")
+    return (Vt.T / sig) @ U.T
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +101,10 @@ def main():
     ap.add_argument("--loop-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
+    ap.add_argument("--random-R", action="store_true",
+                    help="profiling runs: skip calibration, use a random reconstructor of the same shape")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed region, one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
@@ -115,23 +137,18 @@ def main():
     log("calibration")
     t0 = time.time()
     amp = plan.pupil.astype(np.float64)
-    modes = kl_modes(amp, cfg.pixel_m, ATMO2.L0_m, N_KL_MODES)
-    M = modes.shape[0]
-    modes_dev = torch.from_numpy(modes.astype(np.float32)).to(dev)
-    IM = np.empty((ns, M))
     s_buf = torch.empty((B, ns), device=dev)
-    for i0 in range(0, M, B // 2):
-        idx = list(range(i0, min(M, i0 + B // 2)))
-        push = torch.cat([PUSH_PULL_NM * modes_dev[idx], -PUSH_PULL_NM * modes_dev[idx]]).contiguous()
-        sl = torch.empty((push.shape[0], ns), device=dev)
-        plan.measure_into(push, None, sl)
-        sl = sl.cpu().numpy().astype(np.float64)
-        n = len(idx)
-        IM[:, idx] = ((sl[:n] - sl[n:]) / (2.0 * PUSH_PULL_NM)).T
-    U, sig, Vt = np.linalg.svd(IM, full_matrices=False)
-    R_host = (Vt.T / sig) @ U.T
+    if args.random_R:
+        args.no_loop = True
+        M = N_KL_MODES
+        R_host = np.random.default_rng(0).standard_normal((M, ns)) * 1e-2
+    else:
+        modes = kl_modes(amp, cfg.pixel_m, ATMO2.L0_m, N_KL_MODES)
+        M = modes.shape[0]
+        modes_dev = torch.from_numpy(modes.astype(np.float32)).to(dev)
+        R_host = calibrate(plan, modes_dev, B, ns, PUSH_PULL_NM, torch, dev)
     R = torch.from_numpy(R_host.astype(np.float32)).to(dev).contiguous()
-    log(f"calibration {time.time() - t0:.1f}s, cond {sig[0] / sig[-1]:.1f}")
+    log(f"calibration {time.time() - t0:.1f}s")
 
     modes_out = torch.empty((B, M), device=dev)
 
@@ -158,6 +175,16 @@ def main():
     ms_step = ms_total / args.steps
     fps = B * args.steps / (ms_total / 1e3)
     log(f"{fps:.0f} frames/s, {ms_step:.3f} ms/step (wall {wall:.2f}s) kernels {kt}")
+
+    if args.copy_mb:
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty(n, device=dev)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy of {args.copy_mb} MiB done")
+        del src, dst
 
     # Roofline of the column pass (dominant kernel).
     n_launch = kt["slices"]

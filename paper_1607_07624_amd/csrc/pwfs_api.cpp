@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <complex>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -15,7 +16,7 @@
 #include "pwfs_launch.h"
 
 namespace pwfs {
-struct cpx {
+struct alignas(8) cpx {
   float re, im;
 };
 }  // namespace pwfs
@@ -91,9 +92,10 @@ struct pwfs_plan_s {
   std::vector<int> valid;
   // device tables
   float* amp = nullptr;
-  cpx* ramp_a = nullptr;
-  cpx* ramp_b = nullptr;
-  cpx* twist = nullptr;
+  cpx* in_a = nullptr;
+  cpx* f_a = nullptr;
+  cpx* in_b = nullptr;
+  cpx* f_b = nullptr;
   cpx* mid = nullptr;
   cpx* outw = nullptr;
   int* k_order = nullptr;
@@ -103,6 +105,7 @@ struct pwfs_plan_s {
   // workspace
   cpx* Rw = nullptr;
   float* partial = nullptr;
+  float* pupils = nullptr;
   float* zero_opd = nullptr;
   float* tmp_slopes = nullptr;
   size_t ws_bytes = 0;
@@ -154,8 +157,8 @@ int validate(const pwfs_config_t* c) {
 void free_plan(pwfs_plan_s* p) {
   if (!p) return;
   DeviceGuard g(p->device);
-  void* ptrs[] = {p->amp, p->ramp_a, p->ramp_b, p->twist, p->mid, p->outw, p->k_order, p->k_ia,
-                  p->d_valid, p->sref, p->Rw, p->partial, p->zero_opd, p->tmp_slopes};
+  void* ptrs[] = {p->amp, p->in_a, p->f_a, p->in_b, p->f_b, p->mid, p->outw, p->k_order, p->k_ia,
+                  p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->zero_opd, p->tmp_slopes};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto* pool : {&p->ev_used, &p->ev_free})
@@ -179,12 +182,13 @@ int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* s
     split_work(p, Bs, &a.a_chunk, &a.k_chunk, &a.n_chunks);
     a.kphase = p->kphase;
     a.opd = opd + (size_t)b0 * p->P * p->P;
-    a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : nullptr;
+    a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : p->pupils;
     a.slopes = slopes ? slopes + (size_t)b0 * 2 * p->nv : nullptr;
     a.amp = p->amp;
-    a.ramp_a = p->ramp_a;
-    a.ramp_b = p->ramp_b;
-    a.twist = p->twist;
+    a.in_a = p->in_a;
+    a.f_a = p->f_a;
+    a.in_b = p->in_b;
+    a.f_b = p->f_b;
     a.mid = p->mid;
     a.outw = p->outw;
     a.k_order = p->k_order;
@@ -310,21 +314,44 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
     delete p;
     return fail(PWFS_ERR_INVALID_ARG, "internal: modulation ordering");
   }
+  // Tilt ramps r(x) = exp(i 2 pi t (x - xc) / N) (FP64), alone and times the
+  // twist w_N^{(2q+1) x} of the two quads.
   const double xc = 0.5 * (P - 1);
-  std::vector<cpx> ramp_a((size_t)p->n_a * P), ramp_b((size_t)K * P);
+  std::vector<std::complex<double>> tw(2 * (size_t)P);
+  for (int q = 0; q < 2; ++q)
+    for (int x = 0; x < P; ++x) {
+      const long n = ((long)(2 * q + 1) * x) % N;
+      const double ang = -2.0 * M_PI * (double)n / (double)N;
+      tw[(size_t)q * P + x] = {std::cos(ang), std::sin(ang)};
+    }
+  auto ramp = [&](double tilt, int x) {
+    const double turns = tilt * ((double)x - xc) / (double)N;
+    const double f = turns - std::floor(turns);
+    return std::complex<double>(std::cos(2.0 * M_PI * f), std::sin(2.0 * M_PI * f));
+  };
+  auto to32 = [](std::complex<double> z) { return cpx{(float)z.real(), (float)z.imag()}; };
+  std::vector<cpx> in_a((size_t)p->n_a * 2 * P), f_a((size_t)p->n_a * P), in_b((size_t)K * 2 * P),
+      f_b((size_t)K * P);
   for (int ia = 0; ia < p->n_a; ++ia) {
     const double a = rho * std::cos(2.0 * M_PI * (double)ia / (double)K);
-    for (int x = 0; x < P; ++x) ramp_a[(size_t)ia * P + x] = unit_turns(a * ((double)x - xc) / (double)N);
+    for (int x = 0; x < P; ++x) {
+      const std::complex<double> r = ramp(a, x);
+      f_a[(size_t)ia * P + x] = to32(r);
+      for (int q = 0; q < 2; ++q) in_a[((size_t)ia * 2 + q) * P + x] = to32(r * tw[(size_t)q * P + x]);
+    }
   }
   for (int k = 0; k < K; ++k) {
     const double bk = rho * std::sin(2.0 * M_PI * (double)k / (double)K);
-    for (int y = 0; y < P; ++y) ramp_b[(size_t)k * P + y] = unit_turns(bk * ((double)y - xc) / (double)N);
+    for (int y = 0; y < P; ++y) {
+      const std::complex<double> r = ramp(bk, y);
+      f_b[(size_t)k * P + y] = to32(r);
+      for (int q = 0; q < 2; ++q) in_b[((size_t)k * 2 + q) * P + y] = to32(r * tw[(size_t)q * P + y]);
+    }
   }
   // Pyramid line-operator tables.
-  std::vector<cpx> twist(2 * (size_t)P), outw(2 * (size_t)P), mid(4 * (size_t)p->E);
+  std::vector<cpx> outw(2 * (size_t)P), mid(4 * (size_t)p->E);
   for (int q = 0; q < 2; ++q)
     for (int x = 0; x < P; ++x) {
-      twist[(size_t)q * P + x] = unit_frac((long)(2 * q + 1) * x, N, +1);
       cpx w = unit_frac((long)(2 * q + 1) * x, N, -1);
       const float sc = (float)(2.0 / (double)N);
       outw[(size_t)q * P + x] = {w.re * sc, w.im * sc};
@@ -343,9 +370,10 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   const size_t rw_elems = (size_t)bm * p->n_a * 2 * P * P;
   struct A { void** ptr; size_t bytes; const char* what; } allocs[] = {
       {(void**)&p->amp, amp.size() * sizeof(float), "amp"},
-      {(void**)&p->ramp_a, ramp_a.size() * sizeof(cpx), "ramp_a"},
-      {(void**)&p->ramp_b, ramp_b.size() * sizeof(cpx), "ramp_b"},
-      {(void**)&p->twist, twist.size() * sizeof(cpx), "twist"},
+      {(void**)&p->in_a, in_a.size() * sizeof(cpx), "in_a"},
+      {(void**)&p->f_a, f_a.size() * sizeof(cpx), "f_a"},
+      {(void**)&p->in_b, in_b.size() * sizeof(cpx), "in_b"},
+      {(void**)&p->f_b, f_b.size() * sizeof(cpx), "f_b"},
       {(void**)&p->mid, mid.size() * sizeof(cpx), "mid"},
       {(void**)&p->outw, outw.size() * sizeof(cpx), "outw"},
       {(void**)&p->k_order, (size_t)K * sizeof(int), "k_order"},
@@ -354,6 +382,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {(void**)&p->sref, (size_t)2 * p->nv * sizeof(float), "sref"},
       {(void**)&p->Rw, rw_elems * sizeof(cpx), "row-pass workspace"},
       {(void**)&p->partial, partial_elems * sizeof(float), "pupil partials"},
+      {(void**)&p->pupils, (size_t)bm * 4 * S * S * sizeof(float), "pupil scratch"},
       {(void**)&p->zero_opd, (size_t)P * P * sizeof(float), "zero opd"},
       {(void**)&p->tmp_slopes, (size_t)2 * p->nv * sizeof(float), "reference scratch"},
   };
@@ -367,9 +396,10 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   }
   struct C { void* dst; const void* src; size_t bytes; } copies[] = {
       {p->amp, amp.data(), amp.size() * sizeof(float)},
-      {p->ramp_a, ramp_a.data(), ramp_a.size() * sizeof(cpx)},
-      {p->ramp_b, ramp_b.data(), ramp_b.size() * sizeof(cpx)},
-      {p->twist, twist.data(), twist.size() * sizeof(cpx)},
+      {p->in_a, in_a.data(), in_a.size() * sizeof(cpx)},
+      {p->f_a, f_a.data(), f_a.size() * sizeof(cpx)},
+      {p->in_b, in_b.data(), in_b.size() * sizeof(cpx)},
+      {p->f_b, f_b.data(), f_b.size() * sizeof(cpx)},
       {p->mid, mid.data(), mid.size() * sizeof(cpx)},
       {p->outw, outw.data(), outw.size() * sizeof(cpx)},
       {p->k_order, k_order.data(), (size_t)K * sizeof(int)},

@@ -12,7 +12,7 @@
 
 namespace pwfs {
 
-struct cpx {
+struct alignas(8) cpx {
   float re, im;
 };
 

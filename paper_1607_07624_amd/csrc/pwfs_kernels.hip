@@ -78,20 +78,21 @@ __device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ m
   fence();
 }
 
-// Full 1-D pyramid operator for one line.  load_f(m) returns f(l + 4 m) for
-// this lane's line (f = tilted input field).  On return quad 0 holds
-// y_L(l + 4 m) and quad 1 holds y_H(l + 4 m) in v[m].
-//   twist[q * P + x] = w_N^{(2q+1) x},  outw[q * P + j] = (2/N) w_N^{-(2q+1) j}.
-template <int E, typename LoadF>
-__device__ __forceinline__ void line_op(cpx (&v)[E], LoadF&& load_f, const cpx* __restrict__ twist,
+// Full 1-D pyramid operator for one line.
+//   load_in(m)  = f(x) w_N^{(2q+1) x} at x = l + 4 m (tilted input times this
+//                 quad's twist, one complex product from a combined table);
+//   load_f(m)   = f(l + 4 m) (needed by quad 0 for y_L = f - y_H);
+//   outw[q * P + j] = (2/N) w_N^{-(2q+1) j}.
+// On return quad 0 holds y_L(l + 4 m) and quad 1 holds y_H(l + 4 m) in v[m].
+template <int E, typename LoadIn, typename LoadF>
+__device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadF&& load_f,
                                         const cpx* __restrict__ mid, const cpx* __restrict__ outw,
                                         int q, int l) {
   constexpr int P = 4 * E;
-  const cpx* tw = twist + q * P + l;
   static_for<0, E>([&](auto m_) {
     constexpr int m = decltype(m_)::value;
     if constexpr (m % 8 == 0 && m > 0) fence();
-    v[m] = cmul(load_f(m), tw[4 * m]);
+    v[m] = load_in(m);
   });
   fence();
   half_band<E>(v, mid, l);
@@ -113,18 +114,31 @@ __device__ __forceinline__ size_t rw_index(int xp, int y, int P) {
   return ((size_t)(xp >> 3) * (size_t)(P >> 2) + (size_t)(y >> 2)) * 32u + (size_t)((xp & 7) * 4 + (y & 3));
 }
 
+// Wave-cooperative copy of n16 16-byte words (global -> LDS).
+__device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __restrict__ src, int n16, int lane) {
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  for (int i = lane; i < n16; i += 64) d[i] = s[i];
+}
+
 // ---------------------------------------------------------------------------
 // Row pass.  Block = one wave = 8 pupil rows of one frame, looping over a
 // chunk of distinct x tilts.  The pupil field A exp(i phi) of the 8 rows is
-// staged once in LDS; the phase is formed and range-reduced in FP64.
+// staged once in LDS (phase formed and range-reduced in FP64); the tilt
+// tables of each x tilt and the constant pyramid tables are staged in LDS.
+//   in_a[ia][q][x] = r_a(x) w_N^{(2q+1) x},  f_a[ia][x] = r_a(x).
 template <int E>
 __global__ __launch_bounds__(64) void row_pass_kernel(
     const float* __restrict__ opd, const float* __restrict__ amp, double kphase,
-    const cpx* __restrict__ ramp_a, const cpx* __restrict__ twist, const cpx* __restrict__ mid,
+    const cpx* __restrict__ in_a, const cpx* __restrict__ f_a, const cpx* __restrict__ mid,
     const cpx* __restrict__ outw, cpx* __restrict__ Rw, int n_a, int a_chunk) {
   constexpr int P = 4 * E;
   constexpr int LDP = P + 4;
   __shared__ cpx field[8 * LDP];
+  __shared__ __align__(16) cpx s_in[2 * P];
+  __shared__ __align__(16) cpx s_f[P];
+  __shared__ __align__(16) cpx s_mid[4 * E];
+  __shared__ __align__(16) cpx s_out[2 * P];
   const int lane = threadIdx.x;
   const int t = lane >> 3, q = (lane >> 2) & 1, l = lane & 3;
   const int y0 = blockIdx.x * 8;
@@ -143,60 +157,93 @@ __global__ __launch_bounds__(64) void row_pass_kernel(
     const float A = amp[y * P + x];
     field[r * LDP + x] = {A * c, A * s};
   }
-  __syncthreads();
+  copy16(s_mid, mid, (4 * E) / 2, lane);
+  copy16(s_out, outw, P, lane);
   const int a1 = min(a0 + a_chunk, n_a);
   const cpx* frow = field + t * LDP + l;
   const int y = y0 + t;
   for (int ia = a0; ia < a1; ++ia) {
-    const cpx* ra = ramp_a + (size_t)ia * P + l;
-    auto load_f = [&](int m) { return cmul(frow[4 * m], ra[4 * m]); };
+    __syncthreads();
+    copy16(s_in, in_a + (size_t)ia * 2 * P, P, lane);
+    copy16(s_f, f_a + (size_t)ia * P, P / 2, lane);
+    __syncthreads();
+    const cpx* tin = s_in + q * P + l;
+    const cpx* tf = s_f + l;
     cpx v[E];
-    line_op<E>(v, load_f, opaque(twist), opaque(mid), opaque(outw), q, l);
-    cpx* out = Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P);
+    line_op<E>(v, [&](int m) { return cmul(frow[4 * m], tin[4 * m]); },
+               [&](int m) { return cmul(frow[4 * m], tf[4 * m]); }, s_mid, s_out, q, l);
+    // Element (x' = qP + l + 4m, y) sits at base + (m >> 1) 8P + (m & 1) 16
+    // (see rw_index); each address is formed just before its store so the
+    // compiler does not keep E 64-bit addresses live across the transforms.
+    cpx* out = Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P) + rw_index(q * P + l, y, P);
+    fence();
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
-      out[rw_index(q * P + l + 4 * m, y, P)] = v[m];
+      cpx* o = out + (size_t)((m >> 1) * 8 * P + (m & 1) * 16);
+      asm volatile("" : "+v"(o));
+      *o = v[m];
     });
   }
 }
 
 // ---------------------------------------------------------------------------
 // Column pass.  Block = one wave = 8 adjacent columns x' of one frame and
-// one chunk of modulation points.  Each team accumulates |E|^2 of its
-// column over the chunk in registers; the wave then bins b x b through LDS
-// and writes its part of the chunk's four pupil images.
+// one chunk of modulation points.  In the intermediate layout the 8 columns
+// form one contiguous block of 8P complex values, staged in LDS once per
+// distinct x tilt (k and K-k are adjacent in the modulation order and
+// share it).  Each team accumulates |E|^2 of its column over the chunk in
+// registers; the wave then bins b x b through LDS and writes its part of
+// the chunk's four pupil images.
+//   in_b[k][q][y] = r_b(y) w_N^{(2q+1) y},  f_b[k][y] = r_b(y).
 template <int E>
 __global__ __launch_bounds__(64) void col_pass_kernel(
-    const cpx* __restrict__ Rw, const cpx* __restrict__ ramp_b, const int* __restrict__ k_order,
-    const int* __restrict__ k_ia, const cpx* __restrict__ twist, const cpx* __restrict__ mid,
+    const cpx* __restrict__ Rw, const cpx* __restrict__ in_b, const cpx* __restrict__ f_b,
+    const int* __restrict__ k_order, const int* __restrict__ k_ia, const cpx* __restrict__ mid,
     const cpx* __restrict__ outw, float* __restrict__ partial, int n_a, int K, int k_chunk,
     int n_chunks, int n_bin) {
   constexpr int P = 4 * E;
-  __shared__ float tile[8 * 2 * P];
+  __shared__ __align__(16) cpx s_col[8 * P];
+  __shared__ __align__(16) cpx s_in[2 * P];
+  __shared__ __align__(16) cpx s_f[P];
+  __shared__ __align__(16) cpx s_mid[4 * E];
+  __shared__ __align__(16) cpx s_out[2 * P];
   const int lane = threadIdx.x;
   const int t = lane >> 3, q = (lane >> 2) & 1, l = lane & 3;
   const int X0 = blockIdx.x * 8;
   const int chunk = blockIdx.y;
   const size_t fr = blockIdx.z;
-  const int xp = X0 + t;
   float acc[E];
   static_for<0, E>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
+  copy16(s_mid, mid, (4 * E) / 2, lane);
+  copy16(s_out, outw, P, lane);
   const int kb = chunk * k_chunk;
   const int ke = min(kb + k_chunk, K);
-  // Column xp, rows y = l + 4 m: base of the (x'/8, y/4 = m) tiles for this lane.
-  const size_t col_off = (size_t)(xp >> 3) * (size_t)(P >> 2) * 32u + (size_t)((xp & 7) * 4 + l);
+  const cpx* frame = Rw + fr * (size_t)n_a * (size_t)(2 * P * P) + (size_t)(X0 >> 3) * (size_t)(8 * P);
+  const cpx* col = s_col + t * 4 + l;           // element (x' = X0 + t, y = l + 4 m) at col[32 m]
+  const cpx* tin = s_in + q * P + l;
+  const cpx* tf = s_f + l;
+  int cur_ia = -1;
   for (int kk = kb; kk < ke; ++kk) {
     const int k = k_order[kk];
-    const cpx* src = Rw + (fr * (size_t)n_a + k_ia[k]) * (size_t)(2 * P * P) + col_off;
-    const cpx* rb = ramp_b + (size_t)k * P + l;
-    auto load_f = [&](int m) { return cmul(src[32 * m], rb[4 * m]); };
+    const int ia = k_ia[k];
+    __syncthreads();
+    if (ia != cur_ia) {
+      copy16(s_col, frame + (size_t)ia * (size_t)(2 * P * P), 4 * P, lane);
+      cur_ia = ia;
+    }
+    copy16(s_in, in_b + (size_t)k * 2 * P, P, lane);
+    copy16(s_f, f_b + (size_t)k * P, P / 2, lane);
+    __syncthreads();
     cpx v[E];
-    line_op<E>(v, load_f, opaque(twist), opaque(mid), opaque(outw), q, l);
+    line_op<E>(v, [&](int m) { return cmul(col[32 * m], tin[4 * m]); },
+               [&](int m) { return cmul(col[32 * m], tf[4 * m]); }, s_mid, s_out, q, l);
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
       acc[m] = fmaf(v[m].re, v[m].re, fmaf(v[m].im, v[m].im, acc[m]));
     });
   }
+  __syncthreads();
+  float* tile = reinterpret_cast<float*>(s_col);   // [8 cols][2 windows][P rows]
   float* my = tile + (t * 2 + q) * P + l;
   static_for<0, E>([&](auto m_) {
     constexpr int m = decltype(m_)::value;
@@ -215,65 +262,66 @@ __global__ __launch_bounds__(64) void col_pass_kernel(
     const int iy = rem - qq * S;
     float s = 0.f;
     for (int dx = 0; dx < n_bin; ++dx) {
-      const float* col = tile + ((bc * n_bin + dx) * 2 + qq) * P + iy * n_bin;
-      for (int dy = 0; dy < n_bin; ++dy) s += col[dy];
+      const float* c = tile + ((bc * n_bin + dx) * 2 + qq) * P + iy * n_bin;
+      for (int dy = 0; dy < n_bin; ++dy) s += c[dy];
     }
     dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = s;
   }
 }
 
 // ---------------------------------------------------------------------------
-// Slopes.  One block per frame: sum the chunk partials (fixed order),
-// scale by 1/K, optionally write the pupils, then the flux normalisation
-// (fixed-order tree) and the reference-subtracted slopes.  The partials are
-// re-read in the second sweep rather than staged, so any pupil size fits.
-__device__ __forceinline__ float chunk_sum(const float* __restrict__ pp, int n_chunks, size_t stride,
-                                           size_t idx, float inv_k) {
+// Pupil reduction: sum of the chunk partials in chunk order (fixed order,
+// loads issued four at a time), scaled by 1/K.  One thread per binned pixel.
+__global__ __launch_bounds__(256) void pupil_reduce_kernel(const float* __restrict__ partial, int n_chunks,
+                                                           int n4ss, float inv_k, float* __restrict__ pupils) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const size_t fr = blockIdx.y;
+  if (i >= n4ss) return;
+  const size_t stride = (size_t)n4ss;
+  const float* pp = partial + fr * (size_t)n_chunks * stride + i;
   float s = 0.f;
-  for (int c = 0; c < n_chunks; ++c) s += pp[(size_t)c * stride + idx];
-  return s * inv_k;
+  int c = 0;
+  for (; c + 4 <= n_chunks; c += 4) {
+    const float a = pp[(size_t)c * stride], b = pp[(size_t)(c + 1) * stride];
+    const float d = pp[(size_t)(c + 2) * stride], e = pp[(size_t)(c + 3) * stride];
+    s += a;
+    s += b;
+    s += d;
+    s += e;
+  }
+  for (; c < n_chunks; ++c) s += pp[(size_t)c * stride];
+  pupils[fr * stride + i] = s * inv_k;
 }
 
-__global__ __launch_bounds__(256) void slopes_kernel(
-    const float* __restrict__ partial, int n_chunks, int S, float inv_k,
-    const int* __restrict__ valid, int nv, const float* __restrict__ sref, int norm_mode,
-    float* __restrict__ pupils, float* __restrict__ slopes) {
-  __shared__ float red[256];
+// Slopes.  One block of 1024 threads per frame: mean total flux over the
+// valid subapertures (fixed-order tree), then reference-subtracted slopes.
+__global__ __launch_bounds__(1024) void slopes_kernel(const float* __restrict__ pupils, int S,
+                                                      const int* __restrict__ valid, int nv,
+                                                      const float* __restrict__ sref, int norm_mode,
+                                                      float* __restrict__ slopes) {
+  __shared__ float red[1024];
   const int tid = threadIdx.x;
   const size_t fr = blockIdx.x;
   const size_t SS = (size_t)S * S;
-  const size_t stride = 4 * SS;
-  const float* pp = partial + fr * (size_t)n_chunks * stride;
-  if (pupils) {
-    float* po = pupils + fr * stride;
-    for (size_t i = tid; i < stride; i += 256) po[i] = chunk_sum(pp, n_chunks, stride, i, inv_k);
-  }
-  if (!slopes) return;
+  const float* pp = pupils + fr * 4 * SS;
   float loc = 0.f;
   if (norm_mode == 0) {
-    for (int v = tid; v < nv; v += 256) {
+    for (int v = tid; v < nv; v += 1024) {
       const size_t j = (size_t)valid[v];
-      const float i0 = chunk_sum(pp, n_chunks, stride, j, inv_k);
-      const float i1 = chunk_sum(pp, n_chunks, stride, SS + j, inv_k);
-      const float i2 = chunk_sum(pp, n_chunks, stride, 2 * SS + j, inv_k);
-      const float i3 = chunk_sum(pp, n_chunks, stride, 3 * SS + j, inv_k);
-      loc += (i0 + i1) + (i2 + i3);
+      loc += (pp[j] + pp[SS + j]) + (pp[2 * SS + j] + pp[3 * SS + j]);
     }
   }
   red[tid] = loc;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = 512; st > 0; st >>= 1) {
     if (tid < st) red[tid] += red[tid + st];
     __syncthreads();
   }
   const float mean_flux = red[0] / (float)nv;
   float* so = slopes + fr * 2 * (size_t)nv;
-  for (int v = tid; v < nv; v += 256) {
+  for (int v = tid; v < nv; v += 1024) {
     const size_t j = (size_t)valid[v];
-    const float i0 = chunk_sum(pp, n_chunks, stride, j, inv_k);
-    const float i1 = chunk_sum(pp, n_chunks, stride, SS + j, inv_k);
-    const float i2 = chunk_sum(pp, n_chunks, stride, 2 * SS + j, inv_k);
-    const float i3 = chunk_sum(pp, n_chunks, stride, 3 * SS + j, inv_k);
+    const float i0 = pp[j], i1 = pp[SS + j], i2 = pp[2 * SS + j], i3 = pp[3 * SS + j];
     const float n = norm_mode ? ((i0 + i1) + (i2 + i3)) : mean_flux;
     so[v] = ((i1 + i3) - (i0 + i2)) / n - sref[v];
     so[nv + v] = ((i2 + i3) - (i0 + i1)) / n - sref[nv + v];
@@ -324,16 +372,16 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R,
 template <int E>
 static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
   dim3 grid(a.P / 8, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
-  hipLaunchKernelGGL(row_pass_kernel<E>, grid, dim3(64), 0, st, a.opd, a.amp, a.kphase, a.ramp_a,
-                     a.twist, a.mid, a.outw, a.Rw, a.n_a, a.a_chunk);
+  hipLaunchKernelGGL(row_pass_kernel<E>, grid, dim3(64), 0, st, a.opd, a.amp, a.kphase, a.in_a, a.f_a,
+                     a.mid, a.outw, a.Rw, a.n_a, a.a_chunk);
   return hipGetLastError();
 }
 
 template <int E>
 static hipError_t launch_cols(const MeasureArgs& a, hipStream_t st) {
   dim3 grid(2 * a.P / 8, a.n_chunks, a.B);
-  hipLaunchKernelGGL(col_pass_kernel<E>, grid, dim3(64), 0, st, a.Rw, a.ramp_b, a.k_order, a.k_ia,
-                     a.twist, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
+  hipLaunchKernelGGL(col_pass_kernel<E>, grid, dim3(64), 0, st, a.Rw, a.in_b, a.f_b, a.k_order, a.k_ia,
+                     a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
   return hipGetLastError();
 }
 
@@ -357,9 +405,15 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
   const int S = a.P / a.n_bin;
-  hipLaunchKernelGGL(slopes_kernel, dim3(a.B), dim3(256), 0, st, a.partial, a.n_chunks, S,
-                     1.0f / (float)a.K, a.valid, a.nv, a.sref, a.norm_mode, a.pupils, a.slopes);
+  const int n4ss = 4 * S * S;
+  hipLaunchKernelGGL(pupil_reduce_kernel, dim3((n4ss + 255) / 256, a.B), dim3(256), 0, st, a.partial,
+                     a.n_chunks, n4ss, 1.0f / (float)a.K, a.pupils);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (a.slopes) {
+    hipLaunchKernelGGL(slopes_kernel, dim3(a.B), dim3(1024), 0, st, a.pupils, S, a.valid, a.nv, a.sref,
+                       a.norm_mode, a.slopes);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
   return hipSuccess;
 }

@@ -17,13 +17,14 @@ struct MeasureArgs {
   double kphase;  // 2 pi 1e-9 / lambda
   // inputs / outputs
   const float* opd;
-  float* pupils;
-  float* slopes;
+  float* pupils;       // [B][4][S][S]: the caller's buffer or the plan's scratch
+  float* slopes;       // [B][2 nv] or NULL
   // plan tables
   const float* amp;
-  const cpx* ramp_a;   // [n_a][P]
-  const cpx* ramp_b;   // [K][P]
-  const cpx* twist;    // [2][P]
+  const cpx* in_a;     // [n_a][2][P]  r_a(x) w_N^{(2q+1)x}
+  const cpx* f_a;      // [n_a][P]     r_a(x)
+  const cpx* in_b;     // [K][2][P]    r_b(y) w_N^{(2q+1)y}
+  const cpx* f_b;      // [K][P]       r_b(y)
   const cpx* mid;      // [4][P/4]
   const cpx* outw;     // [2][P]
   const int* k_order;  // [K]
