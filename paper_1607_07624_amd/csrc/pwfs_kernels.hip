@@ -39,6 +39,8 @@
 #include "pwfs_launch.h"
 
 #include <algorithm>
+#include <cstdint>
+#include <type_traits>
 
 namespace pwfs {
 
@@ -114,58 +116,62 @@ __device__ __forceinline__ size_t rw_index(int xp, int y, int P) {
   return ((size_t)(xp >> 3) * (size_t)(P >> 2) + (size_t)(y >> 2)) * 32u + (size_t)((xp & 7) * 4 + (y & 3));
 }
 
-// Wave-cooperative copy of n16 16-byte words (global -> LDS).
-__device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __restrict__ src, int n16, int lane) {
+// Block-cooperative copy of n16 16-byte words (global -> LDS).
+__device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __restrict__ src, int n16,
+                                       int tid, int nthreads) {
   uint4* d = reinterpret_cast<uint4*>(dst);
   const uint4* s = reinterpret_cast<const uint4*>(src);
-  for (int i = lane; i < n16; i += 64) d[i] = s[i];
+  for (int i = tid; i < n16; i += nthreads) d[i] = s[i];
 }
 
 // ---------------------------------------------------------------------------
-// Row pass.  Block = one wave = 8 pupil rows of one frame, looping over a
-// chunk of distinct x tilts.  The pupil field A exp(i phi) of the 8 rows is
-// staged once in LDS (phase formed and range-reduced in FP64); the tilt
-// tables of each x tilt and the constant pyramid tables are staged in LDS.
+// Row pass.  Block = 4 waves = 32 pupil rows of one frame (8 rows per wave),
+// looping over a chunk of distinct x tilts.  The pupil field A exp(i phi)
+// of the 32 rows is staged once in LDS (phase formed and range-reduced in
+// FP64); the tilt tables of each x tilt and the constant pyramid tables are
+// staged in LDS and shared by the four waves.
 //   in_a[ia][q][x] = r_a(x) w_N^{(2q+1) x},  f_a[ia][x] = r_a(x).
 template <int E>
-__global__ __launch_bounds__(64) void row_pass_kernel(
+__global__ __launch_bounds__(256) void row_pass_kernel(
     const float* __restrict__ opd, const float* __restrict__ amp, double kphase,
     const cpx* __restrict__ in_a, const cpx* __restrict__ f_a, const cpx* __restrict__ mid,
     const cpx* __restrict__ outw, cpx* __restrict__ Rw, int n_a, int a_chunk) {
   constexpr int P = 4 * E;
   constexpr int LDP = P + 4;
-  __shared__ cpx field[8 * LDP];
+  __shared__ cpx field[32 * LDP];
   __shared__ __align__(16) cpx s_in[2 * P];
   __shared__ __align__(16) cpx s_f[P];
   __shared__ __align__(16) cpx s_mid[4 * E];
   __shared__ __align__(16) cpx s_out[2 * P];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int t = lane >> 3, q = (lane >> 2) & 1, l = lane & 3;
-  const int y0 = blockIdx.x * 8;
+  const int yb = blockIdx.x * 32;
   const int a0 = blockIdx.y * a_chunk;
   const size_t fr = blockIdx.z;
-  const float* op = opd + fr * (size_t)P * P;
+  const float* op = opd + fr * (size_t)P * P + (size_t)yb * P;
+  const float* am = amp + (size_t)yb * P;
   constexpr double two_pi = 6.283185307179586476925286766559;
   constexpr double inv_two_pi = 0.15915494309189533576888376337251;
-  for (int i = lane; i < 8 * P; i += 64) {
+  for (int i = tid; i < 32 * P; i += 256) {
     const int r = i / P, x = i - r * P;
-    const int y = y0 + r;
-    const double th = (double)op[y * P + x] * kphase;
+    const double th = (double)op[i] * kphase;
     const double red = fma(-rint(th * inv_two_pi), two_pi, th);
-    float s, c;
-    sincosf((float)red, &s, &c);
-    const float A = amp[y * P + x];
-    field[r * LDP + x] = {A * c, A * s};
+    float sn, cs;
+    sincosf((float)red, &sn, &cs);
+    const float A = am[i];
+    field[r * LDP + x] = {A * cs, A * sn};
   }
-  copy16(s_mid, mid, (4 * E) / 2, lane);
-  copy16(s_out, outw, P, lane);
+  copy16(s_mid, mid, (4 * E) / 2, tid, 256);
+  copy16(s_out, outw, P, tid, 256);
   const int a1 = min(a0 + a_chunk, n_a);
-  const cpx* frow = field + t * LDP + l;
-  const int y = y0 + t;
+  const int r = wave * 8 + t;                     // row within the block
+  const cpx* frow = field + r * LDP + l;
+  const int y = yb + r;
   for (int ia = a0; ia < a1; ++ia) {
     __syncthreads();
-    copy16(s_in, in_a + (size_t)ia * 2 * P, P, lane);
-    copy16(s_f, f_a + (size_t)ia * P, P / 2, lane);
+    copy16(s_in, in_a + (size_t)ia * 2 * P, P, tid, 256);
+    copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
     __syncthreads();
     const cpx* tin = s_in + q * P + l;
     const cpx* tf = s_f + l;
@@ -187,39 +193,45 @@ __global__ __launch_bounds__(64) void row_pass_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Column pass.  Block = one wave = 8 adjacent columns x' of one frame and
-// one chunk of modulation points.  In the intermediate layout the 8 columns
-// form one contiguous block of 8P complex values, staged in LDS once per
-// distinct x tilt (k and K-k are adjacent in the modulation order and
-// share it).  Each team accumulates |E|^2 of its column over the chunk in
-// registers; the wave then bins b x b through LDS and writes its part of
+// Column pass.  Block = 4 waves = 32 adjacent columns x' of one frame (8 per
+// wave) and one chunk of modulation points.  In the intermediate layout the
+// 32 columns form one contiguous block of 32P complex values, staged in LDS
+// once per distinct x tilt (k and K-k are adjacent in the modulation order
+// and share it).  Each team accumulates |E|^2 of its column over the chunk
+// in registers.  With QB (binning a multiple of 4) the four rows 4m..4m+3,
+// held by the four lanes of a quad, are summed by a DPP quad reduction as
+// they are accumulated, and lane l keeps the row groups m = 4i + l.  The
+// block then finishes the b x b binning through LDS and writes its part of
 // the chunk's four pupil images.
 //   in_b[k][q][y] = r_b(y) w_N^{(2q+1) y},  f_b[k][y] = r_b(y).
-template <int E>
-__global__ __launch_bounds__(64) void col_pass_kernel(
+template <int E, bool QB>
+__global__ __launch_bounds__(256) void col_pass_kernel(
     const cpx* __restrict__ Rw, const cpx* __restrict__ in_b, const cpx* __restrict__ f_b,
     const int* __restrict__ k_order, const int* __restrict__ k_ia, const cpx* __restrict__ mid,
     const cpx* __restrict__ outw, float* __restrict__ partial, int n_a, int K, int k_chunk,
     int n_chunks, int n_bin) {
   constexpr int P = 4 * E;
-  __shared__ __align__(16) cpx s_col[8 * P];
+  constexpr int NA = QB ? E / 4 : E;            // accumulators per lane
+  __shared__ __align__(16) cpx s_col[32 * P];
   __shared__ __align__(16) cpx s_in[2 * P];
   __shared__ __align__(16) cpx s_f[P];
   __shared__ __align__(16) cpx s_mid[4 * E];
   __shared__ __align__(16) cpx s_out[2 * P];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int t = lane >> 3, q = (lane >> 2) & 1, l = lane & 3;
-  const int X0 = blockIdx.x * 8;
+  const int X0 = blockIdx.x * 32;
   const int chunk = blockIdx.y;
   const size_t fr = blockIdx.z;
-  float acc[E];
-  static_for<0, E>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
-  copy16(s_mid, mid, (4 * E) / 2, lane);
-  copy16(s_out, outw, P, lane);
+  float acc[NA];
+  static_for<0, NA>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
+  copy16(s_mid, mid, (4 * E) / 2, tid, 256);
+  copy16(s_out, outw, P, tid, 256);
   const int kb = chunk * k_chunk;
   const int ke = min(kb + k_chunk, K);
   const cpx* frame = Rw + fr * (size_t)n_a * (size_t)(2 * P * P) + (size_t)(X0 >> 3) * (size_t)(8 * P);
-  const cpx* col = s_col + t * 4 + l;           // element (x' = X0 + t, y = l + 4 m) at col[32 m]
+  const int c = wave * 8 + t;                      // column within the block
+  const cpx* col = s_col + wave * 8 * P + t * 4 + l;   // element (x' = X0 + c, y = l + 4m) at col[32 m]
   const cpx* tin = s_in + q * P + l;
   const cpx* tf = s_f + l;
   int cur_ia = -1;
@@ -228,44 +240,75 @@ __global__ __launch_bounds__(64) void col_pass_kernel(
     const int ia = k_ia[k];
     __syncthreads();
     if (ia != cur_ia) {
-      copy16(s_col, frame + (size_t)ia * (size_t)(2 * P * P), 4 * P, lane);
+      copy16(s_col, frame + (size_t)ia * (size_t)(2 * P * P), 16 * P, tid, 256);
       cur_ia = ia;
     }
-    copy16(s_in, in_b + (size_t)k * 2 * P, P, lane);
-    copy16(s_f, f_b + (size_t)k * P, P / 2, lane);
+    copy16(s_in, in_b + (size_t)k * 2 * P, P, tid, 256);
+    copy16(s_f, f_b + (size_t)k * P, P / 2, tid, 256);
     __syncthreads();
     cpx v[E];
     line_op<E>(v, [&](int m) { return cmul(col[32 * m], tin[4 * m]); },
                [&](int m) { return cmul(col[32 * m], tf[4 * m]); }, s_mid, s_out, q, l);
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
-      acc[m] = fmaf(v[m].re, v[m].re, fmaf(v[m].im, v[m].im, acc[m]));
+      float e = fmaf(v[m].re, v[m].re, v[m].im * v[m].im);
+      if constexpr (QB) {
+        e += quad_perm<0xB1>(e);                   // lanes (0,1), (2,3)
+        e += quad_perm<0x4E>(e);                   // lanes (0,2), (1,3)
+        acc[m >> 2] += (l == (m & 3)) ? e : 0.f;
+      } else {
+        acc[m] += e;
+      }
     });
   }
   __syncthreads();
-  float* tile = reinterpret_cast<float*>(s_col);   // [8 cols][2 windows][P rows]
-  float* my = tile + (t * 2 + q) * P + l;
-  static_for<0, E>([&](auto m_) {
-    constexpr int m = decltype(m_)::value;
-    my[4 * m] = acc[m];
-  });
-  __syncthreads();
+  float* tile = reinterpret_cast<float*>(s_col);
   const int S = P / n_bin;
-  const int nbc = 8 / n_bin;
+  const int nbc = 32 / n_bin;
   const int xw = X0 >= P ? 1 : 0;
   const int ix0 = (X0 - xw * P) / n_bin;
   float* dst = partial + (fr * (size_t)n_chunks + chunk) * (size_t)(4 * S * S);
-  for (int o = lane; o < nbc * 2 * S; o += 64) {
-    const int bc = o / (2 * S);
-    const int rem = o - bc * 2 * S;
-    const int qq = rem / S;
-    const int iy = rem - qq * S;
-    float s = 0.f;
-    for (int dx = 0; dx < n_bin; ++dx) {
-      const float* c = tile + ((bc * n_bin + dx) * 2 + qq) * P + iy * n_bin;
-      for (int dy = 0; dy < n_bin; ++dy) s += c[dy];
+  if constexpr (QB) {
+    // tile[c][q][g]: sum over rows 4g..4g+3 of column c, window q.
+    float* my = tile + (c * 2 + q) * (P / 4) + l;
+    static_for<0, NA>([&](auto i_) {
+      constexpr int i = decltype(i_)::value;
+      my[4 * i] = acc[i];
+    });
+    __syncthreads();
+    const int gpb = n_bin / 4;                     // row groups per bin
+    for (int o = tid; o < nbc * 2 * S; o += 256) {
+      const int bc = o / (2 * S);
+      const int rem = o - bc * 2 * S;
+      const int qq = rem / S;
+      const int iy = rem - qq * S;
+      float sum = 0.f;
+      for (int dx = 0; dx < n_bin; ++dx) {
+        const float* g = tile + ((bc * n_bin + dx) * 2 + qq) * (P / 4) + iy * gpb;
+        for (int dg = 0; dg < gpb; ++dg) sum += g[dg];
+      }
+      dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = sum;
     }
-    dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = s;
+  } else {
+    // tile[c][q][row]
+    float* my = tile + (c * 2 + q) * P + l;
+    static_for<0, NA>([&](auto m_) {
+      constexpr int m = decltype(m_)::value;
+      my[4 * m] = acc[m];
+    });
+    __syncthreads();
+    for (int o = tid; o < nbc * 2 * S; o += 256) {
+      const int bc = o / (2 * S);
+      const int rem = o - bc * 2 * S;
+      const int qq = rem / S;
+      const int iy = rem - qq * S;
+      float sum = 0.f;
+      for (int dx = 0; dx < n_bin; ++dx) {
+        const float* g = tile + ((bc * n_bin + dx) * 2 + qq) * P + iy * n_bin;
+        for (int dy = 0; dy < n_bin; ++dy) sum += g[dy];
+      }
+      dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = sum;
+    }
   }
 }
 
@@ -329,27 +372,47 @@ __global__ __launch_bounds__(1024) void slopes_kernel(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// m = alpha R s + beta m.  One wave per row of R; lanes stride the row
-// (coalesced), each lane keeps BT batch accumulators, butterfly reduction.
-template <int BT>
+// m = alpha R s + beta m.  A block of 4 waves handles 4 / WPR rows; each row
+// is split over WPR waves (long rows) whose lanes stride it with float4 (or
+// scalar) loads, each lane keeping BT batch accumulators.  Butterfly
+// reduction inside each wave, then the WPR wave partials are added in wave
+// order through LDS: a fixed summation order, bitwise reproducible.
+template <int BT, int VEC>
 __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R, int M, int ns,
                                                      const float* __restrict__ s, int B, float alpha,
-                                                     float beta, float* __restrict__ m) {
+                                                     float beta, float* __restrict__ m, int wpr) {
+  __shared__ float part[4][BT];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + wave;
-  if (i >= M) return;
+  const int rows_per_block = 4 / wpr;
+  const int i = blockIdx.x * rows_per_block + wave / wpr;
+  const int slice = wave % wpr;
   const int b0 = blockIdx.y * BT;
   const int nb = min(BT, B - b0);
   float acc[BT];
 #pragma unroll
   for (int bb = 0; bb < BT; ++bb) acc[bb] = 0.f;
-  const float* Ri = R + (size_t)i * ns;
-  const float* sb = s + (size_t)b0 * ns;
-  for (int j = lane; j < ns; j += 64) {
-    const float r = Ri[j];
+  if (i < M) {
+    const int nv = ns / VEC;
+    using V = typename std::conditional<VEC == 4, float4, float>::type;
+    const V* Ri = reinterpret_cast<const V*>(R + (size_t)i * ns);
+    const V* sb = reinterpret_cast<const V*>(s + (size_t)b0 * ns);
+    for (int j = slice * 64 + lane; j < nv; j += 64 * wpr) {
+      const V r = Ri[j];
 #pragma unroll
-    for (int bb = 0; bb < BT; ++bb)
-      if (bb < nb) acc[bb] = fmaf(r, sb[(size_t)bb * ns + j], acc[bb]);
+      for (int bb = 0; bb < BT; ++bb) {
+        if (bb < nb) {
+          const V x = sb[(size_t)bb * nv + j];
+          if constexpr (VEC == 4) {
+            acc[bb] = fmaf(r.x, x.x, acc[bb]);
+            acc[bb] = fmaf(r.y, x.y, acc[bb]);
+            acc[bb] = fmaf(r.z, x.z, acc[bb]);
+            acc[bb] = fmaf(r.w, x.w, acc[bb]);
+          } else {
+            acc[bb] = fmaf(r, x, acc[bb]);
+          }
+        }
+      }
+    }
   }
 #pragma unroll
   for (int bb = 0; bb < BT; ++bb) {
@@ -358,12 +421,14 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R,
   }
   if (lane == 0) {
 #pragma unroll
-    for (int bb = 0; bb < BT; ++bb) {
-      if (bb < nb) {
-        float* mm = m + (size_t)(b0 + bb) * M + i;
-        *mm = beta != 0.f ? fmaf(alpha, acc[bb], beta * *mm) : alpha * acc[bb];
-      }
-    }
+    for (int bb = 0; bb < BT; ++bb) part[wave][bb] = acc[bb];
+  }
+  __syncthreads();
+  if (slice == 0 && lane < nb && i < M) {
+    float tot = 0.f;
+    for (int w = 0; w < wpr; ++w) tot += part[wave + w][lane];
+    float* mm = m + (size_t)(b0 + lane) * M + i;
+    *mm = beta != 0.f ? fmaf(alpha, tot, beta * *mm) : alpha * tot;
   }
 }
 
@@ -371,17 +436,21 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R,
 // Host launchers.
 template <int E>
 static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
-  dim3 grid(a.P / 8, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
-  hipLaunchKernelGGL(row_pass_kernel<E>, grid, dim3(64), 0, st, a.opd, a.amp, a.kphase, a.in_a, a.f_a,
+  dim3 grid(a.P / 32, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
+  hipLaunchKernelGGL(row_pass_kernel<E>, grid, dim3(256), 0, st, a.opd, a.amp, a.kphase, a.in_a, a.f_a,
                      a.mid, a.outw, a.Rw, a.n_a, a.a_chunk);
   return hipGetLastError();
 }
 
 template <int E>
 static hipError_t launch_cols(const MeasureArgs& a, hipStream_t st) {
-  dim3 grid(2 * a.P / 8, a.n_chunks, a.B);
-  hipLaunchKernelGGL(col_pass_kernel<E>, grid, dim3(64), 0, st, a.Rw, a.in_b, a.f_b, a.k_order, a.k_ia,
-                     a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
+  dim3 grid(2 * a.P / 32, a.n_chunks, a.B);
+  if (a.n_bin % 4 == 0)
+    hipLaunchKernelGGL((col_pass_kernel<E, true>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
+                       a.k_ia, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
+  else
+    hipLaunchKernelGGL((col_pass_kernel<E, false>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
+                       a.k_ia, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
   return hipGetLastError();
 }
 
@@ -430,17 +499,30 @@ hipError_t launch_fill(float* p, size_t n, float v, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int BT>
+static void launch_recon_bt(const float* R, int M, int ns, const float* s, int B, float alpha, float beta,
+                            float* m, hipStream_t st) {
+  const bool vec = (ns % 4 == 0) && ((uintptr_t)R % 16 == 0) && ((uintptr_t)s % 16 == 0);
+  const int nv = vec ? ns / 4 : ns;
+  const int wpr = nv >= 384 ? 4 : (nv >= 192 ? 2 : 1);
+  const int rpb = 4 / wpr;
+  dim3 grid((M + rpb - 1) / rpb, (B + BT - 1) / BT);
+  if (vec)
+    hipLaunchKernelGGL((recon_kernel<BT, 4>), grid, dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m, wpr);
+  else
+    hipLaunchKernelGGL((recon_kernel<BT, 1>), grid, dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m, wpr);
+}
+
 hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, float alpha,
                         float beta, float* m, hipStream_t st) {
-  const int gx = (M + 3) / 4;
-  if (B <= 1) {
-    hipLaunchKernelGGL(recon_kernel<1>, dim3(gx, B), dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m);
-  } else if (B <= 4) {
-    hipLaunchKernelGGL(recon_kernel<4>, dim3(gx, 1), dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m);
-  } else {
-    hipLaunchKernelGGL(recon_kernel<8>, dim3(gx, (B + 7) / 8), dim3(256), 0, st, R, M, ns, s, B,
-                       alpha, beta, m);
-  }
+  if (B <= 1)
+    launch_recon_bt<1>(R, M, ns, s, B, alpha, beta, m, st);
+  else if (B <= 4)
+    launch_recon_bt<4>(R, M, ns, s, B, alpha, beta, m, st);
+  else if (B <= 8)
+    launch_recon_bt<8>(R, M, ns, s, B, alpha, beta, m, st);
+  else
+    launch_recon_bt<16>(R, M, ns, s, B, alpha, beta, m, st);
   return hipGetLastError();
 }
 
