@@ -32,6 +32,26 @@ import numpy as np
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per 16-frame column-pass launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# recorded in profiles/pwfs_measure_n640_p160_k48_b16.md (scaled by the copy-kernel factors
+# 2.0 / 1.0).  Valid only for the kernel sources with these hashes; reported as null otherwise.
+COUNTER_TRAFFIC = {
+    "sources_sha1": {"pwfs_kernels.hip": "2d7ca6f979d9eb8bc29f336b4290b4653815a922",
+                     "pwfs_dft.h": "b9f0efe9263005de788f876c2146edfa2d2b9d54"},
+    "batch": 16,
+    "col_pass_bytes": (90699.7 * 2.0 + 1600.0 * 1.0) * 1024,
+}
+
+
+def counter_traffic(batch):
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1607_07624_amd", "csrc")
+    for name, h in COUNTER_TRAFFIC["sources_sha1"].items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest() != h:
+                return None
+    return COUNTER_TRAFFIC["col_pass_bytes"] if batch == COUNTER_TRAFFIC["batch"] else None
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -197,7 +217,10 @@ def main():
     achieved = fl_col / (col_ms * 1e-3) / 1e12
     conv = lines_col * 2 * 5 * cfg.n_fft * np.log2(cfg.n_fft)     # 5 N log2 N convention, N = 640
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": counter_traffic(B), "traffic_unit": "bytes per launch (rocprofv3 counters)",
+                "hbm_frac_of_peak": (round(counter_traffic(B) / (col_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+                                     if counter_traffic(B) else None),
                 "kernel": "col_pass_kernel<40>", "kernel_ms": round(col_ms, 4),
                 "flop_per_launch": int(fl_col),
                 "convention_5NlogN_tflops": round(conv / (col_ms * 1e-3) / 1e12, 2)}
