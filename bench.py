@@ -93,24 +93,6 @@ def line_flops(P: int, intensity: bool) -> int:
     return 2 * projection + f + twist + out + acc
 
 
-def calibrate(plan, modes_dev, B, ns, eps_nm, torch, dev):
-    """Push-pull interaction matrix measured on the GPU, full-SVD pseudo-inverse (FP64, host)."""
-    M = modes_dev.shape[0]
-    IM = np.empty((ns, M))
-    h = max(1, B // 2)
-    for i0 in range(0, M, h):
-        idx = list(range(i0, min(M, i0 + h)))
-        push = torch.cat([eps_nm * modes_dev[idx], -eps_nm * modes_dev[idx]]).contiguous()
-        sl = torch.empty((push.shape[0], ns), device=dev)
-        plan.measure_into(push, None, sl)
-        sl = sl.cpu().numpy().astype(np.float64)
-        n = len(idx)
-        IM[:, idx] = ((sl[:n] - sl[n:]) / (2.0 * eps_nm)).T
-    U, sig, Vt = np.linalg.svd(IM, full_matrices=False)
-    log(f"IM condition number {sig[0] / sig[-1]:.1f}")
-    return (Vt.T / sig) @ U.T
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +116,7 @@ def main():
 
     import torch
     import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd.loop import calibrate, ClosedLoop, residual_rms_nm
     from synth.configs import CFG2, ATMO2, CFG4_R0_RANGE, N_KL_MODES, PUSH_PULL_NM, LOOP_GAIN, \
         LOOP_DELAY, LOOP_SETTLE_STEPS
     from synth.screens import open_loop_batch, frozen_flow_sequence
@@ -166,8 +149,10 @@ def main():
         modes = kl_modes(amp, cfg.pixel_m, ATMO2.L0_m, N_KL_MODES)
         M = modes.shape[0]
         modes_dev = torch.from_numpy(modes.astype(np.float32)).to(dev)
-        R_host = calibrate(plan, modes_dev, B, ns, PUSH_PULL_NM, torch, dev)
-    R = torch.from_numpy(R_host.astype(np.float32)).to(dev).contiguous()
+        R, _, sig = calibrate(plan, modes.astype(np.float32), PUSH_PULL_NM, dev)
+        log(f"IM condition number {sig[0] / sig[-1]:.1f}")
+    if args.random_R:
+        R = torch.from_numpy(R_host.astype(np.float32)).to(dev).contiguous()
     log(f"calibration {time.time() - t0:.1f}s")
 
     modes_out = torch.empty((B, M), device=dev)
@@ -252,30 +237,17 @@ def main():
         log("closed loop")
         T = args.loop_steps
         seq = torch.from_numpy(frozen_flow_sequence(cfg, ATMO2, T, seed=2024)).to(dev)
-        BKL = modes_dev.reshape(M, P * P).t().contiguous()          # [P*P, M]
-        c_hist = torch.zeros((T + LOOP_DELAY, M), device=dev)      # c(t) at row t + delay
-        res = torch.empty((T, P * P), device=dev)
-        sl = torch.empty((1, ns), device=dev)
+        cl = ClosedLoop(plan1, modes_dev, R, LOOP_GAIN, LOOP_DELAY)
         torch.cuda.synchronize()
         ev0.record()
-        for t in range(T):
-            r_t = res[t:t + 1]
-            r_t.copy_(seq[t].reshape(1, -1))
-            pw.recon_apply(BKL, c_hist[t:t + 1], -1.0, 1.0, r_t)    # u(t) = c(t - delay)
-            plan1.measure_into(r_t.view(1, P, P), None, sl)
-            c_next = c_hist[t + LOOP_DELAY:t + LOOP_DELAY + 1]
-            c_next.copy_(c_hist[t + LOOP_DELAY - 1:t + LOOP_DELAY] if t > 0 else torch.zeros_like(c_next))
-            pw.recon_apply(R, sl, LOOP_GAIN, 1.0, c_next)
+        res, _ = cl.run(seq)
         ev1.record()
         torch.cuda.synchronize()
         loop_ms = ev0.elapsed_time(ev1)
-        rr = res.cpu().numpy().astype(np.float64)[:, amp.ravel() > 0]
-        rr -= rr.mean(axis=1, keepdims=True)
-        per_step = np.sqrt((rr ** 2).mean(axis=1))
-        ol = seq.cpu().numpy().astype(np.float64).reshape(T, -1)[:, amp.ravel() > 0]
-        ol -= ol.mean(axis=1, keepdims=True)
+        per_step = residual_rms_nm(res.cpu().numpy(), amp)
+        ol = residual_rms_nm(seq.cpu().numpy().reshape(T, -1), amp)
         loop = {"steps": T, "residual_nm_rms": round(float(np.sqrt(np.mean(per_step[LOOP_SETTLE_STEPS:] ** 2))), 2),
-                "open_loop_nm_rms": round(float(np.sqrt(np.mean(ol ** 2))), 2),
+                "open_loop_nm_rms": round(float(np.sqrt(np.mean(ol[LOOP_SETTLE_STEPS:] ** 2))), 2),
                 "steps_per_s": round(T / (loop_ms / 1e3), 1), "gain": LOOP_GAIN, "delay": LOOP_DELAY,
                 "reconstructor": "linear (KL 600, push-pull IM, full-SVD pinv)"}
         log(f"loop {loop}")
