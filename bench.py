@@ -103,6 +103,9 @@ def main():
     ap.add_argument("--loop-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
+    ap.add_argument("--no-cnn", action="store_true", help="skip training and evaluating the learned reconstructor")
+    ap.add_argument("--cnn-frames", type=int, default=200000)
+    ap.add_argument("--cnn-epochs", type=int, default=4)
     ap.add_argument("--random-R", action="store_true",
                     help="profiling runs: skip calibration, use a random reconstructor of the same shape")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -143,6 +146,7 @@ def main():
     s_buf = torch.empty((B, ns), device=dev)
     if args.random_R:
         args.no_loop = True
+        args.no_cnn = True
         M = N_KL_MODES
         R_host = np.random.default_rng(0).standard_normal((M, ns)) * 1e-2
     else:
@@ -252,6 +256,46 @@ def main():
                 "reconstructor": "linear (KL 600, push-pull IM, full-SVD pinv)"}
         log(f"loop {loop}")
 
+    # Learned reconstructor: trained on GPU-generated frames with the project's
+    # kernels, compared with the linear one (held-out open-loop error, closed loop).
+    learned = None
+    if not args.no_cnn:
+        from synth.screens import CropBank
+        from synth.configs import AtmoConfig
+        from paper_1607_07624_amd.learned import train_reconstructor, open_loop_errors
+        log("learned reconstructor: data + training")
+        bank = CropBank(cfg, ATMO2.L0_m, n_screens=4, screen_n=4096, seed=4242)
+        net, info = train_reconstructor(plan, modes.astype(np.float32), amp, bank, args.cnn_frames, seed=5,
+                                        epochs=args.cnn_epochs, log=log)
+        log(f"training {info}")
+        ev_strong = open_loop_errors(plan, net, R, modes.astype(np.float32), amp, bank, 2048, seed=990,
+                                     r0_range=(0.06, 0.1))
+        ev_all = open_loop_errors(plan, net, R, modes.astype(np.float32), amp, bank, 2048, seed=991,
+                                  r0_range=(0.06, 0.2))
+        loops = {}
+        for r0 in (0.12, 0.08):
+            atm = AtmoConfig(r0_m=r0, L0_m=ATMO2.L0_m, wind_m_s=ATMO2.wind_m_s, frame_rate_hz=ATMO2.frame_rate_hz)
+            sq = torch.from_numpy(frozen_flow_sequence(cfg, atm, T, seed=2024)).to(dev)
+            row = {}
+            for name, nn_ in (("linear", None), ("cnn", net)):
+                cl = ClosedLoop(plan1, modes_dev, R, LOOP_GAIN, LOOP_DELAY, net=nn_)
+                torch.cuda.synchronize()
+                ev0.record()
+                rs, _ = cl.run(sq)
+                ev1.record()
+                torch.cuda.synchronize()
+                ps = residual_rms_nm(rs.cpu().numpy(), amp)
+                row[name] = {"residual_nm_rms": round(float(np.sqrt(np.mean(ps[LOOP_SETTLE_STEPS:] ** 2))), 2),
+                             "steps_per_s": round(T / (ev0.elapsed_time(ev1) / 1e3), 1)}
+                if nn_ is not None:
+                    row[name]["fallback_step"] = cl.fallback_step
+            loops[f"r0_{r0}"] = row
+            log(f"loop r0={r0}: {row}")
+        learned = {"training": {k: v for k, v in info.items() if k != "loss_history"},
+                   "loss_first_last": [round(info["loss_history"][0], 4), round(info["loss_history"][-1], 4)],
+                   "open_loop_error_r0_0.06_0.1": ev_strong, "open_loop_error_r0_0.06_0.2": ev_all,
+                   "closed_loop": loops}
+
     # CPU baseline: the FP64 oracle on the host cores, small sample.
     cpu = None
     if not args.no_cpu:
@@ -280,6 +324,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "loop": loop,
+        "learned": learned,
         "kernels": extra,
     }
     print(json.dumps(out), flush=True)

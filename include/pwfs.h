@@ -133,7 +133,8 @@ int pwfs_timing_read(pwfs_plan_t plan, double* ms_row, double* ms_col, double* m
  *   d_R  device, M * n_s float, row-major [mode][slope].
  *   d_s  device, B * n_s float.
  *   d_m  device, B * M float, read (when beta != 0) and written.
- * FP32 with FP32 accumulation in a fixed order (bitwise reproducible).
+ * FP32 with FP32 accumulation in a fixed order (bitwise reproducible):
+ * vector FMAs for B <= 16, FP32 MFMA for larger batches.
  * Asynchronous on `stream`. */
 int recon_apply(const float* d_R, int32_t M, int32_t n_s, const float* d_s, int32_t B,
                 float alpha, float beta, float* d_m, void* stream);

@@ -1,0 +1,365 @@
+// cnn_api.cpp -- C ABI of the learned modal reconstructor: parameter and
+// workspace management, forward / backward / Adam sequencing.
+#include "../../include/pwfs_cnn.h"
+#include "../../include/pwfs.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "cnn_launch.h"
+
+using pwfs::cnn::GemmArgs;
+
+namespace pwfs {
+int set_last_error(int status, const std::string& msg);   // shared with the sensor ABI (pwfs_last_error)
+}
+
+namespace {
+
+enum { PWFS_CNN_ERR_INVALID_ARG = PWFS_ERR_INVALID_ARG, PWFS_CNN_ERR_NO_DEVICE = PWFS_ERR_NO_DEVICE,
+       PWFS_CNN_ERR_OOM = PWFS_ERR_OUT_OF_MEMORY, PWFS_CNN_ERR_HIP = PWFS_ERR_HIP };
+
+int fail(int status, const std::string& msg) { return pwfs::set_last_error(status, msg); }
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PWFS_CNN_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int dev_alloc(void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (bytes == 0) return 0;
+  const char* fi = std::getenv("PWFS_FAULT_INJECT");
+  if (fi && std::strcmp(fi, "oom") == 0) return fail(PWFS_CNN_ERR_OOM, std::string("injected OOM: ") + what);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(PWFS_CNN_ERR_OOM, std::string("hipMalloc(") + what + "): " + hipGetErrorString(e));
+  }
+  return 0;
+}
+
+}  // namespace
+
+struct pwfs_cnn_s {
+  pwfs_cnn_config_t cfg{};
+  int device = 0;
+  int S = 0, S1 = 0, S2 = 0, S3 = 0, c1 = 0, c2 = 0, c3 = 0, hidden = 0, nout = 0, flat = 0, bm = 0;
+  size_t off[10] = {};   // w1 b1 w2 b2 w3 b3 fw1 fb1 fw2 fb2
+  size_t n_params = 0;
+  long step = 0;
+  // parameters
+  float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+  uint16_t* wb = nullptr;
+  // activations (bf16) and FP32 work buffers
+  uint16_t *xb = nullptr, *cols1 = nullptr, *a1 = nullptr, *cols2 = nullptr, *a2 = nullptr, *cols3 = nullptr,
+           *a3 = nullptr, *h = nullptr, *doutb = nullptr, *dzb = nullptr;
+  float *out = nullptr, *dout = nullptr, *gtmp = nullptr, *dz = nullptr, *part = nullptr, *loss = nullptr;
+  size_t part_elems = 0;
+};
+
+namespace {
+
+void free_net(pwfs_cnn_s* n) {
+  if (!n) return;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(n->device);
+  void* ptrs[] = {n->w, n->m, n->v, n->g, n->wb, n->xb, n->cols1, n->a1, n->cols2, n->a2, n->cols3, n->a3,
+                  n->h, n->doutb, n->dzb, n->out, n->dout, n->gtmp, n->dz, n->part, n->loss};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (prev >= 0) (void)hipSetDevice(prev);
+  delete n;
+}
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != d) (void)hipSetDevice(d);
+  }
+  ~DevGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+#define CK(expr)                                  \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+// Y = X W^T + bias (ReLU), X [M][K] bf16, W [N][K] bf16.
+GemmArgs fwd_args(const uint16_t* X, const uint16_t* W, const float* bias, int M, int N, int K, bool relu,
+                  float* C, uint16_t* Cb) {
+  GemmArgs a{};
+  a.A = X; a.sam = K; a.sak = 1;
+  a.B = W; a.sbk = 1; a.sbn = K;
+  a.C = C; a.ldc = N; a.Cb = Cb; a.ldcb = N;
+  a.bias = bias; a.M = M; a.N = N; a.K = K; a.alpha = 1.f; a.beta = 0.f; a.relu = relu ? 1 : 0;
+  return a;
+}
+// dW [N][K] = dY^T X, dY [R][N] bf16, X [R][K] bf16.
+GemmArgs wgrad_args(const uint16_t* dY, const uint16_t* X, int R, int N, int K, float* dW) {
+  GemmArgs a{};
+  a.A = dY; a.sam = 1; a.sak = N;
+  a.B = X; a.sbk = K; a.sbn = 1;
+  a.C = dW; a.ldc = K;
+  a.M = N; a.N = K; a.K = R; a.alpha = 1.f;
+  return a;
+}
+// dX [R][K] = dY W, dY [R][N] bf16, W [N][K] bf16.
+GemmArgs dgrad_args(const uint16_t* dY, const uint16_t* W, int R, int N, int K, float* dX) {
+  GemmArgs a{};
+  a.A = dY; a.sam = N; a.sak = 1;
+  a.B = W; a.sbk = K; a.sbn = 1;
+  a.C = dX; a.ldc = K;
+  a.M = R; a.N = K; a.K = N; a.alpha = 1.f;
+  return a;
+}
+
+// Forward pass; the last layer writes out_alpha * net(x) + out_beta * out into
+// `out` (NULL: the internal output buffer, alpha 1, beta 0).
+int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out = nullptr,
+                float out_alpha = 1.f, float out_beta = 0.f) {
+  const size_t in_elems = (size_t)B * n->S * n->S * 4;
+  CK(pwfs::cnn::to_bf16(x, in_elems, n->xb, st));
+  const float* W = n->w;
+  const uint16_t* Wb = n->wb;
+  CK(pwfs::cnn::im2col(n->xb, B, n->S, n->S, 4, n->cols1, st));
+  CK(pwfs::cnn::gemm(fwd_args(n->cols1, Wb + n->off[0], W + n->off[1], B * n->S1 * n->S1, n->c1, 36, true,
+                              nullptr, n->a1), n->part, n->part_elems, st));
+  CK(pwfs::cnn::im2col(n->a1, B, n->S1, n->S1, n->c1, n->cols2, st));
+  CK(pwfs::cnn::gemm(fwd_args(n->cols2, Wb + n->off[2], W + n->off[3], B * n->S2 * n->S2, n->c2, n->c1 * 9, true,
+                              nullptr, n->a2), n->part, n->part_elems, st));
+  CK(pwfs::cnn::im2col(n->a2, B, n->S2, n->S2, n->c2, n->cols3, st));
+  CK(pwfs::cnn::gemm(fwd_args(n->cols3, Wb + n->off[4], W + n->off[5], B * n->S3 * n->S3, n->c3, n->c2 * 9, true,
+                              nullptr, n->a3), n->part, n->part_elems, st));
+  CK(pwfs::cnn::gemm(fwd_args(n->a3, Wb + n->off[6], W + n->off[7], B, n->hidden, n->flat, true, nullptr, n->h),
+                     n->part, n->part_elems, st));
+  GemmArgs last = fwd_args(n->h, Wb + n->off[8], W + n->off[9], B, n->nout, n->hidden, false,
+                           out ? out : n->out, nullptr);
+  if (out) {
+    last.alpha = out_alpha;
+    last.beta = out_beta;
+  }
+  CK(pwfs::cnn::gemm(last, n->part, n->part_elems, st));
+  return 0;
+}
+
+int run_backward(pwfs_cnn_s* n, const float* target, int B, float* loss, hipStream_t st) {
+  const uint16_t* Wb = n->wb;
+  float* G = n->g;
+  CK(pwfs::cnn::mse(n->out, target, B * n->nout, n->dout, n->doutb, loss, st));
+  // fc2
+  CK(pwfs::cnn::gemm(wgrad_args(n->doutb, n->h, B, n->nout, n->hidden, G + n->off[8]), n->part, n->part_elems, st));
+  CK(pwfs::cnn::colsum(n->dout, B, n->nout, G + n->off[9], st));
+  CK(pwfs::cnn::gemm(dgrad_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->gtmp), n->part, n->part_elems, st));
+  CK(pwfs::cnn::relu_mask(n->gtmp, n->h, (size_t)B * n->hidden, n->dz, n->dzb, st));
+  // fc1
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->a3, B, n->hidden, n->flat, G + n->off[6]), n->part, n->part_elems, st));
+  CK(pwfs::cnn::colsum(n->dz, B, n->hidden, G + n->off[7], st));
+  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[6], B, n->hidden, n->flat, n->gtmp), n->part, n->part_elems, st));
+  CK(pwfs::cnn::relu_mask(n->gtmp, n->a3, (size_t)B * n->flat, n->dz, n->dzb, st));
+  // conv3
+  const int R3 = B * n->S3 * n->S3, R2 = B * n->S2 * n->S2, R1 = B * n->S1 * n->S1;
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols3, R3, n->c3, n->c2 * 9, G + n->off[4]), n->part, n->part_elems, st));
+  CK(pwfs::cnn::colsum(n->dz, R3, n->c3, G + n->off[5], st));
+  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), n->part, n->part_elems, st));
+  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S2, n->S2, n->c2, n->a2, n->dz, n->dzb, st));
+  // conv2
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols2, R2, n->c2, n->c1 * 9, G + n->off[2]), n->part, n->part_elems, st));
+  CK(pwfs::cnn::colsum(n->dz, R2, n->c2, G + n->off[3], st));
+  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, n->part_elems, st));
+  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dz, n->dzb, st));
+  // conv1
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols1, R1, n->c1, 36, G + n->off[0]), n->part, n->part_elems, st));
+  CK(pwfs::cnn::colsum(n->dz, R1, n->c1, G + n->off[1], st));
+  return 0;
+}
+
+int check_batch(pwfs_cnn_s* n, int B) {
+  if (!n) return fail(PWFS_CNN_ERR_INVALID_ARG, "network is NULL");
+  if (B < 0 || B > n->bm) return fail(PWFS_CNN_ERR_INVALID_ARG, "B must be in [0, batch_max]");
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
+  if (!out) return fail(PWFS_CNN_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!c) return fail(PWFS_CNN_ERR_INVALID_ARG, "cfg is NULL");
+  if (c->reserved != 0 || c->n_sub < 4 || c->n_sub > 256 || c->c1 < 1 || c->c1 > 256 || c->c2 < 1 ||
+      c->c2 > 256 || c->c3 < 1 || c->c3 > 256 || c->hidden < 1 || c->hidden > 16384 || c->n_out < 1 ||
+      c->n_out > 16384 || c->batch_max < 1 || c->batch_max > 65535)
+    return fail(PWFS_CNN_ERR_INVALID_ARG, "configuration out of range");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(PWFS_CNN_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  auto* n = new pwfs_cnn_s();
+  n->cfg = *c;
+  (void)hipGetDevice(&n->device);
+  n->S = c->n_sub;
+  n->S1 = (n->S + 1) / 2;
+  n->S2 = (n->S1 + 1) / 2;
+  n->S3 = (n->S2 + 1) / 2;
+  n->c1 = c->c1; n->c2 = c->c2; n->c3 = c->c3;
+  n->hidden = c->hidden; n->nout = c->n_out; n->bm = c->batch_max;
+  n->flat = n->S3 * n->S3 * n->c3;
+  const size_t sizes[10] = {(size_t)n->c1 * 4 * 9, (size_t)n->c1, (size_t)n->c2 * n->c1 * 9, (size_t)n->c2,
+                            (size_t)n->c3 * n->c2 * 9, (size_t)n->c3, (size_t)n->hidden * n->flat,
+                            (size_t)n->hidden, (size_t)n->nout * n->hidden, (size_t)n->nout};
+  size_t o = 0;
+  for (int i = 0; i < 10; ++i) {
+    n->off[i] = o;
+    o += sizes[i];   // packed, C order
+  }
+  n->n_params = o;
+  const size_t B = (size_t)n->bm;
+  const size_t R1 = B * n->S1 * n->S1, R2 = B * n->S2 * n->S2, R3 = B * n->S3 * n->S3;
+  const size_t gtmp = std::max({B * n->hidden, B * n->flat, R3 * n->c2 * 9, R2 * n->c1 * 9});
+  const size_t dz = std::max({B * n->hidden, B * n->flat, R2 * n->c2, R1 * n->c1});
+  n->part_elems = std::max<size_t>({(size_t)4 << 20, (size_t)64 * n->c1 * 36, (size_t)64 * n->c2 * n->c1 * 9,
+                                    (size_t)64 * n->c3 * n->c2 * 9});
+  struct A { void** p; size_t bytes; const char* what; } al[] = {
+      {(void**)&n->w, n->n_params * 4, "params"}, {(void**)&n->m, n->n_params * 4, "adam m"},
+      {(void**)&n->v, n->n_params * 4, "adam v"}, {(void**)&n->g, n->n_params * 4, "grads"},
+      {(void**)&n->wb, n->n_params * 2, "bf16 params"},
+      {(void**)&n->xb, B * n->S * n->S * 4 * 2, "input"}, {(void**)&n->cols1, R1 * 36 * 2, "cols1"},
+      {(void**)&n->a1, R1 * n->c1 * 2, "a1"}, {(void**)&n->cols2, R2 * n->c1 * 9 * 2, "cols2"},
+      {(void**)&n->a2, R2 * n->c2 * 2, "a2"}, {(void**)&n->cols3, R3 * n->c2 * 9 * 2, "cols3"},
+      {(void**)&n->a3, R3 * n->c3 * 2, "a3"}, {(void**)&n->h, B * n->hidden * 2, "hidden"},
+      {(void**)&n->doutb, B * n->nout * 2, "dout bf16"}, {(void**)&n->dzb, dz * 2, "dz bf16"},
+      {(void**)&n->out, B * n->nout * 4, "out"}, {(void**)&n->dout, B * n->nout * 4, "dout"},
+      {(void**)&n->gtmp, gtmp * 4, "data gradients"}, {(void**)&n->dz, dz * 4, "dz"},
+      {(void**)&n->part, n->part_elems * 4, "split-K partials"}, {(void**)&n->loss, 4, "loss"},
+  };
+  for (auto& a : al) {
+    int s = dev_alloc(a.p, a.bytes, a.what);
+    if (s) {
+      free_net(n);
+      return s;
+    }
+  }
+  hipError_t e;
+  if ((e = hipMemset(n->w, 0, n->n_params * 4)) != hipSuccess || (e = hipMemset(n->m, 0, n->n_params * 4)) != hipSuccess ||
+      (e = hipMemset(n->v, 0, n->n_params * 4)) != hipSuccess || (e = hipMemset(n->wb, 0, n->n_params * 2)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
+    free_net(n);
+    return hip_fail(e, "pwfs_cnn_create");
+  }
+  *out = n;
+  return 0;
+}
+
+int pwfs_cnn_num_params(pwfs_cnn_t n, int64_t* np) {
+  if (!n || !np) return fail(PWFS_CNN_ERR_INVALID_ARG, "network or output is NULL");
+  *np = (int64_t)n->n_params;
+  return 0;
+}
+
+int pwfs_cnn_set_params(pwfs_cnn_t n, const float* d, void* stream) {
+  if (!n || !d) return fail(PWFS_CNN_ERR_INVALID_ARG, "network or params is NULL");
+  DevGuard g(n->device);
+  hipStream_t st = (hipStream_t)stream;
+  CK(hipMemcpyAsync(n->w, d, n->n_params * 4, hipMemcpyDeviceToDevice, st));
+  CK(pwfs::cnn::to_bf16(n->w, n->n_params, n->wb, st));
+  CK(pwfs::cnn::fill0(n->m, n->n_params, st));
+  CK(pwfs::cnn::fill0(n->v, n->n_params, st));
+  n->step = 0;
+  return 0;
+}
+
+int pwfs_cnn_get_params(pwfs_cnn_t n, float* d, void* stream) {
+  if (!n || !d) return fail(PWFS_CNN_ERR_INVALID_ARG, "network or params is NULL");
+  DevGuard g(n->device);
+  CK(hipMemcpyAsync(d, n->w, n->n_params * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return 0;
+}
+
+int pwfs_cnn_prepare(const float* d_pupils, const float* d_ref, const int32_t* d_valid, int32_t nv, int32_t B,
+                     int32_t S, float* d_x, void* stream) {
+  if (B < 0 || nv <= 0 || S <= 0 || nv > S * S) return fail(PWFS_CNN_ERR_INVALID_ARG, "bad sizes");
+  if (B == 0) return 0;
+  if (!d_pupils || !d_ref || !d_valid || !d_x) return fail(PWFS_CNN_ERR_INVALID_ARG, "NULL pointer");
+  CK(pwfs::cnn::prepare(d_pupils, d_ref, d_valid, nv, B, S, d_x, (hipStream_t)stream));
+  return 0;
+}
+
+int pwfs_cnn_forward(pwfs_cnn_t n, const float* d_x, int32_t B, float* d_out, void* stream) {
+  int s = check_batch(n, B);
+  if (s) return s;
+  if (B == 0) return 0;
+  if (!d_x || !d_out) return fail(PWFS_CNN_ERR_INVALID_ARG, "NULL pointer");
+  DevGuard g(n->device);
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = run_forward(n, d_x, B, st))) return s;
+  CK(hipMemcpyAsync(d_out, n->out, (size_t)B * n->nout * 4, hipMemcpyDeviceToDevice, st));
+  return 0;
+}
+
+int pwfs_cnn_forward_acc(pwfs_cnn_t n, const float* d_x, int32_t B, float alpha, float beta, float* d_out,
+                         void* stream) {
+  int s = check_batch(n, B);
+  if (s) return s;
+  if (B == 0) return 0;
+  if (!d_x || !d_out) return fail(PWFS_CNN_ERR_INVALID_ARG, "NULL pointer");
+  if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PWFS_CNN_ERR_INVALID_ARG, "alpha/beta not finite");
+  DevGuard g(n->device);
+  return run_forward(n, d_x, B, (hipStream_t)stream, d_out, alpha, beta);
+}
+
+int pwfs_cnn_gradients(pwfs_cnn_t n, const float* d_x, const float* d_target, int32_t B, float* d_grads,
+                       float* d_loss, void* stream) {
+  int s = check_batch(n, B);
+  if (s) return s;
+  if (B == 0) return 0;
+  if (!d_x || !d_target) return fail(PWFS_CNN_ERR_INVALID_ARG, "NULL pointer");
+  DevGuard g(n->device);
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = run_forward(n, d_x, B, st))) return s;
+  if ((s = run_backward(n, d_target, B, d_loss ? d_loss : n->loss, st))) return s;
+  if (d_grads) CK(hipMemcpyAsync(d_grads, n->g, n->n_params * 4, hipMemcpyDeviceToDevice, st));
+  return 0;
+}
+
+int pwfs_cnn_train_step(pwfs_cnn_t n, const float* d_x, const float* d_target, int32_t B, float lr, float beta1,
+                        float beta2, float eps, float* d_loss, void* stream) {
+  int s = check_batch(n, B);
+  if (s) return s;
+  if (B == 0) return 0;
+  if (!d_x || !d_target) return fail(PWFS_CNN_ERR_INVALID_ARG, "NULL pointer");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(PWFS_CNN_ERR_INVALID_ARG, "optimizer hyper-parameters out of range");
+  DevGuard g(n->device);
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = run_forward(n, d_x, B, st))) return s;
+  if ((s = run_backward(n, d_target, B, d_loss ? d_loss : n->loss, st))) return s;
+  n->step += 1;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)n->step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)n->step));
+  CK(pwfs::cnn::adam(n->w, n->g, n->m, n->v, n->wb, n->n_params, lr, beta1, beta2, eps, c1, c2, st));
+  return 0;
+}
+
+void pwfs_cnn_destroy(pwfs_cnn_t n) {
+  if (!n) return;
+  {
+    DevGuard g(n->device);
+    (void)hipDeviceSynchronize();
+  }
+  free_net(n);
+}
+
+}  // extern "C"

@@ -84,6 +84,10 @@ struct DeviceGuard {
 
 }  // namespace
 
+namespace pwfs {
+int set_last_error(int status, const std::string& msg) { return fail(status, msg); }
+}  // namespace pwfs
+
 struct pwfs_plan_s {
   pwfs_config_t cfg{};
   int device = 0;
@@ -517,7 +521,7 @@ int recon_apply(const float* d_R, int32_t M, int32_t n_s, const float* d_s, int3
   if (B == 0) return PWFS_OK;
   if (!d_R || !d_s || !d_m) return fail(PWFS_ERR_INVALID_ARG, "NULL matrix or vector");
   if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PWFS_ERR_INVALID_ARG, "alpha/beta not finite");
-  if (B > 65535 * 8) return fail(PWFS_ERR_UNSUPPORTED, "B too large");
+  if (B > 65535 * 8 || M > 65535 * 4) return fail(PWFS_ERR_UNSUPPORTED, "B or M too large");
   hipError_t e = pwfs::launch_recon(d_R, M, n_s, d_s, B, alpha, beta, d_m, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "recon_apply launch");
   return PWFS_OK;

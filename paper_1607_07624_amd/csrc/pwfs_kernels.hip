@@ -433,6 +433,54 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R,
 }
 
 // ---------------------------------------------------------------------------
+// Batched m = alpha R s + beta m for B > 16 frames: a dense FP32 product
+// C[b][i] = sum_k s[b][k] R[i][k] on v_mfma_f32_32x32x2f32 (FP32 operands and
+// accumulation, fixed order).  Block = 4 waves, tile 64 frames x 64 rows of
+// R, K step 32 through LDS; lane l feeds A(b = l % 32, k = l / 32) and
+// B(i = l % 32, k = l / 32); accumulator v of lane l is
+// C(8 (v / 4) + 4 (l / 32) + v % 4, l % 32).
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void recon_mfma_kernel(const float* __restrict__ R, int M, int ns,
+                                                          const float* __restrict__ s, int B, float alpha,
+                                                          float beta, float* __restrict__ m) {
+  __shared__ float As[64][33];
+  __shared__ float Bs[64][33];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int b0 = blockIdx.y * 64, i0 = blockIdx.x * 64;
+  f32x16_t acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  for (int k0 = 0; k0 < ns; k0 += 32) {
+    for (int e = tid; e < 2048; e += 256) {
+      const int r = e >> 5, kk = e & 31;
+      const int gk = k0 + kk;
+      const int gb = b0 + r, gi = i0 + r;
+      As[r][kk] = (gb < B && gk < ns) ? s[(size_t)gb * ns + gk] : 0.f;
+      Bs[r][kk] = (gi < M && gk < ns) ? R[(size_t)gi * ns + gk] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 2) {
+      const float a = As[wm * 32 + (lane & 31)][kk + (lane >> 5)];
+      const float b = Bs[wn * 32 + (lane & 31)][kk + (lane >> 5)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int i = i0 + wn * 32 + (lane & 31);
+  if (i >= M) return;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int b = b0 + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    if (b >= B) continue;
+    float* mm = m + (size_t)b * M + i;
+    *mm = beta != 0.f ? fmaf(alpha, acc[v], beta * *mm) : alpha * acc[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers.
 template <int E>
 static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
@@ -515,6 +563,11 @@ static void launch_recon_bt(const float* R, int M, int ns, const float* s, int B
 
 hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, float alpha,
                         float beta, float* m, hipStream_t st) {
+  if (B > 16) {
+    hipLaunchKernelGGL(recon_mfma_kernel, dim3((M + 63) / 64, (B + 63) / 64), dim3(256), 0, st, R, M, ns, s, B,
+                       alpha, beta, m);
+    return hipGetLastError();
+  }
   if (B <= 1)
     launch_recon_bt<1>(R, M, ns, s, B, alpha, beta, m, st);
   else if (B <= 4)

@@ -1,0 +1,186 @@
+"""Learned modal reconstructor: training-set generation on the GPU, training
+loop and checkpoints, driven through the C ABI (pwfs_measure, recon_apply,
+pwfs_cnn_*).
+
+Training inputs are simulator frames: seeded screens (open loop) and
+partially corrected screens (the DM path removes a random fraction of the
+first n KL modes, as an integrator loop does), measured by the pyramid plan,
+turned into network inputs by pwfs_cnn_prepare; labels are the KL
+coefficients of the measured screen (projection through recon_apply),
+divided by one global scale so the loss is a wavefront error in scaled nm^2.
+After training the scale is folded into the last layer, so the network
+outputs modal coefficients in nm, the same units as R s.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from ._lib import recon_apply
+from .cnn import CNN, prepare, he_init, PARAM_ORDER
+
+
+class TrainingSet:
+    def __init__(self, x, y, label_scale):
+        self.x, self.y, self.label_scale = x, y, label_scale
+
+
+def projector(modes: np.ndarray, pupil: np.ndarray, device="cuda"):
+    """Projection matrix [M, P*P] (modes / n_pix) as a device tensor: c = Proj opd."""
+    import torch
+    n_pix = float((pupil > 0).sum())
+    M = modes.shape[0]
+    return torch.from_numpy((modes.reshape(M, -1) / n_pix).astype(np.float32)).to(device).contiguous()
+
+
+def make_training_set(plan, bank, modes: np.ndarray, pupil: np.ndarray, n_frames: int, seed: int,
+                      r0_range=(0.06, 0.2), corrected_fraction=0.5, batch=256, label_scale=None,
+                      device="cuda") -> TrainingSet:
+    """Generate n_frames (input, label) pairs on the GPU."""
+    import torch
+    rng = np.random.default_rng(seed)
+    P, S, M = plan.cfg.n_pupil, plan.n_sub, modes.shape[0]
+    proj = projector(modes, pupil, device)
+    BKL = torch.from_numpy(modes.reshape(M, -1).T.astype(np.float32)).to(device).contiguous()
+    valid = torch.from_numpy(plan.valid.astype(np.int32)).to(device)
+    zero = torch.zeros((1, P, P), device=device)
+    ref = torch.empty((1, 4, S, S), device=device)
+    plan.measure_into(zero, ref, None)
+    X = torch.empty((n_frames, S, S, 4), device=device)
+    Y = torch.empty((n_frames, M), device=device)
+    pup = torch.empty((plan.batch_max, 4, S, S), device=device)
+    for i0 in range(0, n_frames, batch):
+        n = min(batch, n_frames - i0)
+        opd_h, _ = bank.draw(rng, n, r0_range)
+        opd = torch.from_numpy(opd_h).to(device).reshape(n, P * P).contiguous()
+        # Partial correction of a random subset of frames: remove alpha * c_i B_i for
+        # i < n_corr (coefficients scaled on the host, DM path through recon_apply).
+        n_cor = int(round(corrected_fraction * n))
+        if n_cor:
+            c = recon_apply(proj, opd[:n_cor]).cpu().numpy()                 # [n_cor, M]
+            for j in range(n_cor):
+                c[j, rng.integers(20, M + 1):] = 0.0
+                c[j] *= rng.uniform(0.5, 1.0)
+            recon_apply(BKL, torch.from_numpy(c).to(device), -1.0, 1.0, opd[:n_cor])
+        if label_scale is None:
+            c0 = recon_apply(proj, opd).cpu().numpy().astype(np.float64)
+            label_scale = float(np.sqrt(np.mean(c0 ** 2)))
+        recon_apply(proj, opd, 1.0 / label_scale, 0.0, Y[i0:i0 + n])
+        for b0 in range(0, n, plan.batch_max):
+            nb = min(plan.batch_max, n - b0)
+            plan.measure_into(opd[b0:b0 + nb].view(nb, P, P), pup[:nb], None)
+            prepare(pup[:nb], ref[0], valid, X[i0 + b0:i0 + b0 + nb])
+    return TrainingSet(X, Y, label_scale)
+
+
+def train(net: CNN, data: TrainingSet, epochs: int, batch: int, lr: float, seed: int, log=None):
+    """Adam over shuffled mini-batches; returns the mean loss of each epoch."""
+    import torch
+    n = data.x.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    loss = torch.empty(1, device=data.x.device)
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(data.x.device)
+        acc, steps = 0.0, 0
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            xb = data.x.index_select(0, idx).contiguous()
+            yb = data.y.index_select(0, idx).contiguous()
+            net.train_step(xb, yb, lr, loss=loss)
+            if steps % 16 == 0:
+                acc += float(loss.cpu())
+            steps += 1
+        hist.append(acc / max(1, (steps + 15) // 16))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.4f}")
+    return hist
+
+
+def fold_label_scale(net: CNN, scale: float):
+    """Multiply the last layer by the label scale so outputs are in nm."""
+    import torch
+    p = net.get_params().cpu().numpy()
+    off = 0
+    for k in PARAM_ORDER:
+        n = int(np.prod(net.shapes[k]))
+        if k in ("fw2", "fb2"):
+            p[off:off + n] *= scale
+        off += n
+    net.set_params(torch.from_numpy(p))
+
+
+def save_checkpoint(path: str, net: CNN, meta: dict):
+    np.savez(path, params=net.get_params().cpu().numpy(), **{k: np.asarray(v) for k, v in meta.items()})
+
+
+def load_checkpoint(path: str, net: CNN) -> dict:
+    import torch
+    d = np.load(path, allow_pickle=False)
+    net.set_params(torch.from_numpy(d["params"]))
+    return {k: d[k] for k in d.files if k != "params"}
+
+
+def train_reconstructor(plan, modes: np.ndarray, pupil: np.ndarray, bank, n_frames: int, seed: int,
+                        epochs: int = 4, batch: int = 256, lr: float = 1e-3, r0_range=(0.06, 0.2),
+                        log=None, device="cuda"):
+    """Generate the training set, train a CNN from a seeded He initialisation,
+    fold the label scale; returns (net, info)."""
+    import time
+    t0 = time.time()
+    data = make_training_set(plan, bank, modes, pupil, n_frames, seed, r0_range=r0_range, device=device)
+    t_data = time.time() - t0
+    net = CNN(n_sub=plan.n_sub, n_out=modes.shape[0], batch_max=batch)
+    import torch
+    net.set_params(torch.from_numpy(he_init(net.shapes, seed + 1)))
+    t1 = time.time()
+    hist = []
+    for ep in range(epochs):
+        hist += train(net, data, 1, batch, lr * (0.5 ** ep), seed + 10 + ep, log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    fold_label_scale(net, data.label_scale)
+    info = {"frames": n_frames, "epochs": epochs, "batch": batch, "loss_history": hist,
+            "label_scale_nm": data.label_scale, "data_s": round(t_data, 2), "train_s": round(t_train, 2),
+            "train_frames_per_s": round(epochs * n_frames / max(t_train, 1e-9), 1)}
+    del data
+    return net, info
+
+
+def open_loop_errors(plan, net, R_dev, modes: np.ndarray, pupil: np.ndarray, bank, n_frames: int, seed: int,
+                     r0_range, device="cuda"):
+    """Held-out modal reconstruction error (nm RMS over the pupil, within the
+    modal subspace) of the learned and of the linear reconstructor."""
+    import torch
+    data = make_training_set(plan, bank, modes, pupil, n_frames, seed, r0_range=r0_range,
+                             corrected_fraction=0.0, label_scale=1.0, device=device)
+    P = plan.cfg.n_pupil
+    pred = torch.empty_like(data.y)
+    for b0 in range(0, n_frames, net.batch_max):
+        nb = min(net.batch_max, n_frames - b0)
+        net.forward(data.x[b0:b0 + nb].contiguous(), pred[b0:b0 + nb])
+    # linear: measure the same screens again for slopes (same seed -> same screens)
+    rng_frames = make_slopes(plan, bank, modes, pupil, n_frames, seed, r0_range, device)
+    lin = recon_apply(R_dev, rng_frames)
+    y = data.y.cpu().numpy().astype(np.float64)
+    e_cnn = float(np.sqrt(np.mean(np.sum((pred.cpu().numpy() - y) ** 2, axis=1))))
+    e_lin = float(np.sqrt(np.mean(np.sum((lin.cpu().numpy() - y) ** 2, axis=1))))
+    e_0 = float(np.sqrt(np.mean(np.sum(y ** 2, axis=1))))
+    return {"cnn_nm": round(e_cnn, 2), "linear_nm": round(e_lin, 2), "signal_nm": round(e_0, 2),
+            "frames": n_frames, "r0_range": list(r0_range)}
+
+
+def make_slopes(plan, bank, modes, pupil, n_frames, seed, r0_range, device="cuda"):
+    """Slopes of the open-loop screens make_training_set draws for the same seed."""
+    import torch
+    rng = np.random.default_rng(seed)
+    P = plan.cfg.n_pupil
+    out = torch.empty((n_frames, 2 * plan.n_valid), device=device)
+    batch = 256
+    for i0 in range(0, n_frames, batch):
+        n = min(batch, n_frames - i0)
+        opd_h, _ = bank.draw(rng, n, r0_range)
+        opd = torch.from_numpy(opd_h).to(device)
+        for b0 in range(0, n, plan.batch_max):
+            nb = min(plan.batch_max, n - b0)
+            plan.measure_into(opd[b0:b0 + nb].contiguous(), None, out[i0 + b0:i0 + b0 + nb])
+    return out

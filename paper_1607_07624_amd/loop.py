@@ -61,15 +61,37 @@ def calibrate(plan, modes, eps_nm: float, device="cuda"):
 
 
 class ClosedLoop:
-    """Integrator loop of one sensor plan (batch 1) with a modal DM."""
+    """Integrator loop of one sensor plan (batch 1) with a modal DM.
 
-    def __init__(self, plan, modes_dev, R_dev, gain: float, delay: int):
+    With a learned reconstructor (net) the integrator input is the
+    network's modal estimate from the pupil images; the linear
+    reconstructor R judges it every `judge_every` steps and takes over for
+    the rest of the run if the network output is not finite or the linear
+    estimate of the modal residual, ||R s||, exceeds `judge_growth` times
+    its median over the steps judged so far (a diverging loop)."""
+
+    def __init__(self, plan, modes_dev, R_dev, gain: float, delay: int, net=None,
+                 judge_every: int = 20, judge_growth: float = 4.0):
         import torch
         self.plan, self.R, self.gain, self.delay = plan, R_dev, float(gain), int(delay)
         M, P, _ = modes_dev.shape
         self.M, self.P = M, P
+        dev = modes_dev.device
         self.BKL = modes_dev.reshape(M, P * P).t().contiguous()     # [P*P, M]
-        self.s = torch.empty((1, 2 * plan.n_valid), device=modes_dev.device)
+        self.s = torch.empty((1, 2 * plan.n_valid), device=dev)
+        self.net = net
+        self.judge_every, self.judge_growth = judge_every, judge_growth
+        self.fallback_step = None
+        if net is not None:
+            from .cnn import prepare
+            self._prepare = prepare
+            S = plan.n_sub
+            self.pupils = torch.empty((1, 4, S, S), device=dev)
+            self.ref = torch.empty((1, 4, S, S), device=dev)
+            plan.measure_into(torch.zeros((1, P, P), device=dev), self.ref, None)
+            self.valid = torch.from_numpy(plan.valid.astype(np.int32)).to(dev)
+            self.x = torch.empty((1, S, S, 4), device=dev)
+            self.m_lin = torch.empty((1, M), device=dev)
 
     def run(self, opd_seq_dev, residuals_dev=None):
         """Run len(opd_seq) steps; returns (residual OPD [T, P*P], commands c(t) [T, M])."""
@@ -79,15 +101,33 @@ class ClosedLoop:
         dev = opd_seq_dev.device
         res = residuals_dev if residuals_dev is not None else torch.empty((T, P * P), device=dev)
         hist = torch.zeros((T + d, M), device=dev)                   # c(t) is row t + d
+        learned = self.net is not None
+        judged = []
+        self.fallback_step = None
         for t in range(T):
             r_t = res[t:t + 1]
             r_t.copy_(opd_seq_dev[t].reshape(1, -1))
             recon_apply(self.BKL, hist[t:t + 1], -1.0, 1.0, r_t)     # u(t) = c(t - d)
-            self.plan.measure_into(r_t.view(1, P, P), None, self.s)
             c_next = hist[t + d:t + d + 1]
             if t > 0:
                 c_next.copy_(hist[t + d - 1:t + d])
-            recon_apply(self.R, self.s, self.gain, 1.0, c_next)
+            if learned:
+                self.plan.measure_into(r_t.view(1, P, P), self.pupils, self.s)
+                self._prepare(self.pupils, self.ref[0], self.valid, self.x)
+                self.net.forward_acc(self.x, c_next, self.gain, 1.0)
+                if t % self.judge_every == 0:
+                    recon_apply(self.R, self.s, 1.0, 0.0, self.m_lin)
+                    e = float(np.linalg.norm(self.m_lin.cpu().numpy()))
+                    ok = bool(np.isfinite(c_next.cpu().numpy()).all())
+                    judged.append(e)
+                    if not ok or (len(judged) > 5 and e > self.judge_growth * float(np.median(judged))):
+                        learned = False
+                        self.fallback_step = t
+                        c_next.copy_(hist[t + d - 1:t + d] if t > 0 else torch.zeros_like(c_next))
+                        recon_apply(self.R, self.s, self.gain, 1.0, c_next)
+            else:
+                self.plan.measure_into(r_t.view(1, P, P), None, self.s)
+                recon_apply(self.R, self.s, self.gain, 1.0, c_next)
         return res, hist[d:]
 
 

@@ -97,3 +97,40 @@ def tilt_opd_nm(P: int, alpha_lod: float, wavelength_m: float, axis: str = "x") 
     x = np.arange(P) - c
     ramp = np.broadcast_to(x[None, :] if axis == "x" else x[:, None], (P, P))
     return alpha_lod * ramp / P * wavelength_m * 1e9
+
+
+class CropBank:
+    """Random P x P crops of a few large von Karman screens (input generation).
+
+    For a fixed outer scale the von Karman phase PSD scales as r0^(-5/3), so
+    a screen drawn at r0_ref becomes a screen at r0 when multiplied by
+    (r0_ref / r0)^(5/6); each crop also gets one of the 8 square symmetries.
+    Crops of one screen overlap, which is acceptable for training inputs.
+    """
+
+    def __init__(self, cfg: SensorConfig, L0_m: float, n_screens: int, screen_n: int, seed: int,
+                 r0_ref_m: float = 0.1):
+        self.P = cfg.n_pupil
+        self.r0_ref = r0_ref_m
+        rng = np.random.default_rng(int(seed))
+        self.screens = [von_karman_opd_nm(screen_n, cfg.pixel_m, r0_ref_m, L0_m, rng).astype(np.float32)
+                        for _ in range(n_screens)]
+
+    def draw(self, rng: np.random.Generator, n: int, r0_range) -> tuple[np.ndarray, np.ndarray]:
+        """(opd [n, P, P] float32 nm, r0 [n])."""
+        P = self.P
+        out = np.empty((n, P, P), np.float32)
+        r0 = rng.uniform(*r0_range, size=n)
+        for i in range(n):
+            s = self.screens[rng.integers(len(self.screens))]
+            y, x = rng.integers(0, s.shape[0] - P, size=2)
+            c = s[y:y + P, x:x + P]
+            sym = rng.integers(8)
+            if sym & 1:
+                c = c[::-1]
+            if sym & 2:
+                c = c[:, ::-1]
+            if sym & 4:
+                c = c.T
+            out[i] = c * np.float32((self.r0_ref / r0[i]) ** (5.0 / 6.0))
+        return out, r0

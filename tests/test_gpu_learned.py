@@ -1,0 +1,62 @@
+"""Learned reconstructor trained on simulator frames: what it gains over the
+linear reconstructor, and the linear reconstructor as its fallback/judge."""
+import numpy as np
+import pytest
+
+from synth.configs import CFG2, ATMO2, PUSH_PULL_NM, LOOP_GAIN, LOOP_DELAY
+from synth.screens import CropBank, frozen_flow_sequence
+from synth.kl import kl_modes
+from tests.gpu_common import torch_cuda, say
+
+pytestmark = pytest.mark.gpu
+
+_STATE = {}
+
+
+def _setup():
+    if _STATE:
+        return _STATE
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd.loop import calibrate
+    torch = torch_cuda()
+    plan = pw.Plan(CFG2, batch_max=16)
+    pupil = plan.pupil.astype(np.float64)
+    modes = kl_modes(pupil, CFG2.pixel_m, ATMO2.L0_m, 600).astype(np.float32)
+    R, _, _ = calibrate(plan, modes, PUSH_PULL_NM)
+    bank = CropBank(CFG2, ATMO2.L0_m, n_screens=2, screen_n=2048, seed=77)
+    _STATE.update(plan=plan, pupil=pupil, modes=modes, R=R, bank=bank, torch=torch)
+    return _STATE
+
+
+def test_trained_cnn_beats_linear_in_open_loop_strong_turbulence():
+    from paper_1607_07624_amd.learned import train_reconstructor, open_loop_errors
+    st = _setup()
+    net, info = train_reconstructor(st["plan"], st["modes"], st["pupil"], st["bank"], n_frames=24576,
+                                    seed=1, epochs=3, batch=256, lr=1e-3, log=say)
+    say(f"[gpu] cnn training: {info}")
+    assert info["loss_history"][-1] < 0.5 * info["loss_history"][0]
+    ev = open_loop_errors(st["plan"], net, st["R"], st["modes"], st["pupil"], st["bank"], 1024, seed=999,
+                          r0_range=(0.06, 0.1))
+    say(f"[gpu] open-loop modal error, r0 in [0.06, 0.1] m: {ev}")
+    assert ev["cnn_nm"] < ev["linear_nm"]
+    st["net"] = net
+
+
+def test_linear_judge_takes_over_from_a_broken_network():
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd.cnn import CNN
+    from paper_1607_07624_amd.loop import ClosedLoop, residual_rms_nm
+    st = _setup()
+    torch = st["torch"]
+    net = CNN(n_sub=CFG2.n_sub, n_out=600, batch_max=4)
+    net.set_params(torch.full((net.n_params,), float("nan"), device="cuda"))
+    plan1 = pw.Plan(CFG2, batch_max=1)
+    modes_dev = torch.from_numpy(st["modes"]).cuda()
+    seq = torch.from_numpy(frozen_flow_sequence(CFG2, ATMO2, 60, seed=3)).cuda()
+    cl = ClosedLoop(plan1, modes_dev, st["R"], LOOP_GAIN, LOOP_DELAY, net=net)
+    res_c, _ = cl.run(seq)
+    assert cl.fallback_step == 0
+    lin = ClosedLoop(plan1, modes_dev, st["R"], LOOP_GAIN, LOOP_DELAY)
+    res_l, _ = lin.run(seq)
+    torch.cuda.synchronize()
+    assert torch.equal(res_c, res_l)
