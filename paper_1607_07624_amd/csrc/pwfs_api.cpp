@@ -55,21 +55,6 @@ int dev_alloc(void** p, size_t bytes, const char* what) {
   return PWFS_OK;
 }
 
-// exp(-2 pi i n / d) with the integer ratio reduced first (FP64).
-cpx unit_frac(long n, long d, int sign) {
-  n %= d;
-  if (n < 0) n += d;
-  const double ang = 2.0 * M_PI * (double)n / (double)d;
-  return {(float)std::cos(ang), (float)(-sign * std::sin(ang))};
-}
-
-// exp(+2 pi i t) for a real number of turns t (FP64, fractional part first).
-cpx unit_turns(double t) {
-  const double f = t - std::floor(t);
-  const double ang = 2.0 * M_PI * f;
-  return {(float)std::cos(ang), (float)std::sin(ang)};
-}
-
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -110,6 +95,7 @@ struct pwfs_plan_s {
   cpx* Rw = nullptr;
   float* partial = nullptr;
   float* pupils = nullptr;
+  cpx* field = nullptr;
   float* zero_opd = nullptr;
   float* tmp_slopes = nullptr;
   size_t ws_bytes = 0;
@@ -162,7 +148,7 @@ void free_plan(pwfs_plan_s* p) {
   if (!p) return;
   DeviceGuard g(p->device);
   void* ptrs[] = {p->amp, p->in_a, p->f_a, p->in_b, p->f_b, p->mid, p->outw, p->k_order, p->k_ia,
-                  p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->zero_opd, p->tmp_slopes};
+                  p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->field, p->zero_opd, p->tmp_slopes};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto* pool : {&p->ev_used, &p->ev_free})
@@ -200,6 +186,7 @@ int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* s
     a.valid = p->d_valid;
     a.sref = sref;
     a.Rw = p->Rw;
+    a.field = p->field;
     a.partial = p->partial;
     hipEvent_t* ev = nullptr;
     if (p->timing) {
@@ -352,16 +339,30 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       for (int q = 0; q < 2; ++q) in_b[((size_t)k * 2 + q) * P + y] = to32(r * tw[(size_t)q * P + y]);
     }
   }
-  // Pyramid line-operator tables.
-  std::vector<cpx> outw(2 * (size_t)P), mid(4 * (size_t)p->E);
+  // Pyramid line-operator tables: output twiddles (4/N) w_N^{-(2q+1) j} and,
+  // per quad lane l and in-lane frequency k, the folded mix coefficients
+  // A_l / 2 = (1 - i) conj(w_l) w_{l+1} / 2, B_l / 2 = (1 + i) conj(w_l) w_{l-1} / 2
+  // with w_l = w_P^{l k} (FP64, lanes mod 4).
+  std::vector<cpx> outw(2 * (size_t)P), mid(8 * (size_t)p->E);
   for (int q = 0; q < 2; ++q)
     for (int x = 0; x < P; ++x) {
-      cpx w = unit_frac((long)(2 * q + 1) * x, N, -1);
-      const float sc = (float)(2.0 / (double)N);
-      outw[(size_t)q * P + x] = {w.re * sc, w.im * sc};
+      const long n = ((long)(2 * q + 1) * x) % N;
+      const double ang = 2.0 * M_PI * (double)n / (double)N;
+      const double sc = 4.0 / (double)N;
+      outw[(size_t)q * P + x] = {(float)(sc * std::cos(ang)), (float)(sc * std::sin(ang))};
     }
+  auto wlk = [&](int l, int k) {
+    const long n = ((long)l * k) % P;
+    const double ang = -2.0 * M_PI * (double)n / (double)P;
+    return std::complex<double>(std::cos(ang), std::sin(ang));
+  };
   for (int l = 0; l < 4; ++l)
-    for (int k = 0; k < p->E; ++k) mid[(size_t)l * p->E + k] = unit_frac((long)l * k, P, +1);
+    for (int k = 0; k < p->E; ++k) {
+      const std::complex<double> A = std::complex<double>(0.5, -0.5) * std::conj(wlk(l, k)) * wlk((l + 1) & 3, k);
+      const std::complex<double> Bc = std::complex<double>(0.5, 0.5) * std::conj(wlk(l, k)) * wlk((l + 3) & 3, k);
+      mid[((size_t)l * p->E + k) * 2] = to32(A);
+      mid[((size_t)l * p->E + k) * 2 + 1] = to32(Bc);
+    }
 
   // Device buffers.
   int bm = cfg->batch_max;
@@ -387,6 +388,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {(void**)&p->Rw, rw_elems * sizeof(cpx), "row-pass workspace"},
       {(void**)&p->partial, partial_elems * sizeof(float), "pupil partials"},
       {(void**)&p->pupils, (size_t)bm * 4 * S * S * sizeof(float), "pupil scratch"},
+      {(void**)&p->field, (size_t)bm * P * P * sizeof(cpx), "pupil field"},
       {(void**)&p->zero_opd, (size_t)P * P * sizeof(float), "zero opd"},
       {(void**)&p->tmp_slopes, (size_t)2 * p->nv * sizeof(float), "reference scratch"},
   };

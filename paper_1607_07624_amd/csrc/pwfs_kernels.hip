@@ -56,24 +56,32 @@ __device__ __forceinline__ const T* opaque(const T* p) {
   return p;
 }
 
-// Half-band projection of the E samples held by this lane (see header).
-// mid[l * E + k] = w_P^{l k}.
+// Half-band projection of the E samples held by this lane (see header), up to
+// a factor 1/2 that the output table absorbs.  The forward twiddle w_l =
+// w_P^{l k}, the quad mix and the conjugate twiddle are folded into
+//   V_l = v_l + (A_l / 2) v_{l+1} + (B_l / 2) v_{l-1},
+//   A_l = (1 - i) conj(w_l) w_{l+1},  B_l = (1 + i) conj(w_l) w_{l-1}   (lanes mod 4),
+// mid[(l * E + k) * 2 + {0, 1}] = {A_l(k) / 2, B_l(k) / 2}.
 template <int E>
 __device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ mid, int l) {
   Dft<E, +1>::run(v);
   fence();
-  const cpx* ml = mid + l * E;
+  const cpx* ml = mid + l * 2 * E;
   static_for<0, E>([&](auto k_) {
     constexpr int k = decltype(k_)::value;
     if constexpr (k % 8 == 0 && k > 0) fence();
-    const cpx w = ml[k];
-    const cpx y = cmul(v[k], w);
-    const float pr = quad_perm<0x39>(y.re), pim = quad_perm<0x39>(y.im);  // lane l+1
-    const float nr = quad_perm<0x93>(y.re), nim = quad_perm<0x93>(y.im);  // lane l-1
-    const float sr = pr + nr, si = pim + nim;
-    const float dr = nr - pr, di = nim - pim;
-    const cpx V = {fmaf(2.f, y.re, sr - di), fmaf(2.f, y.im, si + dr)};
-    v[k] = cmulc(V, w);
+    const cpx a = ml[2 * k], b = ml[2 * k + 1];
+    const float pr = quad_perm<0x39>(v[k].re), pim = quad_perm<0x39>(v[k].im);  // lane l+1
+    const float nr = quad_perm<0x93>(v[k].re), nim = quad_perm<0x93>(v[k].im);  // lane l-1
+    float re = fmaf(a.re, pr, v[k].re);
+    re = fmaf(-a.im, pim, re);
+    re = fmaf(b.re, nr, re);
+    re = fmaf(-b.im, nim, re);
+    float im = fmaf(a.re, pim, v[k].im);
+    im = fmaf(a.im, pr, im);
+    im = fmaf(b.re, nim, im);
+    im = fmaf(b.im, nr, im);
+    v[k] = {re, im};
   });
   fence();
   Dft<E, -1>::run(v);
@@ -84,7 +92,7 @@ __device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ m
 //   load_in(m)  = f(x) w_N^{(2q+1) x} at x = l + 4 m (tilted input times this
 //                 quad's twist, one complex product from a combined table);
 //   load_f(m)   = f(l + 4 m) (needed by quad 0 for y_L = f - y_H);
-//   outw[q * P + j] = (2/N) w_N^{-(2q+1) j}.
+//   outw[q * P + j] = (4/N) w_N^{-(2q+1) j}  (2/N times the 2 the half-band step leaves out).
 // On return quad 0 holds y_L(l + 4 m) and quad 1 holds y_H(l + 4 m) in v[m].
 template <int E, typename LoadIn, typename LoadF>
 __device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadF&& load_f,
@@ -125,23 +133,37 @@ __device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __res
 }
 
 // ---------------------------------------------------------------------------
+// Pupil field A exp(i phi), phi = 2 pi opd 1e-9 / lambda formed and reduced
+// modulo 2 pi in FP64, then FP32 sincos; once per frame.
+__global__ __launch_bounds__(256) void field_kernel(const float* __restrict__ opd, const float* __restrict__ amp,
+                                                    double kphase, int PP, size_t n, cpx* __restrict__ field) {
+  constexpr double two_pi = 6.283185307179586476925286766559;
+  constexpr double inv_two_pi = 0.15915494309189533576888376337251;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const double th = (double)opd[i] * kphase;
+    const double red = fma(-rint(th * inv_two_pi), two_pi, th);
+    float sn, cs;
+    sincosf((float)red, &sn, &cs);
+    const float A = amp[i % PP];
+    field[i] = {A * cs, A * sn};
+  }
+}
+
 // Row pass.  Block = 4 waves = 32 pupil rows of one frame (8 rows per wave),
-// looping over a chunk of distinct x tilts.  The pupil field A exp(i phi)
-// of the 32 rows is staged once in LDS (phase formed and range-reduced in
-// FP64); the tilt tables of each x tilt and the constant pyramid tables are
-// staged in LDS and shared by the four waves.
+// looping over a chunk of distinct x tilts.  The pupil field of the 32 rows
+// is staged once in LDS; the tilt tables of each x tilt and the constant
+// pyramid tables are staged in LDS and shared by the four waves.
 //   in_a[ia][q][x] = r_a(x) w_N^{(2q+1) x},  f_a[ia][x] = r_a(x).
 template <int E>
 __global__ __launch_bounds__(256) void row_pass_kernel(
-    const float* __restrict__ opd, const float* __restrict__ amp, double kphase,
-    const cpx* __restrict__ in_a, const cpx* __restrict__ f_a, const cpx* __restrict__ mid,
-    const cpx* __restrict__ outw, cpx* __restrict__ Rw, int n_a, int a_chunk) {
+    const cpx* __restrict__ fieldg, const cpx* __restrict__ in_a, const cpx* __restrict__ f_a,
+    const cpx* __restrict__ mid, const cpx* __restrict__ outw, cpx* __restrict__ Rw, int n_a, int a_chunk) {
   constexpr int P = 4 * E;
   constexpr int LDP = P + 4;
-  __shared__ cpx field[32 * LDP];
+  __shared__ __align__(16) cpx field[32 * LDP];
   __shared__ __align__(16) cpx s_in[2 * P];
   __shared__ __align__(16) cpx s_f[P];
-  __shared__ __align__(16) cpx s_mid[4 * E];
+  __shared__ __align__(16) cpx s_mid[8 * E];
   __shared__ __align__(16) cpx s_out[2 * P];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -149,20 +171,13 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
   const int yb = blockIdx.x * 32;
   const int a0 = blockIdx.y * a_chunk;
   const size_t fr = blockIdx.z;
-  const float* op = opd + fr * (size_t)P * P + (size_t)yb * P;
-  const float* am = amp + (size_t)yb * P;
-  constexpr double two_pi = 6.283185307179586476925286766559;
-  constexpr double inv_two_pi = 0.15915494309189533576888376337251;
-  for (int i = tid; i < 32 * P; i += 256) {
-    const int r = i / P, x = i - r * P;
-    const double th = (double)op[i] * kphase;
-    const double red = fma(-rint(th * inv_two_pi), two_pi, th);
-    float sn, cs;
-    sincosf((float)red, &sn, &cs);
-    const float A = am[i];
-    field[r * LDP + x] = {A * cs, A * sn};
+  // 32 field rows (contiguous in HBM) -> LDS rows of stride LDP, 16 bytes per move.
+  const uint4* src = reinterpret_cast<const uint4*>(fieldg + (fr * (size_t)P + yb) * (size_t)P);
+  for (int e = tid; e < 32 * (P / 2); e += 256) {
+    const int r = e / (P / 2), c2 = e - r * (P / 2);
+    *reinterpret_cast<uint4*>(field + r * LDP + 2 * c2) = src[e];
   }
-  copy16(s_mid, mid, (4 * E) / 2, tid, 256);
+  copy16(s_mid, mid, 4 * E, tid, 256);
   copy16(s_out, outw, P, tid, 256);
   const int a1 = min(a0 + a_chunk, n_a);
   const int r = wave * 8 + t;                     // row within the block
@@ -215,7 +230,7 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   __shared__ __align__(16) cpx s_col[32 * P];
   __shared__ __align__(16) cpx s_in[2 * P];
   __shared__ __align__(16) cpx s_f[P];
-  __shared__ __align__(16) cpx s_mid[4 * E];
+  __shared__ __align__(16) cpx s_mid[8 * E];
   __shared__ __align__(16) cpx s_out[2 * P];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -225,7 +240,7 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   const size_t fr = blockIdx.z;
   float acc[NA];
   static_for<0, NA>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
-  copy16(s_mid, mid, (4 * E) / 2, tid, 256);
+  copy16(s_mid, mid, 4 * E, tid, 256);
   copy16(s_out, outw, P, tid, 256);
   const int kb = chunk * k_chunk;
   const int ke = min(kb + k_chunk, K);
@@ -484,9 +499,14 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(const float* __restrict
 // Host launchers.
 template <int E>
 static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
+  const size_t n = (size_t)a.B * a.P * a.P;
+  const unsigned fb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(field_kernel, dim3(fb), dim3(256), 0, st, a.opd, a.amp, a.kphase, a.P * a.P, n, a.field);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   dim3 grid(a.P / 32, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
-  hipLaunchKernelGGL(row_pass_kernel<E>, grid, dim3(256), 0, st, a.opd, a.amp, a.kphase, a.in_a, a.f_a,
-                     a.mid, a.outw, a.Rw, a.n_a, a.a_chunk);
+  hipLaunchKernelGGL(row_pass_kernel<E>, grid, dim3(256), 0, st, a.field, a.in_a, a.f_a, a.mid, a.outw, a.Rw,
+                     a.n_a, a.a_chunk);
   return hipGetLastError();
 }
 

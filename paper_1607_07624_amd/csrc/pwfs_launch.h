@@ -25,13 +25,14 @@ struct MeasureArgs {
   const cpx* f_a;      // [n_a][P]     r_a(x)
   const cpx* in_b;     // [K][2][P]    r_b(y) w_N^{(2q+1)y}
   const cpx* f_b;      // [K][P]       r_b(y)
-  const cpx* mid;      // [4][P/4]
+  const cpx* mid;      // [4][P/4][2]  folded mix coefficients (A/2, B/2) per lane
   const cpx* outw;     // [2][P]
   const int* k_order;  // [K]
   const int* k_ia;     // [K]
   const int* valid;    // [nv]
   const float* sref;   // [2 nv]
   // workspace
+  cpx* field;          // [B][P][P]    A exp(i phi)
   cpx* Rw;             // [B][n_a][2P][P]
   float* partial;      // [B][n_chunks][4][S][S]
 };

@@ -88,3 +88,26 @@ def test_no_device_is_an_error_not_a_fallback():
     env = dict(os.environ, HIP_VISIBLE_DEVICES="-1", ROCR_VISIBLE_DEVICES="-1")
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert out.stdout.strip().splitlines()[-1] == "-3", out.stdout + out.stderr
+
+
+def test_cnn_abi_validation_and_no_device():
+    from paper_1607_07624_amd.cnn import _lib, cnn_config
+    lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.pwfs_cnn_create(None, ctypes.byref(h)) == -1
+    bad = cnn_config(n_sub=2, c1=32, c2=64, c3=64, hidden=2048, n_out=600, batch_max=4, reserved=0)
+    assert lib.pwfs_cnn_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    bad.n_sub, bad.reserved = 40, 7
+    assert lib.pwfs_cnn_create(ctypes.byref(bad), ctypes.byref(h)) == -1
+    assert lib.pwfs_cnn_forward(None, None, 1, None, None) == -1
+    assert lib.pwfs_cnn_prepare(None, None, None, 0, 1, 40, None, None) == -1
+    assert lib.pwfs_cnn_prepare(None, None, None, 10, 0, 40, None, None) == 0      # empty batch
+    lib.pwfs_cnn_destroy(None)
+    code = ("import ctypes, sys; sys.path.insert(0, %r)\n"
+            "from paper_1607_07624_amd.cnn import _lib, cnn_config\n"
+            "lib = _lib(); h = ctypes.c_void_p()\n"
+            "c = cnn_config(n_sub=40, c1=32, c2=64, c3=64, hidden=2048, n_out=600, batch_max=4, reserved=0)\n"
+            "print(lib.pwfs_cnn_create(ctypes.byref(c), ctypes.byref(h)))\n") % ROOT
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="-1", ROCR_VISIBLE_DEVICES="-1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.stdout.strip().splitlines()[-1] == "-3", out.stdout + out.stderr
