@@ -70,7 +70,10 @@ typedef struct {
   int32_t norm_mode;  /* 0: global mean flux over valid subapertures; 1: per subaperture. */
   int32_t batch_max;  /* largest batch the workspace is sized for (larger batches are     */
                       /* processed in slices of batch_max frames).                         */
-  int32_t reserved;   /* must be 0                                                         */
+  int32_t flags;      /* 0 for the default FP64-generated tables and FP64 phase formation.  */
+                      /* Precision study only: bit 0 generates the tilt-ramp, twist and   */
+                      /* pyramid tables in FP32, bit 1 forms and reduces the phase in     */
+                      /* FP32; other bits must be 0.                                       */
   double diameter_m;      /* D (informational: the sensor works in pixels)                */
   double wavelength_m;    /* lambda                                                       */
   double mod_radius_lod;  /* r_mod in lambda / D, >= 0                                    */

@@ -26,7 +26,7 @@ class PwfsError(RuntimeError):
 class config_struct(ctypes.Structure):
     _fields_ = [("n_fft", ctypes.c_int32), ("n_pupil", ctypes.c_int32), ("n_bin", ctypes.c_int32),
                 ("n_mod", ctypes.c_int32), ("face_shift", ctypes.c_int32), ("norm_mode", ctypes.c_int32),
-                ("batch_max", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("batch_max", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("diameter_m", ctypes.c_double), ("wavelength_m", ctypes.c_double),
                 ("mod_radius_lod", ctypes.c_double), ("obstruction", ctypes.c_double)]
 
@@ -89,24 +89,28 @@ def _need(t, torch, dtype, numel, name):
         raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor with {numel} elements")
 
 
-def make_config(cfg, batch_max: int) -> config_struct:
+FLAG_FP32_TABLES = 1
+FLAG_FP32_PHASE = 2
+
+
+def make_config(cfg, batch_max: int, flags: int = 0) -> config_struct:
     """Lower a sensor configuration record (attributes as in synth.configs.SensorConfig)."""
     return config_struct(n_fft=cfg.n_fft, n_pupil=cfg.n_pupil, n_bin=cfg.n_bin, n_mod=cfg.n_mod,
                          face_shift=cfg.face_shift, norm_mode=cfg.norm_mode, batch_max=batch_max,
-                         reserved=0, diameter_m=cfg.diameter_m, wavelength_m=cfg.wavelength_m,
+                         flags=flags, diameter_m=cfg.diameter_m, wavelength_m=cfg.wavelength_m,
                          mod_radius_lod=cfg.mod_radius_lod, obstruction=cfg.obstruction)
 
 
 class Plan:
     """pwfs_plan / pwfs_measure / pwfs_destroy for one sensor geometry."""
 
-    def __init__(self, cfg, batch_max: int = 16, pupil_amp: np.ndarray | None = None):
+    def __init__(self, cfg, batch_max: int = 16, pupil_amp: np.ndarray | None = None, flags: int = 0):
         import torch
         self._torch = torch
         self.lib = load_library()
         self.cfg = cfg
         self.device = torch.cuda.current_device()
-        c = make_config(cfg, batch_max)
+        c = make_config(cfg, batch_max, flags)
         amp = None
         if pupil_amp is not None:
             amp = np.ascontiguousarray(pupil_amp, dtype=np.float32)

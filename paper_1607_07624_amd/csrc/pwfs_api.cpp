@@ -122,7 +122,7 @@ void split_work(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk, int* n_
 
 int validate(const pwfs_config_t* c) {
   if (!c) return fail(PWFS_ERR_INVALID_ARG, "cfg is NULL");
-  if (c->reserved != 0) return fail(PWFS_ERR_INVALID_ARG, "reserved field must be 0");
+  if (c->flags & ~3) return fail(PWFS_ERR_INVALID_ARG, "unknown flag bits");
   if (c->n_pupil <= 0 || c->n_fft <= 0 || c->n_bin <= 0 || c->n_mod <= 0 || c->batch_max <= 0)
     return fail(PWFS_ERR_INVALID_ARG, "sizes must be positive");
   if (c->n_pupil % c->n_bin != 0) return fail(PWFS_ERR_INVALID_ARG, "n_pupil must be a multiple of n_bin");
@@ -171,6 +171,7 @@ int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* s
     a.B = Bs;
     split_work(p, Bs, &a.a_chunk, &a.k_chunk, &a.n_chunks);
     a.kphase = p->kphase;
+    a.fp32_phase = (p->cfg.flags & 2) != 0;
     a.opd = opd + (size_t)b0 * p->P * p->P;
     a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : p->pupils;
     a.slopes = slopes ? slopes + (size_t)b0 * 2 * p->nv : nullptr;
@@ -308,14 +309,23 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   // Tilt ramps r(x) = exp(i 2 pi t (x - xc) / N) (FP64), alone and times the
   // twist w_N^{(2q+1) x} of the two quads.
   const double xc = 0.5 * (P - 1);
+  const bool t32 = (cfg->flags & 1) != 0;   // precision study: FP32-generated tables
   std::vector<std::complex<double>> tw(2 * (size_t)P);
   for (int q = 0; q < 2; ++q)
     for (int x = 0; x < P; ++x) {
       const long n = ((long)(2 * q + 1) * x) % N;
       const double ang = -2.0 * M_PI * (double)n / (double)N;
-      tw[(size_t)q * P + x] = {std::cos(ang), std::sin(ang)};
+      const float angf = -2.0f * (float)M_PI * (float)n / (float)N;
+      tw[(size_t)q * P + x] = t32 ? std::complex<double>(std::cos(angf), std::sin(angf))
+                                  : std::complex<double>(std::cos(ang), std::sin(ang));
     }
   auto ramp = [&](double tilt, int x) {
+    if (t32) {
+      const float turns = (float)tilt * ((float)x - (float)xc) / (float)N;
+      const float f = turns - std::floor(turns);
+      const float ang = 2.0f * (float)M_PI * f;
+      return std::complex<double>(std::cos(ang), std::sin(ang));
+    }
     const double turns = tilt * ((double)x - xc) / (double)N;
     const double f = turns - std::floor(turns);
     return std::complex<double>(std::cos(2.0 * M_PI * f), std::sin(2.0 * M_PI * f));
@@ -347,12 +357,17 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   for (int q = 0; q < 2; ++q)
     for (int x = 0; x < P; ++x) {
       const long n = ((long)(2 * q + 1) * x) % N;
-      const double ang = 2.0 * M_PI * (double)n / (double)N;
+      const double ang = t32 ? (double)(2.0f * (float)M_PI * (float)n / (float)N) : 2.0 * M_PI * (double)n / (double)N;
       const double sc = 4.0 / (double)N;
-      outw[(size_t)q * P + x] = {(float)(sc * std::cos(ang)), (float)(sc * std::sin(ang))};
+      outw[(size_t)q * P + x] = t32 ? cpx{(float)sc * std::cos((float)ang), (float)sc * std::sin((float)ang)}
+                                    : cpx{(float)(sc * std::cos(ang)), (float)(sc * std::sin(ang))};
     }
   auto wlk = [&](int l, int k) {
     const long n = ((long)l * k) % P;
+    if (t32) {
+      const float angf = -2.0f * (float)M_PI * (float)n / (float)P;
+      return std::complex<double>(std::cos(angf), std::sin(angf));
+    }
     const double ang = -2.0 * M_PI * (double)n / (double)P;
     return std::complex<double>(std::cos(ang), std::sin(ang));
   };

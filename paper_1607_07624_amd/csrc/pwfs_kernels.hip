@@ -135,15 +135,23 @@ __device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __res
 // ---------------------------------------------------------------------------
 // Pupil field A exp(i phi), phi = 2 pi opd 1e-9 / lambda formed and reduced
 // modulo 2 pi in FP64, then FP32 sincos; once per frame.
+// (fp32_phase, precision study only: phase formed in FP32 and passed to
+// sincosf unreduced.)
 __global__ __launch_bounds__(256) void field_kernel(const float* __restrict__ opd, const float* __restrict__ amp,
-                                                    double kphase, int PP, size_t n, cpx* __restrict__ field) {
+                                                    double kphase, int fp32_phase, int PP, size_t n,
+                                                    cpx* __restrict__ field) {
   constexpr double two_pi = 6.283185307179586476925286766559;
   constexpr double inv_two_pi = 0.15915494309189533576888376337251;
+  const float kphase_f = (float)kphase;
   for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const double th = (double)opd[i] * kphase;
-    const double red = fma(-rint(th * inv_two_pi), two_pi, th);
     float sn, cs;
-    sincosf((float)red, &sn, &cs);
+    if (fp32_phase) {
+      sincosf(opd[i] * kphase_f, &sn, &cs);
+    } else {
+      const double th = (double)opd[i] * kphase;
+      const double red = fma(-rint(th * inv_two_pi), two_pi, th);
+      sincosf((float)red, &sn, &cs);
+    }
     const float A = amp[i % PP];
     field[i] = {A * cs, A * sn};
   }
@@ -501,7 +509,8 @@ template <int E>
 static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
   const size_t n = (size_t)a.B * a.P * a.P;
   const unsigned fb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(field_kernel, dim3(fb), dim3(256), 0, st, a.opd, a.amp, a.kphase, a.P * a.P, n, a.field);
+  hipLaunchKernelGGL(field_kernel, dim3(fb), dim3(256), 0, st, a.opd, a.amp, a.kphase, a.fp32_phase, a.P * a.P, n,
+                     a.field);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   dim3 grid(a.P / 32, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);

@@ -15,6 +15,7 @@ struct MeasureArgs {
   // batch slice and work split
   int B, a_chunk, k_chunk, n_chunks;
   double kphase;  // 2 pi 1e-9 / lambda
+  int fp32_phase; // precision study: form and reduce the phase in FP32
   // inputs / outputs
   const float* opd;
   float* pupils;       // [B][4][S][S]: the caller's buffer or the plan's scratch

@@ -53,7 +53,7 @@ def _plan_status(**over):
 @pytest.mark.parametrize("over,status", [
     (dict(n_pupil=0), -1), (dict(n_bin=3), -1), (dict(batch_max=0), -1),
     (dict(wavelength_m=0.0), -1), (dict(mod_radius_lod=-1.0), -1), (dict(obstruction=1.0), -1),
-    (dict(norm_mode=2), -1), (dict(reserved=1), -1), (dict(face_shift=-3), -1),
+    (dict(norm_mode=2), -1), (dict(flags=4), -1), (dict(face_shift=-3), -1),
     (dict(n_fft=600), -2), (dict(face_shift=100), -2), (dict(n_pupil=96, n_fft=384), -2),
     (dict(n_bin=5), -2), (dict(n_mod=2000), -2),
 ])
