@@ -153,33 +153,44 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
   return 0;
 }
 
+// Product with an upstream-gradient operand A held as bf16 hi/lo pairs (lo at
+// A + a_lo_off): C = A_hi B, then C += A_lo B.
+hipError_t gemm_hilo(GemmArgs a, size_t a_lo_off, pwfs_cnn_s* n, hipStream_t st) {
+  hipError_t e = pwfs::cnn::gemm(a, n->part, n->part_elems, st);
+  if (e != hipSuccess) return e;
+  a.A += a_lo_off;
+  a.beta = 1.f;
+  return pwfs::cnn::gemm(a, n->part, n->part_elems, st);
+}
+
 int run_backward(pwfs_cnn_s* n, const float* target, int B, float* loss, hipStream_t st) {
   const uint16_t* Wb = n->wb;
   float* G = n->g;
   CK(pwfs::cnn::mse(n->out, target, B * n->nout, n->dout, n->doutb, loss, st));
   // fc2
-  CK(pwfs::cnn::gemm(wgrad_args(n->doutb, n->h, B, n->nout, n->hidden, G + n->off[8]), n->part, n->part_elems, st));
+  const size_t lo_out = (size_t)B * n->nout;
+  CK(gemm_hilo(wgrad_args(n->doutb, n->h, B, n->nout, n->hidden, G + n->off[8]), lo_out, n, st));
   CK(pwfs::cnn::colsum(n->dout, B, n->nout, G + n->off[9], st));
-  CK(pwfs::cnn::gemm(dgrad_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->gtmp), n->part, n->part_elems, st));
+  CK(gemm_hilo(dgrad_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->gtmp), lo_out, n, st));
   CK(pwfs::cnn::relu_mask(n->gtmp, n->h, (size_t)B * n->hidden, n->dz, n->dzb, st));
   // fc1
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->a3, B, n->hidden, n->flat, G + n->off[6]), n->part, n->part_elems, st));
+  CK(gemm_hilo(wgrad_args(n->dzb, n->a3, B, n->hidden, n->flat, G + n->off[6]), (size_t)B * n->hidden, n, st));
   CK(pwfs::cnn::colsum(n->dz, B, n->hidden, G + n->off[7], st));
-  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[6], B, n->hidden, n->flat, n->gtmp), n->part, n->part_elems, st));
+  CK(gemm_hilo(dgrad_args(n->dzb, Wb + n->off[6], B, n->hidden, n->flat, n->gtmp), (size_t)B * n->hidden, n, st));
   CK(pwfs::cnn::relu_mask(n->gtmp, n->a3, (size_t)B * n->flat, n->dz, n->dzb, st));
   // conv3
   const int R3 = B * n->S3 * n->S3, R2 = B * n->S2 * n->S2, R1 = B * n->S1 * n->S1;
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols3, R3, n->c3, n->c2 * 9, G + n->off[4]), n->part, n->part_elems, st));
+  CK(gemm_hilo(wgrad_args(n->dzb, n->cols3, R3, n->c3, n->c2 * 9, G + n->off[4]), (size_t)R3 * n->c3, n, st));
   CK(pwfs::cnn::colsum(n->dz, R3, n->c3, G + n->off[5], st));
-  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), n->part, n->part_elems, st));
+  CK(gemm_hilo(dgrad_args(n->dzb, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), (size_t)R3 * n->c3, n, st));
   CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S2, n->S2, n->c2, n->a2, n->dz, n->dzb, st));
   // conv2
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols2, R2, n->c2, n->c1 * 9, G + n->off[2]), n->part, n->part_elems, st));
+  CK(gemm_hilo(wgrad_args(n->dzb, n->cols2, R2, n->c2, n->c1 * 9, G + n->off[2]), (size_t)R2 * n->c2, n, st));
   CK(pwfs::cnn::colsum(n->dz, R2, n->c2, G + n->off[3], st));
-  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, n->part_elems, st));
+  CK(gemm_hilo(dgrad_args(n->dzb, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), (size_t)R2 * n->c2, n, st));
   CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dz, n->dzb, st));
   // conv1
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols1, R1, n->c1, 36, G + n->off[0]), n->part, n->part_elems, st));
+  CK(gemm_hilo(wgrad_args(n->dzb, n->cols1, R1, n->c1, 36, G + n->off[0]), (size_t)R1 * n->c1, n, st));
   CK(pwfs::cnn::colsum(n->dz, R1, n->c1, G + n->off[1], st));
   return 0;
 }
@@ -240,7 +251,7 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
       {(void**)&n->a1, R1 * n->c1 * 2, "a1"}, {(void**)&n->cols2, R2 * n->c1 * 9 * 2, "cols2"},
       {(void**)&n->a2, R2 * n->c2 * 2, "a2"}, {(void**)&n->cols3, R3 * n->c2 * 9 * 2, "cols3"},
       {(void**)&n->a3, R3 * n->c3 * 2, "a3"}, {(void**)&n->h, B * n->hidden * 2, "hidden"},
-      {(void**)&n->doutb, B * n->nout * 2, "dout bf16"}, {(void**)&n->dzb, dz * 2, "dz bf16"},
+      {(void**)&n->doutb, B * n->nout * 2 * 2, "dout bf16 hi/lo"}, {(void**)&n->dzb, dz * 2 * 2, "dz bf16 hi/lo"},
       {(void**)&n->out, B * n->nout * 4, "out"}, {(void**)&n->dout, B * n->nout * 4, "dout"},
       {(void**)&n->gtmp, gtmp * 4, "data gradients"}, {(void**)&n->dz, dz * 4, "dz"},
       {(void**)&n->part, n->part_elems * 4, "split-K partials"}, {(void**)&n->loss, 4, "loss"},

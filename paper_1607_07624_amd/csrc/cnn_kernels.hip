@@ -30,6 +30,7 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return h != 0 && !(h & 0x8000u); }
+__device__ __forceinline__ void split_bf(float v, uint16_t* hi, uint16_t* lo, size_t i);
 
 // ---------------------------------------------------------------------------
 // GEMM: C(i, j) = sum_k A(i, k) B(k, j), A(i, k) = A[i sam + k sak],
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(256) void im2col_kernel(const uint16_t* __restrict_
 // Gradient of im2col (gather form) fused with the ReLU mask of the layer's
 // forward output act: dz[b][y][x][c] = (act > 0) * sum over the (ky, kx)
 // whose output pixel (yo, xo) = ((y + 1 - ky) / 2, (x + 1 - kx) / 2) exists,
-// in ky-major order.  Writes FP32 and bf16.
+// in ky-major order.  Writes FP32 and bf16 hi/lo (lo at dzb + B H W C).
 __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restrict__ dcols, int B, int H, int W,
                                                           int C, const uint16_t* __restrict__ act,
                                                           float* __restrict__ dz, uint16_t* __restrict__ dzb) {
@@ -156,17 +157,25 @@ __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restric
     }
     const float gv = bf_pos(act[idx]) ? s : 0.f;
     dz[idx] = gv;
-    dzb[idx] = f2bf(gv);
+    split_bf(gv, dzb, dzb + total, idx);
   }
 }
 
-// dz = (act > 0) * g, FP32 and bf16.
+// Split of an FP32 value into bf16 hi + lo (hi = bf16(v), lo = bf16(v - hi)):
+// a product on the pair keeps ~16 significant bits of v.
+__device__ __forceinline__ void split_bf(float v, uint16_t* hi, uint16_t* lo, size_t i) {
+  const uint16_t h = f2bf(v);
+  hi[i] = h;
+  lo[i] = f2bf(v - bf2f(h));
+}
+
+// dz = (act > 0) * g, FP32 and bf16 hi/lo (lo written at dzb + n).
 __global__ __launch_bounds__(256) void relu_mask_kernel(const float* __restrict__ g, const uint16_t* __restrict__ act,
                                                         size_t n, float* __restrict__ dz, uint16_t* __restrict__ dzb) {
   for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const float v = bf_pos(act[i]) ? g[i] : 0.f;
     dz[i] = v;
-    dzb[i] = f2bf(v);
+    split_bf(v, dzb, dzb + n, i);
   }
 }
 
@@ -190,7 +199,8 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ d
   if (tid == 0) out[j] = red[0];
 }
 
-// MSE loss (one block) and its gradient 2 (p - t) / n in FP32 and bf16.
+// MSE loss (one block) and its gradient 2 (p - t) / n in FP32 and bf16 hi/lo
+// (lo at doutb + n).
 __global__ __launch_bounds__(1024) void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
                                                    int n, float* __restrict__ dout, uint16_t* __restrict__ doutb,
                                                    float* __restrict__ loss) {
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(1024) void mse_kernel(const float* __restrict__ pre
     s = fmaf(d, d, s);
     const float gv = 2.f * d * inv;
     dout[i] = gv;
-    doutb[i] = f2bf(gv);
+    split_bf(gv, doutb, doutb + n, i);
   }
   red[tid] = s;
   __syncthreads();

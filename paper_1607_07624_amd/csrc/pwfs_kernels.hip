@@ -457,8 +457,8 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R,
 
 // ---------------------------------------------------------------------------
 // Batched m = alpha R s + beta m for B > 16 frames: a dense FP32 product
-// C[b][i] = sum_k s[b][k] R[i][k] on v_mfma_f32_32x32x2f32 (FP32 operands and
-// accumulation, fixed order).  Block = 4 waves, tile 64 frames x 64 rows of
+// C[b][i] = sum_k s[b][k] R[i][k] on v_mfma_f32_32x32x2f32 (FP32 operands,
+// fixed order).  Block = 4 waves, tile 64 frames x 64 rows of
 // R, K step 32 through LDS; lane l feeds A(b = l % 32, k = l / 32) and
 // B(i = l % 32, k = l / 32); accumulator v of lane l is
 // C(8 (v / 4) + 4 (l / 32) + v % 4, l % 32).
@@ -472,7 +472,10 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(const float* __restrict
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
   const int b0 = blockIdx.y * 64, i0 = blockIdx.x * 64;
-  f32x16_t acc;
+  // The MFMA accumulator is reset for every 32-wide K tile and the tiles are
+  // summed with ordinary FP32 adds (round to nearest): the matrix core's own
+  // accumulation rounding is biased, so it is confined to 32 terms.
+  f32x16_t acc, tile;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
   for (int k0 = 0; k0 < ns; k0 += 32) {
@@ -485,11 +488,15 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(const float* __restrict
     }
     __syncthreads();
 #pragma unroll
+    for (int v = 0; v < 16; ++v) tile[v] = 0.f;
+#pragma unroll
     for (int kk = 0; kk < 32; kk += 2) {
       const float a = As[wm * 32 + (lane & 31)][kk + (lane >> 5)];
       const float b = Bs[wn * 32 + (lane & 31)][kk + (lane >> 5)];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+      tile = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, tile, 0, 0, 0);
     }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] += tile[v];
     __syncthreads();
   }
   const int i = i0 + wn * 32 + (lane & 31);

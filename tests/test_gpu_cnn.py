@@ -1,11 +1,16 @@
 """CNN reconstructor kernels (through the C ABI) against the FP64 oracle.
 
-Both sides use the same bf16-rounded weights and inputs; the GPU rounds
-every GEMM operand (activations, upstream gradients) to bf16 and
-accumulates in FP32, the oracle computes in FP64.  Gate (per tensor,
-relative L2): forward outputs and parameter gradients <= 2e-2 -- a few
-bf16 roundings (2^-9 relative each) compounded over five layers.  Adam and
-input preparation are FP32 elementwise: 1e-5.
+Both sides use the same bf16-rounded weights and inputs.  The GPU stores
+hidden activations in bf16 (the operands of the next products), carries
+upstream gradients as bf16 hi/lo pairs (~16 bits) and accumulates in FP32.
+Two gates per tensor (relative L2):
+  * against the exact FP64 oracle: <= 2e-2.  Each stored activation is
+    rounded by up to 2^-9; the first-layer weight gradient sums many terms
+    of both signs, which amplifies that relative error by ~10x;
+  * against the oracle with the same bf16 activation rounding
+    (act_round=bf16_round): <= 2e-3 -- what remains is FP32 accumulation,
+    the hi/lo gradient split and rare rounding-boundary flips.
+Adam and input preparation are FP32 elementwise: 1e-5.
 """
 import numpy as np
 import pytest
@@ -59,9 +64,11 @@ def test_forward_matches_oracle(cfg, B):
     net, torch, p, po, x, xb, tgt = _setup(cfg, B, 3)
     out = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     ref, _ = ocnn.forward(po, xb.astype(np.float64))
-    e = rel_l2(out, ref)
-    say(f"[gpu] cnn forward {cfg['n_sub']}x{cfg['n_out']} B={B}: rel err {e:.3e}")
+    refq, _ = ocnn.forward(po, xb.astype(np.float64), act_round=ocnn.bf16_round)
+    e, eq = rel_l2(out, ref), rel_l2(out, refq)
+    say(f"[gpu] cnn forward {cfg['n_sub']}x{cfg['n_out']} B={B}: rel err {e:.3e} (exact), {eq:.3e} (bf16 act)")
     assert e <= 2e-2
+    assert eq <= 2e-3
 
 
 @pytest.mark.parametrize("cfg,B", [(SMALL, 5), (FULL, 16)], ids=["small", "full"])
@@ -70,13 +77,18 @@ def test_gradients_match_oracle(cfg, B):
     g, loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda())
     g = g.cpu().numpy()
     lo, go, _ = ocnn.loss_and_grads(po, xb.astype(np.float64), tgt.astype(np.float64))
+    lq, gq, _ = ocnn.loss_and_grads(po, xb.astype(np.float64), tgt.astype(np.float64),
+                                    act_round=ocnn.bf16_round)
     assert abs(float(loss.cpu()) - lo) <= 2e-2 * lo
+    assert abs(float(loss.cpu()) - lq) <= 2e-3 * lq
     off = 0
     for k in ocnn.PARAM_ORDER:
         n = int(np.prod(net.shapes[k]))
         e = rel_l2(g[off:off + n], go[k].ravel())
-        say(f"[gpu] cnn grad {k}: rel err {e:.3e}")
+        eq = rel_l2(g[off:off + n], gq[k].ravel())
+        say(f"[gpu] cnn grad {k}: rel err {e:.3e} (exact FP64), {eq:.3e} (bf16 activations)")
         assert e <= 2e-2, k
+        assert eq <= 2e-3, k
         off += n
     g2, _ = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda())
     assert np.array_equal(g, g2.cpu().numpy())          # deterministic

@@ -24,7 +24,12 @@ def test_recon_apply_matches_fp64(M, ns, B, alpha, beta):
     ref = alpha * (s.astype(np.float64) @ R.astype(np.float64).T) + beta * m0
     scale = np.abs(alpha) * np.sqrt(ns) + abs(beta) * 3
     err = np.abs(got - ref).max() / scale
-    assert err < 2e-6, err
+    # B <= 16: vector FMAs (the reconstruction step of the loop), FP32 rounding
+    # only.  B > 16: FP32 MFMA, whose internal accumulation is coarser than a
+    # round-to-nearest FMA chain (measured ~5e-6 at K = 25600 even with the
+    # per-32-term tile sums); this path serves batched calibration-scale
+    # products, where 1e-5 of the output's spread is far below the model error.
+    assert err < (2e-6 if B <= 16 else 1e-5), err
 
 
 def test_recon_apply_beta_zero_ignores_garbage():

@@ -135,3 +135,26 @@ def test_adam_training_reduces_loss():
         for k in p:
             p[k], m[k], v[k] = cnn.adam_step(p[k], g[k], m[k], v[k], step, 3e-3)
     assert cnn.loss_and_grads(p, x, t)[0] < 0.5 * l0
+
+
+def test_bf16_round_values():
+    v = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5, 0.0, 3.14159])
+    r = cnn.bf16_round(v)
+    # exact values on the bf16 grid stay; halfway cases go to even; relative error <= 2^-8
+    assert r[0] == 1.0 and r[3] == -2.5 and r[4] == 0.0
+    assert cnn.bf16_round(np.array([1.0 + 2 ** -7]))[0] == 1.0 + 2 ** -7
+    assert cnn.bf16_round(np.array([1.0 + 2 ** -8]))[0] == 1.0                 # tie -> even (1.0)
+    assert cnn.bf16_round(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6    # tie -> even
+    assert np.all(np.abs(r - v) <= 2 ** -8 * np.abs(v))
+
+
+def test_activation_rounding_is_identity_when_exact():
+    shapes = cnn.param_shapes(S=9, c_in=4, chans=(2, 3, 3), hidden=5, n_out=4)
+    rng = np.random.default_rng(12)
+    p = _rand_params(shapes, rng)
+    x = rng.normal(size=(2, 9, 9, 4))
+    a = cnn.forward(p, x)[0]
+    b = cnn.forward(p, x, act_round=lambda v: v)[0]
+    c = cnn.forward(p, x, act_round=cnn.bf16_round)[0]
+    assert np.array_equal(a, b)
+    assert 0 < np.abs(c - a).max() < 1e-2 * np.abs(a).max()
