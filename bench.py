@@ -262,11 +262,19 @@ def main():
     if not args.no_cnn:
         from synth.screens import CropBank
         from synth.configs import AtmoConfig
-        from paper_1607_07624_amd.learned import train_reconstructor, open_loop_errors
+        from paper_1607_07624_amd.learned import train_reconstructor, open_loop_errors, ResidualBank
         log("learned reconstructor: data + training")
+        T = args.loop_steps
         bank = CropBank(cfg, ATMO2.L0_m, n_screens=4, screen_n=4096, seed=4242)
+        t_res = time.time()
+        resid = ResidualBank.from_loops(plan1, modes_dev, R, cfg, ATMO2.L0_m, ATMO2.wind_m_s, ATMO2.frame_rate_hz,
+                                        n_loops=12, steps=1500, settle=LOOP_SETTLE_STEPS, seed=77,
+                                        r0_range=(0.06, 0.2), gain=LOOP_GAIN, delay=LOOP_DELAY, stride=2)
+        log(f"residual bank {tuple(resid.frames.shape)} in {time.time() - t_res:.1f}s")
         net, info = train_reconstructor(plan, modes.astype(np.float32), amp, bank, args.cnn_frames, seed=5,
-                                        epochs=args.cnn_epochs, log=log)
+                                        epochs=args.cnn_epochs, residuals=resid, log=log)
+        info["residual_bank_frames"] = int(resid.frames.shape[0])
+        del resid
         log(f"training {info}")
         ev_strong = open_loop_errors(plan, net, R, modes.astype(np.float32), amp, bank, 2048, seed=990,
                                      r0_range=(0.06, 0.1))

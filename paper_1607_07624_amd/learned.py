@@ -32,10 +32,56 @@ def projector(modes: np.ndarray, pupil: np.ndarray, device="cuda"):
     return torch.from_numpy((modes.reshape(M, -1) / n_pix).astype(np.float32)).to(device).contiguous()
 
 
+class ResidualBank:
+    """Residual screens of linear closed loops (frozen flow, random r0),
+    the 'partially corrected phase' half of the training set.  Frames are
+    drawn with one of the 8 square symmetries (a symmetry of a screen is a
+    screen; its label is recomputed from the transformed screen)."""
+
+    def __init__(self, frames_dev):
+        self.frames = frames_dev            # [F, P, P] float32, device
+
+    @staticmethod
+    def from_loops(plan1, modes_dev, R_dev, cfg, L0_m, wind_m_s, rate_hz, n_loops, steps, settle, seed,
+                   r0_range, gain, delay, stride=1):
+        import torch
+        from synth.configs import AtmoConfig
+        from synth.screens import frozen_flow_sequence
+        from .loop import ClosedLoop
+        rng = np.random.default_rng(seed)
+        P = cfg.n_pupil
+        out = []
+        for i in range(n_loops):
+            r0 = float(rng.uniform(*r0_range))
+            atm = AtmoConfig(r0_m=r0, L0_m=L0_m, wind_m_s=wind_m_s, frame_rate_hz=rate_hz)
+            seq = torch.from_numpy(frozen_flow_sequence(cfg, atm, steps, seed=int(rng.integers(1 << 30)),
+                                                        screen_n=2048)).to(modes_dev.device)
+            res, _ = ClosedLoop(plan1, modes_dev, R_dev, gain, delay).run(seq)
+            out.append(res[settle::stride].reshape(-1, P, P).clone())
+        return ResidualBank(torch.cat(out))
+
+    def draw(self, rng: np.random.Generator, n: int):
+        import torch
+        idx = torch.from_numpy(rng.integers(0, self.frames.shape[0], size=n)).to(self.frames.device)
+        x = self.frames.index_select(0, idx)
+        sym = int(rng.integers(8))
+        if sym & 1:
+            x = x.flip(1)
+        if sym & 2:
+            x = x.flip(2)
+        if sym & 4:
+            x = x.transpose(1, 2)
+        return x.contiguous()
+
+
 def make_training_set(plan, bank, modes: np.ndarray, pupil: np.ndarray, n_frames: int, seed: int,
                       r0_range=(0.06, 0.2), corrected_fraction=0.5, batch=256, label_scale=None,
-                      device="cuda") -> TrainingSet:
-    """Generate n_frames (input, label) pairs on the GPU."""
+                      residuals: "ResidualBank | None" = None, device="cuda") -> TrainingSet:
+    """Generate n_frames (input, label) pairs on the GPU.  A fraction
+    corrected_fraction of each batch is partially corrected: residual
+    screens of linear closed loops when a ResidualBank is given, otherwise
+    open-loop screens with a random fraction of their first KL modes
+    removed through the DM path."""
     import torch
     rng = np.random.default_rng(seed)
     P, S, M = plan.cfg.n_pupil, plan.n_sub, modes.shape[0]
@@ -55,7 +101,9 @@ def make_training_set(plan, bank, modes: np.ndarray, pupil: np.ndarray, n_frames
         # Partial correction of a random subset of frames: remove alpha * c_i B_i for
         # i < n_corr (coefficients scaled on the host, DM path through recon_apply).
         n_cor = int(round(corrected_fraction * n))
-        if n_cor:
+        if n_cor and residuals is not None:
+            opd[:n_cor] = residuals.draw(rng, n_cor).reshape(n_cor, P * P)
+        elif n_cor:
             c = recon_apply(proj, opd[:n_cor]).cpu().numpy()                 # [n_cor, M]
             for j in range(n_cor):
                 c[j, rng.integers(20, M + 1):] = 0.0
@@ -97,15 +145,25 @@ def train(net: CNN, data: TrainingSet, epochs: int, batch: int, lr: float, seed:
 
 
 def fold_label_scale(net: CNN, scale: float):
-    """Multiply the last layer by the label scale so outputs are in nm."""
+    """Multiply the last layer by the label scale so outputs are in nm, and
+    remove the network's output for a flat wavefront (zero input) from the
+    last bias, so that a perfectly corrected frame gives exactly zero and
+    an integrator fed by the network has no constant drift."""
     import torch
     p = net.get_params().cpu().numpy()
     off = 0
+    offs = {}
     for k in PARAM_ORDER:
         n = int(np.prod(net.shapes[k]))
+        offs[k] = (off, n)
         if k in ("fw2", "fb2"):
             p[off:off + n] *= scale
         off += n
+    net.set_params(torch.from_numpy(p))
+    zero = torch.zeros((1, net.n_sub, net.n_sub, 4), device="cuda")
+    b0 = net.forward(zero).cpu().numpy()[0].astype(np.float64)
+    o, n = offs["fb2"]
+    p[o:o + n] = (p[o:o + n].astype(np.float64) - b0).astype(np.float32)
     net.set_params(torch.from_numpy(p))
 
 
@@ -122,12 +180,13 @@ def load_checkpoint(path: str, net: CNN) -> dict:
 
 def train_reconstructor(plan, modes: np.ndarray, pupil: np.ndarray, bank, n_frames: int, seed: int,
                         epochs: int = 4, batch: int = 256, lr: float = 1e-3, r0_range=(0.06, 0.2),
-                        log=None, device="cuda"):
+                        residuals=None, log=None, device="cuda"):
     """Generate the training set, train a CNN from a seeded He initialisation,
-    fold the label scale; returns (net, info)."""
+    fold the label scale and the zero-input offset; returns (net, info)."""
     import time
     t0 = time.time()
-    data = make_training_set(plan, bank, modes, pupil, n_frames, seed, r0_range=r0_range, device=device)
+    data = make_training_set(plan, bank, modes, pupil, n_frames, seed, r0_range=r0_range,
+                             residuals=residuals, device=device)
     t_data = time.time() - t0
     net = CNN(n_sub=plan.n_sub, n_out=modes.shape[0], batch_max=batch)
     import torch

@@ -66,9 +66,10 @@ class ClosedLoop:
     With a learned reconstructor (net) the integrator input is the
     network's modal estimate from the pupil images; the linear
     reconstructor R judges it every `judge_every` steps and takes over for
-    the rest of the run if the network output is not finite or the linear
-    estimate of the modal residual, ||R s||, exceeds `judge_growth` times
-    its median over the steps judged so far (a diverging loop)."""
+    the rest of the run (integrator restarted from zero) if the network
+    output is not finite, or the linear estimate of the modal residual,
+    ||R s||, exceeds `judge_growth` times the smallest value judged so far
+    or twice the first (open-loop) value: a diverging loop."""
 
     def __init__(self, plan, modes_dev, R_dev, gain: float, delay: int, net=None,
                  judge_every: int = 20, judge_growth: float = 4.0):
@@ -120,10 +121,11 @@ class ClosedLoop:
                     e = float(np.linalg.norm(self.m_lin.cpu().numpy()))
                     ok = bool(np.isfinite(c_next.cpu().numpy()).all())
                     judged.append(e)
-                    if not ok or (len(judged) > 5 and e > self.judge_growth * float(np.median(judged))):
+                    diverging = len(judged) >= 3 and (e > self.judge_growth * min(judged) or e > 2.0 * judged[0])
+                    if not ok or diverging:
                         learned = False
                         self.fallback_step = t
-                        c_next.copy_(hist[t + d - 1:t + d] if t > 0 else torch.zeros_like(c_next))
+                        hist[: t + d + 1].zero_()
                         recon_apply(self.R, self.s, self.gain, 1.0, c_next)
             else:
                 self.plan.measure_into(r_t.view(1, P, P), None, self.s)
