@@ -15,7 +15,8 @@
  * fw2 [n_out][hidden], fb2 (C order).  Products run on bf16 MFMA with FP32
  * accumulation (weights and activations rounded to bf16 as GEMM operands);
  * biases, loss, gradients, Adam moments and master weights are FP32.
- * Loss: mean over all outputs of (prediction - target)^2.
+ * Loss: mean over all outputs of w_b (prediction - target)^2, with an optional
+ * weight w_b per frame (1 when no weights are given).
  *
  * Memory and errors follow pwfs.h: "device" pointers are caller-owned
  * allocations on the device current at create time; calls are
@@ -75,15 +76,16 @@ int pwfs_cnn_forward_acc(pwfs_cnn_t net, const float* d_x, int32_t B, float alph
                          void* stream);
 
 /* Loss and parameter gradients (flat FP32, same order as the parameters)
- * for targets d_target [B][n_out]; d_loss (1 float) and d_grads may be NULL. */
-int pwfs_cnn_gradients(pwfs_cnn_t net, const float* d_x, const float* d_target, int32_t B,
-                       float* d_grads, float* d_loss, void* stream);
+ * for targets d_target [B][n_out] and per-frame weights d_weights [B] (NULL:
+ * all 1); d_loss (1 float) and d_grads may be NULL. */
+int pwfs_cnn_gradients(pwfs_cnn_t net, const float* d_x, const float* d_target, const float* d_weights,
+                       int32_t B, float* d_grads, float* d_loss, void* stream);
 
-/* One training step: forward, MSE loss, backward, Adam update of the FP32
+/* One training step (weights as in pwfs_cnn_gradients): forward, MSE loss, backward, Adam update of the FP32
  * master weights (step count incremented), bf16 weight copies refreshed.
  * d_loss (1 float, may be NULL) receives the loss before the update. */
-int pwfs_cnn_train_step(pwfs_cnn_t net, const float* d_x, const float* d_target, int32_t B,
-                        float lr, float beta1, float beta2, float eps, float* d_loss, void* stream);
+int pwfs_cnn_train_step(pwfs_cnn_t net, const float* d_x, const float* d_target, const float* d_weights,
+                        int32_t B, float lr, float beta1, float beta2, float eps, float* d_loss, void* stream);
 
 /* Release everything (synchronises the device). */
 void pwfs_cnn_destroy(pwfs_cnn_t net);

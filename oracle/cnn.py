@@ -17,7 +17,8 @@ integrator.  Architecture (fixed here, the paper has no learned part):
 Parameters: conv weights [Cout, Cin, 3, 3], biases [Cout]; fc weights
 [Nout, Nin], biases [Nout].  The flat parameter vector concatenates
 w1, b1, w2, b2, w3, b3, fw1, fb1, fw2, fb2 in that order, C-contiguous.
-Loss: mean over all outputs of (prediction - target)^2.
+Loss: mean over all outputs of w_b (prediction - target)^2 with an optional
+per-frame weight w_b (1 by default).
 Adam: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
 w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 """
@@ -111,10 +112,11 @@ def forward(p: dict, x: np.ndarray, act_round=None):
     return out, (x, a1, a2, a3, f, h)
 
 
-def mse(pred: np.ndarray, target: np.ndarray):
-    """(loss, d loss / d pred)."""
+def mse(pred: np.ndarray, target: np.ndarray, weights=None):
+    """(loss, d loss / d pred); weights [B] scale each frame's squared error."""
     d = pred - target
-    return float(np.mean(d * d)), 2.0 * d / d.size
+    w = np.ones(d.shape[0]) if weights is None else np.asarray(weights, np.float64)
+    return float(np.mean(w[:, None] * d * d)), 2.0 * w[:, None] * d / d.size
 
 
 def backward(p: dict, cache, dout: np.ndarray) -> dict:
@@ -135,9 +137,9 @@ def backward(p: dict, cache, dout: np.ndarray) -> dict:
     return g
 
 
-def loss_and_grads(p: dict, x: np.ndarray, target: np.ndarray, act_round=None):
+def loss_and_grads(p: dict, x: np.ndarray, target: np.ndarray, act_round=None, weights=None):
     pred, cache = forward(p, x, act_round)
-    loss, dout = mse(pred, target)
+    loss, dout = mse(pred, target, weights)
     return loss, backward(p, cache, dout), pred
 
 

@@ -27,8 +27,8 @@ def _lib():
         lib.pwfs_cnn_prepare.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp]
         lib.pwfs_cnn_forward.argtypes = [vp, vp, i32, vp, vp]
         lib.pwfs_cnn_forward_acc.argtypes = [vp, vp, i32, f32, f32, vp, vp]
-        lib.pwfs_cnn_gradients.argtypes = [vp, vp, vp, i32, vp, vp, vp]
-        lib.pwfs_cnn_train_step.argtypes = [vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
+        lib.pwfs_cnn_gradients.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+        lib.pwfs_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
         lib.pwfs_cnn_destroy.argtypes = [vp]
         lib.pwfs_cnn_destroy.restype = None
         for n in ("pwfs_cnn_create", "pwfs_cnn_num_params", "pwfs_cnn_set_params", "pwfs_cnn_get_params",
@@ -117,24 +117,28 @@ class CNN:
                                              self._s()), "pwfs_cnn_forward_acc")
         return out
 
-    def gradients(self, x, target):
+    def gradients(self, x, target, weights=None):
         t = self._torch
         B = x.shape[0]
         _need(x, t, t.float32, B * self.n_sub * self.n_sub * 4, "x")
         _need(target, t, t.float32, B * self.n_out, "target")
+        if weights is not None:
+            _need(weights, t, t.float32, B, "weights")
         g = t.empty(self.n_params, dtype=t.float32, device=x.device)
         loss = t.empty(1, dtype=t.float32, device=x.device)
-        _check(self.lib.pwfs_cnn_gradients(self.handle, _ptr(x), _ptr(target), B, _ptr(g), _ptr(loss), self._s()),
-               "pwfs_cnn_gradients")
+        _check(self.lib.pwfs_cnn_gradients(self.handle, _ptr(x), _ptr(target), _ptr(weights), B, _ptr(g),
+                                           _ptr(loss), self._s()), "pwfs_cnn_gradients")
         return g, loss
 
-    def train_step(self, x, target, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
+    def train_step(self, x, target, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss=None, weights=None):
         t = self._torch
         B = x.shape[0]
         _need(x, t, t.float32, B * self.n_sub * self.n_sub * 4, "x")
         _need(target, t, t.float32, B * self.n_out, "target")
-        _check(self.lib.pwfs_cnn_train_step(self.handle, _ptr(x), _ptr(target), B, lr, beta1, beta2, eps,
-                                            _ptr(loss), self._s()), "pwfs_cnn_train_step")
+        if weights is not None:
+            _need(weights, t, t.float32, B, "weights")
+        _check(self.lib.pwfs_cnn_train_step(self.handle, _ptr(x), _ptr(target), _ptr(weights), B, lr, beta1, beta2,
+                                            eps, _ptr(loss), self._s()), "pwfs_cnn_train_step")
         return loss
 
     def close(self):

@@ -163,10 +163,10 @@ hipError_t gemm_hilo(GemmArgs a, size_t a_lo_off, pwfs_cnn_s* n, hipStream_t st)
   return pwfs::cnn::gemm(a, n->part, n->part_elems, st);
 }
 
-int run_backward(pwfs_cnn_s* n, const float* target, int B, float* loss, hipStream_t st) {
+int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B, float* loss, hipStream_t st) {
   const uint16_t* Wb = n->wb;
   float* G = n->g;
-  CK(pwfs::cnn::mse(n->out, target, B * n->nout, n->dout, n->doutb, loss, st));
+  CK(pwfs::cnn::mse(n->out, target, weights, B * n->nout, n->nout, n->dout, n->doutb, loss, st));
   // fc2
   const size_t lo_out = (size_t)B * n->nout;
   CK(gemm_hilo(wgrad_args(n->doutb, n->h, B, n->nout, n->hidden, G + n->off[8]), lo_out, n, st));
@@ -331,8 +331,8 @@ int pwfs_cnn_forward_acc(pwfs_cnn_t n, const float* d_x, int32_t B, float alpha,
   return run_forward(n, d_x, B, (hipStream_t)stream, d_out, alpha, beta);
 }
 
-int pwfs_cnn_gradients(pwfs_cnn_t n, const float* d_x, const float* d_target, int32_t B, float* d_grads,
-                       float* d_loss, void* stream) {
+int pwfs_cnn_gradients(pwfs_cnn_t n, const float* d_x, const float* d_target, const float* d_weights, int32_t B,
+                       float* d_grads, float* d_loss, void* stream) {
   int s = check_batch(n, B);
   if (s) return s;
   if (B == 0) return 0;
@@ -340,13 +340,13 @@ int pwfs_cnn_gradients(pwfs_cnn_t n, const float* d_x, const float* d_target, in
   DevGuard g(n->device);
   hipStream_t st = (hipStream_t)stream;
   if ((s = run_forward(n, d_x, B, st))) return s;
-  if ((s = run_backward(n, d_target, B, d_loss ? d_loss : n->loss, st))) return s;
+  if ((s = run_backward(n, d_target, d_weights, B, d_loss ? d_loss : n->loss, st))) return s;
   if (d_grads) CK(hipMemcpyAsync(d_grads, n->g, n->n_params * 4, hipMemcpyDeviceToDevice, st));
   return 0;
 }
 
-int pwfs_cnn_train_step(pwfs_cnn_t n, const float* d_x, const float* d_target, int32_t B, float lr, float beta1,
-                        float beta2, float eps, float* d_loss, void* stream) {
+int pwfs_cnn_train_step(pwfs_cnn_t n, const float* d_x, const float* d_target, const float* d_weights, int32_t B,
+                        float lr, float beta1, float beta2, float eps, float* d_loss, void* stream) {
   int s = check_batch(n, B);
   if (s) return s;
   if (B == 0) return 0;
@@ -356,7 +356,7 @@ int pwfs_cnn_train_step(pwfs_cnn_t n, const float* d_x, const float* d_target, i
   DevGuard g(n->device);
   hipStream_t st = (hipStream_t)stream;
   if ((s = run_forward(n, d_x, B, st))) return s;
-  if ((s = run_backward(n, d_target, B, d_loss ? d_loss : n->loss, st))) return s;
+  if ((s = run_backward(n, d_target, d_weights, B, d_loss ? d_loss : n->loss, st))) return s;
   n->step += 1;
   const float c1 = (float)(1.0 - std::pow((double)beta1, (double)n->step));
   const float c2 = (float)(1.0 - std::pow((double)beta2, (double)n->step));

@@ -199,10 +199,12 @@ __global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ d
   if (tid == 0) out[j] = red[0];
 }
 
-// MSE loss (one block) and its gradient 2 (p - t) / n in FP32 and bf16 hi/lo
-// (lo at doutb + n).
+// Weighted MSE loss (one block): loss = sum_i w[i / n_out] (p_i - t_i)^2 / n,
+// gradient 2 w (p - t) / n in FP32 and bf16 hi/lo (lo at doutb + n); w = 1
+// when weights is NULL.
 __global__ __launch_bounds__(1024) void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
-                                                   int n, float* __restrict__ dout, uint16_t* __restrict__ doutb,
+                                                   const float* __restrict__ weights, int n, int n_out,
+                                                   float* __restrict__ dout, uint16_t* __restrict__ doutb,
                                                    float* __restrict__ loss) {
   __shared__ float red[1024];
   const int tid = threadIdx.x;
@@ -210,8 +212,9 @@ __global__ __launch_bounds__(1024) void mse_kernel(const float* __restrict__ pre
   float s = 0.f;
   for (int i = tid; i < n; i += 1024) {
     const float d = pred[i] - target[i];
-    s = fmaf(d, d, s);
-    const float gv = 2.f * d * inv;
+    const float w = weights ? weights[i / n_out] : 1.f;
+    s = fmaf(w * d, d, s);
+    const float gv = 2.f * w * d * inv;
     dout[i] = gv;
     split_bf(gv, doutb, doutb + n, i);
   }
@@ -332,9 +335,9 @@ hipError_t colsum(const float* dz, int rows, int N, float* out, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t mse(const float* pred, const float* target, int n, float* dout, uint16_t* doutb, float* loss,
-               hipStream_t st) {
-  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, st, pred, target, n, dout, doutb, loss);
+hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, float* dout,
+               uint16_t* doutb, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, st, pred, target, weights, n, n_out, dout, doutb, loss);
   return hipGetLastError();
 }
 

@@ -35,8 +35,8 @@ hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uin
 hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, float* dz, uint16_t* dzb, hipStream_t st);
 hipError_t to_bf16(const float* x, size_t n, uint16_t* y, hipStream_t st);
 hipError_t colsum(const float* dz, int rows, int N, float* out, hipStream_t st);
-hipError_t mse(const float* pred, const float* target, int n, float* dout, uint16_t* doutb, float* loss,
-               hipStream_t st);
+hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, float* dout,
+               uint16_t* doutb, float* loss, hipStream_t st);
 hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, size_t n, float lr, float b1, float b2,
                 float eps, float c1, float c2, hipStream_t st);
 hipError_t fill0(float* p, size_t n, hipStream_t st);

@@ -20,8 +20,20 @@ from .cnn import CNN, prepare, he_init, PARAM_ORDER
 
 
 class TrainingSet:
-    def __init__(self, x, y, label_scale):
-        self.x, self.y, self.label_scale = x, y, label_scale
+    def __init__(self, x, y, label_scale, w=None):
+        self.x, self.y, self.label_scale, self.w = x, y, label_scale, w
+
+    def set_relative_weights(self, floor_nm: float):
+        """Per-frame loss weights 1 / (rms(label)^2 + floor^2), normalised to
+        mean 1: each frame's error counts relative to its own size, so the
+        small residuals of a closed loop are learned as accurately as large
+        open-loop aberrations (computed on the host from the labels)."""
+        import torch
+        y = self.y.cpu().numpy().astype(np.float64)
+        f = floor_nm / self.label_scale
+        w = 1.0 / (np.mean(y * y, axis=1) + f * f)
+        w /= w.mean()
+        self.w = torch.from_numpy(w.astype(np.float32)).to(self.y.device)
 
 
 def projector(modes: np.ndarray, pupil: np.ndarray, device="cuda"):
@@ -134,7 +146,8 @@ def train(net: CNN, data: TrainingSet, epochs: int, batch: int, lr: float, seed:
             idx = perm[b0:b0 + batch]
             xb = data.x.index_select(0, idx).contiguous()
             yb = data.y.index_select(0, idx).contiguous()
-            net.train_step(xb, yb, lr, loss=loss)
+            wb = data.w.index_select(0, idx).contiguous() if data.w is not None else None
+            net.train_step(xb, yb, lr, loss=loss, weights=wb)
             if steps % 16 == 0:
                 acc += float(loss.cpu())
             steps += 1
@@ -180,13 +193,15 @@ def load_checkpoint(path: str, net: CNN) -> dict:
 
 def train_reconstructor(plan, modes: np.ndarray, pupil: np.ndarray, bank, n_frames: int, seed: int,
                         epochs: int = 4, batch: int = 256, lr: float = 1e-3, r0_range=(0.06, 0.2),
-                        residuals=None, log=None, device="cuda"):
+                        residuals=None, weight_floor_nm: float | None = 20.0, log=None, device="cuda"):
     """Generate the training set, train a CNN from a seeded He initialisation,
     fold the label scale and the zero-input offset; returns (net, info)."""
     import time
     t0 = time.time()
     data = make_training_set(plan, bank, modes, pupil, n_frames, seed, r0_range=r0_range,
                              residuals=residuals, device=device)
+    if weight_floor_nm is not None:
+        data.set_relative_weights(weight_floor_nm)
     t_data = time.time() - t0
     net = CNN(n_sub=plan.n_sub, n_out=modes.shape[0], batch_max=batch)
     import torch
@@ -199,6 +214,7 @@ def train_reconstructor(plan, modes: np.ndarray, pupil: np.ndarray, bank, n_fram
     t_train = time.time() - t1
     fold_label_scale(net, data.label_scale)
     info = {"frames": n_frames, "epochs": epochs, "batch": batch, "loss_history": hist,
+            "loss": "relative (per-frame weights, floor %s nm)" % weight_floor_nm if weight_floor_nm else "MSE",
             "label_scale_nm": data.label_scale, "data_s": round(t_data, 2), "train_s": round(t_train, 2),
             "train_frames_per_s": round(epochs * n_frames / max(t_train, 1e-9), 1)}
     del data

@@ -65,14 +65,17 @@ class ClosedLoop:
 
     With a learned reconstructor (net) the integrator input is the
     network's modal estimate from the pupil images; the linear
-    reconstructor R judges it every `judge_every` steps and takes over for
-    the rest of the run (integrator restarted from zero) if the network
-    output is not finite, or the linear estimate of the modal residual,
-    ||R s||, exceeds `judge_growth` times the smallest value judged so far
-    or twice the first (open-loop) value: a diverging loop."""
+    reconstructor R judges it every `judge_every` steps from its own
+    estimate of the modal residual, e = ||R s||, and takes over for the
+    rest of the run (integrator restarted from zero) if the network output
+    is not finite, if after `judge_settle` steps e has not fallen below
+    half its open-loop value e(0) (the loop did not close; with large
+    errors the sensor saturates, so e alone cannot show how far it
+    diverged), or if e exceeds `judge_growth` times its best value since
+    then (the loop is diverging)."""
 
     def __init__(self, plan, modes_dev, R_dev, gain: float, delay: int, net=None,
-                 judge_every: int = 20, judge_growth: float = 4.0):
+                 judge_every: int = 10, judge_growth: float = 4.0, judge_settle: int = 50):
         import torch
         self.plan, self.R, self.gain, self.delay = plan, R_dev, float(gain), int(delay)
         M, P, _ = modes_dev.shape
@@ -81,7 +84,7 @@ class ClosedLoop:
         self.BKL = modes_dev.reshape(M, P * P).t().contiguous()     # [P*P, M]
         self.s = torch.empty((1, 2 * plan.n_valid), device=dev)
         self.net = net
-        self.judge_every, self.judge_growth = judge_every, judge_growth
+        self.judge_every, self.judge_growth, self.judge_settle = judge_every, judge_growth, judge_settle
         self.fallback_step = None
         if net is not None:
             from .cnn import prepare
@@ -120,9 +123,12 @@ class ClosedLoop:
                     recon_apply(self.R, self.s, 1.0, 0.0, self.m_lin)
                     e = float(np.linalg.norm(self.m_lin.cpu().numpy()))
                     ok = bool(np.isfinite(c_next.cpu().numpy()).all())
-                    judged.append(e)
-                    diverging = len(judged) >= 3 and (e > self.judge_growth * min(judged) or e > 2.0 * judged[0])
-                    if not ok or diverging:
+                    judged.append((t, e))
+                    e0 = judged[0][1]
+                    settled = [v for (tt, v) in judged if tt >= self.judge_settle]
+                    not_closed = t >= self.judge_settle and e > 0.5 * e0
+                    diverging = len(settled) >= 2 and e > self.judge_growth * min(settled)
+                    if not ok or not_closed or diverging:
                         learned = False
                         self.fallback_step = t
                         hist[: t + d + 1].zero_()

@@ -79,14 +79,17 @@ def test_forward_matches_oracle(cfg, B):
     assert eq <= TOL_Q["small" if cfg is SMALL else "full"]
 
 
-@pytest.mark.parametrize("cfg,B", [(SMALL, 5), (FULL, 16)], ids=["small", "full"])
-def test_gradients_match_oracle(cfg, B):
+@pytest.mark.parametrize("cfg,B,weighted", [(SMALL, 5, False), (FULL, 16, False), (SMALL, 6, True)],
+                         ids=["small", "full", "small-weighted"])
+def test_gradients_match_oracle(cfg, B, weighted):
     net, torch, p, po, x, xb, tgt = _setup(cfg, B, 5)
-    g, loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda())
+    w = np.random.default_rng(6).uniform(0.2, 3.0, B).astype(np.float32) if weighted else None
+    g, loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda(),
+                            None if w is None else torch.from_numpy(w).cuda())
     g = g.cpu().numpy()
-    lo, go, _ = ocnn.loss_and_grads(po, xb.astype(np.float64), tgt.astype(np.float64))
+    lo, go, _ = ocnn.loss_and_grads(po, xb.astype(np.float64), tgt.astype(np.float64), weights=w)
     lq, gq, _ = ocnn.loss_and_grads(po, xb.astype(np.float64), tgt.astype(np.float64),
-                                    act_round=ocnn.bf16_round)
+                                    act_round=ocnn.bf16_round, weights=w)
     assert abs(float(loss.cpu()) - lo) <= 2e-2 * lo
     tq = TOL_Q["small" if cfg is SMALL else "full"]
     assert abs(float(loss.cpu()) - lq) <= tq * lq
@@ -99,7 +102,8 @@ def test_gradients_match_oracle(cfg, B):
         assert e <= 2e-2, k
         assert eq <= tq, k
         off += n
-    g2, _ = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda())
+    g2, _ = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda(),
+                          None if w is None else torch.from_numpy(w).cuda())
     assert np.array_equal(g, g2.cpu().numpy())          # deterministic
 
 

@@ -41,12 +41,13 @@ def test_conv_forward_matches_direct_sum():
     assert np.abs(y - ref).max() < 1e-12
 
 
-def _fd_check(shapes, S, c_in, B, coords_per_tensor=None, seed=1):
+def _fd_check(shapes, S, c_in, B, coords_per_tensor=None, seed=1, weighted=False):
     rng = np.random.default_rng(seed)
     p = _rand_params(shapes, rng)
     x = rng.normal(size=(B, S, S, c_in))
     t = rng.normal(size=(B, shapes["fb2"][0]))
-    loss, g, _ = cnn.loss_and_grads(p, x, t)
+    w = rng.uniform(0.2, 3.0, B) if weighted else None
+    loss, g, _ = cnn.loss_and_grads(p, x, t, weights=w)
     h = 1e-6
     worst = 0.0
     for k in cnn.PARAM_ORDER:
@@ -56,9 +57,9 @@ def _fd_check(shapes, S, c_in, B, coords_per_tensor=None, seed=1):
         for i in idx:
             old = flat[i]
             flat[i] = old + h
-            lp = cnn.mse(cnn.forward(p, x)[0], t)[0]
+            lp = cnn.mse(cnn.forward(p, x)[0], t, w)[0]
             flat[i] = old - h
-            lm = cnn.mse(cnn.forward(p, x)[0], t)[0]
+            lm = cnn.mse(cnn.forward(p, x)[0], t, w)[0]
             flat[i] = old
             fd = (lp - lm) / (2 * h)
             an = g[k].ravel()[i]
@@ -72,6 +73,18 @@ def test_backward_matches_finite_differences_small_net():
     shapes = cnn.param_shapes(S=9, c_in=4, chans=(2, 3, 3), hidden=5, n_out=4)
     assert shapes["fw1"] == (5, 2 * 2 * 3)          # 9 -> 5 -> 3 -> 2
     assert _fd_check(shapes, S=9, c_in=4, B=3) < 1e-6
+
+
+def test_weighted_loss_gradients_and_unit_weights():
+    shapes = cnn.param_shapes(S=9, c_in=4, chans=(2, 3, 3), hidden=5, n_out=4)
+    assert _fd_check(shapes, S=9, c_in=4, B=3, weighted=True) < 1e-6
+    rng = np.random.default_rng(3)
+    pred, t = rng.normal(size=(4, 6)), rng.normal(size=(4, 6))
+    l1, g1 = cnn.mse(pred, t)
+    l2, g2 = cnn.mse(pred, t, np.ones(4))
+    assert l1 == l2 and np.array_equal(g1, g2)
+    l3, _ = cnn.mse(pred, t, np.array([1.0, 0.0, 0.0, 0.0]))
+    assert np.isclose(l3, np.sum((pred[0] - t[0]) ** 2) / pred.size)
 
 
 def test_backward_matches_finite_differences_full_size_sampled():
