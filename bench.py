@@ -271,7 +271,7 @@ def main():
                                         n_loops=12, steps=1500, settle=LOOP_SETTLE_STEPS, seed=77,
                                         r0_range=(0.06, 0.2), gain=LOOP_GAIN, delay=LOOP_DELAY, stride=2)
         log(f"residual bank {tuple(resid.frames.shape)} in {time.time() - t_res:.1f}s")
-        net, info = train_reconstructor(plan, modes.astype(np.float32), amp, bank, args.cnn_frames, seed=5,
+        net, info = train_reconstructor(plan, R, modes.astype(np.float32), amp, bank, args.cnn_frames, seed=5,
                                         epochs=args.cnn_epochs, residuals=resid, log=log)
         info["residual_bank_frames"] = int(resid.frames.shape[0])
         del resid
@@ -297,6 +297,8 @@ def main():
                              "steps_per_s": round(T / (ev0.elapsed_time(ev1) / 1e3), 1)}
                 if nn_ is not None:
                     row[name]["fallback_step"] = cl.fallback_step
+                    g = [v for (tt, v) in cl.judged if tt >= cl.judge_settle]
+                    row[name]["optical_gain_mean"] = round(float(np.mean(g)), 3) if g else None
             loops[f"r0_{r0}"] = row
             log(f"loop r0={r0}: {row}")
         learned = {"training": {k: v for k, v in info.items() if k != "loss_history"},

@@ -2,14 +2,21 @@
 loop and checkpoints, driven through the C ABI (pwfs_measure, recon_apply,
 pwfs_cnn_*).
 
+The learned reconstructor estimates the modal coefficients as the linear
+estimate plus a network correction, c = R s + f(x): the network sees the
+pupil images (pwfs_cnn_prepare) and learns what the linear reconstructor
+misses, chiefly the loss of pyramid sensitivity (optical gain) when the
+residual is large and the non-linear response to strong aberrations; a
+network that outputs zero is the linear reconstructor.
+
 Training inputs are simulator frames: seeded screens (open loop) and
-partially corrected screens (the DM path removes a random fraction of the
-first n KL modes, as an integrator loop does), measured by the pyramid plan,
-turned into network inputs by pwfs_cnn_prepare; labels are the KL
-coefficients of the measured screen (projection through recon_apply),
-divided by one global scale so the loss is a wavefront error in scaled nm^2.
-After training the scale is folded into the last layer, so the network
-outputs modal coefficients in nm, the same units as R s.
+partially corrected screens (residuals of linear closed loops, or screens
+with a random fraction of their first KL modes removed through the DM
+path), measured by the pyramid plan.  Labels are the KL coefficients of the
+measured screen minus the linear estimate, c_true - R s (both products
+through recon_apply), divided by one global scale.  After training the
+scale is folded into the last layer, so the network outputs nm, the same
+units as R s.
 """
 from __future__ import annotations
 
@@ -20,18 +27,20 @@ from .cnn import CNN, prepare, he_init, PARAM_ORDER
 
 
 class TrainingSet:
-    def __init__(self, x, y, label_scale, w=None):
-        self.x, self.y, self.label_scale, self.w = x, y, label_scale, w
+    """x [F, S, S, 4] network inputs, y [F, M] scaled labels (device),
+    frame_rms [F] RMS over the modes of each frame's true coefficients, nm
+    (host), w [F] per-frame loss weights or None."""
+
+    def __init__(self, x, y, label_scale, frame_rms, w=None):
+        self.x, self.y, self.label_scale, self.frame_rms, self.w = x, y, label_scale, frame_rms, w
 
     def set_relative_weights(self, floor_nm: float):
-        """Per-frame loss weights 1 / (rms(label)^2 + floor^2), normalised to
-        mean 1: each frame's error counts relative to its own size, so the
-        small residuals of a closed loop are learned as accurately as large
-        open-loop aberrations (computed on the host from the labels)."""
+        """Per-frame loss weights 1 / (frame_rms^2 + floor^2), normalised to
+        mean 1: each frame's error counts relative to the size of its
+        wavefront error, so the small residuals of a closed loop are learned
+        as accurately as large open-loop aberrations."""
         import torch
-        y = self.y.cpu().numpy().astype(np.float64)
-        f = floor_nm / self.label_scale
-        w = 1.0 / (np.mean(y * y, axis=1) + f * f)
+        w = 1.0 / (self.frame_rms.astype(np.float64) ** 2 + float(floor_nm) ** 2)
         w /= w.mean()
         self.w = torch.from_numpy(w.astype(np.float32)).to(self.y.device)
 
@@ -86,17 +95,18 @@ class ResidualBank:
         return x.contiguous()
 
 
-def make_training_set(plan, bank, modes: np.ndarray, pupil: np.ndarray, n_frames: int, seed: int,
+def make_training_set(plan, bank, R_dev, modes: np.ndarray, pupil: np.ndarray, n_frames: int, seed: int,
                       r0_range=(0.06, 0.2), corrected_fraction=0.5, batch=256, label_scale=None,
                       residuals: "ResidualBank | None" = None, device="cuda") -> TrainingSet:
     """Generate n_frames (input, label) pairs on the GPU.  A fraction
     corrected_fraction of each batch is partially corrected: residual
     screens of linear closed loops when a ResidualBank is given, otherwise
     open-loop screens with a random fraction of their first KL modes
-    removed through the DM path."""
+    removed through the DM path.  Labels: (c_true - R s) / label_scale."""
     import torch
     rng = np.random.default_rng(seed)
     P, S, M = plan.cfg.n_pupil, plan.n_sub, modes.shape[0]
+    ns = 2 * plan.n_valid
     proj = projector(modes, pupil, device)
     BKL = torch.from_numpy(modes.reshape(M, -1).T.astype(np.float32)).to(device).contiguous()
     valid = torch.from_numpy(plan.valid.astype(np.int32)).to(device)
@@ -105,7 +115,10 @@ def make_training_set(plan, bank, modes: np.ndarray, pupil: np.ndarray, n_frames
     plan.measure_into(zero, ref, None)
     X = torch.empty((n_frames, S, S, 4), device=device)
     Y = torch.empty((n_frames, M), device=device)
+    rms = np.empty(n_frames)
     pup = torch.empty((plan.batch_max, 4, S, S), device=device)
+    sl = torch.empty((batch, ns), device=device)
+    ct = torch.empty((batch, M), device=device)
     for i0 in range(0, n_frames, batch):
         n = min(batch, n_frames - i0)
         opd_h, _ = bank.draw(rng, n, r0_range)
@@ -121,15 +134,20 @@ def make_training_set(plan, bank, modes: np.ndarray, pupil: np.ndarray, n_frames
                 c[j, rng.integers(20, M + 1):] = 0.0
                 c[j] *= rng.uniform(0.5, 1.0)
             recon_apply(BKL, torch.from_numpy(c).to(device), -1.0, 1.0, opd[:n_cor])
-        if label_scale is None:
-            c0 = recon_apply(proj, opd).cpu().numpy().astype(np.float64)
-            label_scale = float(np.sqrt(np.mean(c0 ** 2)))
-        recon_apply(proj, opd, 1.0 / label_scale, 0.0, Y[i0:i0 + n])
         for b0 in range(0, n, plan.batch_max):
             nb = min(plan.batch_max, n - b0)
-            plan.measure_into(opd[b0:b0 + nb].view(nb, P, P), pup[:nb], None)
+            plan.measure_into(opd[b0:b0 + nb].view(nb, P, P), pup[:nb], sl[b0:b0 + nb])
             prepare(pup[:nb], ref[0], valid, X[i0 + b0:i0 + b0 + nb])
-    return TrainingSet(X, Y, label_scale)
+        recon_apply(proj, opd, 1.0, 0.0, ct[:n])
+        c_h = ct[:n].cpu().numpy().astype(np.float64)
+        rms[i0:i0 + n] = np.sqrt(np.mean(c_h * c_h, axis=1))
+        if label_scale is None:
+            lin = recon_apply(R_dev, sl[:n]).cpu().numpy().astype(np.float64)
+            label_scale = float(np.sqrt(np.mean((c_h - lin) ** 2)))
+        y = Y[i0:i0 + n]
+        recon_apply(proj, opd, 1.0 / label_scale, 0.0, y)
+        recon_apply(R_dev, sl[:n], -1.0 / label_scale, 1.0, y)
+    return TrainingSet(X, Y, label_scale, rms)
 
 
 def train(net: CNN, data: TrainingSet, epochs: int, batch: int, lr: float, seed: int, log=None):
@@ -191,14 +209,14 @@ def load_checkpoint(path: str, net: CNN) -> dict:
     return {k: d[k] for k in d.files if k != "params"}
 
 
-def train_reconstructor(plan, modes: np.ndarray, pupil: np.ndarray, bank, n_frames: int, seed: int,
+def train_reconstructor(plan, R_dev, modes: np.ndarray, pupil: np.ndarray, bank, n_frames: int, seed: int,
                         epochs: int = 4, batch: int = 256, lr: float = 1e-3, r0_range=(0.06, 0.2),
                         residuals=None, weight_floor_nm: float | None = 20.0, log=None, device="cuda"):
     """Generate the training set, train a CNN from a seeded He initialisation,
     fold the label scale and the zero-input offset; returns (net, info)."""
     import time
     t0 = time.time()
-    data = make_training_set(plan, bank, modes, pupil, n_frames, seed, r0_range=r0_range,
+    data = make_training_set(plan, bank, R_dev, modes, pupil, n_frames, seed, r0_range=r0_range,
                              residuals=residuals, device=device)
     if weight_floor_nm is not None:
         data.set_relative_weights(weight_floor_nm)
@@ -214,6 +232,7 @@ def train_reconstructor(plan, modes: np.ndarray, pupil: np.ndarray, bank, n_fram
     t_train = time.time() - t1
     fold_label_scale(net, data.label_scale)
     info = {"frames": n_frames, "epochs": epochs, "batch": batch, "loss_history": hist,
+            "target": "correction to the linear estimate, c_true - R s",
             "loss": "relative (per-frame weights, floor %s nm)" % weight_floor_nm if weight_floor_nm else "MSE",
             "label_scale_nm": data.label_scale, "data_s": round(t_data, 2), "train_s": round(t_train, 2),
             "train_frames_per_s": round(epochs * n_frames / max(t_train, 1e-9), 1)}
@@ -224,38 +243,19 @@ def train_reconstructor(plan, modes: np.ndarray, pupil: np.ndarray, bank, n_fram
 def open_loop_errors(plan, net, R_dev, modes: np.ndarray, pupil: np.ndarray, bank, n_frames: int, seed: int,
                      r0_range, device="cuda"):
     """Held-out modal reconstruction error (nm RMS over the pupil, within the
-    modal subspace) of the learned and of the linear reconstructor."""
+    modal subspace) of the learned (R s + f(x)) and of the linear (R s)
+    reconstructor on open-loop screens."""
     import torch
-    data = make_training_set(plan, bank, modes, pupil, n_frames, seed, r0_range=r0_range,
+    data = make_training_set(plan, bank, R_dev, modes, pupil, n_frames, seed, r0_range=r0_range,
                              corrected_fraction=0.0, label_scale=1.0, device=device)
-    P = plan.cfg.n_pupil
+    M = modes.shape[0]
     pred = torch.empty_like(data.y)
     for b0 in range(0, n_frames, net.batch_max):
         nb = min(net.batch_max, n_frames - b0)
         net.forward(data.x[b0:b0 + nb].contiguous(), pred[b0:b0 + nb])
-    # linear: measure the same screens again for slopes (same seed -> same screens)
-    rng_frames = make_slopes(plan, bank, modes, pupil, n_frames, seed, r0_range, device)
-    lin = recon_apply(R_dev, rng_frames)
-    y = data.y.cpu().numpy().astype(np.float64)
+    y = data.y.cpu().numpy().astype(np.float64)                 # c_true - R s, nm
     e_cnn = float(np.sqrt(np.mean(np.sum((pred.cpu().numpy() - y) ** 2, axis=1))))
-    e_lin = float(np.sqrt(np.mean(np.sum((lin.cpu().numpy() - y) ** 2, axis=1))))
-    e_0 = float(np.sqrt(np.mean(np.sum(y ** 2, axis=1))))
+    e_lin = float(np.sqrt(np.mean(np.sum(y ** 2, axis=1))))
+    e_0 = float(np.sqrt(np.mean(M * data.frame_rms ** 2)))
     return {"cnn_nm": round(e_cnn, 2), "linear_nm": round(e_lin, 2), "signal_nm": round(e_0, 2),
             "frames": n_frames, "r0_range": list(r0_range)}
-
-
-def make_slopes(plan, bank, modes, pupil, n_frames, seed, r0_range, device="cuda"):
-    """Slopes of the open-loop screens make_training_set draws for the same seed."""
-    import torch
-    rng = np.random.default_rng(seed)
-    P = plan.cfg.n_pupil
-    out = torch.empty((n_frames, 2 * plan.n_valid), device=device)
-    batch = 256
-    for i0 in range(0, n_frames, batch):
-        n = min(batch, n_frames - i0)
-        opd_h, _ = bank.draw(rng, n, r0_range)
-        opd = torch.from_numpy(opd_h).to(device)
-        for b0 in range(0, n, plan.batch_max):
-            nb = min(plan.batch_max, n - b0)
-            plan.measure_into(opd[b0:b0 + nb].contiguous(), None, out[i0 + b0:i0 + b0 + nb])
-    return out

@@ -63,19 +63,27 @@ def calibrate(plan, modes, eps_nm: float, device="cuda"):
 class ClosedLoop:
     """Integrator loop of one sensor plan (batch 1) with a modal DM.
 
-    With a learned reconstructor (net) the integrator input is the
-    network's modal estimate from the pupil images; the linear
-    reconstructor R judges it every `judge_every` steps from its own
-    estimate of the modal residual, e = ||R s||, and takes over for the
-    rest of the run (integrator restarted from zero) if the network output
-    is not finite, if after `judge_settle` steps e has not fallen below
-    half its open-loop value e(0) (the loop did not close; with large
-    errors the sensor saturates, so e alone cannot show how far it
-    diverged), or if e exceeds `judge_growth` times its best value since
-    then (the loop is diverging)."""
+    With a learned reconstructor (net) the integrator input is the linear
+    estimate plus the network's correction from the pupil images,
+    c(t) = c(t-1) + g (R s(t) + f(x(t))).  The linear reconstructor judges
+    it every `judge_every` steps by measuring the sensor's optical gain at
+    the current residual r(t): push-pull probes r(t) +- a B_k of a few modes
+    (a = probe_nm), measured and reconstructed by R, give
+    gamma = mean_k [R (s+ - s-)]_k / (2 a), the quantity a modal dither
+    measures on a real system.  gamma is ~1 at a flat wavefront, drops as
+    the residual grows and goes to ~0 once the sensor has lost track (neither
+    the slope RMS nor the size of R s shows this: both shrink again at very
+    large residuals, where the phase wraps inside each subaperture).  The
+    linear reconstructor takes over for the rest of the run (integrator
+    restarted from zero) if the commands are not finite, if after
+    `judge_settle` steps gamma is below `gain_min` (the loop did not close),
+    or if gamma falls below `gain_drop` times its best value since then (the
+    loop is diverging).  `judged` keeps the (t, gamma) pairs of the last
+    run."""
 
     def __init__(self, plan, modes_dev, R_dev, gain: float, delay: int, net=None,
-                 judge_every: int = 10, judge_growth: float = 4.0, judge_settle: int = 50):
+                 judge_every: int = 10, judge_settle: int = 50, gain_min: float = 0.1,
+                 gain_drop: float = 0.5, probe_modes=(0, 1, 20, 100), probe_nm: float = 20.0):
         import torch
         self.plan, self.R, self.gain, self.delay = plan, R_dev, float(gain), int(delay)
         M, P, _ = modes_dev.shape
@@ -84,8 +92,10 @@ class ClosedLoop:
         self.BKL = modes_dev.reshape(M, P * P).t().contiguous()     # [P*P, M]
         self.s = torch.empty((1, 2 * plan.n_valid), device=dev)
         self.net = net
-        self.judge_every, self.judge_growth, self.judge_settle = judge_every, judge_growth, judge_settle
+        self.judge_every, self.judge_settle = judge_every, judge_settle
+        self.gain_min, self.gain_drop = gain_min, gain_drop
         self.fallback_step = None
+        self.judged = []
         if net is not None:
             from .cnn import prepare
             self._prepare = prepare
@@ -95,7 +105,42 @@ class ClosedLoop:
             plan.measure_into(torch.zeros((1, P, P), device=dev), self.ref, None)
             self.valid = torch.from_numpy(plan.valid.astype(np.int32)).to(dev)
             self.x = torch.empty((1, S, S, 4), device=dev)
-            self.m_lin = torch.empty((1, M), device=dev)
+            self.probe_modes = [int(k) for k in probe_modes if 0 <= int(k) < M]
+            self.probe_nm = float(probe_nm)
+            npb = len(self.probe_modes)
+            coef = np.zeros((2 * npb, M), np.float32)
+            for j, k in enumerate(self.probe_modes):
+                coef[2 * j, k], coef[2 * j + 1, k] = self.probe_nm, -self.probe_nm
+            self.probe_coef = torch.from_numpy(coef).to(dev)
+            self.probe_screen = torch.empty((1, P * P), device=dev)
+            self.probe_s = torch.empty((2 * npb, 2 * plan.n_valid), device=dev)
+            self.probe_est = torch.empty((2 * npb, M), device=dev)
+
+    def optical_gain(self, r_t) -> float:
+        """Mean push-pull response of the linear reconstructor to the probe
+        modes around the residual r_t [1, P*P] (library kernels; host mean)."""
+        P = self.P
+        for j in range(self.probe_s.shape[0]):
+            self.probe_screen.copy_(r_t)
+            recon_apply(self.BKL, self.probe_coef[j:j + 1], 1.0, 1.0, self.probe_screen)
+            self.plan.measure_into(self.probe_screen.view(1, P, P), None, self.probe_s[j:j + 1])
+        recon_apply(self.R, self.probe_s, 1.0, 0.0, self.probe_est)
+        est = self.probe_est.cpu().numpy().astype(np.float64)
+        g = [(est[2 * j, k] - est[2 * j + 1, k]) / (2.0 * self.probe_nm) for j, k in enumerate(self.probe_modes)]
+        return float(np.mean(g))
+
+    def _judge(self, t: int, r_t, c_next) -> bool:
+        """True when the learned reconstructor must hand over (host logic)."""
+        ok = bool(np.isfinite(c_next.cpu().numpy()).all())
+        if not ok:
+            self.judged.append((t, float("nan")))
+            return True
+        gam = self.optical_gain(r_t)
+        self.judged.append((t, gam))
+        if t < self.judge_settle:
+            return False
+        settled = [v for (tt, v) in self.judged if tt >= self.judge_settle]
+        return gam < self.gain_min or gam < self.gain_drop * max(settled)
 
     def run(self, opd_seq_dev, residuals_dev=None):
         """Run len(opd_seq) steps; returns (residual OPD [T, P*P], commands c(t) [T, M])."""
@@ -106,7 +151,7 @@ class ClosedLoop:
         res = residuals_dev if residuals_dev is not None else torch.empty((T, P * P), device=dev)
         hist = torch.zeros((T + d, M), device=dev)                   # c(t) is row t + d
         learned = self.net is not None
-        judged = []
+        self.judged = []
         self.fallback_step = None
         for t in range(T):
             r_t = res[t:t + 1]
@@ -117,22 +162,14 @@ class ClosedLoop:
                 c_next.copy_(hist[t + d - 1:t + d])
             if learned:
                 self.plan.measure_into(r_t.view(1, P, P), self.pupils, self.s)
+                recon_apply(self.R, self.s, self.gain, 1.0, c_next)
                 self._prepare(self.pupils, self.ref[0], self.valid, self.x)
                 self.net.forward_acc(self.x, c_next, self.gain, 1.0)
-                if t % self.judge_every == 0:
-                    recon_apply(self.R, self.s, 1.0, 0.0, self.m_lin)
-                    e = float(np.linalg.norm(self.m_lin.cpu().numpy()))
-                    ok = bool(np.isfinite(c_next.cpu().numpy()).all())
-                    judged.append((t, e))
-                    e0 = judged[0][1]
-                    settled = [v for (tt, v) in judged if tt >= self.judge_settle]
-                    not_closed = t >= self.judge_settle and e > 0.5 * e0
-                    diverging = len(settled) >= 2 and e > self.judge_growth * min(settled)
-                    if not ok or not_closed or diverging:
-                        learned = False
-                        self.fallback_step = t
-                        hist[: t + d + 1].zero_()
-                        recon_apply(self.R, self.s, self.gain, 1.0, c_next)
+                if t % self.judge_every == 0 and self._judge(t, r_t, c_next):
+                    learned = False
+                    self.fallback_step = t
+                    hist[: t + d + 1].zero_()
+                    recon_apply(self.R, self.s, self.gain, 1.0, c_next)
             else:
                 self.plan.measure_into(r_t.view(1, P, P), None, self.s)
                 recon_apply(self.R, self.s, self.gain, 1.0, c_next)

@@ -31,7 +31,7 @@ def _setup():
 def test_trained_cnn_beats_linear_in_open_loop_strong_turbulence():
     from paper_1607_07624_amd.learned import train_reconstructor, open_loop_errors
     st = _setup()
-    net, info = train_reconstructor(st["plan"], st["modes"], st["pupil"], st["bank"], n_frames=49152,
+    net, info = train_reconstructor(st["plan"], st["R"], st["modes"], st["pupil"], st["bank"], n_frames=49152,
                                     seed=1, epochs=4, batch=256, lr=1e-3, log=say)
     say(f"[gpu] cnn training: {info}")
     assert info["loss_history"][-1] < 0.7 * info["loss_history"][0]
@@ -60,3 +60,41 @@ def test_linear_judge_takes_over_from_a_broken_network():
     res_l, _ = lin.run(seq)
     torch.cuda.synchronize()
     assert torch.equal(res_c, res_l)
+
+
+def test_linear_judge_takes_over_from_a_diverging_network():
+    """A network whose output is a large, input-independent command drives the
+    integrator away; the optical-gain probe sees the sensor lose track once the
+    settling time is over, the linear reconstructor takes over from zero
+    commands and closes the loop again."""
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd.cnn import CNN, he_init, PARAM_ORDER
+    from paper_1607_07624_amd.loop import ClosedLoop, residual_rms_nm
+    st = _setup()
+    torch = st["torch"]
+    net = CNN(n_sub=CFG2.n_sub, n_out=600, batch_max=4)
+    p = he_init(net.shapes, 321)
+    off = 0
+    for k in PARAM_ORDER:
+        n = int(np.prod(net.shapes[k]))
+        if k in ("fw2", "fb2"):
+            p[off:off + n] *= 300.0
+        off += n
+    net.set_params(torch.from_numpy(p))
+    plan1 = pw.Plan(CFG2, batch_max=1)
+    modes_dev = torch.from_numpy(st["modes"]).cuda()
+    T = 200
+    seq = torch.from_numpy(frozen_flow_sequence(CFG2, ATMO2, T, seed=5)).cuda()
+    cl = ClosedLoop(plan1, modes_dev, st["R"], LOOP_GAIN, LOOP_DELAY, net=net)
+    res_c, _ = cl.run(seq)
+    say(f"[gpu] diverging network: fallback at {cl.fallback_step}, judged {cl.judged}")
+    assert cl.fallback_step == cl.judge_settle
+    assert all(g > 0.0 for _, g in cl.judged[:1])
+    lin = ClosedLoop(plan1, modes_dev, st["R"], LOOP_GAIN, LOOP_DELAY)
+    res_l, _ = lin.run(seq)
+    pc = residual_rms_nm(res_c.cpu().numpy(), st["pupil"])
+    pl = residual_rms_nm(res_l.cpu().numpy(), st["pupil"])
+    say(f"[gpu] residual at fallback {pc[cl.fallback_step]:.0f} nm; last 50 steps: "
+        f"after fallback {np.sqrt(np.mean(pc[-50:] ** 2)):.1f}, linear {np.sqrt(np.mean(pl[-50:] ** 2)):.1f} nm")
+    assert pc[cl.fallback_step] > 5.0 * pl[cl.fallback_step]
+    assert np.sqrt(np.mean(pc[-50:] ** 2)) < 1.5 * np.sqrt(np.mean(pl[-50:] ** 2))
