@@ -56,6 +56,17 @@ __device__ __forceinline__ const T* opaque(const T* p) {
   return p;
 }
 
+// LDS copies of the pyramid tables are padded so that a ds_read of a quad's
+// four lanes (mix table, rows of 2E values) or of a team's two quads (input
+// and output tables, halves of P values) spreads over distinct banks: both
+// 2E and P complex values are multiples of the bank-set width here.
+template <int E>
+struct TabLds {
+  static constexpr int P = 4 * E;
+  static constexpr int QO = P + 4;        // offset of quad 1's half of an input / output table
+  static constexpr int MS = 2 * E + 2;    // per-lane row stride of the mix table
+};
+
 // Half-band projection of the E samples held by this lane (see header), up to
 // a factor 1/2 that the output table absorbs.  The forward twiddle w_l =
 // w_P^{l k}, the quad mix and the conjugate twiddle are folded into
@@ -66,7 +77,7 @@ template <int E>
 __device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ mid, int l) {
   Dft<E, +1>::run(v);
   fence();
-  const cpx* ml = mid + l * 2 * E;
+  const cpx* ml = mid + l * TabLds<E>::MS;
   static_for<0, E>([&](auto k_) {
     constexpr int k = decltype(k_)::value;
     if constexpr (k % 8 == 0 && k > 0) fence();
@@ -106,7 +117,7 @@ __device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadF&& l
   });
   fence();
   half_band<E>(v, mid, l);
-  const cpx* ow = outw + q * P + l;
+  const cpx* ow = outw + q * TabLds<E>::QO + l;
   const float keep = (q == 0) ? 1.f : 0.f;   // quad 0 adds f back (y_L = f - y_H)
   const float sgn = (q == 0) ? -1.f : 1.f;
   static_for<0, E>([&](auto m_) {
@@ -130,6 +141,23 @@ __device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __res
   uint4* d = reinterpret_cast<uint4*>(dst);
   const uint4* s = reinterpret_cast<const uint4*>(src);
   for (int i = tid; i < n16; i += nthreads) d[i] = s[i];
+}
+
+// Table [2][P] (quad 0 half, quad 1 half) -> LDS with quad 1 at TabLds::QO.
+template <int E>
+__device__ __forceinline__ void stage_quads(cpx* __restrict__ dst, const cpx* __restrict__ src, int tid) {
+  constexpr int P = 4 * E;
+  copy16(dst, src, P / 2, tid, 256);
+  copy16(dst + TabLds<E>::QO, src + P, P / 2, tid, 256);
+}
+
+// Mix table [4][2E] -> LDS rows of stride TabLds::MS.
+template <int E>
+__device__ __forceinline__ void stage_mid(cpx* __restrict__ dst, const cpx* __restrict__ src, int tid) {
+  for (int i = tid; i < 4 * E; i += 256) {
+    const int l = i / E, r = i - l * E;
+    reinterpret_cast<uint4*>(dst + l * TabLds<E>::MS)[r] = reinterpret_cast<const uint4*>(src + l * 2 * E)[r];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -169,10 +197,10 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
   constexpr int P = 4 * E;
   constexpr int LDP = P + 4;
   __shared__ __align__(16) cpx field[32 * LDP];
-  __shared__ __align__(16) cpx s_in[2 * P];
+  __shared__ __align__(16) cpx s_in[2 * P + 4];
   __shared__ __align__(16) cpx s_f[P];
-  __shared__ __align__(16) cpx s_mid[8 * E];
-  __shared__ __align__(16) cpx s_out[2 * P];
+  __shared__ __align__(16) cpx s_mid[4 * TabLds<E>::MS];
+  __shared__ __align__(16) cpx s_out[2 * P + 4];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int t = lane >> 3, q = (lane >> 2) & 1, l = lane & 3;
@@ -185,18 +213,18 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
     const int r = e / (P / 2), c2 = e - r * (P / 2);
     *reinterpret_cast<uint4*>(field + r * LDP + 2 * c2) = src[e];
   }
-  copy16(s_mid, mid, 4 * E, tid, 256);
-  copy16(s_out, outw, P, tid, 256);
+  stage_mid<E>(s_mid, mid, tid);
+  stage_quads<E>(s_out, outw, tid);
   const int a1 = min(a0 + a_chunk, n_a);
   const int r = wave * 8 + t;                     // row within the block
   const cpx* frow = field + r * LDP + l;
   const int y = yb + r;
   for (int ia = a0; ia < a1; ++ia) {
     __syncthreads();
-    copy16(s_in, in_a + (size_t)ia * 2 * P, P, tid, 256);
+    stage_quads<E>(s_in, in_a + (size_t)ia * 2 * P, tid);
     copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
     __syncthreads();
-    const cpx* tin = s_in + q * P + l;
+    const cpx* tin = s_in + q * TabLds<E>::QO + l;
     const cpx* tf = s_f + l;
     cpx v[E];
     line_op<E>(v, [&](int m) { return cmul(frow[4 * m], tin[4 * m]); },
@@ -236,10 +264,10 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   constexpr int P = 4 * E;
   constexpr int NA = QB ? E / 4 : E;            // accumulators per lane
   __shared__ __align__(16) cpx s_col[32 * P];
-  __shared__ __align__(16) cpx s_in[2 * P];
+  __shared__ __align__(16) cpx s_in[2 * P + 4];
   __shared__ __align__(16) cpx s_f[P];
-  __shared__ __align__(16) cpx s_mid[8 * E];
-  __shared__ __align__(16) cpx s_out[2 * P];
+  __shared__ __align__(16) cpx s_mid[4 * TabLds<E>::MS];
+  __shared__ __align__(16) cpx s_out[2 * P + 4];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int t = lane >> 3, q = (lane >> 2) & 1, l = lane & 3;
@@ -248,14 +276,14 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   const size_t fr = blockIdx.z;
   float acc[NA];
   static_for<0, NA>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
-  copy16(s_mid, mid, 4 * E, tid, 256);
-  copy16(s_out, outw, P, tid, 256);
+  stage_mid<E>(s_mid, mid, tid);
+  stage_quads<E>(s_out, outw, tid);
   const int kb = chunk * k_chunk;
   const int ke = min(kb + k_chunk, K);
   const cpx* frame = Rw + fr * (size_t)n_a * (size_t)(2 * P * P) + (size_t)(X0 >> 3) * (size_t)(8 * P);
   const int c = wave * 8 + t;                      // column within the block
   const cpx* col = s_col + wave * 8 * P + t * 4 + l;   // element (x' = X0 + c, y = l + 4m) at col[32 m]
-  const cpx* tin = s_in + q * P + l;
+  const cpx* tin = s_in + q * TabLds<E>::QO + l;
   const cpx* tf = s_f + l;
   int cur_ia = -1;
   for (int kk = kb; kk < ke; ++kk) {
@@ -266,7 +294,7 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
       copy16(s_col, frame + (size_t)ia * (size_t)(2 * P * P), 16 * P, tid, 256);
       cur_ia = ia;
     }
-    copy16(s_in, in_b + (size_t)k * 2 * P, P, tid, 256);
+    stage_quads<E>(s_in, in_b + (size_t)k * 2 * P, tid);
     copy16(s_f, f_b + (size_t)k * P, P / 2, tid, 256);
     __syncthreads();
     cpx v[E];
