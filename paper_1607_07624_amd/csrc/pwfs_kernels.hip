@@ -143,6 +143,20 @@ __device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __res
   for (int i = tid; i < n16; i += nthreads) d[i] = s[i];
 }
 
+// Block copy of exactly 256 N 16-byte words: every load is issued before the
+// first LDS write, so a thread waits for one memory round trip, not N.
+template <int N>
+__device__ __forceinline__ void copy16_n(void* __restrict__ dst, const void* __restrict__ src, int tid) {
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4 r[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = s[tid + 256 * i];
+  fence();
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[tid + 256 * i] = r[i];
+}
+
 // Table [2][P] (quad 0 half, quad 1 half) -> LDS with quad 1 at TabLds::QO.
 template <int E>
 __device__ __forceinline__ void stage_quads(cpx* __restrict__ dst, const cpx* __restrict__ src, int tid) {
@@ -208,10 +222,20 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
   const int a0 = blockIdx.y * a_chunk;
   const size_t fr = blockIdx.z;
   // 32 field rows (contiguous in HBM) -> LDS rows of stride LDP, 16 bytes per move.
+  // 32 P / 2 = 256 (P / 16) words per block, all loads issued before the LDS writes.
   const uint4* src = reinterpret_cast<const uint4*>(fieldg + (fr * (size_t)P + yb) * (size_t)P);
-  for (int e = tid; e < 32 * (P / 2); e += 256) {
-    const int r = e / (P / 2), c2 = e - r * (P / 2);
-    *reinterpret_cast<uint4*>(field + r * LDP + 2 * c2) = src[e];
+  {
+    constexpr int NW = P / 16;
+    uint4 w[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = src[tid + 256 * i];
+    fence();
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const int e = tid + 256 * i;
+      const int r = e / (P / 2), c2 = e - r * (P / 2);
+      *reinterpret_cast<uint4*>(field + r * LDP + 2 * c2) = w[i];
+    }
   }
   stage_mid<E>(s_mid, mid, tid);
   stage_quads<E>(s_out, outw, tid);
@@ -291,7 +315,7 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
     const int ia = k_ia[k];
     __syncthreads();
     if (ia != cur_ia) {
-      copy16(s_col, frame + (size_t)ia * (size_t)(2 * P * P), 16 * P, tid, 256);
+      copy16_n<P / 16>(s_col, frame + (size_t)ia * (size_t)(2 * P * P), tid);   // 16 P words
       cur_ia = ia;
     }
     stage_quads<E>(s_in, in_b + (size_t)k * 2 * P, tid);
@@ -449,18 +473,23 @@ __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R,
     const V* sb = reinterpret_cast<const V*>(s + (size_t)b0 * ns);
     for (int j = slice * 64 + lane; j < nv; j += 64 * wpr) {
       const V r = Ri[j];
+      // All BT loads are issued before the first product (the fence keeps the
+      // scheduler from interleaving load, wait and use frame by frame);
+      // frames past the last one re-read the last frame (in bounds, never
+      // stored), so there are no branches between the loads.
+      V x[BT];
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) x[bb] = sb[(size_t)min(bb, nb - 1) * nv + j];
+      fence();
 #pragma unroll
       for (int bb = 0; bb < BT; ++bb) {
-        if (bb < nb) {
-          const V x = sb[(size_t)bb * nv + j];
-          if constexpr (VEC == 4) {
-            acc[bb] = fmaf(r.x, x.x, acc[bb]);
-            acc[bb] = fmaf(r.y, x.y, acc[bb]);
-            acc[bb] = fmaf(r.z, x.z, acc[bb]);
-            acc[bb] = fmaf(r.w, x.w, acc[bb]);
-          } else {
-            acc[bb] = fmaf(r, x, acc[bb]);
-          }
+        if constexpr (VEC == 4) {
+          acc[bb] = fmaf(r.x, x[bb].x, acc[bb]);
+          acc[bb] = fmaf(r.y, x[bb].y, acc[bb]);
+          acc[bb] = fmaf(r.z, x[bb].z, acc[bb]);
+          acc[bb] = fmaf(r.w, x[bb].w, acc[bb]);
+        } else {
+          acc[bb] = fmaf(r, x[bb], acc[bb]);
         }
       }
     }
