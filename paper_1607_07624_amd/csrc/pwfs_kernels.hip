@@ -447,68 +447,80 @@ __global__ __launch_bounds__(1024) void slopes_kernel(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// m = alpha R s + beta m.  A block of 4 waves handles 4 / WPR rows; each row
-// is split over WPR waves (long rows) whose lanes stride it with float4 (or
-// scalar) loads, each lane keeping BT batch accumulators.  Butterfly
-// reduction inside each wave, then the WPR wave partials are added in wave
-// order through LDS: a fixed summation order, bitwise reproducible.
-template <int BT, int VEC>
+// m = alpha R s + beta m.  A block of 4 waves handles RW (4 / WPR) rows; each
+// group of RW rows is split over WPR waves (long rows) whose lanes stride it
+// with float4 (or scalar) loads, each lane keeping RW x BT accumulators, so
+// one load of a slope vector feeds RW rows.  Butterfly reduction inside each
+// wave, then the WPR wave partials are added in wave order through LDS: a
+// fixed summation order, bitwise reproducible.  Rows and frames past the
+// ends are clamped to the last one for loading (in bounds, never stored).
+template <int BT, int VEC, int RW>
 __global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R, int M, int ns,
                                                      const float* __restrict__ s, int B, float alpha,
                                                      float beta, float* __restrict__ m, int wpr) {
-  __shared__ float part[4][BT];
+  __shared__ float part[4][RW * BT];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rows_per_block = 4 / wpr;
-  const int i = blockIdx.x * rows_per_block + wave / wpr;
+  const int groups_per_block = 4 / wpr;
+  const int i0 = (blockIdx.x * groups_per_block + wave / wpr) * RW;
   const int slice = wave % wpr;
   const int b0 = blockIdx.y * BT;
   const int nb = min(BT, B - b0);
-  float acc[BT];
+  float acc[RW][BT];
 #pragma unroll
-  for (int bb = 0; bb < BT; ++bb) acc[bb] = 0.f;
-  if (i < M) {
+  for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+    for (int bb = 0; bb < BT; ++bb) acc[rr][bb] = 0.f;
+  if (i0 < M) {
     const int nv = ns / VEC;
     using V = typename std::conditional<VEC == 4, float4, float>::type;
-    const V* Ri = reinterpret_cast<const V*>(R + (size_t)i * ns);
     const V* sb = reinterpret_cast<const V*>(s + (size_t)b0 * ns);
     for (int j = slice * 64 + lane; j < nv; j += 64 * wpr) {
-      const V r = Ri[j];
-      // All BT loads are issued before the first product (the fence keeps the
-      // scheduler from interleaving load, wait and use frame by frame);
-      // frames past the last one re-read the last frame (in bounds, never
-      // stored), so there are no branches between the loads.
-      V x[BT];
+      // All loads are issued before the first product (the fence keeps the
+      // scheduler from interleaving load, wait and use one at a time).
+      V r[RW], x[BT];
+#pragma unroll
+      for (int rr = 0; rr < RW; ++rr) r[rr] = reinterpret_cast<const V*>(R + (size_t)min(i0 + rr, M - 1) * ns)[j];
 #pragma unroll
       for (int bb = 0; bb < BT; ++bb) x[bb] = sb[(size_t)min(bb, nb - 1) * nv + j];
       fence();
 #pragma unroll
-      for (int bb = 0; bb < BT; ++bb) {
-        if constexpr (VEC == 4) {
-          acc[bb] = fmaf(r.x, x[bb].x, acc[bb]);
-          acc[bb] = fmaf(r.y, x[bb].y, acc[bb]);
-          acc[bb] = fmaf(r.z, x[bb].z, acc[bb]);
-          acc[bb] = fmaf(r.w, x[bb].w, acc[bb]);
-        } else {
-          acc[bb] = fmaf(r, x[bb], acc[bb]);
+      for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+        for (int bb = 0; bb < BT; ++bb) {
+          if constexpr (VEC == 4) {
+            acc[rr][bb] = fmaf(r[rr].x, x[bb].x, acc[rr][bb]);
+            acc[rr][bb] = fmaf(r[rr].y, x[bb].y, acc[rr][bb]);
+            acc[rr][bb] = fmaf(r[rr].z, x[bb].z, acc[rr][bb]);
+            acc[rr][bb] = fmaf(r[rr].w, x[bb].w, acc[rr][bb]);
+          } else {
+            acc[rr][bb] = fmaf(r[rr], x[bb], acc[rr][bb]);
+          }
         }
-      }
     }
   }
 #pragma unroll
-  for (int bb = 0; bb < BT; ++bb) {
+  for (int rr = 0; rr < RW; ++rr)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc[bb] += __shfl_xor(acc[bb], off);
-  }
+    for (int bb = 0; bb < BT; ++bb) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[rr][bb] += __shfl_xor(acc[rr][bb], off);
+    }
   if (lane == 0) {
 #pragma unroll
-    for (int bb = 0; bb < BT; ++bb) part[wave][bb] = acc[bb];
+    for (int rr = 0; rr < RW; ++rr)
+#pragma unroll
+      for (int bb = 0; bb < BT; ++bb) part[wave][rr * BT + bb] = acc[rr][bb];
   }
   __syncthreads();
-  if (slice == 0 && lane < nb && i < M) {
-    float tot = 0.f;
-    for (int w = 0; w < wpr; ++w) tot += part[wave + w][lane];
-    float* mm = m + (size_t)(b0 + lane) * M + i;
-    *mm = beta != 0.f ? fmaf(alpha, tot, beta * *mm) : alpha * tot;
+  if (slice == 0 && lane < nb * RW) {
+    const int rr = lane / nb, bl = lane - rr * nb;
+    const int i = i0 + rr;
+    if (i < M) {
+      float tot = 0.f;
+      for (int w = 0; w < wpr; ++w) tot += part[wave + w][rr * BT + bl];
+      float* mm = m + (size_t)(b0 + bl) * M + i;
+      *mm = beta != 0.f ? fmaf(alpha, tot, beta * *mm) : alpha * tot;
+    }
   }
 }
 
@@ -640,18 +652,18 @@ hipError_t launch_fill(float* p, size_t n, float v, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int BT>
+template <int BT, int RW>
 static void launch_recon_bt(const float* R, int M, int ns, const float* s, int B, float alpha, float beta,
                             float* m, hipStream_t st) {
   const bool vec = (ns % 4 == 0) && ((uintptr_t)R % 16 == 0) && ((uintptr_t)s % 16 == 0);
   const int nv = vec ? ns / 4 : ns;
   const int wpr = nv >= 384 ? 4 : (nv >= 192 ? 2 : 1);
-  const int rpb = 4 / wpr;
+  const int rpb = RW * (4 / wpr);
   dim3 grid((M + rpb - 1) / rpb, (B + BT - 1) / BT);
   if (vec)
-    hipLaunchKernelGGL((recon_kernel<BT, 4>), grid, dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m, wpr);
+    hipLaunchKernelGGL((recon_kernel<BT, 4, RW>), grid, dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m, wpr);
   else
-    hipLaunchKernelGGL((recon_kernel<BT, 1>), grid, dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m, wpr);
+    hipLaunchKernelGGL((recon_kernel<BT, 1, RW>), grid, dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m, wpr);
 }
 
 hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, float alpha,
@@ -662,13 +674,13 @@ hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, fl
     return hipGetLastError();
   }
   if (B <= 1)
-    launch_recon_bt<1>(R, M, ns, s, B, alpha, beta, m, st);
+    launch_recon_bt<1, 1>(R, M, ns, s, B, alpha, beta, m, st);
   else if (B <= 4)
-    launch_recon_bt<4>(R, M, ns, s, B, alpha, beta, m, st);
+    launch_recon_bt<4, 1>(R, M, ns, s, B, alpha, beta, m, st);
   else if (B <= 8)
-    launch_recon_bt<8>(R, M, ns, s, B, alpha, beta, m, st);
+    launch_recon_bt<8, 2>(R, M, ns, s, B, alpha, beta, m, st);
   else
-    launch_recon_bt<16>(R, M, ns, s, B, alpha, beta, m, st);
+    launch_recon_bt<16, 2>(R, M, ns, s, B, alpha, beta, m, st);
   return hipGetLastError();
 }
 
