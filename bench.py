@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--no-cnn", action="store_true", help="skip training and evaluating the learned reconstructor")
     ap.add_argument("--cnn-frames", type=int, default=200000)
     ap.add_argument("--cnn-epochs", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default work split")
     ap.add_argument("--random-R", action="store_true",
                     help="profiling runs: skip calibration, use a random reconstructor of the same shape")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -119,7 +120,7 @@ def main():
 
     import torch
     import paper_1607_07624_amd as pw
-    from paper_1607_07624_amd.loop import calibrate, ClosedLoop, residual_rms_nm
+    from paper_1607_07624_amd.loop import calibrate, ClosedLoop, BatchedLoop, residual_rms_nm
     from synth.configs import CFG2, ATMO2, CFG4_R0_RANGE, N_KL_MODES, PUSH_PULL_NM, LOOP_GAIN, \
         LOOP_DELAY, LOOP_SETTLE_STEPS
     from synth.screens import open_loop_batch, frozen_flow_sequence
@@ -164,6 +165,14 @@ def main():
     def step():
         plan.measure_into(opd, None, s_buf)
         pw.recon_apply(R, s_buf, 1.0, 0.0, modes_out)
+
+    # Work split chosen by the library's autotuner (set-up, outside the timed region).
+    schedule = {"B": B, "a_chunk": None, "k_chunk": None, "autotuned": False}
+    schedule["a_chunk"], schedule["k_chunk"] = plan.get_schedule(B)
+    if not args.no_autotune:
+        schedule = plan.autotune(B, reps=5)
+        schedule["autotuned"] = True
+        log(f"autotune {schedule}")
 
     for _ in range(args.warmup):
         step()
@@ -255,6 +264,27 @@ def main():
                 "steps_per_s": round(T / (loop_ms / 1e3), 1), "gain": LOOP_GAIN, "delay": LOOP_DELAY,
                 "reconstructor": "linear (KL 600, push-pull IM, full-SVD pinv)"}
         log(f"loop {loop}")
+        # Monte-Carlo realisations advanced as one batch (one measure of B frames per step).
+        nr = B
+        seqs = np.stack([frozen_flow_sequence(cfg, ATMO2, T, seed=3000 + i, screen_n=1024) for i in range(nr)],
+                        axis=1)
+        seqs = torch.from_numpy(seqs).to(dev)
+        bl = BatchedLoop(plan, modes_dev, R, LOOP_GAIN, LOOP_DELAY)
+        torch.cuda.synchronize()
+        ev0.record()
+        resb, _ = bl.run(seqs)
+        ev1.record()
+        torch.cuda.synchronize()
+        bl_ms = ev0.elapsed_time(ev1)
+        resb = resb.cpu().numpy()
+        per_real = [float(np.sqrt(np.mean(residual_rms_nm(resb[:, i], amp)[LOOP_SETTLE_STEPS:] ** 2)))
+                    for i in range(nr)]
+        del seqs, resb
+        loop["batched"] = {"realisations": nr, "steps": T,
+                           "realisation_steps_per_s": round(nr * T / (bl_ms / 1e3), 1),
+                           "residual_nm_rms_mean": round(float(np.mean(per_real)), 2),
+                           "residual_nm_rms_std": round(float(np.std(per_real)), 2)}
+        log(f"batched loops {loop['batched']}")
 
     # Learned reconstructor: trained on GPU-generated frames with the project's
     # kernels, compared with the linear one (held-out open-loop error, closed loop).
@@ -336,6 +366,7 @@ def main():
         "loop": loop,
         "learned": learned,
         "kernels": extra,
+        "schedule": schedule,
     }
     print(json.dumps(out), flush=True)
 

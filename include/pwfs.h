@@ -130,6 +130,34 @@ int pwfs_timing_enable(pwfs_plan_t plan, int enable);
 int pwfs_timing_read(pwfs_plan_t plan, double* ms_row, double* ms_col, double* ms_slopes,
                      int64_t* n_slices);
 
+/* Work split ("schedule") that pwfs_measure uses for a slice of B frames
+ * (1 <= B <= batch_max; a call with more frames than batch_max runs in
+ * slices of batch_max and a last, smaller slice): a_chunk distinct x tilts per
+ * row-pass block and k_chunk modulation points per column-pass block.  The
+ * modulation sum of the pyramid intensity (mean over the K points, Sec. 4,
+ * Tab. 1 "pyramid") is accumulated per chunk and the chunks are added in
+ * order, so a schedule changes only the FP32 summation order: results agree
+ * to rounding and are bitwise reproducible for a fixed schedule.
+ * pwfs_get_schedule returns the schedule in force (the library's default
+ * unless one was set or tuned for this B).  pwfs_set_schedule fixes one;
+ * a_chunk = k_chunk = 0 restores the default; PWFS_ERR_INVALID_ARG when
+ * a_chunk is outside [1, number of distinct x tilts], k_chunk outside
+ * [1, n_mod], or the chunk partials would not fit the plan's workspace. */
+int pwfs_get_schedule(pwfs_plan_t plan, int32_t B, int32_t* a_chunk, int32_t* k_chunk);
+int pwfs_set_schedule(pwfs_plan_t plan, int32_t B, int32_t a_chunk, int32_t k_chunk);
+
+/* Autotuner: times the row pass for every distinct number of x-tilt chunks
+ * and then the column pass (with the chunk reduction and the slopes) for
+ * every distinct number of modulation chunks that fits the workspace, on B
+ * flat frames, best of `reps` launches each (1..1000), and keeps the
+ * fastest schedule for slices of B frames (a candidate must beat the best
+ * so far by 2 %).  It allocates and frees a temporary input and output of
+ * B frames and waits for `stream`: a set-up call, not for the hot path.
+ * ms_default / ms_tuned (may be NULL) receive the measured time of one
+ * B-frame call with the default and with the chosen schedule. */
+int pwfs_autotune(pwfs_plan_t plan, int32_t B, int32_t reps, void* stream, double* ms_default,
+                  double* ms_tuned);
+
 /* Modal reconstruction and integration, m = alpha * R s + beta * m for each
  * of B vectors (an integrator step is alpha = gain, beta = 1; the DM
  * projection opd -= B_KL u is alpha = -1, beta = 1 with R = B_KL).

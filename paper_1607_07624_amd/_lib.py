@@ -56,6 +56,10 @@ def load_library():
     lib.pwfs_timing_enable.argtypes = [vp, ctypes.c_int]
     lib.pwfs_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.pwfs_get_schedule.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.pwfs_set_schedule.argtypes = [vp, i32, i32, i32]
+    lib.pwfs_autotune.argtypes = [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
     lib.pwfs_destroy.argtypes = [vp]
     lib.pwfs_destroy.restype = None
     lib.pwfs_strerror.argtypes = [ctypes.c_int]
@@ -64,7 +68,8 @@ def load_library():
     lib.pwfs_last_error.restype = ctypes.c_char_p
     for name in ("pwfs_plan", "pwfs_plan_info", "pwfs_get_valid", "pwfs_get_reference",
                  "pwfs_set_reference", "pwfs_measure", "recon_apply", "pwfs_get_pupil",
-                 "pwfs_timing_enable", "pwfs_timing_read"):
+                 "pwfs_timing_enable", "pwfs_timing_read", "pwfs_get_schedule", "pwfs_set_schedule",
+                 "pwfs_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -153,6 +158,24 @@ class Plan:
         _check(self.lib.pwfs_timing_read(self.handle, ctypes.byref(r), ctypes.byref(c), ctypes.byref(s),
                                          ctypes.byref(n)), "pwfs_timing_read")
         return {"row_ms": r.value, "col_ms": c.value, "slopes_ms": s.value, "slices": n.value}
+
+    def get_schedule(self, B: int) -> tuple:
+        """(a_chunk, k_chunk) pwfs_measure uses for slices of B frames."""
+        a, k = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.pwfs_get_schedule(self.handle, int(B), ctypes.byref(a), ctypes.byref(k)), "pwfs_get_schedule")
+        return a.value, k.value
+
+    def set_schedule(self, B: int, a_chunk: int, k_chunk: int):
+        """Fix the schedule for slices of B frames ((0, 0): back to the default)."""
+        _check(self.lib.pwfs_set_schedule(self.handle, int(B), int(a_chunk), int(k_chunk)), "pwfs_set_schedule")
+
+    def autotune(self, B: int, reps: int = 5) -> dict:
+        """Run the library's autotuner for slices of B frames (waits for the stream)."""
+        d0, d1 = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.pwfs_autotune(self.handle, int(B), int(reps), _stream_handle(self._torch, self.device),
+                                       ctypes.byref(d0), ctypes.byref(d1)), "pwfs_autotune")
+        a, k = self.get_schedule(B)
+        return {"B": int(B), "a_chunk": a, "k_chunk": k, "ms_default": d0.value, "ms_tuned": d1.value}
 
     def set_reference(self, sref=None):
         t = self._torch

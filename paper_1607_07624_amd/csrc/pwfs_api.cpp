@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -99,6 +100,8 @@ struct pwfs_plan_s {
   float* zero_opd = nullptr;
   float* tmp_slopes = nullptr;
   size_t ws_bytes = 0;
+  size_t partial_cap = 0;                       // floats in `partial`
+  std::map<int, std::array<int, 2>> sched;      // slice size -> {a_chunk, k_chunk}
   std::vector<float> amp_host;
   // per-kernel timing
   bool timing = false;
@@ -107,17 +110,36 @@ struct pwfs_plan_s {
 
 namespace {
 
-void split_work(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk, int* n_chunks) {
-  const long target = 2048;  // waves per pass: several per SIMD of the 256-CU chip
+// Default work split for a slice of B frames: enough waves per pass to keep
+// several in flight on every SIMD of the 256-CU chip.
+void default_split(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk) {
+  const long target = 2048;
   const long row_waves = (long)(p->P / 8) * p->n_a * B;
   int ac = (int)std::max<long>(1, row_waves / target);
   *a_chunk = std::min(ac, p->n_a);
   const long col_tiles = (long)(2 * p->P / 8) * B;
   long nc = (target + col_tiles - 1) / col_tiles;
   nc = std::max<long>(1, std::min<long>(nc, p->K));
-  int kc = (int)((p->K + nc - 1) / nc);
-  *k_chunk = kc;
-  *n_chunks = (p->K + kc - 1) / kc;
+  *k_chunk = (int)((p->K + nc - 1) / nc);
+}
+
+// Split used by pwfs_measure: a schedule set for this slice size, else the default.
+void split_work(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk, int* n_chunks) {
+  auto it = p->sched.find(B);
+  if (it != p->sched.end()) {
+    *a_chunk = it->second[0];
+    *k_chunk = it->second[1];
+  } else {
+    default_split(p, B, a_chunk, k_chunk);
+  }
+  *n_chunks = (p->K + *k_chunk - 1) / *k_chunk;
+}
+
+// A schedule is usable when its chunk partials fit the plan's workspace.
+bool schedule_fits(const pwfs_plan_s* p, int B, int a_chunk, int k_chunk) {
+  if (B < 1 || B > p->batch_max || a_chunk < 1 || a_chunk > p->n_a || k_chunk < 1 || k_chunk > p->K) return false;
+  const size_t nc = (size_t)((p->K + k_chunk - 1) / k_chunk);
+  return (size_t)B * nc * 4 * p->S * p->S <= p->partial_cap;
 }
 
 int validate(const pwfs_config_t* c) {
@@ -157,38 +179,44 @@ void free_plan(pwfs_plan_s* p) {
   delete p;
 }
 
+pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int Bs, float* pupils, float* slopes,
+                             const float* sref) {
+  pwfs::MeasureArgs a{};
+  a.P = p->P;
+  a.n_bin = p->b;
+  a.K = p->K;
+  a.n_a = p->n_a;
+  a.nv = p->nv;
+  a.norm_mode = p->cfg.norm_mode;
+  a.B = Bs;
+  split_work(p, Bs, &a.a_chunk, &a.k_chunk, &a.n_chunks);
+  a.kphase = p->kphase;
+  a.fp32_phase = (p->cfg.flags & 2) != 0;
+  a.opd = opd + (size_t)b0 * p->P * p->P;
+  a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : p->pupils;
+  a.slopes = slopes ? slopes + (size_t)b0 * 2 * p->nv : nullptr;
+  a.amp = p->amp;
+  a.in_a = p->in_a;
+  a.f_a = p->f_a;
+  a.in_b = p->in_b;
+  a.f_b = p->f_b;
+  a.mid = p->mid;
+  a.outw = p->outw;
+  a.k_order = p->k_order;
+  a.k_ia = p->k_ia;
+  a.valid = p->d_valid;
+  a.sref = sref;
+  a.Rw = p->Rw;
+  a.field = p->field;
+  a.partial = p->partial;
+  return a;
+}
+
 int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* slopes,
                 const float* sref, hipStream_t st) {
   for (int b0 = 0; b0 < B; b0 += p->batch_max) {
     const int Bs = std::min(p->batch_max, B - b0);
-    pwfs::MeasureArgs a{};
-    a.P = p->P;
-    a.n_bin = p->b;
-    a.K = p->K;
-    a.n_a = p->n_a;
-    a.nv = p->nv;
-    a.norm_mode = p->cfg.norm_mode;
-    a.B = Bs;
-    split_work(p, Bs, &a.a_chunk, &a.k_chunk, &a.n_chunks);
-    a.kphase = p->kphase;
-    a.fp32_phase = (p->cfg.flags & 2) != 0;
-    a.opd = opd + (size_t)b0 * p->P * p->P;
-    a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : p->pupils;
-    a.slopes = slopes ? slopes + (size_t)b0 * 2 * p->nv : nullptr;
-    a.amp = p->amp;
-    a.in_a = p->in_a;
-    a.f_a = p->f_a;
-    a.in_b = p->in_b;
-    a.f_b = p->f_b;
-    a.mid = p->mid;
-    a.outw = p->outw;
-    a.k_order = p->k_order;
-    a.k_ia = p->k_ia;
-    a.valid = p->d_valid;
-    a.sref = sref;
-    a.Rw = p->Rw;
-    a.field = p->field;
-    a.partial = p->partial;
+    pwfs::MeasureArgs a = slice_args(p, opd, b0, Bs, pupils, slopes, sref);
     hipEvent_t* ev = nullptr;
     if (p->timing) {
       std::array<hipEvent_t, 4> evs{};
@@ -382,11 +410,15 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   // Device buffers.
   int bm = cfg->batch_max;
   int ac, kc, nc;
+  // Chunk partials for any schedule (up to K chunks per frame): K 4 S^2
+  // floats per frame, an eighth of the row-pass workspace per frame.
   size_t partial_elems = 0;
   for (int B = 1; B <= bm; ++B) {
     split_work(p, B, &ac, &kc, &nc);
     partial_elems = std::max(partial_elems, (size_t)B * nc * 4 * S * S);
   }
+  partial_elems = std::max(partial_elems, (size_t)bm * K * 4 * S * S);
+  p->partial_cap = partial_elems;
   const size_t rw_elems = (size_t)bm * p->n_a * 2 * P * P;
   struct A { void** ptr; size_t bytes; const char* what; } allocs[] = {
       {(void**)&p->amp, amp.size() * sizeof(float), "amp"},
@@ -487,6 +519,116 @@ int pwfs_timing_read(pwfs_plan_t p, double* ms_row, double* ms_col, double* ms_s
   if (ms_col) *ms_col = acc[1];
   if (ms_slopes) *ms_slopes = acc[2];
   if (n_slices) *n_slices = (int64_t)p->ev_used.size();
+  return PWFS_OK;
+}
+
+int pwfs_get_schedule(pwfs_plan_t p, int32_t B, int32_t* a_chunk, int32_t* k_chunk) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (B < 1 || B > p->batch_max) return fail(PWFS_ERR_INVALID_ARG, "B outside [1, batch_max]");
+  int a, k, nc;
+  split_work(p, B, &a, &k, &nc);
+  if (a_chunk) *a_chunk = a;
+  if (k_chunk) *k_chunk = k;
+  return PWFS_OK;
+}
+
+int pwfs_set_schedule(pwfs_plan_t p, int32_t B, int32_t a_chunk, int32_t k_chunk) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (B < 1 || B > p->batch_max) return fail(PWFS_ERR_INVALID_ARG, "B outside [1, batch_max]");
+  if (a_chunk == 0 && k_chunk == 0) {
+    p->sched.erase(B);
+    return PWFS_OK;
+  }
+  if (!schedule_fits(p, B, a_chunk, k_chunk))
+    return fail(PWFS_ERR_INVALID_ARG, "schedule out of range or its partials exceed the plan workspace");
+  p->sched[B] = {a_chunk, k_chunk};
+  return PWFS_OK;
+}
+
+int pwfs_autotune(pwfs_plan_t p, int32_t B, int32_t reps, void* stream, double* ms_default, double* ms_tuned) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (B < 1 || B > p->batch_max) return fail(PWFS_ERR_INVALID_ARG, "B outside [1, batch_max]");
+  if (reps < 1 || reps > 1000) return fail(PWFS_ERR_INVALID_ARG, "reps outside [1, 1000]");
+  DeviceGuard g(p->device);
+  hipStream_t st = (hipStream_t)stream;
+  float* d_opd = nullptr;
+  float* d_sl = nullptr;
+  std::array<hipEvent_t, 4> ev{};
+  int status = PWFS_OK;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+    if (d_opd) (void)hipFree(d_opd);
+    if (d_sl) (void)hipFree(d_sl);
+  };
+  int st_alloc = dev_alloc((void**)&d_opd, (size_t)B * p->P * p->P * sizeof(float), "autotune input");
+  if (st_alloc == PWFS_OK) st_alloc = dev_alloc((void**)&d_sl, (size_t)B * 2 * p->nv * sizeof(float), "autotune slopes");
+  if (st_alloc != PWFS_OK) {
+    cleanup();
+    return st_alloc;
+  }
+  hipError_t e = hipMemsetAsync(d_opd, 0, (size_t)B * p->P * p->P * sizeof(float), st);
+  for (auto& x : ev)
+    if (e == hipSuccess) e = hipEventCreate(&x);
+  if (e != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "autotune setup");
+  }
+  // Best of `reps` timed launches (after one untimed launch) of a schedule:
+  // row pass (with the field) and column pass + chunk reduction + slopes.
+  auto time_schedule = [&](int a_chunk, int k_chunk, double* row_ms, double* col_ms) -> hipError_t {
+    pwfs::MeasureArgs a = slice_args(p, d_opd, 0, B, nullptr, d_sl, p->sref);
+    a.a_chunk = a_chunk;
+    a.k_chunk = k_chunk;
+    a.n_chunks = (p->K + k_chunk - 1) / k_chunk;
+    hipError_t le = pwfs::launch_measure(a, st, nullptr);
+    *row_ms = *col_ms = 1e30;
+    for (int r = 0; r < reps && le == hipSuccess; ++r) {
+      le = pwfs::launch_measure(a, st, ev.data());
+      if (le == hipSuccess) le = hipEventSynchronize(ev[3]);
+      float t0 = 0.f, t1 = 0.f;
+      if (le == hipSuccess) le = hipEventElapsedTime(&t0, ev[0], ev[1]);
+      if (le == hipSuccess) le = hipEventElapsedTime(&t1, ev[1], ev[3]);
+      *row_ms = std::min(*row_ms, (double)t0);
+      *col_ms = std::min(*col_ms, (double)t1);
+    }
+    return le;
+  };
+  int a0, k0;
+  default_split(p, B, &a0, &k0);
+  double row0, col0;
+  e = time_schedule(a0, k0, &row0, &col0);
+  int best_a = a0, best_k = k0;
+  double best_row = row0, best_col = col0;
+  // Row pass: one candidate per distinct number of x-tilt chunks.
+  for (int a = 1; a <= p->n_a && e == hipSuccess; ++a) {
+    if (a > 1 && (p->n_a + a - 1) / a == (p->n_a + a - 2) / (a - 1)) continue;
+    if (a == a0 || !schedule_fits(p, B, a, k0)) continue;
+    double r, c;
+    e = time_schedule(a, k0, &r, &c);
+    if (e == hipSuccess && r < 0.98 * best_row) {
+      best_row = r;
+      best_a = a;
+    }
+  }
+  // Column pass: one candidate per distinct number of modulation chunks.
+  for (int k = 1; k <= p->K && e == hipSuccess; ++k) {
+    if (k > 1 && (p->K + k - 1) / k == (p->K + k - 2) / (k - 1)) continue;
+    if (k == k0 || !schedule_fits(p, B, best_a, k)) continue;
+    double r, c;
+    e = time_schedule(best_a, k, &r, &c);
+    if (e == hipSuccess && c < 0.98 * best_col) {
+      best_col = c;
+      best_k = k;
+    }
+  }
+  if (e != hipSuccess) status = hip_fail(e, "autotune launch");
+  cleanup();
+  if (status != PWFS_OK) return status;
+  p->sched[B] = {best_a, best_k};
+  if (ms_default) *ms_default = row0 + col0;
+  if (ms_tuned) *ms_tuned = best_row + best_col;
   return PWFS_OK;
 }
 

@@ -176,6 +176,47 @@ class ClosedLoop:
         return res, hist[d:]
 
 
+class BatchedLoop:
+    """B independent integrator loops (Monte-Carlo realisations: different
+    screens, same sensor, reconstructor and controller) advanced together,
+    so each step is one pwfs_measure of B frames, one recon_apply over B
+    slope vectors and one batched DM product:
+        u_b(t) = c_b(t - delay),  r_b(t) = opd_b(t) - B u_b(t)
+        c_b(t) = c_b(t-1) + g R s(r_b(t))
+    Each realisation follows exactly the equations of ClosedLoop; only the
+    batching (and with it the plan's work split, i.e. the FP32 summation
+    order of the modulation sum) differs.  B <= plan.batch_max."""
+
+    def __init__(self, plan, modes_dev, R_dev, gain: float, delay: int):
+        import torch
+        self.plan, self.R, self.gain, self.delay = plan, R_dev, float(gain), int(delay)
+        M, P, _ = modes_dev.shape
+        self.M, self.P = M, P
+        self.BKL = modes_dev.reshape(M, P * P).t().contiguous()     # [P*P, M]
+
+    def run(self, opd_seq_dev, residuals_dev=None):
+        """opd_seq_dev [T, B, P, P]; returns (residual OPD [T, B, P*P], commands [T, B, M])."""
+        import torch
+        T, B = opd_seq_dev.shape[0], opd_seq_dev.shape[1]
+        if B > self.plan.batch_max:
+            raise ValueError(f"{B} realisations exceed the plan's batch_max {self.plan.batch_max}")
+        P, M, d = self.P, self.M, self.delay
+        dev = opd_seq_dev.device
+        res = residuals_dev if residuals_dev is not None else torch.empty((T, B, P * P), device=dev)
+        hist = torch.zeros((T + d, B, M), device=dev)                # c(t) is row t + d
+        s = torch.empty((B, 2 * self.plan.n_valid), device=dev)
+        for t in range(T):
+            r_t = res[t]
+            r_t.copy_(opd_seq_dev[t].reshape(B, -1))
+            recon_apply(self.BKL, hist[t], -1.0, 1.0, r_t)
+            c_next = hist[t + d]
+            if t > 0:
+                c_next.copy_(hist[t + d - 1])
+            self.plan.measure_into(r_t.view(B, P, P), None, s)
+            recon_apply(self.R, s, self.gain, 1.0, c_next)
+        return res, hist[d:]
+
+
 def residual_rms_nm(res_host: np.ndarray, pupil: np.ndarray) -> np.ndarray:
     """Piston-removed RMS over the pupil of each residual frame [T, P*P] (FP64)."""
     v = res_host.reshape(res_host.shape[0], -1)[:, pupil.ravel() > 0].astype(np.float64)

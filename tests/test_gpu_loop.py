@@ -93,3 +93,35 @@ def test_closed_loop_matches_oracle_cfg1():
     assert tot_o < 0.5 * tot_ol                   # the loop closes
     assert worst <= 1e-3
     assert abs(tot_g - tot_o) <= 1e-4 * tot_o
+
+
+def test_batched_loops_match_oracle_cfg1():
+    """Three Monte-Carlo realisations advanced as one batch: each follows the
+    oracle's single closed loop on its own sequence to the tolerances above."""
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd.loop import calibrate, BatchedLoop, residual_rms_nm
+    torch = torch_cuda()
+    T, seeds = 150, (11, 12, 13)
+    modes, A = _modes(CFG1, 25.0, 60)
+    atmo = AtmoConfig(r0_m=0.5, L0_m=25.0, wind_m_s=15.0)
+    seqs = np.stack([frozen_flow_sequence(CFG1, atmo, T, seed=sd, screen_n=256) for sd in seeds], axis=1)
+    plan_cal = pw.Plan(CFG1, batch_max=16)
+    R_g, _, _ = calibrate(plan_cal, modes, PUSH_PULL_NM)
+    plan = pw.Plan(CFG1, batch_max=4)
+    bl = BatchedLoop(plan, torch.from_numpy(modes).cuda(), R_g, LOOP_GAIN, LOOP_DELAY)
+    res, _ = bl.run(torch.from_numpy(np.ascontiguousarray(seqs)).cuda())
+    res = res.cpu().numpy()
+    orc = oracle.Oracle(CFG1)
+    meas = lambda r: orc.measure(r)[1]
+    IM_o = orecon.interaction_matrix(meas, modes.astype(np.float64), PUSH_PULL_NM)
+    R_o, _ = orecon.pseudo_inverse(IM_o)
+    for b, sd in enumerate(seeds):
+        rms_g = residual_rms_nm(res[:, b], A)
+        rms_o, _ = orecon.closed_loop(meas, seqs[:, b], modes.astype(np.float64), R_o, LOOP_GAIN, LOOP_DELAY, A)
+        tot_g = orecon.loop_residual_nm(rms_g, LOOP_SETTLE_STEPS)
+        tot_o = orecon.loop_residual_nm(rms_o, LOOP_SETTLE_STEPS)
+        worst = float(np.max(np.abs(rms_g - rms_o) / rms_o))
+        say(f"[gpu] batched loop cfg1 seed {sd}: residual {tot_g:.4f} nm (oracle {tot_o:.4f} nm), "
+            f"worst per-step rel diff {worst:.3e}")
+        assert worst <= 1e-3
+        assert abs(tot_g - tot_o) <= 1e-4 * tot_o

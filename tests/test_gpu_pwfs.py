@@ -136,3 +136,59 @@ def test_bitwise_reproducible_and_empty_batch():
     plan.measure_into(d, pupils, None)
     torch.cuda.synchronize()
     assert torch.equal(pupils, p1)
+
+
+def _slopes_with(plan, d):
+    torch = torch_cuda()
+    _, s = plan.measure(d, want_pupils=False)
+    torch.cuda.synchronize()
+    return s.cpu().numpy()
+
+
+def test_schedules_change_only_rounding_cfg2():
+    """Work splits (x-tilt chunks of the row pass, modulation chunks of the
+    column pass) reorder only the FP32 modulation sum: every schedule,
+    including the extremes and the autotuned one, meets the oracle gate, and
+    a fixed schedule is bitwise reproducible."""
+    import paper_1607_07624_amd as pw
+    torch = torch_cuda()
+    B = 4
+    opd, _ = open_loop_batch(CFG2, ATMO2, [40, 41, 42, 43], r0_range=CFG4_R0_RANGE)
+    plan = pw.Plan(CFG2, batch_max=B)
+    orc = orc_for(CFG2)
+    s_o = [orc.measure(opd[i].astype(np.float64))[1] for i in range(B)]
+    d = torch.from_numpy(np.ascontiguousarray(opd)).cuda()
+    n_a = CFG2.n_mod // 2 + 1
+    default = plan.get_schedule(B)
+    tuned = plan.autotune(B, reps=3)
+    say(f"[gpu] cfg2 B={B}: default schedule {default}, autotuned {tuned}")
+    cases = [("autotuned", None), ("one chunk each", (n_a, CFG2.n_mod)), ("finest", (1, 1)),
+             ("odd chunks", (3, 7))]
+    for name, sch in cases:
+        if sch is not None:
+            plan.set_schedule(B, *sch)
+        assert plan.get_schedule(B) == (sch if sch is not None else (tuned["a_chunk"], tuned["k_chunk"]))
+        s1 = _slopes_with(plan, d)
+        s2 = _slopes_with(plan, d)
+        assert np.array_equal(s1, s2)
+        worst = max(rel_l2(s1[i], s_o[i]) for i in range(B))
+        say(f"[gpu]   schedule {name} {plan.get_schedule(B)}: worst slope rel err {worst:.3e}")
+        assert worst <= SLOPE_TOL
+    plan.set_schedule(B, 0, 0)
+    assert plan.get_schedule(B) == default
+    plan.close()
+
+
+def test_schedule_outside_workspace_is_rejected():
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd._lib import PwfsError
+    torch_cuda()
+    plan = pw.Plan(CFG2, batch_max=16)
+    a, k = plan.get_schedule(16)
+    for bad in ((0, k), (a, 0), (CFG2.n_mod // 2 + 2, k), (a, CFG2.n_mod + 1), (-1, k)):
+        with pytest.raises(PwfsError):
+            plan.set_schedule(16, *bad)
+    with pytest.raises(PwfsError):
+        plan.set_schedule(17, a, k)
+    assert plan.get_schedule(16) == (a, k)
+    plan.close()
