@@ -34,23 +34,27 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per 16-frame column-pass launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # recorded in profiles/pwfs_measure_n640_p160_k48_b16.md (scaled by the copy-kernel factors
-# 2.0 / 1.0).  Valid only for the kernel sources with these hashes; reported as null otherwise.
+# 2.0 / 1.0).  Valid only for the kernel sources with these hashes and this work split
+# (x-tilt chunk, modulation chunk); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "601bcb422aa1e8070c14e546c0bc9eec271e1879",
+    "sources_sha1": {"pwfs_kernels.hip": "fd424b0c2156503d3ce68be4b01982d9bf5dc507",
                      "pwfs_dft.h": "b9f0efe9263005de788f876c2146edfa2d2b9d54"},
     "batch": 16,
-    "col_pass_bytes": (90593.0 * 2.0 + 1600.0 * 1.0) * 1024,
+    "schedule": (3, 6),
+    "col_pass_bytes": (104278.9 * 2.0 + 3200.0 * 1.0) * 1024,
 }
 
 
-def counter_traffic(batch):
+def counter_traffic(batch, schedule):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1607_07624_amd", "csrc")
     for name, h in COUNTER_TRAFFIC["sources_sha1"].items():
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha1(f.read()).hexdigest() != h:
                 return None
-    return COUNTER_TRAFFIC["col_pass_bytes"] if batch == COUNTER_TRAFFIC["batch"] else None
+    if batch != COUNTER_TRAFFIC["batch"] or tuple(schedule) != COUNTER_TRAFFIC["schedule"]:
+        return None
+    return COUNTER_TRAFFIC["col_pass_bytes"]
 
 
 def log(*a):
@@ -107,6 +111,8 @@ def main():
     ap.add_argument("--cnn-frames", type=int, default=200000)
     ap.add_argument("--cnn-epochs", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default work split")
+    ap.add_argument("--schedule", type=str, default=None,
+                    help="A,K: fix the work split (x-tilt chunk, modulation chunk) instead of autotuning")
     ap.add_argument("--random-R", action="store_true",
                     help="profiling runs: skip calibration, use a random reconstructor of the same shape")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -169,7 +175,11 @@ def main():
     # Work split chosen by the library's autotuner (set-up, outside the timed region).
     schedule = {"B": B, "a_chunk": None, "k_chunk": None, "autotuned": False}
     schedule["a_chunk"], schedule["k_chunk"] = plan.get_schedule(B)
-    if not args.no_autotune:
+    if args.schedule:
+        a_k = [int(v) for v in args.schedule.split(",")]
+        plan.set_schedule(B, a_k[0], a_k[1])
+        schedule["a_chunk"], schedule["k_chunk"] = plan.get_schedule(B)
+    elif not args.no_autotune:
         schedule = plan.autotune(B, reps=5)
         schedule["autotuned"] = True
         log(f"autotune {schedule}")
@@ -214,11 +224,12 @@ def main():
     fl_row = lines_row * line_flops(P, False)
     achieved = fl_col / (col_ms * 1e-3) / 1e12
     conv = lines_col * 2 * 5 * cfg.n_fft * np.log2(cfg.n_fft)     # 5 N log2 N convention, N = 640
+    traffic = counter_traffic(B, (schedule["a_chunk"], schedule["k_chunk"]))
     roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": counter_traffic(B), "traffic_unit": "bytes per launch (rocprofv3 counters)",
-                "hbm_frac_of_peak": (round(counter_traffic(B) / (col_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
-                                     if counter_traffic(B) else None),
+                "traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 counters)",
+                "hbm_frac_of_peak": (round(traffic / (col_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+                                     if traffic else None),
                 "kernel": "col_pass_kernel<40>", "kernel_ms": round(col_ms, 4),
                 "flop_per_launch": int(fl_col),
                 "convention_5NlogN_tflops": round(conv / (col_ms * 1e-3) / 1e12, 2)}
