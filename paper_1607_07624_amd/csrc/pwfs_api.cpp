@@ -26,6 +26,9 @@ using pwfs::cpx;
 
 namespace {
 
+// P = 128 and 480 use the 32-lane line teams (P / 16 samples per lane).
+bool long_lines(int P) { return P == 128 || P == 480; }
+
 thread_local std::string g_last_error;
 
 int fail(int status, const std::string& msg) {
@@ -87,6 +90,7 @@ struct pwfs_plan_s {
   cpx* in_b = nullptr;
   cpx* f_b = nullptr;
   cpx* mid = nullptr;
+  cpx* tw16 = nullptr;
   cpx* outw = nullptr;
   int* k_order = nullptr;
   int* k_ia = nullptr;
@@ -111,13 +115,15 @@ struct pwfs_plan_s {
 namespace {
 
 // Default work split for a slice of B frames: enough waves per pass to keep
-// several in flight on every SIMD of the 256-CU chip.
+// several in flight on every SIMD of the 256-CU chip.  A wave holds 8 lines
+// (8-lane teams) or 2 lines (32-lane teams, P = 128 and 480).
 void default_split(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk) {
   const long target = 2048;
-  const long row_waves = (long)(p->P / 8) * p->n_a * B;
+  const long lines_per_wave = long_lines(p->P) ? 2 : 8;
+  const long row_waves = (long)p->P / lines_per_wave * p->n_a * B;
   int ac = (int)std::max<long>(1, row_waves / target);
   *a_chunk = std::min(ac, p->n_a);
-  const long col_tiles = (long)(2 * p->P / 8) * B;
+  const long col_tiles = (long)(2 * p->P) / lines_per_wave * B;   // waves per modulation chunk
   long nc = (target + col_tiles - 1) / col_tiles;
   nc = std::max<long>(1, std::min<long>(nc, p->K));
   *k_chunk = (int)((p->K + nc - 1) / nc);
@@ -157,11 +163,12 @@ int validate(const pwfs_config_t* c) {
   if (c->n_fft != 4 * c->n_pupil) return fail(PWFS_ERR_UNSUPPORTED, "n_fft must equal 4 * n_pupil");
   if (c->face_shift != 0 && c->face_shift != c->n_fft / 4)
     return fail(PWFS_ERR_UNSUPPORTED, "face_shift must be n_fft / 4");
-  const int E = c->n_pupil / 4;
-  if (c->n_pupil % 8 != 0 || !(E == 8 || E == 16 || E == 40))
-    return fail(PWFS_ERR_UNSUPPORTED, "n_pupil must be 32, 64 or 160");
-  if (!(c->n_bin == 1 || c->n_bin == 2 || c->n_bin == 4 || c->n_bin == 8))
-    return fail(PWFS_ERR_UNSUPPORTED, "n_bin must be 1, 2, 4 or 8");
+  const int P = c->n_pupil;
+  if (!(P == 32 || P == 64 || P == 160 || P == 128 || P == 480))
+    return fail(PWFS_ERR_UNSUPPORTED, "n_pupil must be 32, 64, 128, 160 or 480");
+  const bool b_pow2 = c->n_bin == 1 || c->n_bin == 2 || c->n_bin == 4 || c->n_bin == 8;
+  if (!(b_pow2 || (long_lines(P) && c->n_bin == 5 && P % 10 == 0)))
+    return fail(PWFS_ERR_UNSUPPORTED, "n_bin must be 1, 2, 4 or 8 (or 5 with n_pupil 480)");
   if (c->batch_max > 65535) return fail(PWFS_ERR_UNSUPPORTED, "batch_max > 65535");
   return PWFS_OK;
 }
@@ -169,7 +176,7 @@ int validate(const pwfs_config_t* c) {
 void free_plan(pwfs_plan_s* p) {
   if (!p) return;
   DeviceGuard g(p->device);
-  void* ptrs[] = {p->amp, p->in_a, p->f_a, p->in_b, p->f_b, p->mid, p->outw, p->k_order, p->k_ia,
+  void* ptrs[] = {p->amp, p->in_a, p->f_a, p->in_b, p->f_b, p->mid, p->tw16, p->outw, p->k_order, p->k_ia,
                   p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->field, p->zero_opd, p->tmp_slopes};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -201,6 +208,7 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
   a.in_b = p->in_b;
   a.f_b = p->f_b;
   a.mid = p->mid;
+  a.tw16 = p->tw16;
   a.outw = p->outw;
   a.k_order = p->k_order;
   a.k_ia = p->k_ia;
@@ -399,13 +407,35 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
     const double ang = -2.0 * M_PI * (double)n / (double)P;
     return std::complex<double>(std::cos(ang), std::sin(ang));
   };
-  for (int l = 0; l < 4; ++l)
-    for (int k = 0; k < p->E; ++k) {
-      const std::complex<double> A = std::complex<double>(0.5, -0.5) * std::conj(wlk(l, k)) * wlk((l + 1) & 3, k);
-      const std::complex<double> Bc = std::complex<double>(0.5, 0.5) * std::conj(wlk(l, k)) * wlk((l + 3) & 3, k);
-      mid[((size_t)l * p->E + k) * 2] = to32(A);
-      mid[((size_t)l * p->E + k) * 2 + 1] = to32(Bc);
-    }
+  auto mix = [&](int l, int k, cpx* dst) {
+    dst[0] = to32(std::complex<double>(0.5, -0.5) * std::conj(wlk(l, k)) * wlk((l + 1) & 3, k));
+    dst[1] = to32(std::complex<double>(0.5, 0.5) * std::conj(wlk(l, k)) * wlk((l + 3) & 3, k));
+  };
+  const bool lines32 = long_lines(P);
+  const int E16 = P / 16;
+  std::vector<cpx> tw16(lines32 ? 4 * (size_t)E16 : 1);
+  if (!lines32) {
+    for (int l = 0; l < 4; ++l)
+      for (int k = 0; k < p->E; ++k) mix(l, k, &mid[((size_t)l * p->E + k) * 2]);
+  } else {
+    // Lane 4 l1 + l2 of a 16-lane row holds in-lane frequency k1 of outer
+    // lane l1 at t' = k1 + E16 rev(l2) after the subgroup DFT_4; its
+    // twiddle before that DFT is w_{4 E16}^{l2 k1}.
+    const int rev2[4] = {0, 2, 1, 3};
+    for (int l16 = 0; l16 < 16; ++l16)
+      for (int k1 = 0; k1 < E16; ++k1) mix(l16 >> 2, k1 + E16 * rev2[l16 & 3], &mid[((size_t)l16 * E16 + k1) * 2]);
+    for (int l2 = 0; l2 < 4; ++l2)
+      for (int k1 = 0; k1 < E16; ++k1) {
+        const long n = (long)l2 * k1;
+        if (t32) {
+          const float angf = -2.0f * (float)M_PI * (float)n / (float)(4 * E16);
+          tw16[(size_t)l2 * E16 + k1] = cpx{std::cos(angf), std::sin(angf)};
+        } else {
+          const double ang = -2.0 * M_PI * (double)n / (double)(4 * E16);
+          tw16[(size_t)l2 * E16 + k1] = cpx{(float)std::cos(ang), (float)std::sin(ang)};
+        }
+      }
+  }
 
   // Device buffers.
   int bm = cfg->batch_max;
@@ -427,6 +457,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {(void**)&p->in_b, in_b.size() * sizeof(cpx), "in_b"},
       {(void**)&p->f_b, f_b.size() * sizeof(cpx), "f_b"},
       {(void**)&p->mid, mid.size() * sizeof(cpx), "mid"},
+      {(void**)&p->tw16, tw16.size() * sizeof(cpx), "tw16"},
       {(void**)&p->outw, outw.size() * sizeof(cpx), "outw"},
       {(void**)&p->k_order, (size_t)K * sizeof(int), "k_order"},
       {(void**)&p->k_ia, (size_t)K * sizeof(int), "k_ia"},
@@ -454,6 +485,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {p->in_b, in_b.data(), in_b.size() * sizeof(cpx)},
       {p->f_b, f_b.data(), f_b.size() * sizeof(cpx)},
       {p->mid, mid.data(), mid.size() * sizeof(cpx)},
+      {p->tw16, tw16.data(), tw16.size() * sizeof(cpx)},
       {p->outw, outw.data(), outw.size() * sizeof(cpx)},
       {p->k_order, k_order.data(), (size_t)K * sizeof(int)},
       {p->k_ia, k_ia.data(), (size_t)K * sizeof(int)},

@@ -247,4 +247,41 @@ __device__ __forceinline__ float swap_quads(float v) {
   return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
 }
 
+// DPP row rotations inside each 16-lane row: lane i reads lane (i + 4) mod 16
+// (row_ror:12) or lane (i - 4) mod 16 (row_ror:4).
+__device__ __forceinline__ float row_from_plus4(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x12C, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float row_from_minus4(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, true));
+}
+// Lane i reads lane i ^ 16 (partner projection of a 32-lane team), ds_swizzle bit mode.
+__device__ __forceinline__ float swap_halves(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+
+// Radix-2 butterfly between the lanes of a quad paired by the DPP pattern PERM
+// (0x4E: lane ^ 2, 0xB1: lane ^ 1): self + partner on the lane whose pair bit
+// is clear (sgn = +1), partner - self on the other (sgn = -1).
+template <int PERM>
+__device__ __forceinline__ cpx quad_bfly(cpx v, float sgn) {
+  const float pr = quad_perm<PERM>(v.re), pi = quad_perm<PERM>(v.im);
+  return {fmaf(sgn, v.re, pr), fmaf(sgn, v.im, pi)};
+}
+// DFT_4 across the lanes l of a quad, X[k] = sum_l x_l exp(-2 pi i l k / 4),
+// decimation in frequency: lane l receives X[rev(l)], rev = (0, 2, 1, 3).
+// sA = -1 on lanes with bit 1 set, sB = -1 on lanes with bit 0 set, l3: lane 3.
+__device__ __forceinline__ cpx quad_dft4_fwd(cpx v, float sA, float sB, bool l3) {
+  cpx u = quad_bfly<0x4E>(v, sA);
+  u = l3 ? cpx{u.im, -u.re} : u;  // times -i
+  return quad_bfly<0xB1>(u, sB);
+}
+// Inverse, x_l = sum_k X[k] exp(+2 pi i l k / 4) (no 1/4), from lane l holding
+// X[rev(l)] to lane l holding x_l.
+__device__ __forceinline__ cpx quad_dft4_inv(cpx v, float sA, float sB, bool l3) {
+  cpx p = quad_bfly<0xB1>(v, sB);
+  p = l3 ? cpx{-p.im, p.re} : p;  // times +i
+  return quad_bfly<0x4E>(p, sA);
+}
+
 }  // namespace pwfs

@@ -56,6 +56,8 @@ def _plan_status(**over):
     (dict(norm_mode=2), -1), (dict(flags=4), -1), (dict(face_shift=-3), -1),
     (dict(n_fft=600), -2), (dict(face_shift=100), -2), (dict(n_pupil=96, n_fft=384), -2),
     (dict(n_bin=5), -2), (dict(n_mod=2000), -2),
+    (dict(n_pupil=480, n_fft=1920, n_bin=3), -2), (dict(n_pupil=480, n_fft=1920, n_bin=6), -2),
+    (dict(n_pupil=128, n_fft=512, n_bin=5), -1), (dict(n_pupil=320, n_fft=1280), -2),
 ])
 def test_plan_rejects_bad_config_before_touching_a_device(over, status):
     st, msg = _plan_status(**over)

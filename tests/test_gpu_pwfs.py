@@ -7,7 +7,7 @@ accumulation over the modulation points and bins).
 import numpy as np
 import pytest
 
-from synth.configs import CFG1, CFG2, ATMO1, ATMO2, CFG4_R0_RANGE, SensorConfig
+from synth.configs import CFG1, CFG2, CFG3, ATMO1, ATMO2, CFG4_R0_RANGE, SensorConfig, AtmoConfig
 from synth.screens import open_loop_batch, tilt_opd_nm
 import oracle
 from tests.gpu_common import torch_cuda, rel_l2, say
@@ -21,6 +21,15 @@ CFG_P64 = SensorConfig(name="p64_k12_b8", n_fft=256, n_pupil=64, n_bin=8, n_mod=
                        mod_radius_lod=2.0, wavelength_m=850e-9, diameter_m=4.0, obstruction=0.2)
 CFG_P64N = SensorConfig(name="p64_k9_b1_norm1", n_fft=256, n_pupil=64, n_bin=1, n_mod=9,
                         mod_radius_lod=1.5, wavelength_m=650e-9, diameter_m=4.0, norm_mode=1)
+
+# Long lines (32-lane teams): P = 128 and 480.
+CFG_P128 = SensorConfig(name="p128_k16_b4", n_fft=512, n_pupil=128, n_bin=4, n_mod=16,
+                        mod_radius_lod=3.0, wavelength_m=750e-9, diameter_m=8.0)
+CFG_P128N = SensorConfig(name="p128_k9_b1_obs_norm1", n_fft=512, n_pupil=128, n_bin=1, n_mod=9,
+                         mod_radius_lod=2.0, wavelength_m=650e-9, diameter_m=6.0, obstruction=0.15, norm_mode=1)
+CFG_P480B8 = SensorConfig(name="p480_k8_b8", n_fft=1920, n_pupil=480, n_bin=8, n_mod=8,
+                          mod_radius_lod=2.0, wavelength_m=850e-9, diameter_m=39.0)
+ATMO3 = AtmoConfig(r0_m=0.15, L0_m=25.0)
 
 _ORC = {}
 
@@ -192,3 +201,34 @@ def test_schedule_outside_workspace_is_rejected():
         plan.set_schedule(17, a, k)
     assert plan.get_schedule(16) == (a, k)
     plan.close()
+
+
+def test_long_lines_p128():
+    """32-lane line teams (P = 16 E, E = 8): binning 4 over four screens, and
+    binning 1 with a central obstruction and per-subaperture normalisation
+    (ragged slices of 3)."""
+    opd, _ = open_loop_batch(CFG_P128, ATMO1, [20, 21, 22, 23])
+    _check_batch(CFG_P128, opd, batch_max=4)
+    opd, _ = open_loop_batch(CFG_P128N, ATMO1, [24, 25, 26, 27, 28])
+    _check_batch(CFG_P128N, opd, batch_max=3)
+
+
+def test_long_lines_p480_binning8():
+    opd, _ = open_loop_batch(CFG_P480B8, ATMO3, [30, 31])
+    _check_batch(CFG_P480B8, opd, batch_max=2)
+
+
+def test_cfg3_frame_and_reference():
+    """The 40 m class geometry: N = 1920, P = 480, K = 64, binning 5 (S = 96,
+    7232 valid subapertures); one screen and the flat reference."""
+    import paper_1607_07624_amd as pw
+    torch_cuda()
+    orc = orc_for(CFG3)
+    plan = pw.Plan(CFG3, batch_max=1)
+    assert plan.n_valid == orc.n_valid == 7232
+    e = float(np.abs(plan.s_ref.astype(np.float64) - orc.s_ref).max())
+    say(f"[gpu] cfg3: reference slope max abs err {e:.3e}")
+    assert e <= 1e-6
+    plan.close()
+    opd, _ = open_loop_batch(CFG3, ATMO3, [33])
+    _check_batch(CFG3, opd, batch_max=1)
