@@ -97,6 +97,71 @@ def line_flops(P: int, intensity: bool) -> int:
     return 2 * projection + f + twist + out + acc
 
 
+def line_flops16(P: int, intensity: bool) -> int:
+    """Same operator for long lines (P = 16 E, a projection on 16 lanes): per
+    lane DFT_E and its inverse, the subgroup twiddle and its conjugate, the two
+    radix-2 DPP stages of DFT_4 each way and the 3-tap mix."""
+    E = P // 16
+    projection = 16 * (2 * dft_flops(E) + 36 * E)
+    f = 6 * P
+    twist = 2 * 6 * P
+    out = 2 * 6 * P + 2 * P + 2 * P
+    acc = 2 * 2 * P * 2 if intensity else 0
+    return 2 * projection + f + twist + out + acc
+
+
+def multi_source_leg(args, log):
+    """Six guide stars through three layers, sensed at 650 and 850 nm (40 m
+    class geometry) by two plans captured in one HIP graph."""
+    import torch
+    from synth.configs import CFG3, CFG3_850, ATMO3, CFG3_LAYERS, CFG3_GS_ARCSEC
+    from synth.screens import layered_opd_nm
+    from paper_1607_07624_amd.multisource import MultiSourceSensor
+    ns = len(CFG3_GS_ARCSEC)
+    ms = MultiSourceSensor([CFG3, CFG3_850], n_sources=ns, autotune=True, reps=3)
+    ms.opd.copy_(torch.from_numpy(layered_opd_nm(CFG3, ATMO3, CFG3_LAYERS, CFG3_GS_ARCSEC, seed=7)))
+    ms.capture()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = args.multi_reps
+    for _ in range(3):
+        ms.measure()
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(reps):
+        ms.measure()
+    ev1.record()
+    torch.cuda.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / reps
+    ev0.record()
+    for _ in range(reps):
+        ms.measure_eager()
+    ev1.record()
+    torch.cuda.synchronize()
+    eager_ms = ev0.elapsed_time(ev1) / reps
+    kernels = []
+    for p, cfg in zip(ms.plans, (CFG3, CFG3_850)):
+        p.timing_enable(True)
+        for _ in range(reps):
+            p.measure_into(ms.opd, None, ms.slopes[0] if p is ms.plans[0] else ms.slopes[1])
+        kt = p.timing_read()
+        p.timing_enable(False)
+        n = kt["slices"]
+        col_ms = kt["col_ms"] / n
+        lines = cfg.n_mod * 2 * cfg.n_pupil * ns
+        kernels.append({"wavelength_nm": round(cfg.wavelength_m * 1e9), "row_ms": round(kt["row_ms"] / n, 4),
+                        "col_ms": round(col_ms, 4), "slopes_ms": round(kt["slopes_ms"] / n, 4),
+                        "col_tflops": round(lines * line_flops16(cfg.n_pupil, True) / (col_ms * 1e-3) / 1e12, 2)})
+    out = {"workload": "40 m class: N=1920, P=480, K=64, b=5 (7232 valid); 6 guide stars at 45 arcsec, "
+                       "3 layers (0/5/12 km), 650 + 850 nm",
+           "sensor_frames_per_call": 2 * ns, "graph_ms": round(graph_ms, 4), "eager_ms": round(eager_ms, 4),
+           "sensor_frames_per_s": round(2 * ns / (graph_ms * 1e-3), 1),
+           "schedules": [{k: v for k, v in s_.items() if k in ("a_chunk", "k_chunk")} for s_ in ms.schedules],
+           "kernels": kernels}
+    ms.close()
+    log(f"multi-source {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +176,8 @@ def main():
     ap.add_argument("--cnn-frames", type=int, default=200000)
     ap.add_argument("--cnn-epochs", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default work split")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-source 40 m class leg")
+    ap.add_argument("--multi-reps", type=int, default=20)
     ap.add_argument("--schedule", type=str, default=None,
                     help="A,K: fix the work split (x-tilt chunk, modulation chunk) instead of autotuning")
     ap.add_argument("--random-R", action="store_true",
@@ -154,6 +221,7 @@ def main():
     if args.random_R:
         args.no_loop = True
         args.no_cnn = True
+        args.no_multi = True
         M = N_KL_MODES
         R_host = np.random.default_rng(0).standard_normal((M, ns)) * 1e-2
     else:
@@ -347,6 +415,10 @@ def main():
                    "open_loop_error_r0_0.06_0.1": ev_strong, "open_loop_error_r0_0.06_0.2": ev_all,
                    "closed_loop": loops}
 
+    multi = None
+    if not args.no_multi:
+        multi = multi_source_leg(args, log)
+
     # CPU baseline: the FP64 oracle on the host cores, small sample.
     cpu = None
     if not args.no_cpu:
@@ -376,6 +448,7 @@ def main():
         "cpu_baseline": cpu,
         "loop": loop,
         "learned": learned,
+        "multi_source": multi,
         "kernels": extra,
         "schedule": schedule,
     }

@@ -16,6 +16,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, replace, asdict
 
+import numpy as np
+
 
 @dataclass(frozen=True)
 class SensorConfig:
@@ -100,11 +102,20 @@ ATMO2 = AtmoConfig(r0_m=0.12, L0_m=40.0, wind_m_s=15.0, frame_rate_hz=1000.0)
 CFG4_R0_RANGE = (0.08, 0.2)
 CFG4_SEEDS = tuple(range(16))
 
-# 40 m class multi-source sensor (shapes only; batched multi-source
-# sensing is a later extension).
+# 40 m class multi-source sensor: six guide stars on a 45 arcsec ring seen
+# through a three-layer atmosphere, sensed at 650 and 850 nm.  The
+# modulation mirror's angular amplitude is fixed, so the radius is 3 lambda/D
+# at 650 nm and 3 * 650/850 lambda/D at 850 nm.
 CFG3 = SensorConfig(name="cfg3_n1920_p480_k64", n_fft=1920, n_pupil=480, n_bin=5,
                     n_mod=64, mod_radius_lod=3.0, wavelength_m=650e-9,
                     diameter_m=39.0)
+CFG3_850 = SensorConfig(name="cfg3_n1920_p480_k64_850nm", n_fft=1920, n_pupil=480, n_bin=5,
+                        n_mod=64, mod_radius_lod=3.0 * 650.0 / 850.0, wavelength_m=850e-9,
+                        diameter_m=39.0)
+ATMO3 = AtmoConfig(r0_m=0.15, L0_m=25.0)
+CFG3_LAYERS = ((0.0, 0.6), (5000.0, 0.25), (12000.0, 0.15))       # (altitude m, Cn2 fraction)
+CFG3_GS_ARCSEC = tuple((45.0 * float(np.cos(2 * np.pi * i / 6)), 45.0 * float(np.sin(2 * np.pi * i / 6)))
+                       for i in range(6))
 
 # Closed-loop constants of the integrator (gain of the LBT-like loop,
 # delay of the paper's example control block).

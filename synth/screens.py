@@ -134,3 +134,34 @@ class CropBank:
                 c = c.T
             out[i] = c * np.float32((self.r0_ref / r0[i]) ** (5.0 / 6.0))
         return out, r0
+
+
+def layered_opd_nm(cfg: SensorConfig, atmo: AtmoConfig, layers, directions_arcsec, seed: int,
+                   screen_n: int = 1024) -> np.ndarray:
+    """OPD seen by several guide stars through a layered atmosphere.
+
+    layers: (altitude m, Cn2 fraction) pairs; each layer is a von Karman
+    screen with r0_layer = r0 * fraction^(-3/5) (so the fractions add up in
+    r0^(-5/3)).  A star at angle (tx, ty) sees layer h shifted by h * (tx, ty)
+    (natural guide stars, no cone effect); the shift is applied by bilinear
+    interpolation in FP64.  Returns [n_dir, P, P] float32 nm."""
+    P = cfg.n_pupil
+    rng = np.random.default_rng(int(seed))
+    arcsec = np.pi / (180.0 * 3600.0)
+    out = np.zeros((len(directions_arcsec), P, P))
+    for h, frac in layers:
+        r0 = atmo.r0_m * float(frac) ** (-3.0 / 5.0)
+        scr = von_karman_opd_nm(screen_n, cfg.pixel_m, r0, atmo.L0_m, rng, atmo.r0_wavelength_m)
+        for i, (tx, ty) in enumerate(directions_arcsec):
+            sx = h * tx * arcsec / cfg.pixel_m
+            sy = h * ty * arcsec / cfg.pixel_m
+            x0 = (screen_n - P) / 2.0 + sx
+            y0 = (screen_n - P) / 2.0 + sy
+            ix, iy = int(np.floor(x0)), int(np.floor(y0))
+            fx, fy = x0 - ix, y0 - iy
+            if ix < 0 or iy < 0 or ix + P + 1 > screen_n or iy + P + 1 > screen_n:
+                raise ValueError("screen too small for the guide-star separation")
+            blk = scr[iy:iy + P + 1, ix:ix + P + 1]
+            out[i] += ((1 - fy) * ((1 - fx) * blk[:-1, :-1] + fx * blk[:-1, 1:])
+                       + fy * ((1 - fx) * blk[1:, :-1] + fx * blk[1:, 1:]))
+    return out.astype(np.float32)

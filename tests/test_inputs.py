@@ -60,3 +60,23 @@ def test_kl_modes_orthonormal_pistonfree_tiptilt_first():
     for i in (0, 1):
         v = B[i][A > 0] / np.linalg.norm(B[i][A > 0])
         assert np.linalg.norm(tt @ v) > 0.98
+
+
+def test_layered_opd_ground_layer_and_integer_shift():
+    """Single ground layer: every direction sees the same crop.  A layer whose
+    shift is a whole number of pixels is the shifted crop of the same screen
+    (bilinear weights 0/1), with r0 scaled by fraction^(-3/5)."""
+    from synth.configs import SensorConfig, AtmoConfig
+    from synth.screens import layered_opd_nm, von_karman_opd_nm
+    cfg = SensorConfig(name="t", n_fft=128, n_pupil=32, n_bin=2, n_mod=8, mod_radius_lod=3.0,
+                       wavelength_m=750e-9, diameter_m=8.0)
+    atmo = AtmoConfig(r0_m=0.2, L0_m=20.0)
+    dirs = ((0.0, 0.0), (10.0, -5.0), (-7.0, 3.0))
+    o = layered_opd_nm(cfg, atmo, ((0.0, 1.0),), dirs, seed=3, screen_n=128)
+    assert np.array_equal(o[0], o[1]) and np.array_equal(o[0], o[2])
+    arcsec = np.pi / (180 * 3600)
+    h = 3 * cfg.pixel_m / (10.0 * arcsec)             # 10 arcsec -> exactly 3 px in x
+    o2 = layered_opd_nm(cfg, atmo, ((h, 0.5),), ((10.0, 0.0),), seed=4, screen_n=128)
+    scr = von_karman_opd_nm(128, cfg.pixel_m, 0.2 * 0.5 ** (-0.6), 20.0, np.random.default_rng(4), 500e-9)
+    c = (128 - 32) // 2
+    assert np.allclose(o2[0], scr[c:c + 32, c + 3:c + 35].astype(np.float32), atol=1e-3)
