@@ -307,6 +307,9 @@ def main():
 
     # B = 1 latency (one frame per call, same path).
     plan1 = pw.Plan(cfg, batch_max=1)
+    if not args.no_autotune and not args.schedule:
+        extra["b1_schedule"] = plan1.autotune(1, reps=5)
+        log(f"autotune B=1 {extra['b1_schedule']}")
     s1 = torch.empty((1, ns), device=dev)
     m1 = torch.empty((1, M), device=dev)
     o1 = opd[:1].contiguous()

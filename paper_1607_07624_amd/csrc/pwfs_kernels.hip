@@ -309,6 +309,10 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   const cpx* col = s_col + wave * 8 * P + t * 4 + l;   // element (x' = X0 + c, y = l + 4m) at col[32 m]
   const cpx* tin = s_in + q * TabLds<E>::QO + l;
   const cpx* tf = s_f + l;
+  // With QB, lane l keeps the row groups m = 4 i + l: one FMA with a 0/1 mask
+  // per group instead of a select and an add.
+  float keepm[4];
+  static_for<0, 4>([&](auto j_) { keepm[decltype(j_)::value] = (l == decltype(j_)::value) ? 1.f : 0.f; });
   int cur_ia = -1;
   for (int kk = kb; kk < ke; ++kk) {
     const int k = k_order[kk];
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
       if constexpr (QB) {
         e += quad_perm<0xB1>(e);                   // lanes (0,1), (2,3)
         e += quad_perm<0x4E>(e);                   // lanes (0,2), (1,3)
-        acc[m >> 2] += (l == (m & 3)) ? e : 0.f;
+        acc[m >> 2] = fmaf(keepm[m & 3], e, acc[m >> 2]);
       } else {
         acc[m] += e;
       }
