@@ -130,6 +130,52 @@ int pwfs_timing_enable(pwfs_plan_t plan, int enable);
 int pwfs_timing_read(pwfs_plan_t plan, double* ms_row, double* ms_col, double* ms_slopes,
                      int64_t* n_slices);
 
+/* Detector (the paper's CCD object, Sec. 4, Tab. 1 "ccd": it integrates the
+ * intensity over the exposure into pixels with photon noise and readout noise;
+ * the quantum efficiency, band, source magnitude and exposure enter through
+ * the photo-electron budget).  With a detector set, pwfs_measure passes the
+ * binned images through it: d_pupils receives detector pixels (electrons) and
+ * the slopes are computed from them (the reference slopes stay the noiseless
+ * flat-wavefront ones).
+ *   electrons_per_frame  mean photo-electrons that a flat wavefront deposits in
+ *                        the four binned pupil images (flux x band x collecting
+ *                        area x exposure x QE); the gain is this budget divided
+ *                        by the sum of the plan's flat-wavefront images;
+ *                        0 removes the detector (noiseless images).
+ *   readout_noise_e      Gaussian readout noise per binned pixel, electrons RMS.
+ *   seed                 key of the random numbers.
+ * Pixel = k + ron z with k ~ Poisson(gain I) and z ~ N(0, 1), drawn from the
+ * counter-based generator Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+ * SC'11) with key = seed and counter = (pixel index within the frame, frame
+ * index low word, frame index high word, draw word): the noise of a frame
+ * depends only on (seed, frame index, pixel), not on batching or schedule.
+ * The count multiplies uniforms (x + 1/2) 2^-32 in FP64 (draw words 0, 1, ...)
+ * until the product falls to exp(-lam / n) or below, for each of
+ * n = ceil(lam / 500) equal pieces of lam = gain I; above lam = 1e4 it is the
+ * normal approximation floor(lam + sqrt(lam) z' + 1/2), clipped at 0.  z and
+ * z' are Box-Muller deviates of draw word 2^31.
+ * Frame indices: pwfs_measure gives its B frames the indices f, f+1, ...,
+ * f+B-1 with f the plan's frame counter, then advances the counter by B;
+ * pwfs_set_detector resets it to 0, pwfs_set_frame_counter sets it.
+ * PWFS_ERR_INVALID_ARG for a negative or non-finite budget or noise. */
+typedef struct {
+  double electrons_per_frame;
+  double readout_noise_e;
+  uint64_t seed;
+} pwfs_detector_t;
+
+int pwfs_set_detector(pwfs_plan_t plan, const pwfs_detector_t* det /* NULL = noiseless */);
+/* Gain (electrons per unit intensity, 0 without a detector) and the next frame index. */
+int pwfs_get_detector(pwfs_plan_t plan, float* gain, uint64_t* next_frame);
+int pwfs_set_frame_counter(pwfs_plan_t plan, uint64_t frame);
+
+/* The detector alone: d_pixels [B][4][S][S] from noiseless images
+ * d_intensity [B][4][S][S] (device), frame b using index frame0 + b.
+ * Requires a detector set on the plan (PWFS_ERR_INVALID_ARG otherwise).
+ * Asynchronous on `stream`; does not touch the plan's frame counter. */
+int pwfs_detect(pwfs_plan_t plan, const float* d_intensity, int32_t B, uint64_t frame0, float* d_pixels,
+                void* stream);
+
 /* Work split ("schedule") that pwfs_measure uses for a slice of B frames
  * (1 <= B <= batch_max; a call with more frames than batch_max runs in
  * slices of batch_max and a last, smaller slice): a_chunk distinct x tilts per

@@ -23,6 +23,11 @@ class PwfsError(RuntimeError):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({detail})")
 
 
+class detector_struct(ctypes.Structure):
+    _fields_ = [("electrons_per_frame", ctypes.c_double), ("readout_noise_e", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
 class config_struct(ctypes.Structure):
     _fields_ = [("n_fft", ctypes.c_int32), ("n_pupil", ctypes.c_int32), ("n_bin", ctypes.c_int32),
                 ("n_mod", ctypes.c_int32), ("face_shift", ctypes.c_int32), ("norm_mode", ctypes.c_int32),
@@ -60,6 +65,10 @@ def load_library():
     lib.pwfs_set_schedule.argtypes = [vp, i32, i32, i32]
     lib.pwfs_autotune.argtypes = [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
+    lib.pwfs_set_detector.argtypes = [vp, ctypes.POINTER(detector_struct)]
+    lib.pwfs_get_detector.argtypes = [vp, ctypes.POINTER(f32), ctypes.POINTER(ctypes.c_uint64)]
+    lib.pwfs_set_frame_counter.argtypes = [vp, ctypes.c_uint64]
+    lib.pwfs_detect.argtypes = [vp, vp, i32, ctypes.c_uint64, vp, vp]
     lib.pwfs_destroy.argtypes = [vp]
     lib.pwfs_destroy.restype = None
     lib.pwfs_strerror.argtypes = [ctypes.c_int]
@@ -69,7 +78,8 @@ def load_library():
     for name in ("pwfs_plan", "pwfs_plan_info", "pwfs_get_valid", "pwfs_get_reference",
                  "pwfs_set_reference", "pwfs_measure", "recon_apply", "pwfs_get_pupil",
                  "pwfs_timing_enable", "pwfs_timing_read", "pwfs_get_schedule", "pwfs_set_schedule",
-                 "pwfs_autotune"):
+                 "pwfs_autotune", "pwfs_set_detector", "pwfs_get_detector", "pwfs_set_frame_counter",
+                 "pwfs_detect"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -158,6 +168,32 @@ class Plan:
         _check(self.lib.pwfs_timing_read(self.handle, ctypes.byref(r), ctypes.byref(c), ctypes.byref(s),
                                          ctypes.byref(n)), "pwfs_timing_read")
         return {"row_ms": r.value, "col_ms": c.value, "slopes_ms": s.value, "slices": n.value}
+
+    def set_detector(self, electrons_per_frame: float, readout_noise_e: float = 0.0, seed: int = 0):
+        """Photon + readout noise on the binned images (electrons_per_frame = 0: noiseless)."""
+        d = detector_struct(float(electrons_per_frame), float(readout_noise_e), int(seed))
+        _check(self.lib.pwfs_set_detector(self.handle, ctypes.byref(d)), "pwfs_set_detector")
+
+    def detector(self) -> dict:
+        g, f = ctypes.c_float(), ctypes.c_uint64()
+        _check(self.lib.pwfs_get_detector(self.handle, ctypes.byref(g), ctypes.byref(f)), "pwfs_get_detector")
+        return {"gain": g.value, "next_frame": f.value}
+
+    def set_frame_counter(self, frame: int):
+        _check(self.lib.pwfs_set_frame_counter(self.handle, int(frame)), "pwfs_set_frame_counter")
+
+    def detect(self, intensity, frame0: int, pixels=None):
+        """pwfs_detect: detector pixels from noiseless images [B, 4, S, S] (device tensors)."""
+        torch = self._torch
+        B = intensity.shape[0]
+        S = self.n_sub
+        _need(intensity, torch, torch.float32, B * 4 * S * S, "intensity")
+        if pixels is None:
+            pixels = torch.empty_like(intensity)
+        _need(pixels, torch, torch.float32, B * 4 * S * S, "pixels")
+        _check(self.lib.pwfs_detect(self.handle, _ptr(intensity), int(B), int(frame0), _ptr(pixels),
+                                    _stream_handle(torch, self.device)), "pwfs_detect")
+        return pixels
 
     def get_schedule(self, B: int) -> tuple:
         """(a_chunk, k_chunk) pwfs_measure uses for slices of B frames."""

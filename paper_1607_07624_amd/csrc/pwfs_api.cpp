@@ -105,6 +105,12 @@ struct pwfs_plan_s {
   float* tmp_slopes = nullptr;
   size_t ws_bytes = 0;
   size_t partial_cap = 0;                       // floats in `partial`
+  // detector
+  bool det_on = false;
+  double det_electrons = 0.0, det_ron = 0.0, ref_total = 0.0;  // ref_total: flat-wavefront image sum
+  uint64_t det_seed = 0, frame_next = 0;
+  float det_gain = 0.f;
+  float* pixels = nullptr;                      // [batch_max][4][S][S] detector output scratch
   std::map<int, std::array<int, 2>> sched;      // slice size -> {a_chunk, k_chunk}
   std::vector<float> amp_host;
   // per-kernel timing
@@ -177,7 +183,8 @@ void free_plan(pwfs_plan_s* p) {
   if (!p) return;
   DeviceGuard g(p->device);
   void* ptrs[] = {p->amp, p->in_a, p->f_a, p->in_b, p->f_b, p->mid, p->tw16, p->outw, p->k_order, p->k_ia,
-                  p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->field, p->zero_opd, p->tmp_slopes};
+                  p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->pixels, p->field, p->zero_opd,
+                  p->tmp_slopes};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto* pool : {&p->ev_used, &p->ev_free})
@@ -200,7 +207,13 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
   a.kphase = p->kphase;
   a.fp32_phase = (p->cfg.flags & 2) != 0;
   a.opd = opd + (size_t)b0 * p->P * p->P;
-  a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : p->pupils;
+  a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : (p->det_on ? p->pixels : p->pupils);
+  a.det_on = p->det_on ? 1 : 0;
+  a.det_gain = p->det_gain;
+  a.det_ron = (float)p->det_ron;
+  a.det_seed = p->det_seed;
+  a.frame0 = p->frame_next + (uint64_t)b0;
+  a.intensity = p->pupils;
   a.slopes = slopes ? slopes + (size_t)b0 * 2 * p->nv : nullptr;
   a.amp = p->amp;
   a.in_a = p->in_a;
@@ -243,6 +256,7 @@ int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* s
     hipError_t e = pwfs::launch_measure(a, st, ev);
     if (e != hipSuccess) return hip_fail(e, "pwfs_measure launch");
   }
+  if (p->det_on) p->frame_next += (uint64_t)B;
   return PWFS_OK;
 }
 
@@ -466,6 +480,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {(void**)&p->Rw, rw_elems * sizeof(cpx), "row-pass workspace"},
       {(void**)&p->partial, partial_elems * sizeof(float), "pupil partials"},
       {(void**)&p->pupils, (size_t)bm * 4 * S * S * sizeof(float), "pupil scratch"},
+      {(void**)&p->pixels, (size_t)bm * 4 * S * S * sizeof(float), "detector scratch"},
       {(void**)&p->field, (size_t)bm * P * P * sizeof(cpx), "pupil field"},
       {(void**)&p->zero_opd, (size_t)P * P * sizeof(float), "zero opd"},
       {(void**)&p->tmp_slopes, (size_t)2 * p->nv * sizeof(float), "reference scratch"},
@@ -514,6 +529,17 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
     free_plan(p);
     return hip_fail(e, "reference slopes");
   }
+  // Sum of the flat-wavefront images (the detector's photon budget refers to it).
+  {
+    std::vector<float> flat((size_t)4 * S * S);
+    if ((e = hipMemcpy(flat.data(), p->pupils, flat.size() * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "reference images");
+    }
+    double tot = 0.0;
+    for (float v : flat) tot += (double)v;
+    p->ref_total = tot;
+  }
   *out = p;
   return PWFS_OK;
 }
@@ -551,6 +577,51 @@ int pwfs_timing_read(pwfs_plan_t p, double* ms_row, double* ms_col, double* ms_s
   if (ms_col) *ms_col = acc[1];
   if (ms_slopes) *ms_slopes = acc[2];
   if (n_slices) *n_slices = (int64_t)p->ev_used.size();
+  return PWFS_OK;
+}
+
+int pwfs_set_detector(pwfs_plan_t p, const pwfs_detector_t* d) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (!d || d->electrons_per_frame == 0.0) {
+    p->det_on = false;
+    return PWFS_OK;
+  }
+  if (!(d->electrons_per_frame > 0.0) || !std::isfinite(d->electrons_per_frame) || !(d->readout_noise_e >= 0.0) ||
+      !std::isfinite(d->readout_noise_e))
+    return fail(PWFS_ERR_INVALID_ARG, "electrons_per_frame must be > 0 and readout_noise_e >= 0, both finite");
+  if (!(p->ref_total > 0.0)) return fail(PWFS_ERR_INVALID_ARG, "flat-wavefront images carry no light");
+  p->det_on = true;
+  p->det_electrons = d->electrons_per_frame;
+  p->det_ron = d->readout_noise_e;
+  p->det_seed = d->seed;
+  p->det_gain = (float)(d->electrons_per_frame / p->ref_total);
+  p->frame_next = 0;
+  return PWFS_OK;
+}
+
+int pwfs_get_detector(pwfs_plan_t p, float* gain, uint64_t* next_frame) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (gain) *gain = p->det_on ? p->det_gain : 0.f;
+  if (next_frame) *next_frame = p->frame_next;
+  return PWFS_OK;
+}
+
+int pwfs_set_frame_counter(pwfs_plan_t p, uint64_t frame) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  p->frame_next = frame;
+  return PWFS_OK;
+}
+
+int pwfs_detect(pwfs_plan_t p, const float* d_intensity, int32_t B, uint64_t frame0, float* d_pixels, void* stream) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (!p->det_on) return fail(PWFS_ERR_INVALID_ARG, "no detector set on this plan");
+  if (B < 0 || B > 65535) return fail(PWFS_ERR_INVALID_ARG, "B outside [0, 65535]");
+  if (B == 0) return PWFS_OK;
+  if (!d_intensity || !d_pixels) return fail(PWFS_ERR_INVALID_ARG, "NULL image pointer");
+  DeviceGuard g(p->device);
+  hipError_t e = pwfs::launch_detector(d_intensity, d_pixels, 4 * p->S * p->S, B, frame0, p->det_gain,
+                                       (float)p->det_ron, p->det_seed, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pwfs_detect launch");
   return PWFS_OK;
 }
 

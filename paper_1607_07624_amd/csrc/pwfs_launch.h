@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstdint>
 
 namespace pwfs {
 
@@ -37,12 +38,19 @@ struct MeasureArgs {
   cpx* field;          // [B][P][P]    A exp(i phi)
   cpx* Rw;             // [B][n_a][2P][P]
   float* partial;      // [B][n_chunks][4][S][S]
+  // detector (det_on == 0: the pupils are the noiseless intensity)
+  int det_on;
+  float det_gain, det_ron;   // electrons per unit intensity, readout noise (e- RMS)
+  uint64_t det_seed, frame0; // Philox key, frame index of the slice's first frame
+  float* intensity;          // [B][4][S][S] scratch for the noiseless images when det_on
 };
 
 // ev: NULL, or four events recorded before the row pass, between the passes
 // and after the slopes kernel.
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t stream);
+hipError_t launch_detector(const float* intensity, float* pixels, int npix, int B, uint64_t frame0, float gain,
+                           float ron, uint64_t seed, hipStream_t stream);
 hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, float alpha, float beta,
                         float* m, hipStream_t stream);
 

@@ -126,3 +126,21 @@ N_KL_MODES = 600
 PUSH_PULL_NM = 10.0
 
 CONFIGS = {"cfg1": CFG1, "cfg2": CFG2, "cfg3": CFG3}
+
+
+# Photon budget of the paper's example detector: magnitude-8 source, 300 nm
+# band, QE 0.32, 1 ms exposure, readout noise 1 e-.  Zero point: 3.9e7
+# photons / s / m^2 / nm at magnitude 0 (a magnitude-0 star near 700 nm).
+ZERO_POINT_PH_S_M2_NM = 3.9e7
+DETECTOR_MAG = 8.0
+DETECTOR_BAND_NM = 300.0
+DETECTOR_QE = 0.32
+DETECTOR_RON_E = 1.0
+
+
+def photoelectrons_per_frame(cfg: SensorConfig, magnitude: float = DETECTOR_MAG, band_nm: float = DETECTOR_BAND_NM,
+                             qe: float = DETECTOR_QE, exposure_s: float = 1e-3,
+                             zero_point: float = ZERO_POINT_PH_S_M2_NM) -> float:
+    """Photo-electrons collected by the pupil in one exposure."""
+    area = np.pi * (cfg.diameter_m / 2.0) ** 2 * (1.0 - cfg.obstruction ** 2)
+    return zero_point * 10.0 ** (-0.4 * magnitude) * band_nm * area * exposure_s * qe
