@@ -37,11 +37,12 @@ PEAK_HBM_GBS = 8000.0
 # 2.0 / 1.0).  Valid only for the kernel sources with these hashes and this work split
 # (x-tilt chunk, modulation chunk); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "fd424b0c2156503d3ce68be4b01982d9bf5dc507",
-                     "pwfs_dft.h": "b9f0efe9263005de788f876c2146edfa2d2b9d54"},
+    "sources_sha1": {"pwfs_kernels.hip": "8c387080e72899f1fcd14e57443c71fc1844e7f4",
+                     "pwfs_common.h": "05ad04b20e1339450c0fcb05421ccf490d40edbf",
+                     "pwfs_dft.h": "dc4c8d92932d722a11520e45113183e7ea3c618a"},
     "batch": 16,
     "schedule": (3, 6),
-    "col_pass_bytes": (104278.9 * 2.0 + 3200.0 * 1.0) * 1024,
+    "col_pass_bytes": (104289.2 * 2.0 + 3200.0 * 1.0) * 1024,
 }
 
 
@@ -367,6 +368,34 @@ def main():
                            "residual_nm_rms_mean": round(float(np.mean(per_real)), 2),
                            "residual_nm_rms_std": round(float(np.std(per_real)), 2)}
         log(f"batched loops {loop['batched']}")
+        # The paper's example detector: magnitude-8 source, 300 nm band, QE 0.32, 1 e- readout noise.
+        from synth.configs import photoelectrons_per_frame, DETECTOR_RON_E
+        e_frame = photoelectrons_per_frame(cfg)
+        plan1.set_detector(e_frame, DETECTOR_RON_E, seed=8)
+        cl = ClosedLoop(plan1, modes_dev, R, LOOP_GAIN, LOOP_DELAY)
+        torch.cuda.synchronize()
+        ev0.record()
+        resn, _ = cl.run(seq)
+        ev1.record()
+        torch.cuda.synchronize()
+        per_step = residual_rms_nm(resn.cpu().numpy(), amp)
+        loop["with_detector"] = {"electrons_per_frame": round(e_frame, 1), "readout_noise_e": DETECTOR_RON_E,
+                                 "residual_nm_rms": round(float(np.sqrt(np.mean(per_step[LOOP_SETTLE_STEPS:] ** 2))), 2),
+                                 "steps_per_s": round(T / (ev0.elapsed_time(ev1) / 1e3), 1)}
+        plan1.set_detector(0.0)
+        del resn
+        log(f"loop with detector {loop['with_detector']}")
+        plan.set_detector(e_frame, DETECTOR_RON_E, seed=9)
+        for _ in range(5):
+            step()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(50):
+            step()
+        ev1.record()
+        torch.cuda.synchronize()
+        plan.set_detector(0.0)
+        extra["with_detector_frames_per_s"] = round(B * 50 / (ev0.elapsed_time(ev1) / 1e3), 1)
 
     # Learned reconstructor: trained on GPU-generated frames with the project's
     # kernels, compared with the linear one (held-out open-loop error, closed loop).

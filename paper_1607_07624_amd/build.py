@@ -9,8 +9,9 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libpwfs.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("pwfs_kernels.hip", "pwfs_api.cpp", "cnn_kernels.hip",
-                                                  "cnn_api.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("pwfs_kernels.hip", "pwfs_kernels16.hip",
+                                                  "pwfs_detector.hip", "pwfs_api.cpp",
+                                                  "cnn_kernels.hip", "cnn_api.cpp")]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # Packed FP32 VALU forms stay disabled for all device code.

@@ -1,0 +1,142 @@
+// pwfs_common.h -- device helpers shared by the pyramid line kernels (gfx950):
+// scheduling fences, pointer laundering, the quad-lane half-band projection
+// and line operator, the row-pass intermediate index and LDS staging copies.
+#pragma once
+
+#include "pwfs_dft.h"
+
+#include <cstdint>
+
+namespace pwfs {
+
+// Scheduling fence: keeps the machine scheduler from hoisting the table and
+// field loads of later phases over the register-resident transforms.
+__device__ __forceinline__ void fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// Opaque copy of a wave-uniform pointer: stops loop-invariant code motion
+// from hoisting whole tables out of the modulation loop into registers.
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// LDS copies of the pyramid tables are padded so that a ds_read of a quad's
+// four lanes (mix table, rows of 2E values) or of a team's two quads (input
+// and output tables, halves of P values) spreads over distinct banks: both
+// 2E and P complex values are multiples of the bank-set width here.
+template <int E>
+struct TabLds {
+  static constexpr int P = 4 * E;
+  static constexpr int QO = P + 4;        // offset of quad 1's half of an input / output table
+  static constexpr int MS = 2 * E + 2;    // per-lane row stride of the mix table
+};
+
+// Half-band projection of the E samples held by this lane (see header), up to
+// a factor 1/2 that the output table absorbs.  The forward twiddle w_l =
+// w_P^{l k}, the quad mix and the conjugate twiddle are folded into
+//   V_l = v_l + (A_l / 2) v_{l+1} + (B_l / 2) v_{l-1},
+//   A_l = (1 - i) conj(w_l) w_{l+1},  B_l = (1 + i) conj(w_l) w_{l-1}   (lanes mod 4),
+// mid[(l * E + k) * 2 + {0, 1}] = {A_l(k) / 2, B_l(k) / 2}.
+template <int E>
+__device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ mid, int l) {
+  Dft<E, +1>::run(v);
+  fence();
+  const cpx* ml = mid + l * TabLds<E>::MS;
+  static_for<0, E>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    if constexpr (k % 8 == 0 && k > 0) fence();
+    const cpx a = ml[2 * k], b = ml[2 * k + 1];
+    const float pr = quad_perm<0x39>(v[k].re), pim = quad_perm<0x39>(v[k].im);  // lane l+1
+    const float nr = quad_perm<0x93>(v[k].re), nim = quad_perm<0x93>(v[k].im);  // lane l-1
+    float re = fmaf(a.re, pr, v[k].re);
+    re = fmaf(-a.im, pim, re);
+    re = fmaf(b.re, nr, re);
+    re = fmaf(-b.im, nim, re);
+    float im = fmaf(a.re, pim, v[k].im);
+    im = fmaf(a.im, pr, im);
+    im = fmaf(b.re, nim, im);
+    im = fmaf(b.im, nr, im);
+    v[k] = {re, im};
+  });
+  fence();
+  Dft<E, -1>::run(v);
+  fence();
+}
+
+// Full 1-D pyramid operator for one line.
+//   load_in(m)  = f(x) w_N^{(2q+1) x} at x = l + 4 m (tilted input times this
+//                 quad's twist, one complex product from a combined table);
+//   load_f(m)   = f(l + 4 m) (needed by quad 0 for y_L = f - y_H);
+//   outw[q * P + j] = (4/N) w_N^{-(2q+1) j}  (2/N times the 2 the half-band step leaves out).
+// On return quad 0 holds y_L(l + 4 m) and quad 1 holds y_H(l + 4 m) in v[m].
+template <int E, typename LoadIn, typename LoadF>
+__device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadF&& load_f,
+                                        const cpx* __restrict__ mid, const cpx* __restrict__ outw,
+                                        int q, int l) {
+  constexpr int P = 4 * E;
+  static_for<0, E>([&](auto m_) {
+    constexpr int m = decltype(m_)::value;
+    if constexpr (m % 8 == 0 && m > 0) fence();
+    v[m] = load_in(m);
+  });
+  fence();
+  half_band<E>(v, mid, l);
+  const cpx* ow = outw + q * TabLds<E>::QO + l;
+  const float keep = (q == 0) ? 1.f : 0.f;   // quad 0 adds f back (y_L = f - y_H)
+  const float sgn = (q == 0) ? -1.f : 1.f;
+  static_for<0, E>([&](auto m_) {
+    constexpr int m = decltype(m_)::value;
+    if constexpr (m % 8 == 0 && m > 0) fence();
+    cpx w = cmul(v[m], ow[4 * m]);
+    w.re += swap_quads(w.re);
+    w.im += swap_quads(w.im);
+    const cpx f = load_f(m);
+    v[m] = {fmaf(sgn, w.re, keep * f.re), fmaf(sgn, w.im, keep * f.im)};
+  });
+}
+
+__device__ __forceinline__ size_t rw_index(int xp, int y, int P) {
+  return ((size_t)(xp >> 3) * (size_t)(P >> 2) + (size_t)(y >> 2)) * 32u + (size_t)((xp & 7) * 4 + (y & 3));
+}
+
+// Block-cooperative copy of n16 16-byte words (global -> LDS).
+__device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __restrict__ src, int n16,
+                                       int tid, int nthreads) {
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  for (int i = tid; i < n16; i += nthreads) d[i] = s[i];
+}
+
+// Block copy of exactly 256 N 16-byte words: every load is issued before the
+// first LDS write, so a thread waits for one memory round trip, not N.
+template <int N>
+__device__ __forceinline__ void copy16_n(void* __restrict__ dst, const void* __restrict__ src, int tid) {
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+  uint4 r[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) r[i] = s[tid + 256 * i];
+  fence();
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[tid + 256 * i] = r[i];
+}
+
+// Table [2][P] (quad 0 half, quad 1 half) -> LDS with quad 1 at TabLds::QO.
+template <int E>
+__device__ __forceinline__ void stage_quads(cpx* __restrict__ dst, const cpx* __restrict__ src, int tid) {
+  constexpr int P = 4 * E;
+  copy16(dst, src, P / 2, tid, 256);
+  copy16(dst + TabLds<E>::QO, src + P, P / 2, tid, 256);
+}
+
+// Mix table [4][2E] -> LDS rows of stride TabLds::MS.
+template <int E>
+__device__ __forceinline__ void stage_mid(cpx* __restrict__ dst, const cpx* __restrict__ src, int tid) {
+  for (int i = tid; i < 4 * E; i += 256) {
+    const int l = i / E, r = i - l * E;
+    reinterpret_cast<uint4*>(dst + l * TabLds<E>::MS)[r] = reinterpret_cast<const uint4*>(src + l * 2 * E)[r];
+  }
+}
+
+}  // namespace pwfs

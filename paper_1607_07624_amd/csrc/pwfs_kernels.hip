@@ -35,7 +35,7 @@
 //   Rw[frame][a][x'/8][y/4][x'%8][y%4], x' in [0, 2P) (y_L then y_H), y in [0, P)
 // so that both the row pass's stores and the column pass's loads touch
 // 128-256 contiguous bytes per instruction.
-#include "pwfs_dft.h"
+#include "pwfs_common.h"
 #include "pwfs_launch.h"
 
 #include <algorithm>
@@ -43,136 +43,6 @@
 #include <type_traits>
 
 namespace pwfs {
-
-// Scheduling fence: keeps the machine scheduler from hoisting the table and
-// field loads of later phases over the register-resident transforms.
-__device__ __forceinline__ void fence() { __builtin_amdgcn_sched_barrier(0); }
-
-// Opaque copy of a wave-uniform pointer: stops loop-invariant code motion
-// from hoisting whole tables out of the modulation loop into registers.
-template <typename T>
-__device__ __forceinline__ const T* opaque(const T* p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
-
-// LDS copies of the pyramid tables are padded so that a ds_read of a quad's
-// four lanes (mix table, rows of 2E values) or of a team's two quads (input
-// and output tables, halves of P values) spreads over distinct banks: both
-// 2E and P complex values are multiples of the bank-set width here.
-template <int E>
-struct TabLds {
-  static constexpr int P = 4 * E;
-  static constexpr int QO = P + 4;        // offset of quad 1's half of an input / output table
-  static constexpr int MS = 2 * E + 2;    // per-lane row stride of the mix table
-};
-
-// Half-band projection of the E samples held by this lane (see header), up to
-// a factor 1/2 that the output table absorbs.  The forward twiddle w_l =
-// w_P^{l k}, the quad mix and the conjugate twiddle are folded into
-//   V_l = v_l + (A_l / 2) v_{l+1} + (B_l / 2) v_{l-1},
-//   A_l = (1 - i) conj(w_l) w_{l+1},  B_l = (1 + i) conj(w_l) w_{l-1}   (lanes mod 4),
-// mid[(l * E + k) * 2 + {0, 1}] = {A_l(k) / 2, B_l(k) / 2}.
-template <int E>
-__device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ mid, int l) {
-  Dft<E, +1>::run(v);
-  fence();
-  const cpx* ml = mid + l * TabLds<E>::MS;
-  static_for<0, E>([&](auto k_) {
-    constexpr int k = decltype(k_)::value;
-    if constexpr (k % 8 == 0 && k > 0) fence();
-    const cpx a = ml[2 * k], b = ml[2 * k + 1];
-    const float pr = quad_perm<0x39>(v[k].re), pim = quad_perm<0x39>(v[k].im);  // lane l+1
-    const float nr = quad_perm<0x93>(v[k].re), nim = quad_perm<0x93>(v[k].im);  // lane l-1
-    float re = fmaf(a.re, pr, v[k].re);
-    re = fmaf(-a.im, pim, re);
-    re = fmaf(b.re, nr, re);
-    re = fmaf(-b.im, nim, re);
-    float im = fmaf(a.re, pim, v[k].im);
-    im = fmaf(a.im, pr, im);
-    im = fmaf(b.re, nim, im);
-    im = fmaf(b.im, nr, im);
-    v[k] = {re, im};
-  });
-  fence();
-  Dft<E, -1>::run(v);
-  fence();
-}
-
-// Full 1-D pyramid operator for one line.
-//   load_in(m)  = f(x) w_N^{(2q+1) x} at x = l + 4 m (tilted input times this
-//                 quad's twist, one complex product from a combined table);
-//   load_f(m)   = f(l + 4 m) (needed by quad 0 for y_L = f - y_H);
-//   outw[q * P + j] = (4/N) w_N^{-(2q+1) j}  (2/N times the 2 the half-band step leaves out).
-// On return quad 0 holds y_L(l + 4 m) and quad 1 holds y_H(l + 4 m) in v[m].
-template <int E, typename LoadIn, typename LoadF>
-__device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadF&& load_f,
-                                        const cpx* __restrict__ mid, const cpx* __restrict__ outw,
-                                        int q, int l) {
-  constexpr int P = 4 * E;
-  static_for<0, E>([&](auto m_) {
-    constexpr int m = decltype(m_)::value;
-    if constexpr (m % 8 == 0 && m > 0) fence();
-    v[m] = load_in(m);
-  });
-  fence();
-  half_band<E>(v, mid, l);
-  const cpx* ow = outw + q * TabLds<E>::QO + l;
-  const float keep = (q == 0) ? 1.f : 0.f;   // quad 0 adds f back (y_L = f - y_H)
-  const float sgn = (q == 0) ? -1.f : 1.f;
-  static_for<0, E>([&](auto m_) {
-    constexpr int m = decltype(m_)::value;
-    if constexpr (m % 8 == 0 && m > 0) fence();
-    cpx w = cmul(v[m], ow[4 * m]);
-    w.re += swap_quads(w.re);
-    w.im += swap_quads(w.im);
-    const cpx f = load_f(m);
-    v[m] = {fmaf(sgn, w.re, keep * f.re), fmaf(sgn, w.im, keep * f.im)};
-  });
-}
-
-__device__ __forceinline__ size_t rw_index(int xp, int y, int P) {
-  return ((size_t)(xp >> 3) * (size_t)(P >> 2) + (size_t)(y >> 2)) * 32u + (size_t)((xp & 7) * 4 + (y & 3));
-}
-
-// Block-cooperative copy of n16 16-byte words (global -> LDS).
-__device__ __forceinline__ void copy16(void* __restrict__ dst, const void* __restrict__ src, int n16,
-                                       int tid, int nthreads) {
-  uint4* d = reinterpret_cast<uint4*>(dst);
-  const uint4* s = reinterpret_cast<const uint4*>(src);
-  for (int i = tid; i < n16; i += nthreads) d[i] = s[i];
-}
-
-// Block copy of exactly 256 N 16-byte words: every load is issued before the
-// first LDS write, so a thread waits for one memory round trip, not N.
-template <int N>
-__device__ __forceinline__ void copy16_n(void* __restrict__ dst, const void* __restrict__ src, int tid) {
-  uint4* d = reinterpret_cast<uint4*>(dst);
-  const uint4* s = reinterpret_cast<const uint4*>(src);
-  uint4 r[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) r[i] = s[tid + 256 * i];
-  fence();
-#pragma unroll
-  for (int i = 0; i < N; ++i) d[tid + 256 * i] = r[i];
-}
-
-// Table [2][P] (quad 0 half, quad 1 half) -> LDS with quad 1 at TabLds::QO.
-template <int E>
-__device__ __forceinline__ void stage_quads(cpx* __restrict__ dst, const cpx* __restrict__ src, int tid) {
-  constexpr int P = 4 * E;
-  copy16(dst, src, P / 2, tid, 256);
-  copy16(dst + TabLds<E>::QO, src + P, P / 2, tid, 256);
-}
-
-// Mix table [4][2E] -> LDS rows of stride TabLds::MS.
-template <int E>
-__device__ __forceinline__ void stage_mid(cpx* __restrict__ dst, const cpx* __restrict__ src, int tid) {
-  for (int i = tid; i < 4 * E; i += 256) {
-    const int l = i / E, r = i - l * E;
-    reinterpret_cast<uint4*>(dst + l * TabLds<E>::MS)[r] = reinterpret_cast<const uint4*>(src + l * 2 * E)[r];
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Pupil field A exp(i phi), phi = 2 pi opd 1e-9 / lambda formed and reduced
@@ -391,391 +261,6 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   }
 }
 
-// ===========================================================================
-// Long lines, P = 16 E (P = 128, 480).  The four lanes of the quad form above
-// become four 4-lane subgroups: a projection is held by a row of 16 lanes,
-// lane 4 l1 + l2 holding the samples x = l1 + 4 l2 + 16 m (m < E), so that
-// "outer lane" l1 holds x = l1 + 4 m' with m' = l2 + 4 m as before.  Its
-// DFT over m' (length 4E) is done by the subgroup in four steps:
-//   in-lane DFT_E over m  ->  twiddle w_{4E}^{l2 k1}  ->  DFT_4 across the
-//   subgroup (two DPP radix-2 butterflies; lane l2 ends with t' = k1 + E rev(l2))
-// then the folded 3-tap mix of the quad form runs between outer lanes
-// l1 +- 1, i.e. lanes +-4 of the row (DPP row rotations), with its
-// coefficients tabulated per (lane, k1); then the same four steps inverted.
-// A line takes 32 lanes, the two projections exchanging halves with
-// ds_swizzle (lane ^ 16).
-
-template <int E>
-struct Tab16 {
-  static constexpr int P = 16 * E;
-  static constexpr int QO = P + 16;   // offset of projection 1's half of an input / output table (other bank half)
-  static constexpr int MS = 2 * E + 2;  // per-lane row stride of the mix table
-  static constexpr int TS = E + 1;    // per-l2 row stride of the subgroup twiddles
-  static constexpr int LDP = P + 16;  // field row stride in the row pass (two rows per wave on opposite bank halves)
-  static constexpr int GS = 40;       // y-group stride of the staged columns (column pass)
-};
-
-// mid [16][E][2] = (A/2, B/2) for lane 4 l1 + l2 at t' = k1 + E rev(l2);
-// tw [4][E] = w_{4E}^{l2 k1}; outw [2][P].
-template <int E>
-__device__ __forceinline__ void stage_tables16(cpx* __restrict__ s_mid, cpx* __restrict__ s_tw,
-                                               cpx* __restrict__ s_out, const cpx* __restrict__ mid,
-                                               const cpx* __restrict__ tw, const cpx* __restrict__ outw, int tid,
-                                               int nthreads) {
-  using T = Tab16<E>;
-  for (int i = tid; i < 16 * E; i += nthreads) {
-    const int row = i / E, k = i - row * E;
-    reinterpret_cast<uint4*>(s_mid + row * T::MS)[k] = reinterpret_cast<const uint4*>(mid + row * 2 * E)[k];
-  }
-  for (int i = tid; i < 4 * E; i += nthreads) {
-    const int row = i / E, k = i - row * E;
-    s_tw[row * T::TS + k] = tw[row * E + k];
-  }
-  copy16(s_out, outw, T::P / 2, tid, nthreads);
-  copy16(s_out + T::QO, outw + T::P, T::P / 2, tid, nthreads);
-}
-
-// Half-band projection held by a 16-lane row (see above), up to the factor
-// 1/2 that the output table absorbs.  ml: this lane's mix row, tl: its twiddles.
-template <int E>
-__device__ __forceinline__ void half_band16(cpx (&v)[E], const cpx* __restrict__ ml, const cpx* __restrict__ tl,
-                                            float sA, float sB, bool l3) {
-  Dft<E, +1>::run(v);
-  fence();
-  static_for<0, E>([&](auto k_) {
-    constexpr int k = decltype(k_)::value;
-    if constexpr (k % 8 == 0 && k > 0) fence();
-    v[k] = quad_dft4_fwd(cmul(v[k], tl[k]), sA, sB, l3);
-  });
-  fence();
-  static_for<0, E>([&](auto k_) {
-    constexpr int k = decltype(k_)::value;
-    if constexpr (k % 8 == 0 && k > 0) fence();
-    const cpx a = ml[2 * k], b = ml[2 * k + 1];
-    const float pr = row_from_plus4(v[k].re), pim = row_from_plus4(v[k].im);     // outer lane l1 + 1
-    const float nr = row_from_minus4(v[k].re), nim = row_from_minus4(v[k].im);   // outer lane l1 - 1
-    float re = fmaf(a.re, pr, v[k].re);
-    re = fmaf(-a.im, pim, re);
-    re = fmaf(b.re, nr, re);
-    re = fmaf(-b.im, nim, re);
-    float im = fmaf(a.re, pim, v[k].im);
-    im = fmaf(a.im, pr, im);
-    im = fmaf(b.re, nim, im);
-    im = fmaf(b.im, nr, im);
-    v[k] = {re, im};
-  });
-  fence();
-  static_for<0, E>([&](auto k_) {
-    constexpr int k = decltype(k_)::value;
-    if constexpr (k % 8 == 0 && k > 0) fence();
-    v[k] = cmulc(quad_dft4_inv(v[k], sA, sB, l3), tl[k]);
-  });
-  fence();
-  Dft<E, -1>::run(v);
-  fence();
-}
-
-// Full 1-D pyramid operator of one line held by a 32-lane team.
-//   load_in(m) = f(x) w_N^{(2q+1) x}, load_f(m) = f(x) at x = l1 + 4 l2 + 16 m;
-//   ow = outw + q QO + l1 + 4 l2.
-// On return projection 0 holds y_L(x) and projection 1 holds y_H(x) in v[m].
-template <int E, typename LoadIn, typename LoadF>
-__device__ __forceinline__ void line_op16(cpx (&v)[E], LoadIn&& load_in, LoadF&& load_f, const cpx* __restrict__ ml,
-                                          const cpx* __restrict__ tl, const cpx* __restrict__ ow, int q, float sA,
-                                          float sB, bool l3) {
-  static_for<0, E>([&](auto m_) {
-    constexpr int m = decltype(m_)::value;
-    if constexpr (m % 8 == 0 && m > 0) fence();
-    v[m] = load_in(m);
-  });
-  fence();
-  half_band16<E>(v, ml, tl, sA, sB, l3);
-  const float keep = (q == 0) ? 1.f : 0.f;
-  const float sgn = (q == 0) ? -1.f : 1.f;
-  static_for<0, E>([&](auto m_) {
-    constexpr int m = decltype(m_)::value;
-    if constexpr (m % 8 == 0 && m > 0) fence();
-    cpx w = cmul(v[m], ow[16 * m]);
-    w.re += swap_halves(w.re);
-    w.im += swap_halves(w.im);
-    const cpx f = load_f(m);
-    v[m] = {fmaf(sgn, w.re, keep * f.re), fmaf(sgn, w.im, keep * f.im)};
-  });
-}
-
-// Row pass, long lines.  Block = 4 waves = 8 pupil rows of one frame (two
-// 32-lane teams per wave), looping over a chunk of distinct x tilts.
-template <int E>
-__global__ __launch_bounds__(256) void row_pass16_kernel(
-    const cpx* __restrict__ fieldg, const cpx* __restrict__ in_a, const cpx* __restrict__ f_a,
-    const cpx* __restrict__ mid, const cpx* __restrict__ tw, const cpx* __restrict__ outw, cpx* __restrict__ Rw,
-    int n_a, int a_chunk) {
-  using T = Tab16<E>;
-  constexpr int P = T::P;
-  __shared__ __align__(16) cpx field[8 * T::LDP];
-  __shared__ __align__(16) cpx s_in[2 * T::QO];
-  __shared__ __align__(16) cpx s_f[P];
-  __shared__ __align__(16) cpx s_mid[16 * T::MS];
-  __shared__ __align__(16) cpx s_tw[4 * T::TS];
-  __shared__ __align__(16) cpx s_out[2 * T::QO];
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int team = lane >> 5, q = (lane >> 4) & 1, l16 = lane & 15, l1 = l16 >> 2, l2 = l16 & 3;
-  const int yb = blockIdx.x * 8;
-  const int a0 = blockIdx.y * a_chunk;
-  const size_t fr = blockIdx.z;
-  // 8 field rows (contiguous in HBM, 4 P 16-byte words) -> LDS rows of stride
-  // LDP; every load is issued before the first LDS write.
-  {
-    constexpr int NW = 4 * P;
-    constexpr int NPT = (NW + 255) / 256;
-    const uint4* src = reinterpret_cast<const uint4*>(fieldg + (fr * (size_t)P + yb) * (size_t)P);
-    uint4 w[NPT];
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int e = tid + 256 * i;
-      if (e < NW) w[i] = src[e];
-    }
-    fence();
-#pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int e = tid + 256 * i;
-      if (e < NW) {
-        const int r = e / (P / 2), c2 = e - r * (P / 2);
-        *reinterpret_cast<uint4*>(field + r * T::LDP + 2 * c2) = w[i];
-      }
-    }
-  }
-  stage_tables16<E>(s_mid, s_tw, s_out, mid, tw, outw, tid, 256);
-  const int a1 = min(a0 + a_chunk, n_a);
-  const int r = wave * 2 + team;                  // row within the block
-  const int y = yb + r;
-  const int xl = l1 + 4 * l2;                     // this lane's samples: x = xl + 16 m
-  const cpx* frow = field + r * T::LDP + xl;
-  const cpx* ml = s_mid + l16 * T::MS;
-  const cpx* tl = s_tw + l2 * T::TS;
-  const cpx* ow = s_out + q * T::QO + xl;
-  const cpx* tin = s_in + q * T::QO + xl;
-  const cpx* tf = s_f + xl;
-  const float sA = (l2 & 2) ? -1.f : 1.f, sB = (l2 & 1) ? -1.f : 1.f;
-  const bool l3 = l2 == 3;
-  for (int ia = a0; ia < a1; ++ia) {
-    __syncthreads();
-    copy16(s_in, in_a + (size_t)ia * 2 * P, P / 2, tid, 256);
-    copy16(s_in + T::QO, in_a + (size_t)ia * 2 * P + P, P / 2, tid, 256);
-    copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
-    __syncthreads();
-    cpx v[E];
-    line_op16<E>(v, [&](int m) { return cmul(frow[16 * m], tin[16 * m]); },
-                 [&](int m) { return cmul(frow[16 * m], tf[16 * m]); }, ml, tl, ow, q, sA, sB, l3);
-    // Element (x' = qP + xl + 16 m, y): consecutive m are 16 P apart in the
-    // intermediate layout (two 8-column groups); addresses formed just in time.
-    cpx* out = Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P) + rw_index(q * P + xl, y, P);
-    fence();
-    static_for<0, E>([&](auto m_) {
-      constexpr int m = decltype(m_)::value;
-      cpx* o = out + (size_t)m * 16 * P;
-      asm volatile("" : "+v"(o));
-      *o = v[m];
-    });
-  }
-}
-
-// Column pass, long lines.  Block = CB / 2 waves = CB adjacent columns x' of
-// one frame (one 32-lane team per column) and one chunk of modulation points;
-// CB = 8, or 10 when the binning is 5 (a block must hold whole bins and
-// never straddle the two pupil windows).  The CB columns of one distinct x
-// tilt are gathered from the intermediate into LDS as [y/4][column][y%4]
-// with a y-group stride of 40 values (conflict-free reads); each team
-// accumulates |E|^2 of its column over the chunk in registers, then the
-// block bins b x b through LDS and writes its part of the chunk's pupils.
-template <int E, int CB>
-__global__ __launch_bounds__(32 * CB) void col_pass16_kernel(
-    const cpx* __restrict__ Rw, const cpx* __restrict__ in_b, const cpx* __restrict__ f_b,
-    const int* __restrict__ k_order, const int* __restrict__ k_ia, const cpx* __restrict__ mid,
-    const cpx* __restrict__ tw, const cpx* __restrict__ outw, float* __restrict__ partial, int n_a, int K,
-    int k_chunk, int n_chunks, int n_bin) {
-  using T = Tab16<E>;
-  constexpr int P = T::P;
-  constexpr int NT = 32 * CB;
-  constexpr int G = P / 4;                        // y groups of 4 rows
-  static_assert(4 * CB <= T::GS, "staged columns exceed the y-group stride");
-  __shared__ __align__(16) cpx s_col[G * T::GS];
-  __shared__ __align__(16) cpx s_in[2 * T::QO];
-  __shared__ __align__(16) cpx s_f[P];
-  __shared__ __align__(16) cpx s_mid[16 * T::MS];
-  __shared__ __align__(16) cpx s_tw[4 * T::TS];
-  __shared__ __align__(16) cpx s_out[2 * T::QO];
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int team = lane >> 5, q = (lane >> 4) & 1, l16 = lane & 15, l1 = l16 >> 2, l2 = l16 & 3;
-  const int X0 = blockIdx.x * CB;
-  const int chunk = blockIdx.y;
-  const size_t fr = blockIdx.z;
-  float acc[E];
-  static_for<0, E>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
-  stage_tables16<E>(s_mid, s_tw, s_out, mid, tw, outw, tid, NT);
-  const int kb = chunk * k_chunk;
-  const int ke = min(kb + k_chunk, K);
-  const cpx* frame = Rw + fr * (size_t)n_a * (size_t)(2 * P * P);
-  const int c = wave * 2 + team;                  // column within the block
-  const int xl = l1 + 4 * l2;                     // this lane's rows: y = xl + 16 m
-  const cpx* colp = s_col + l2 * T::GS + c * 4 + l1;   // row y = xl + 16 m at colp[4 m GS]
-  const cpx* ml = s_mid + l16 * T::MS;
-  const cpx* tl = s_tw + l2 * T::TS;
-  const cpx* ow = s_out + q * T::QO + xl;
-  const cpx* tin = s_in + q * T::QO + xl;
-  const cpx* tf = s_f + xl;
-  const float sA = (l2 & 2) ? -1.f : 1.f, sB = (l2 & 1) ? -1.f : 1.f;
-  const bool l3 = l2 == 3;
-  int cur_ia = -1;
-  for (int kk = kb; kk < ke; ++kk) {
-    const int k = k_order[kk];
-    const int ia = k_ia[k];
-    __syncthreads();
-    if (ia != cur_ia) {
-      // (y group g, column c, half h) <- 4 values (y = 4g .. 4g+3) of column X0 + c,
-      // two 16-byte words; all loads issued before the LDS writes.
-      constexpr int NW = G * CB * 2;
-      constexpr int NPT = (NW + NT - 1) / NT;
-      const cpx* src = frame + (size_t)ia * (size_t)(2 * P * P);
-      uint4 w[NPT];
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const int u = tid + NT * i;
-        if (u < NW) {
-          const int g = u / (2 * CB), rem = u - g * (2 * CB), cc = rem >> 1, h = rem & 1;
-          w[i] = *reinterpret_cast<const uint4*>(src + rw_index(X0 + cc, 4 * g, P) + 2 * h);
-        }
-      }
-      fence();
-#pragma unroll
-      for (int i = 0; i < NPT; ++i) {
-        const int u = tid + NT * i;
-        if (u < NW) {
-          const int g = u / (2 * CB), rem = u - g * (2 * CB), cc = rem >> 1, h = rem & 1;
-          *reinterpret_cast<uint4*>(s_col + g * T::GS + cc * 4 + 2 * h) = w[i];
-        }
-      }
-      cur_ia = ia;
-    }
-    copy16(s_in, in_b + (size_t)k * 2 * P, P / 2, tid, NT);
-    copy16(s_in + T::QO, in_b + (size_t)k * 2 * P + P, P / 2, tid, NT);
-    copy16(s_f, f_b + (size_t)k * P, P / 2, tid, NT);
-    __syncthreads();
-    cpx v[E];
-    line_op16<E>(v, [&](int m) { return cmul(colp[4 * m * T::GS], tin[16 * m]); },
-                 [&](int m) { return cmul(colp[4 * m * T::GS], tf[16 * m]); }, ml, tl, ow, q, sA, sB, l3);
-    static_for<0, E>([&](auto m_) {
-      constexpr int m = decltype(m_)::value;
-      acc[m] += fmaf(v[m].re, v[m].re, v[m].im * v[m].im);
-    });
-  }
-  __syncthreads();
-  // tile[c][q][row] (CB 2 P floats, within s_col), then b x b binning.
-  float* tile = reinterpret_cast<float*>(s_col);
-  float* my = tile + (c * 2 + q) * P + xl;
-  static_for<0, E>([&](auto m_) {
-    constexpr int m = decltype(m_)::value;
-    my[16 * m] = acc[m];
-  });
-  __syncthreads();
-  const int S = P / n_bin;
-  const int nbc = CB / n_bin;
-  const int xw = X0 >= P ? 1 : 0;
-  const int ix0 = (X0 - xw * P) / n_bin;
-  float* dst = partial + (fr * (size_t)n_chunks + chunk) * (size_t)(4 * S * S);
-  for (int o = tid; o < nbc * 2 * S; o += NT) {
-    const int bc = o / (2 * S);
-    const int rem = o - bc * 2 * S;
-    const int qq = rem / S;
-    const int iy = rem - qq * S;
-    float sum = 0.f;
-    for (int dx = 0; dx < n_bin; ++dx) {
-      const float* gp = tile + ((bc * n_bin + dx) * 2 + qq) * P + iy * n_bin;
-      for (int dy = 0; dy < n_bin; ++dy) sum += gp[dy];
-    }
-    dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = sum;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Detector (the paper's CCD step: photon noise, readout noise, quantum
-// efficiency folded into the gain).  One thread per binned pixel:
-//   lam = gain * I (FP64 product of FP32 values), k ~ Poisson(lam),
-//   pixel = k + ron z, z ~ N(0, 1).
-// Counter-based random numbers: Philox4x32-10 (Salmon et al., SC'11), key =
-// seed, counter = (pixel, frame low word, frame high word, draw word d).  The
-// count multiplies uniforms u = (x + 1/2) 2^-32 in FP64 (draw words d = 0, 1,
-// ... in order, four uniforms each) until the product falls to exp(-lam/n) or
-// below, for each of n = ceil(lam / 500) equal pieces; above lam = 1e4 it is
-// floor(lam + sqrt(lam) z' + 1/2) clipped at 0.  z and z' are Box-Muller
-// deviates of the draw word 2^31 (uniform pairs 1-2 and 3-4).  Only IEEE
-// products and one FP64 exp take the integer decision.
-__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = (uint32_t)p1;
-    c[2] = n2;
-    c[3] = (uint32_t)p0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-
-__device__ __forceinline__ double u01(uint32_t x) { return ((double)x + 0.5) * 2.3283064365386963e-10; }
-
-__global__ __launch_bounds__(256) void detector_kernel(const float* __restrict__ in, float* __restrict__ out,
-                                                       int npix, uint64_t frame0, float gain, float ron,
-                                                       uint64_t seed) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const size_t b = blockIdx.y;
-  if (j >= npix) return;
-  const uint64_t f = frame0 + b;
-  const uint32_t flo = (uint32_t)f, fhi = (uint32_t)(f >> 32);
-  const uint32_t klo = (uint32_t)seed, khi = (uint32_t)(seed >> 32);
-  const double lam = (double)gain * (double)in[b * (size_t)npix + j];
-  uint32_t w[4] = {(uint32_t)j, flo, fhi, 0x80000000u};
-  philox4x32_10(w, klo, khi);
-  constexpr double two_pi = 6.283185307179586476925286766559;
-  const double z = sqrt(-2.0 * log(u01(w[0]))) * cos(two_pi * u01(w[1]));
-  double k = 0.0;  // whole numbers, exact in FP64 up to 2^53
-  if (lam > 1.0e4) {
-    const double z2 = sqrt(-2.0 * log(u01(w[2]))) * cos(two_pi * u01(w[3]));
-    k = fmax(0.0, floor(lam + sqrt(lam) * z2 + 0.5));
-  } else if (lam > 0.0) {
-    const double npieces = ceil(lam / 500.0);
-    const double L = exp(-(lam / npieces));
-    double p = 1.0, piece = 0.0;
-    uint32_t t = 0;
-    uint32_t buf[4] = {0u, 0u, 0u, 0u};
-    while (piece < npieces) {
-      if ((t & 3u) == 0u) {
-        buf[0] = (uint32_t)j;
-        buf[1] = flo;
-        buf[2] = fhi;
-        buf[3] = t >> 2;
-        philox4x32_10(buf, klo, khi);
-      }
-      const uint32_t x = (t & 3u) == 0u ? buf[0] : (t & 3u) == 1u ? buf[1] : (t & 3u) == 2u ? buf[2] : buf[3];
-      ++t;
-      p *= u01(x);
-      if (p <= L) {
-        piece += 1.0;
-        p = 1.0;
-      } else {
-        k += 1.0;
-      }
-    }
-  }
-  out[b * (size_t)npix + j] = (float)(k + (double)ron * z);
-}
-
 // ---------------------------------------------------------------------------
 // Pupil reduction: sum of the chunk partials in chunk order (fixed order,
 // loads issued four at a time), scaled by 1/K.  One thread per binned pixel.
@@ -970,13 +455,17 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(const float* __restrict
 
 // ---------------------------------------------------------------------------
 // Host launchers.
-template <int E>
-static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
+hipError_t launch_field(const MeasureArgs& a, hipStream_t st) {
   const size_t n = (size_t)a.B * a.P * a.P;
   const unsigned fb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(field_kernel, dim3(fb), dim3(256), 0, st, a.opd, a.amp, a.kphase, a.fp32_phase, a.P * a.P, n,
                      a.field);
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+template <int E>
+static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
+  hipError_t e = launch_field(a, st);
   if (e != hipSuccess) return e;
   dim3 grid(a.P / 32, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
   hipLaunchKernelGGL(row_pass_kernel<E>, grid, dim3(256), 0, st, a.field, a.in_a, a.f_a, a.mid, a.outw, a.Rw,
@@ -996,36 +485,6 @@ static hipError_t launch_cols(const MeasureArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int E>
-static hipError_t launch_rows16(const MeasureArgs& a, hipStream_t st) {
-  const size_t n = (size_t)a.B * a.P * a.P;
-  const unsigned fb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(field_kernel, dim3(fb), dim3(256), 0, st, a.opd, a.amp, a.kphase, a.fp32_phase, a.P * a.P, n,
-                     a.field);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  dim3 grid(a.P / 8, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
-  hipLaunchKernelGGL(row_pass16_kernel<E>, grid, dim3(256), 0, st, a.field, a.in_a, a.f_a, a.mid, a.tw16, a.outw,
-                     a.Rw, a.n_a, a.a_chunk);
-  return hipGetLastError();
-}
-
-template <int E, int CB>
-static hipError_t launch_cols16(const MeasureArgs& a, hipStream_t st) {
-  dim3 grid(2 * a.P / CB, a.n_chunks, a.B);
-  hipLaunchKernelGGL((col_pass16_kernel<E, CB>), grid, dim3(32 * CB), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
-                     a.k_ia, a.mid, a.tw16, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
-  return hipGetLastError();
-}
-
-hipError_t launch_detector(const float* intensity, float* pixels, int npix, int B, uint64_t frame0, float gain,
-                           float ron, uint64_t seed, hipStream_t st) {
-  if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(detector_kernel, dim3((npix + 255) / 256, B), dim3(256), 0, st, intensity, pixels, npix, frame0,
-                     gain, ron, seed);
-  return hipGetLastError();
-}
-
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) {
   hipError_t e = hipSuccess;
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
@@ -1033,8 +492,8 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
     case 32: e = launch_rows<8>(a, st); break;
     case 64: e = launch_rows<16>(a, st); break;
     case 160: e = launch_rows<40>(a, st); break;
-    case 128: e = launch_rows16<8>(a, st); break;
-    case 480: e = launch_rows16<30>(a, st); break;
+    case 128:
+    case 480: e = launch_rows_long(a, st); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
@@ -1043,8 +502,8 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
     case 32: e = launch_cols<8>(a, st); break;
     case 64: e = launch_cols<16>(a, st); break;
     case 160: e = launch_cols<40>(a, st); break;
-    case 128: e = launch_cols16<8, 8>(a, st); break;
-    case 480: e = a.n_bin == 5 ? launch_cols16<30, 10>(a, st) : launch_cols16<30, 8>(a, st); break;
+    case 128:
+    case 480: e = launch_cols_long(a, st); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;

@@ -1,0 +1,352 @@
+// pwfs_kernels16.hip -- pyramid line kernels for long lines, P = 16 E (P = 128, 480), gfx950.
+#include "pwfs_common.h"
+#include "pwfs_launch.h"
+
+#include <algorithm>
+#include <cstdint>
+
+namespace pwfs {
+
+// ===========================================================================
+// Long lines, P = 16 E (P = 128, 480).  The four lanes of the quad form above
+// become four 4-lane subgroups: a projection is held by a row of 16 lanes,
+// lane 4 l1 + l2 holding the samples x = l1 + 4 l2 + 16 m (m < E), so that
+// "outer lane" l1 holds x = l1 + 4 m' with m' = l2 + 4 m as before.  Its
+// DFT over m' (length 4E) is done by the subgroup in four steps:
+//   in-lane DFT_E over m  ->  twiddle w_{4E}^{l2 k1}  ->  DFT_4 across the
+//   subgroup (two DPP radix-2 butterflies; lane l2 ends with t' = k1 + E rev(l2))
+// then the folded 3-tap mix of the quad form runs between outer lanes
+// l1 +- 1, i.e. lanes +-4 of the row (DPP row rotations), with its
+// coefficients tabulated per (lane, k1); then the same four steps inverted.
+// A line takes 32 lanes, the two projections exchanging halves with
+// ds_swizzle (lane ^ 16).
+
+template <int E>
+struct Tab16 {
+  static constexpr int P = 16 * E;
+  static constexpr int QO = P + 16;   // offset of projection 1's half of an input / output table (other bank half)
+  static constexpr int MS = 2 * E + 2;  // per-lane row stride of the mix table
+  static constexpr int TS = E + 1;    // per-l2 row stride of the subgroup twiddles
+  static constexpr int LDP = P + 16;  // field row stride in the row pass (two rows per wave on opposite bank halves)
+  static constexpr int GS = 40;       // y-group stride of the staged columns (column pass)
+};
+
+// mid [16][E][2] = (A/2, B/2) for lane 4 l1 + l2 at t' = k1 + E rev(l2);
+// tw [4][E] = w_{4E}^{l2 k1}; outw [2][P].
+template <int E>
+__device__ __forceinline__ void stage_tables16(cpx* __restrict__ s_mid, cpx* __restrict__ s_tw,
+                                               cpx* __restrict__ s_out, const cpx* __restrict__ mid,
+                                               const cpx* __restrict__ tw, const cpx* __restrict__ outw, int tid,
+                                               int nthreads) {
+  using T = Tab16<E>;
+  for (int i = tid; i < 16 * E; i += nthreads) {
+    const int row = i / E, k = i - row * E;
+    reinterpret_cast<uint4*>(s_mid + row * T::MS)[k] = reinterpret_cast<const uint4*>(mid + row * 2 * E)[k];
+  }
+  for (int i = tid; i < 4 * E; i += nthreads) {
+    const int row = i / E, k = i - row * E;
+    s_tw[row * T::TS + k] = tw[row * E + k];
+  }
+  copy16(s_out, outw, T::P / 2, tid, nthreads);
+  copy16(s_out + T::QO, outw + T::P, T::P / 2, tid, nthreads);
+}
+
+// Half-band projection held by a 16-lane row (see above), up to the factor
+// 1/2 that the output table absorbs.  ml: this lane's mix row, tl: its twiddles.
+template <int E>
+__device__ __forceinline__ void half_band16(cpx (&v)[E], const cpx* __restrict__ ml, const cpx* __restrict__ tl,
+                                            float sA, float sB, bool l3) {
+  Dft<E, +1>::run(v);
+  fence();
+  static_for<0, E>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    if constexpr (k % 8 == 0 && k > 0) fence();
+    v[k] = quad_dft4_fwd(cmul(v[k], tl[k]), sA, sB, l3);
+  });
+  fence();
+  static_for<0, E>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    if constexpr (k % 8 == 0 && k > 0) fence();
+    const cpx a = ml[2 * k], b = ml[2 * k + 1];
+    const float pr = row_from_plus4(v[k].re), pim = row_from_plus4(v[k].im);     // outer lane l1 + 1
+    const float nr = row_from_minus4(v[k].re), nim = row_from_minus4(v[k].im);   // outer lane l1 - 1
+    float re = fmaf(a.re, pr, v[k].re);
+    re = fmaf(-a.im, pim, re);
+    re = fmaf(b.re, nr, re);
+    re = fmaf(-b.im, nim, re);
+    float im = fmaf(a.re, pim, v[k].im);
+    im = fmaf(a.im, pr, im);
+    im = fmaf(b.re, nim, im);
+    im = fmaf(b.im, nr, im);
+    v[k] = {re, im};
+  });
+  fence();
+  static_for<0, E>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    if constexpr (k % 8 == 0 && k > 0) fence();
+    v[k] = cmulc(quad_dft4_inv(v[k], sA, sB, l3), tl[k]);
+  });
+  fence();
+  Dft<E, -1>::run(v);
+  fence();
+}
+
+// Full 1-D pyramid operator of one line held by a 32-lane team.
+//   load_in(m) = f(x) w_N^{(2q+1) x}, load_f(m) = f(x) at x = l1 + 4 l2 + 16 m;
+//   ow = outw + q QO + l1 + 4 l2.
+// On return projection 0 holds y_L(x) and projection 1 holds y_H(x) in v[m].
+template <int E, typename LoadIn, typename LoadF>
+__device__ __forceinline__ void line_op16(cpx (&v)[E], LoadIn&& load_in, LoadF&& load_f, const cpx* __restrict__ ml,
+                                          const cpx* __restrict__ tl, const cpx* __restrict__ ow, int q, float sA,
+                                          float sB, bool l3) {
+  static_for<0, E>([&](auto m_) {
+    constexpr int m = decltype(m_)::value;
+    if constexpr (m % 8 == 0 && m > 0) fence();
+    v[m] = load_in(m);
+  });
+  fence();
+  half_band16<E>(v, ml, tl, sA, sB, l3);
+  const float keep = (q == 0) ? 1.f : 0.f;
+  const float sgn = (q == 0) ? -1.f : 1.f;
+  static_for<0, E>([&](auto m_) {
+    constexpr int m = decltype(m_)::value;
+    if constexpr (m % 8 == 0 && m > 0) fence();
+    cpx w = cmul(v[m], ow[16 * m]);
+    w.re += swap_halves(w.re);
+    w.im += swap_halves(w.im);
+    const cpx f = load_f(m);
+    v[m] = {fmaf(sgn, w.re, keep * f.re), fmaf(sgn, w.im, keep * f.im)};
+  });
+}
+
+// Row pass, long lines.  Block = 4 waves = 8 pupil rows of one frame (two
+// 32-lane teams per wave), looping over a chunk of distinct x tilts.
+template <int E>
+__global__ __launch_bounds__(256) void row_pass16_kernel(
+    const cpx* __restrict__ fieldg, const cpx* __restrict__ in_a, const cpx* __restrict__ f_a,
+    const cpx* __restrict__ mid, const cpx* __restrict__ tw, const cpx* __restrict__ outw, cpx* __restrict__ Rw,
+    int n_a, int a_chunk) {
+  using T = Tab16<E>;
+  constexpr int P = T::P;
+  __shared__ __align__(16) cpx field[8 * T::LDP];
+  __shared__ __align__(16) cpx s_in[2 * T::QO];
+  __shared__ __align__(16) cpx s_f[P];
+  __shared__ __align__(16) cpx s_mid[16 * T::MS];
+  __shared__ __align__(16) cpx s_tw[4 * T::TS];
+  __shared__ __align__(16) cpx s_out[2 * T::QO];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int team = lane >> 5, q = (lane >> 4) & 1, l16 = lane & 15, l1 = l16 >> 2, l2 = l16 & 3;
+  const int yb = blockIdx.x * 8;
+  const int a0 = blockIdx.y * a_chunk;
+  const size_t fr = blockIdx.z;
+  // 8 field rows (contiguous in HBM, 4 P 16-byte words) -> LDS rows of stride
+  // LDP; every load is issued before the first LDS write.
+  {
+    constexpr int NW = 4 * P;
+    constexpr int NPT = (NW + 255) / 256;
+    const uint4* src = reinterpret_cast<const uint4*>(fieldg + (fr * (size_t)P + yb) * (size_t)P);
+    uint4 w[NPT];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int e = tid + 256 * i;
+      if (e < NW) w[i] = src[e];
+    }
+    fence();
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int e = tid + 256 * i;
+      if (e < NW) {
+        const int r = e / (P / 2), c2 = e - r * (P / 2);
+        *reinterpret_cast<uint4*>(field + r * T::LDP + 2 * c2) = w[i];
+      }
+    }
+  }
+  stage_tables16<E>(s_mid, s_tw, s_out, mid, tw, outw, tid, 256);
+  const int a1 = min(a0 + a_chunk, n_a);
+  const int r = wave * 2 + team;                  // row within the block
+  const int y = yb + r;
+  const int xl = l1 + 4 * l2;                     // this lane's samples: x = xl + 16 m
+  const cpx* frow = field + r * T::LDP + xl;
+  const cpx* ml = s_mid + l16 * T::MS;
+  const cpx* tl = s_tw + l2 * T::TS;
+  const cpx* ow = s_out + q * T::QO + xl;
+  const cpx* tin = s_in + q * T::QO + xl;
+  const cpx* tf = s_f + xl;
+  const float sA = (l2 & 2) ? -1.f : 1.f, sB = (l2 & 1) ? -1.f : 1.f;
+  const bool l3 = l2 == 3;
+  for (int ia = a0; ia < a1; ++ia) {
+    __syncthreads();
+    copy16(s_in, in_a + (size_t)ia * 2 * P, P / 2, tid, 256);
+    copy16(s_in + T::QO, in_a + (size_t)ia * 2 * P + P, P / 2, tid, 256);
+    copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
+    __syncthreads();
+    cpx v[E];
+    line_op16<E>(v, [&](int m) { return cmul(frow[16 * m], tin[16 * m]); },
+                 [&](int m) { return cmul(frow[16 * m], tf[16 * m]); }, ml, tl, ow, q, sA, sB, l3);
+    // Element (x' = qP + xl + 16 m, y): consecutive m are 16 P apart in the
+    // intermediate layout (two 8-column groups); addresses formed just in time.
+    cpx* out = Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P) + rw_index(q * P + xl, y, P);
+    fence();
+    static_for<0, E>([&](auto m_) {
+      constexpr int m = decltype(m_)::value;
+      cpx* o = out + (size_t)m * 16 * P;
+      asm volatile("" : "+v"(o));
+      *o = v[m];
+    });
+  }
+}
+
+// Column pass, long lines.  Block = CB / 2 waves = CB adjacent columns x' of
+// one frame (one 32-lane team per column) and one chunk of modulation points;
+// CB = 8, or 10 when the binning is 5 (a block must hold whole bins and
+// never straddle the two pupil windows).  The CB columns of one distinct x
+// tilt are gathered from the intermediate into LDS as [y/4][column][y%4]
+// with a y-group stride of 40 values (conflict-free reads); each team
+// accumulates |E|^2 of its column over the chunk in registers, then the
+// block bins b x b through LDS and writes its part of the chunk's pupils.
+template <int E, int CB>
+__global__ __launch_bounds__(32 * CB) void col_pass16_kernel(
+    const cpx* __restrict__ Rw, const cpx* __restrict__ in_b, const cpx* __restrict__ f_b,
+    const int* __restrict__ k_order, const int* __restrict__ k_ia, const cpx* __restrict__ mid,
+    const cpx* __restrict__ tw, const cpx* __restrict__ outw, float* __restrict__ partial, int n_a, int K,
+    int k_chunk, int n_chunks, int n_bin) {
+  using T = Tab16<E>;
+  constexpr int P = T::P;
+  constexpr int NT = 32 * CB;
+  constexpr int G = P / 4;                        // y groups of 4 rows
+  static_assert(4 * CB <= T::GS, "staged columns exceed the y-group stride");
+  __shared__ __align__(16) cpx s_col[G * T::GS];
+  __shared__ __align__(16) cpx s_in[2 * T::QO];
+  __shared__ __align__(16) cpx s_f[P];
+  __shared__ __align__(16) cpx s_mid[16 * T::MS];
+  __shared__ __align__(16) cpx s_tw[4 * T::TS];
+  __shared__ __align__(16) cpx s_out[2 * T::QO];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int team = lane >> 5, q = (lane >> 4) & 1, l16 = lane & 15, l1 = l16 >> 2, l2 = l16 & 3;
+  const int X0 = blockIdx.x * CB;
+  const int chunk = blockIdx.y;
+  const size_t fr = blockIdx.z;
+  float acc[E];
+  static_for<0, E>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
+  stage_tables16<E>(s_mid, s_tw, s_out, mid, tw, outw, tid, NT);
+  const int kb = chunk * k_chunk;
+  const int ke = min(kb + k_chunk, K);
+  const cpx* frame = Rw + fr * (size_t)n_a * (size_t)(2 * P * P);
+  const int c = wave * 2 + team;                  // column within the block
+  const int xl = l1 + 4 * l2;                     // this lane's rows: y = xl + 16 m
+  const cpx* colp = s_col + l2 * T::GS + c * 4 + l1;   // row y = xl + 16 m at colp[4 m GS]
+  const cpx* ml = s_mid + l16 * T::MS;
+  const cpx* tl = s_tw + l2 * T::TS;
+  const cpx* ow = s_out + q * T::QO + xl;
+  const cpx* tin = s_in + q * T::QO + xl;
+  const cpx* tf = s_f + xl;
+  const float sA = (l2 & 2) ? -1.f : 1.f, sB = (l2 & 1) ? -1.f : 1.f;
+  const bool l3 = l2 == 3;
+  int cur_ia = -1;
+  for (int kk = kb; kk < ke; ++kk) {
+    const int k = k_order[kk];
+    const int ia = k_ia[k];
+    __syncthreads();
+    if (ia != cur_ia) {
+      // (y group g, column c, half h) <- 4 values (y = 4g .. 4g+3) of column X0 + c,
+      // two 16-byte words; all loads issued before the LDS writes.
+      constexpr int NW = G * CB * 2;
+      constexpr int NPT = (NW + NT - 1) / NT;
+      const cpx* src = frame + (size_t)ia * (size_t)(2 * P * P);
+      uint4 w[NPT];
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int u = tid + NT * i;
+        if (u < NW) {
+          const int g = u / (2 * CB), rem = u - g * (2 * CB), cc = rem >> 1, h = rem & 1;
+          w[i] = *reinterpret_cast<const uint4*>(src + rw_index(X0 + cc, 4 * g, P) + 2 * h);
+        }
+      }
+      fence();
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int u = tid + NT * i;
+        if (u < NW) {
+          const int g = u / (2 * CB), rem = u - g * (2 * CB), cc = rem >> 1, h = rem & 1;
+          *reinterpret_cast<uint4*>(s_col + g * T::GS + cc * 4 + 2 * h) = w[i];
+        }
+      }
+      cur_ia = ia;
+    }
+    copy16(s_in, in_b + (size_t)k * 2 * P, P / 2, tid, NT);
+    copy16(s_in + T::QO, in_b + (size_t)k * 2 * P + P, P / 2, tid, NT);
+    copy16(s_f, f_b + (size_t)k * P, P / 2, tid, NT);
+    __syncthreads();
+    cpx v[E];
+    line_op16<E>(v, [&](int m) { return cmul(colp[4 * m * T::GS], tin[16 * m]); },
+                 [&](int m) { return cmul(colp[4 * m * T::GS], tf[16 * m]); }, ml, tl, ow, q, sA, sB, l3);
+    static_for<0, E>([&](auto m_) {
+      constexpr int m = decltype(m_)::value;
+      acc[m] += fmaf(v[m].re, v[m].re, v[m].im * v[m].im);
+    });
+  }
+  __syncthreads();
+  // tile[c][q][row] (CB 2 P floats, within s_col), then b x b binning.
+  float* tile = reinterpret_cast<float*>(s_col);
+  float* my = tile + (c * 2 + q) * P + xl;
+  static_for<0, E>([&](auto m_) {
+    constexpr int m = decltype(m_)::value;
+    my[16 * m] = acc[m];
+  });
+  __syncthreads();
+  const int S = P / n_bin;
+  const int nbc = CB / n_bin;
+  const int xw = X0 >= P ? 1 : 0;
+  const int ix0 = (X0 - xw * P) / n_bin;
+  float* dst = partial + (fr * (size_t)n_chunks + chunk) * (size_t)(4 * S * S);
+  for (int o = tid; o < nbc * 2 * S; o += NT) {
+    const int bc = o / (2 * S);
+    const int rem = o - bc * 2 * S;
+    const int qq = rem / S;
+    const int iy = rem - qq * S;
+    float sum = 0.f;
+    for (int dx = 0; dx < n_bin; ++dx) {
+      const float* gp = tile + ((bc * n_bin + dx) * 2 + qq) * P + iy * n_bin;
+      for (int dy = 0; dy < n_bin; ++dy) sum += gp[dy];
+    }
+    dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = sum;
+  }
+}
+
+template <int E>
+static hipError_t launch_rows16_e(const MeasureArgs& a, hipStream_t st) {
+  hipError_t e = launch_field(a, st);
+  if (e != hipSuccess) return e;
+  dim3 grid(a.P / 8, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
+  hipLaunchKernelGGL(row_pass16_kernel<E>, grid, dim3(256), 0, st, a.field, a.in_a, a.f_a, a.mid, a.tw16, a.outw,
+                     a.Rw, a.n_a, a.a_chunk);
+  return hipGetLastError();
+}
+
+template <int E, int CB>
+static hipError_t launch_cols16_e(const MeasureArgs& a, hipStream_t st) {
+  dim3 grid(2 * a.P / CB, a.n_chunks, a.B);
+  hipLaunchKernelGGL((col_pass16_kernel<E, CB>), grid, dim3(32 * CB), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
+                     a.k_ia, a.mid, a.tw16, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t st) {
+  switch (a.P) {
+    case 128: return launch_rows16_e<8>(a, st);
+    case 480: return launch_rows16_e<30>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t st) {
+  switch (a.P) {
+    case 128: return launch_cols16_e<8, 8>(a, st);
+    case 480: return a.n_bin == 5 ? launch_cols16_e<30, 10>(a, st) : launch_cols16_e<30, 8>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pwfs

@@ -48,6 +48,11 @@ struct MeasureArgs {
 // ev: NULL, or four events recorded before the row pass, between the passes
 // and after the slopes kernel.
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
+// Pieces of launch_measure: the pupil field (one frame slice), and the row and
+// column passes of the long-line kernels (P = 128, 480).
+hipError_t launch_field(const MeasureArgs& a, hipStream_t stream);
+hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t stream);
+hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t stream);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t stream);
 hipError_t launch_detector(const float* intensity, float* pixels, int npix, int B, uint64_t frame0, float gain,
                            float ron, uint64_t seed, hipStream_t stream);
