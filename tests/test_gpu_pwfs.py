@@ -232,3 +232,28 @@ def test_cfg3_frame_and_reference():
     plan.close()
     opd, _ = open_loop_batch(CFG3, ATMO3, [33])
     _check_batch(CFG3, opd, batch_max=1)
+
+
+CFG_K1 = SensorConfig(name="p32_k1_r0_unmodulated", n_fft=128, n_pupil=32, n_bin=2, n_mod=1,
+                      mod_radius_lod=0.0, wavelength_m=750e-9, diameter_m=8.0)
+CFG_K2 = SensorConfig(name="p32_k2_r3", n_fft=128, n_pupil=32, n_bin=2, n_mod=2,
+                      mod_radius_lod=3.0, wavelength_m=750e-9, diameter_m=8.0)
+CFG_K1024 = SensorConfig(name="p32_k1024_r10", n_fft=128, n_pupil=32, n_bin=4, n_mod=1024,
+                         mod_radius_lod=10.0, wavelength_m=750e-9, diameter_m=8.0)
+
+
+@pytest.mark.parametrize("cfg", [CFG_K1, CFG_K2, CFG_K1024], ids=lambda c: c.name)
+def test_degenerate_and_maximum_modulation(cfg):
+    """Unmodulated pyramid (one point at radius 0), two modulation points (one
+    x tilt each, no k / K-k pairing), and the largest supported count
+    (1024 points, 513 distinct x tilts) at a 10 lambda/D radius."""
+    import paper_1607_07624_amd as pw
+    torch_cuda()
+    opd, _ = open_loop_batch(cfg, ATMO1, [50, 51], screen_n=64)
+    plan = pw.Plan(cfg, batch_max=2)
+    orc = orc_for(cfg)
+    e = float(np.abs(plan.s_ref.astype(np.float64) - orc.s_ref).max())
+    say(f"[gpu] {cfg.name}: reference slope max abs err {e:.3e}")
+    assert e <= 1e-6
+    plan.close()
+    _check_batch(cfg, opd, batch_max=2)
