@@ -111,6 +111,21 @@ def line_flops16(P: int, intensity: bool) -> int:
     return 2 * projection + f + twist + out + acc
 
 
+def strehl_stats(cam, res, P, settle):
+    """H-band image quality of a loop's residual screens res [T, P*P] (device):
+    mean short-exposure Strehl ratio after the settle time, and the Strehl
+    ratio of the long-exposure (integrated) PSF, through the PSF camera."""
+    import torch
+    T = res.shape[0]
+    r = res.view(T, P, P)[settle:].contiguous()
+    _, sr = cam.compute(r, want_psf=False)
+    le, _ = cam.compute(r, accumulate=True)
+    N = cam.n_image
+    torch.cuda.synchronize()
+    return {"strehl_h_short_mean": round(float(sr.mean()), 4),
+            "strehl_h_long": round(float(le[N // 2, N // 2]) / (T - settle), 4)}
+
+
 def multi_source_leg(args, log):
     """Six guide stars through three layers, sensed at 650 and 850 nm (40 m
     class geometry) by two plans captured in one HIP graph."""
@@ -346,6 +361,16 @@ def main():
                 "open_loop_nm_rms": round(float(np.sqrt(np.mean(ol[LOOP_SETTLE_STEPS:] ** 2))), 2),
                 "steps_per_s": round(T / (loop_ms / 1e3), 1), "gain": LOOP_GAIN, "delay": LOOP_DELAY,
                 "reconstructor": "linear (KL 600, push-pull IM, full-SVD pinv)"}
+        cam = pw.PsfCamera(P, 8, 1.65e-6, batch_max=B)
+        loop.update(strehl_stats(cam, res, P, LOOP_SETTLE_STEPS))
+        rr = res.view(T, P, P)[LOOP_SETTLE_STEPS:].contiguous()
+        torch.cuda.synchronize()
+        ev0.record()
+        cam.compute(rr, accumulate=True)
+        ev1.record()
+        torch.cuda.synchronize()
+        loop["psf_camera_frames_per_s"] = round(rr.shape[0] / (ev0.elapsed_time(ev1) / 1e3), 1)
+        del rr
         log(f"loop {loop}")
         # Monte-Carlo realisations advanced as one batch (one measure of B frames per step).
         nr = B
@@ -422,6 +447,7 @@ def main():
         ev_all = open_loop_errors(plan, net, R, modes.astype(np.float32), amp, bank, 2048, seed=991,
                                   r0_range=(0.06, 0.2))
         loops = {}
+        cam_h = pw.PsfCamera(P, 8, 1.65e-6, batch_max=16)
         for r0 in (0.12, 0.08):
             atm = AtmoConfig(r0_m=r0, L0_m=ATMO2.L0_m, wind_m_s=ATMO2.wind_m_s, frame_rate_hz=ATMO2.frame_rate_hz)
             sq = torch.from_numpy(frozen_flow_sequence(cfg, atm, T, seed=2024)).to(dev)
@@ -436,6 +462,7 @@ def main():
                 ps = residual_rms_nm(rs.cpu().numpy(), amp)
                 row[name] = {"residual_nm_rms": round(float(np.sqrt(np.mean(ps[LOOP_SETTLE_STEPS:] ** 2))), 2),
                              "steps_per_s": round(T / (ev0.elapsed_time(ev1) / 1e3), 1)}
+                row[name].update(strehl_stats(cam_h, rs, P, LOOP_SETTLE_STEPS))
                 if nn_ is not None:
                     row[name]["fallback_step"] = cl.fallback_step
                     g = [v for (tt, v) in cl.judged if tt >= cl.judge_settle]

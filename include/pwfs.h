@@ -176,6 +176,40 @@ int pwfs_set_frame_counter(pwfs_plan_t plan, uint64_t frame);
 int pwfs_detect(pwfs_plan_t plan, const float* d_intensity, int32_t B, uint64_t frame0, float* d_pixels,
                 void* stream);
 
+/* PSF camera (the paper's PSF object, Sec. 4, Tab. 1 "psf": the image of
+ * the residual wavefront at a science wavelength with a padding factor, its
+ * Strehl ratio, and its integration over the run).
+ *   PSF[v][u] = |FFT2(A exp(i phi))[v - N/2][u - N/2]|^2 / (sum A)^2
+ * on the N x N grid, N = pad * n_pupil (one lambda/D = pad pixels), the pupil
+ * field zero-padded, phi = 2 pi opd[nm] 1e-9 / wavelength, frequency indices
+ * modulo N, zero frequency at (N/2, N/2): a flat wavefront gives exactly 1 there
+ * and the value at (N/2, N/2) is the Strehl ratio.  Supported: n_pupil 32,
+ * 64 or 160, pad 2, 4 or 8.  The pupil amplitude is the same circle as the
+ * sensor plan's (or the caller's P x P host array). */
+typedef struct pwfs_psf_s* pwfs_psf_t;
+typedef struct {
+  int32_t n_pupil;
+  int32_t pad;
+  int32_t batch_max;   /* workspace size in frames */
+  int32_t reserved;    /* must be 0 */
+  double wavelength_m;
+  double obstruction;
+} pwfs_psf_config_t;
+
+int pwfs_psf_create(const pwfs_psf_config_t* cfg, const float* pupil_amp_host, pwfs_psf_t* out);
+/* N, the side of the image. */
+int pwfs_psf_info(pwfs_psf_t cam, int32_t* n_image);
+/* PSFs of B residual screens d_opd_nm [B][P][P] (device, nm).
+ *   accumulate == 0: d_psf [B][N][N] receives each frame's PSF;
+ *   accumulate != 0: d_psf [N][N] is read and receives d_psf + sum over the
+ *                    B frames (added in frame order: a long-exposure image).
+ *   d_strehl [B] (may be NULL): |sum A exp(i phi)|^2 / (sum A)^2 per frame.
+ * Either output may be NULL.  Asynchronous on `stream`; a camera may not run
+ * on two streams at once (shared workspace). */
+int pwfs_psf_compute(pwfs_psf_t cam, const float* d_opd_nm, int32_t B, int32_t accumulate, float* d_psf,
+                     float* d_strehl, void* stream);
+void pwfs_psf_destroy(pwfs_psf_t cam);
+
 /* Work split ("schedule") that pwfs_measure uses for a slice of B frames
  * (1 <= B <= batch_max; a call with more frames than batch_max runs in
  * slices of batch_max and a last, smaller slice): a_chunk distinct x tilts per

@@ -23,6 +23,11 @@ class PwfsError(RuntimeError):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({detail})")
 
 
+class psf_config_struct(ctypes.Structure):
+    _fields_ = [("n_pupil", ctypes.c_int32), ("pad", ctypes.c_int32), ("batch_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("wavelength_m", ctypes.c_double), ("obstruction", ctypes.c_double)]
+
+
 class detector_struct(ctypes.Structure):
     _fields_ = [("electrons_per_frame", ctypes.c_double), ("readout_noise_e", ctypes.c_double),
                 ("seed", ctypes.c_uint64)]
@@ -69,6 +74,11 @@ def load_library():
     lib.pwfs_get_detector.argtypes = [vp, ctypes.POINTER(f32), ctypes.POINTER(ctypes.c_uint64)]
     lib.pwfs_set_frame_counter.argtypes = [vp, ctypes.c_uint64]
     lib.pwfs_detect.argtypes = [vp, vp, i32, ctypes.c_uint64, vp, vp]
+    lib.pwfs_psf_create.argtypes = [ctypes.POINTER(psf_config_struct), vp, ctypes.POINTER(vp)]
+    lib.pwfs_psf_info.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.pwfs_psf_compute.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    lib.pwfs_psf_destroy.argtypes = [vp]
+    lib.pwfs_psf_destroy.restype = None
     lib.pwfs_destroy.argtypes = [vp]
     lib.pwfs_destroy.restype = None
     lib.pwfs_strerror.argtypes = [ctypes.c_int]
@@ -79,7 +89,7 @@ def load_library():
                  "pwfs_set_reference", "pwfs_measure", "recon_apply", "pwfs_get_pupil",
                  "pwfs_timing_enable", "pwfs_timing_read", "pwfs_get_schedule", "pwfs_set_schedule",
                  "pwfs_autotune", "pwfs_set_detector", "pwfs_get_detector", "pwfs_set_frame_counter",
-                 "pwfs_detect"):
+                 "pwfs_detect", "pwfs_psf_create", "pwfs_psf_info", "pwfs_psf_compute"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -273,3 +283,55 @@ def recon_apply(R, s, alpha: float = 1.0, beta: float = 0.0, m=None):
     _check(lib.recon_apply(_ptr(R), M, ns, _ptr(s2), B, float(alpha), float(beta), _ptr(m),
                            _stream_handle(torch, R.device)), "recon_apply")
     return m
+
+
+class PsfCamera:
+    """pwfs_psf_create / pwfs_psf_compute / pwfs_psf_destroy."""
+
+    def __init__(self, n_pupil: int, pad: int, wavelength_m: float, batch_max: int = 16,
+                 obstruction: float = 0.0, pupil_amp: np.ndarray | None = None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.cuda.current_device()
+        c = psf_config_struct(int(n_pupil), int(pad), int(batch_max), 0, float(wavelength_m), float(obstruction))
+        amp = None
+        if pupil_amp is not None:
+            amp = np.ascontiguousarray(pupil_amp, dtype=np.float32)
+            if amp.shape != (n_pupil, n_pupil):
+                raise ValueError("pupil_amp must be P x P")
+        h = ctypes.c_void_p()
+        _check(self.lib.pwfs_psf_create(ctypes.byref(c), amp.ctypes.data if amp is not None else None,
+                                        ctypes.byref(h)), "pwfs_psf_create")
+        self.handle = h
+        n = ctypes.c_int32()
+        _check(self.lib.pwfs_psf_info(h, ctypes.byref(n)), "pwfs_psf_info")
+        self.n_image = n.value
+        self.n_pupil = n_pupil
+
+    def compute(self, opd, psf=None, strehl=None, accumulate: bool = False, want_psf: bool = True):
+        torch = self._torch
+        B = opd.shape[0]
+        P, N = self.n_pupil, self.n_image
+        _need(opd, torch, torch.float32, B * P * P, "opd")
+        if want_psf and psf is None:
+            psf = torch.zeros((N, N) if accumulate else (B, N, N), device=opd.device)
+        if psf is not None:
+            _need(psf, torch, torch.float32, N * N if accumulate else B * N * N, "psf")
+        if strehl is None:
+            strehl = torch.empty(B, device=opd.device)
+        _check(self.lib.pwfs_psf_compute(self.handle, _ptr(opd), int(B), 1 if accumulate else 0,
+                                         _ptr(psf) if psf is not None else None, _ptr(strehl),
+                                         _stream_handle(torch, self.device)), "pwfs_psf_compute")
+        return psf, strehl
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pwfs_psf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -24,7 +24,30 @@ struct alignas(8) cpx {
 
 using pwfs::cpx;
 
+struct pwfs_psf_s {
+  int device = 0, P = 0, pad = 0, N = 0, batch_max = 0;
+  double kphase = 0.0, inv_norm = 0.0;
+  float* amp = nullptr;
+  cpx* twpad = nullptr;
+  cpx* twp = nullptr;
+  cpx* field = nullptr;
+  cpx* Z = nullptr;
+};
+
 namespace {
+
+// Binary circular pupil of diameter P centred at (P-1)/2 (inside iff
+// r^2 <= (P/2)^2), minus a central obstruction of diameter eps P.
+void circle_pupil(int P, double eps, std::vector<float>& amp) {
+  const double c = 0.5 * (P - 1), r2o = 0.25 * P * P;
+  const double r2i = 0.25 * eps * eps * P * P;
+  for (int y = 0; y < P; ++y)
+    for (int x = 0; x < P; ++x) {
+      const double r2 = (x - c) * (x - c) + (y - c) * (y - c);
+      const bool in = r2 <= r2o && (eps <= 0.0 || r2 >= r2i);
+      amp[(size_t)y * P + x] = in ? 1.0f : 0.0f;
+    }
+}
 
 // P = 128 and 480 use the 32-lane line teams (P / 16 samples per lane).
 bool long_lines(int P) { return P == 128 || P == 480; }
@@ -318,14 +341,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       amp[i] = pupil_amp_host[i];
     }
   } else {
-    const double c = 0.5 * (P - 1), r2o = 0.25 * P * P;
-    const double r2i = 0.25 * cfg->obstruction * cfg->obstruction * P * P;
-    for (int y = 0; y < P; ++y)
-      for (int x = 0; x < P; ++x) {
-        const double r2 = (x - c) * (x - c) + (y - c) * (y - c);
-        const bool in = r2 <= r2o && (cfg->obstruction <= 0.0 || r2 >= r2i);
-        amp[(size_t)y * P + x] = in ? 1.0f : 0.0f;
-      }
+    circle_pupil(P, cfg->obstruction, amp);
   }
   // Valid subapertures: block fill fraction >= 0.5.
   const int S = p->S;
@@ -623,6 +639,147 @@ int pwfs_detect(pwfs_plan_t p, const float* d_intensity, int32_t B, uint64_t fra
                                        (float)p->det_ron, p->det_seed, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pwfs_detect launch");
   return PWFS_OK;
+}
+
+static void free_psf(pwfs_psf_s* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  for (void* q : {(void*)c->amp, (void*)c->twpad, (void*)c->twp, (void*)c->field, (void*)c->Z})
+    if (q) (void)hipFree(q);
+  delete c;
+}
+
+int pwfs_psf_create(const pwfs_psf_config_t* cfg, const float* pupil_amp_host, pwfs_psf_t* out) {
+  g_last_error.clear();
+  if (!out) return fail(PWFS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(PWFS_ERR_INVALID_ARG, "cfg is NULL");
+  const int P = cfg->n_pupil, pad = cfg->pad;
+  if (P <= 0 || pad <= 0 || cfg->batch_max <= 0 || cfg->reserved != 0)
+    return fail(PWFS_ERR_INVALID_ARG, "sizes must be positive and reserved 0");
+  if (!(cfg->wavelength_m > 0.0) || !std::isfinite(cfg->wavelength_m) || !(cfg->obstruction >= 0.0) ||
+      !(cfg->obstruction < 1.0))
+    return fail(PWFS_ERR_INVALID_ARG, "wavelength or obstruction out of range");
+  if (!(P == 32 || P == 64 || P == 160)) return fail(PWFS_ERR_UNSUPPORTED, "PSF camera: n_pupil must be 32, 64 or 160");
+  if (!(pad == 2 || pad == 4 || pad == 8)) return fail(PWFS_ERR_UNSUPPORTED, "PSF camera: pad must be 2, 4 or 8");
+  if (cfg->batch_max > 65535) return fail(PWFS_ERR_UNSUPPORTED, "batch_max > 65535");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(PWFS_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  auto* c = new pwfs_psf_s();
+  if ((e = hipGetDevice(&c->device)) != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDevice");
+  }
+  c->P = P;
+  c->pad = pad;
+  c->N = pad * P;
+  c->batch_max = cfg->batch_max;
+  c->kphase = 2.0 * M_PI * 1e-9 / cfg->wavelength_m;
+  std::vector<float> amp((size_t)P * P);
+  if (pupil_amp_host) {
+    for (size_t i = 0; i < amp.size(); ++i) {
+      if (!std::isfinite(pupil_amp_host[i])) {
+        delete c;
+        return fail(PWFS_ERR_INVALID_ARG, "pupil amplitude has non-finite values");
+      }
+      amp[i] = pupil_amp_host[i];
+    }
+  } else {
+    circle_pupil(P, cfg->obstruction, amp);
+  }
+  double sa = 0.0;
+  for (float v : amp) sa += (double)v;
+  if (!(sa > 0.0)) {
+    delete c;
+    return fail(PWFS_ERR_INVALID_ARG, "pupil amplitude sums to zero");
+  }
+  c->inv_norm = 1.0 / (sa * sa);
+  const int E = P / 4, N = c->N;
+  std::vector<cpx> twpad((size_t)pad * P), twp((size_t)4 * E);
+  for (int u1 = 0; u1 < pad; ++u1)
+    for (int x = 0; x < P; ++x) {
+      const double ang = -2.0 * M_PI * (double)(((long)u1 * x) % N) / (double)N;
+      twpad[(size_t)u1 * P + x] = cpx{(float)std::cos(ang), (float)std::sin(ang)};
+    }
+  for (int l = 0; l < 4; ++l)
+    for (int k = 0; k < E; ++k) {
+      const double ang = -2.0 * M_PI * (double)(((long)l * k) % P) / (double)P;
+      twp[(size_t)l * E + k] = cpx{(float)std::cos(ang), (float)std::sin(ang)};
+    }
+  const size_t bm = (size_t)cfg->batch_max;
+  struct A { void** ptr; size_t bytes; const char* what; } allocs[] = {
+      {(void**)&c->amp, amp.size() * sizeof(float), "psf amp"},
+      {(void**)&c->twpad, twpad.size() * sizeof(cpx), "psf padding twiddles"},
+      {(void**)&c->twp, twp.size() * sizeof(cpx), "psf twiddles"},
+      {(void**)&c->field, bm * P * P * sizeof(cpx), "psf field"},
+      {(void**)&c->Z, bm * (size_t)N * P * sizeof(cpx), "psf row transforms"},
+  };
+  for (auto& a : allocs) {
+    int st = dev_alloc(a.ptr, a.bytes, a.what);
+    if (st != PWFS_OK) {
+      free_psf(c);
+      return st;
+    }
+  }
+  if ((e = hipMemcpy(c->amp, amp.data(), amp.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->twpad, twpad.data(), twpad.size() * sizeof(cpx), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->twp, twp.data(), twp.size() * sizeof(cpx), hipMemcpyHostToDevice)) != hipSuccess) {
+    free_psf(c);
+    return hip_fail(e, "psf table upload");
+  }
+  *out = c;
+  return PWFS_OK;
+}
+
+int pwfs_psf_info(pwfs_psf_t c, int32_t* n_image) {
+  if (!c) return fail(PWFS_ERR_INVALID_ARG, "camera is NULL");
+  if (n_image) *n_image = c->N;
+  return PWFS_OK;
+}
+
+int pwfs_psf_compute(pwfs_psf_t c, const float* d_opd_nm, int32_t B, int32_t accumulate, float* d_psf,
+                     float* d_strehl, void* stream) {
+  if (!c) return fail(PWFS_ERR_INVALID_ARG, "camera is NULL");
+  if (B < 0) return fail(PWFS_ERR_INVALID_ARG, "B must be >= 0");
+  if (B == 0 || (!d_psf && !d_strehl)) return PWFS_OK;
+  if (!d_opd_nm) return fail(PWFS_ERR_INVALID_ARG, "d_opd_nm is NULL");
+  DeviceGuard g(c->device);
+  const size_t NN = (size_t)c->N * c->N;
+  for (int b0 = 0; b0 < B; b0 += c->batch_max) {
+    const int Bs = std::min(c->batch_max, B - b0);
+    pwfs::PsfArgs a{};
+    a.P = c->P;
+    a.pad = c->pad;
+    a.B = Bs;
+    a.accumulate = accumulate ? 1 : 0;
+    a.kphase = c->kphase;
+    a.inv_norm = (float)c->inv_norm;
+    a.inv_norm_d = c->inv_norm;
+    a.opd = d_opd_nm + (size_t)b0 * c->P * c->P;
+    a.amp = c->amp;
+    a.twpad = c->twpad;
+    a.twp = c->twp;
+    a.field = c->field;
+    a.Z = c->Z;
+    a.psf = d_psf ? (accumulate ? d_psf : d_psf + (size_t)b0 * NN) : nullptr;
+    a.strehl = d_strehl ? d_strehl + b0 : nullptr;
+    hipError_t e = pwfs::launch_psf(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "pwfs_psf_compute launch");
+  }
+  return PWFS_OK;
+}
+
+void pwfs_psf_destroy(pwfs_psf_t c) {
+  if (!c) return;
+  {
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+  }
+  free_psf(c);
 }
 
 int pwfs_get_schedule(pwfs_plan_t p, int32_t B, int32_t* a_chunk, int32_t* k_chunk) {

@@ -455,6 +455,14 @@ __global__ __launch_bounds__(256) void recon_mfma_kernel(const float* __restrict
 
 // ---------------------------------------------------------------------------
 // Host launchers.
+hipError_t launch_field_raw(const float* opd, const float* amp, double kphase, int P, int B, cpx* field,
+                            hipStream_t st) {
+  const size_t n = (size_t)B * P * P;
+  const unsigned fb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(field_kernel, dim3(fb), dim3(256), 0, st, opd, amp, kphase, 0, P * P, n, field);
+  return hipGetLastError();
+}
+
 hipError_t launch_field(const MeasureArgs& a, hipStream_t st) {
   const size_t n = (size_t)a.B * a.P * a.P;
   const unsigned fb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);

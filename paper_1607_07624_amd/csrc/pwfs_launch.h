@@ -45,12 +45,32 @@ struct MeasureArgs {
   float* intensity;          // [B][4][S][S] scratch for the noiseless images when det_on
 };
 
+// PSF camera: field at the science wavelength, zero-padded 2-D transform,
+// |.|^2 / (sum A)^2 centred (or accumulated over the frames), Strehl ratios.
+struct PsfArgs {
+  int P, pad, B, accumulate;
+  double kphase;       // 2 pi 1e-9 / lambda
+  float inv_norm;      // 1 / (sum A)^2
+  double inv_norm_d;
+  const float* opd;    // [B][P][P] nm
+  const float* amp;    // [P][P]
+  const cpx* twpad;    // [pad][P]  w_N^{u1 x}
+  const cpx* twp;      // [4][P/4]  w_P^{l k1}
+  cpx* field;          // [B][P][P]
+  cpx* Z;              // [B][N][P]
+  float* psf;          // [B][N][N], or [N][N] accumulated; may be NULL
+  float* strehl;       // [B] or NULL
+};
+
 // ev: NULL, or four events recorded before the row pass, between the passes
 // and after the slopes kernel.
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
 // Pieces of launch_measure: the pupil field (one frame slice), and the row and
 // column passes of the long-line kernels (P = 128, 480).
 hipError_t launch_field(const MeasureArgs& a, hipStream_t stream);
+hipError_t launch_field_raw(const float* opd, const float* amp, double kphase, int P, int B, cpx* field,
+                            hipStream_t stream);
+hipError_t launch_psf(const PsfArgs& a, hipStream_t stream);
 hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t stream);
 hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t stream);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t stream);

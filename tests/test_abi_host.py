@@ -113,3 +113,18 @@ def test_cnn_abi_validation_and_no_device():
     env = dict(os.environ, HIP_VISIBLE_DEVICES="-1", ROCR_VISIBLE_DEVICES="-1")
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert out.stdout.strip().splitlines()[-1] == "-3", out.stdout + out.stderr
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(n_pupil=128), -2), (dict(pad=3), -2), (dict(wavelength_m=0.0), -1), (dict(reserved=1), -1),
+    (dict(batch_max=0), -1), (dict(obstruction=1.0), -1),
+])
+def test_psf_camera_rejects_bad_config_before_touching_a_device(over, status):
+    from paper_1607_07624_amd._lib import psf_config_struct
+    lib = pw.load_library()
+    c = psf_config_struct(160, 8, 4, 0, 1.65e-6, 0.0)
+    for k, v in over.items():
+        setattr(c, k, v)
+    h = ctypes.c_void_p()
+    assert lib.pwfs_psf_create(ctypes.byref(c), None, ctypes.byref(h)) == status
+    assert lib.pwfs_last_error().decode()
