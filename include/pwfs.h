@@ -176,6 +176,35 @@ int pwfs_set_frame_counter(pwfs_plan_t plan, uint64_t frame);
 int pwfs_detect(pwfs_plan_t plan, const float* d_intensity, int32_t B, uint64_t frame0, float* d_pixels,
                 void* stream);
 
+/* Shack-Hartmann sensor (the paper's second sensor type, Sec. 1 and Sec. 6;
+ * the geometry is fixed by this library): n_sub x n_sub square subapertures
+ * of s = n_pupil / n_sub pixels; valid subapertures by the sensor's
+ * fill-fraction rule (>= 0.5).  For each the field E = A exp(i phi) is
+ * zero-padded to M = pad s and
+ *   spot[v][u] = |sum_{y,x} E[y][x] exp(-2 pi i ((v - M/2) y + (u - M/2) x) / M)|^2
+ * (one spot pixel = lambda / (pad d)); the slopes are the centre of gravity
+ * over the M x M box, [cx over valid ; cy over valid] in spot pixels, minus
+ * the slopes of a flat wavefront (measured at creation).  Supported: s <= 8,
+ * pad 2 or 4, pad s <= 32, n_pupil <= 1024.  d_spots [B][n_valid][M][M] and
+ * d_slopes [B][2 n_valid] (device, either may be NULL).  Asynchronous on
+ * `stream`; a sensor may not run on two streams at once. */
+typedef struct pwfs_sh_s* pwfs_sh_t;
+typedef struct {
+  int32_t n_pupil;
+  int32_t n_sub;
+  int32_t pad;
+  int32_t batch_max;
+  double wavelength_m;
+  double obstruction;
+} pwfs_sh_config_t;
+
+int pwfs_sh_create(const pwfs_sh_config_t* cfg, const float* pupil_amp_host, pwfs_sh_t* out);
+int pwfs_sh_info(pwfs_sh_t sh, int32_t* n_valid, int32_t* spot_side);
+int pwfs_sh_get_valid(pwfs_sh_t sh, int32_t* idx_host);
+int pwfs_sh_get_reference(pwfs_sh_t sh, float* sref_host);
+int pwfs_sh_measure(pwfs_sh_t sh, const float* d_opd_nm, int32_t B, float* d_spots, float* d_slopes, void* stream);
+void pwfs_sh_destroy(pwfs_sh_t sh);
+
 /* PSF camera (the paper's PSF object, Sec. 4, Tab. 1 "psf": the image of
  * the residual wavefront at a science wavelength with a padding factor, its
  * Strehl ratio, and its integration over the run).

@@ -5,8 +5,8 @@ sensor path; this package only marshals arguments to it.  Loading fails
 loudly when the library is missing or no device is present: there is no
 CPU implementation behind these names.
 """
-from ._lib import (PwfsError, Plan, PsfCamera, recon_apply, library_path, load_library,
+from ._lib import (PwfsError, Plan, PsfCamera, ShPlan, recon_apply, library_path, load_library,
                    STATUS_NAMES, config_struct)
 
-__all__ = ["PwfsError", "Plan", "PsfCamera", "recon_apply", "library_path", "load_library",
+__all__ = ["PwfsError", "Plan", "PsfCamera", "ShPlan", "recon_apply", "library_path", "load_library",
            "STATUS_NAMES", "config_struct"]

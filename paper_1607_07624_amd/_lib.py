@@ -23,6 +23,11 @@ class PwfsError(RuntimeError):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({detail})")
 
 
+class sh_config_struct(ctypes.Structure):
+    _fields_ = [("n_pupil", ctypes.c_int32), ("n_sub", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("batch_max", ctypes.c_int32), ("wavelength_m", ctypes.c_double), ("obstruction", ctypes.c_double)]
+
+
 class psf_config_struct(ctypes.Structure):
     _fields_ = [("n_pupil", ctypes.c_int32), ("pad", ctypes.c_int32), ("batch_max", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("wavelength_m", ctypes.c_double), ("obstruction", ctypes.c_double)]
@@ -74,6 +79,13 @@ def load_library():
     lib.pwfs_get_detector.argtypes = [vp, ctypes.POINTER(f32), ctypes.POINTER(ctypes.c_uint64)]
     lib.pwfs_set_frame_counter.argtypes = [vp, ctypes.c_uint64]
     lib.pwfs_detect.argtypes = [vp, vp, i32, ctypes.c_uint64, vp, vp]
+    lib.pwfs_sh_create.argtypes = [ctypes.POINTER(sh_config_struct), vp, ctypes.POINTER(vp)]
+    lib.pwfs_sh_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.pwfs_sh_get_valid.argtypes = [vp, vp]
+    lib.pwfs_sh_get_reference.argtypes = [vp, vp]
+    lib.pwfs_sh_measure.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.pwfs_sh_destroy.argtypes = [vp]
+    lib.pwfs_sh_destroy.restype = None
     lib.pwfs_psf_create.argtypes = [ctypes.POINTER(psf_config_struct), vp, ctypes.POINTER(vp)]
     lib.pwfs_psf_info.argtypes = [vp, ctypes.POINTER(i32)]
     lib.pwfs_psf_compute.argtypes = [vp, vp, i32, i32, vp, vp, vp]
@@ -89,7 +101,8 @@ def load_library():
                  "pwfs_set_reference", "pwfs_measure", "recon_apply", "pwfs_get_pupil",
                  "pwfs_timing_enable", "pwfs_timing_read", "pwfs_get_schedule", "pwfs_set_schedule",
                  "pwfs_autotune", "pwfs_set_detector", "pwfs_get_detector", "pwfs_set_frame_counter",
-                 "pwfs_detect", "pwfs_psf_create", "pwfs_psf_info", "pwfs_psf_compute"):
+                 "pwfs_detect", "pwfs_psf_create", "pwfs_psf_info", "pwfs_psf_compute", "pwfs_sh_create",
+                 "pwfs_sh_info", "pwfs_sh_get_valid", "pwfs_sh_get_reference", "pwfs_sh_measure"):
         getattr(lib, name).restype = ctypes.c_int
     _LIB = lib
     return lib
@@ -328,6 +341,76 @@ class PsfCamera:
     def close(self):
         if getattr(self, "handle", None):
             self.lib.pwfs_psf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ShPlan:
+    """pwfs_sh_create / pwfs_sh_measure / pwfs_sh_destroy, with the same
+    measure_into / n_valid / batch_max interface as Plan (so calibration and
+    the closed loops drive either sensor)."""
+
+    def __init__(self, n_pupil: int, n_sub: int, pad: int, wavelength_m: float, batch_max: int = 16,
+                 obstruction: float = 0.0, pupil_amp: np.ndarray | None = None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.cuda.current_device()
+        c = sh_config_struct(int(n_pupil), int(n_sub), int(pad), int(batch_max), float(wavelength_m),
+                             float(obstruction))
+        amp = None
+        if pupil_amp is not None:
+            amp = np.ascontiguousarray(pupil_amp, dtype=np.float32)
+        h = ctypes.c_void_p()
+        _check(self.lib.pwfs_sh_create(ctypes.byref(c), amp.ctypes.data if amp is not None else None,
+                                       ctypes.byref(h)), "pwfs_sh_create")
+        self.handle = h
+        nv, m = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.pwfs_sh_info(h, ctypes.byref(nv), ctypes.byref(m)), "pwfs_sh_info")
+        self.n_valid, self.spot_side = nv.value, m.value
+        self.n_pupil, self.n_sub, self.batch_max = n_pupil, n_sub, batch_max
+
+    @property
+    def valid(self) -> np.ndarray:
+        out = np.empty(self.n_valid, np.int32)
+        _check(self.lib.pwfs_sh_get_valid(self.handle, out.ctypes.data), "pwfs_sh_get_valid")
+        return out
+
+    @property
+    def s_ref(self) -> np.ndarray:
+        out = np.empty(2 * self.n_valid, np.float32)
+        _check(self.lib.pwfs_sh_get_reference(self.handle, out.ctypes.data), "pwfs_sh_get_reference")
+        return out
+
+    def measure_into(self, opd, spots=None, slopes=None):
+        torch = self._torch
+        B = opd.shape[0]
+        P, nv, M = self.n_pupil, self.n_valid, self.spot_side
+        _need(opd, torch, torch.float32, B * P * P, "opd")
+        if spots is not None:
+            _need(spots, torch, torch.float32, B * nv * M * M, "spots")
+        if slopes is not None:
+            _need(slopes, torch, torch.float32, B * 2 * nv, "slopes")
+        _check(self.lib.pwfs_sh_measure(self.handle, _ptr(opd), int(B), _ptr(spots) if spots is not None else None,
+                                        _ptr(slopes) if slopes is not None else None,
+                                        _stream_handle(torch, self.device)), "pwfs_sh_measure")
+
+    def measure(self, opd, want_spots: bool = True):
+        torch = self._torch
+        B = opd.shape[0]
+        spots = torch.empty((B, self.n_valid, self.spot_side, self.spot_side), device=opd.device) if want_spots else None
+        slopes = torch.empty((B, 2 * self.n_valid), device=opd.device)
+        self.measure_into(opd, spots, slopes)
+        return spots, slopes
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.pwfs_sh_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

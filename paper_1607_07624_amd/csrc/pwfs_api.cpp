@@ -24,6 +24,19 @@ struct alignas(8) cpx {
 
 using pwfs::cpx;
 
+struct pwfs_sh_s {
+  int device = 0, P = 0, S = 0, s = 0, M = 0, nv = 0, batch_max = 0;
+  double kphase = 0.0;
+  std::vector<int> valid;
+  float* amp = nullptr;
+  int* d_valid = nullptr;
+  cpx* twm = nullptr;
+  float* sref = nullptr;
+  cpx* field = nullptr;
+  float* zero_opd = nullptr;
+  float* tmp = nullptr;
+};
+
 struct pwfs_psf_s {
   int device = 0, P = 0, pad = 0, N = 0, batch_max = 0;
   double kphase = 0.0, inv_norm = 0.0;
@@ -639,6 +652,175 @@ int pwfs_detect(pwfs_plan_t p, const float* d_intensity, int32_t B, uint64_t fra
                                        (float)p->det_ron, p->det_seed, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "pwfs_detect launch");
   return PWFS_OK;
+}
+
+static void free_sh(pwfs_sh_s* c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  for (void* q : {(void*)c->amp, (void*)c->d_valid, (void*)c->twm, (void*)c->sref, (void*)c->field,
+                  (void*)c->zero_opd, (void*)c->tmp})
+    if (q) (void)hipFree(q);
+  delete c;
+}
+
+static hipError_t run_sh(pwfs_sh_s* c, const float* opd, int B, float* spots, float* slopes, const float* sref,
+                         hipStream_t st) {
+  for (int b0 = 0; b0 < B; b0 += c->batch_max) {
+    const int Bs = std::min(c->batch_max, B - b0);
+    pwfs::ShArgs a{};
+    a.P = c->P;
+    a.S = c->S;
+    a.s = c->s;
+    a.M = c->M;
+    a.nv = c->nv;
+    a.B = Bs;
+    a.kphase = c->kphase;
+    a.opd = opd + (size_t)b0 * c->P * c->P;
+    a.amp = c->amp;
+    a.valid = c->d_valid;
+    a.twm = c->twm;
+    a.sref = sref;
+    a.field = c->field;
+    a.spots = spots ? spots + (size_t)b0 * c->nv * c->M * c->M : nullptr;
+    a.slopes = slopes ? slopes + (size_t)b0 * 2 * c->nv : nullptr;
+    hipError_t e = pwfs::launch_sh(a, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int pwfs_sh_create(const pwfs_sh_config_t* cfg, const float* pupil_amp_host, pwfs_sh_t* out) {
+  g_last_error.clear();
+  if (!out) return fail(PWFS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(PWFS_ERR_INVALID_ARG, "cfg is NULL");
+  const int P = cfg->n_pupil, S = cfg->n_sub, pad = cfg->pad;
+  if (P <= 0 || S <= 0 || pad <= 0 || cfg->batch_max <= 0) return fail(PWFS_ERR_INVALID_ARG, "sizes must be positive");
+  if (P % S != 0) return fail(PWFS_ERR_INVALID_ARG, "n_pupil must be a multiple of n_sub");
+  if (!(cfg->wavelength_m > 0.0) || !std::isfinite(cfg->wavelength_m) || !(cfg->obstruction >= 0.0) ||
+      !(cfg->obstruction < 1.0))
+    return fail(PWFS_ERR_INVALID_ARG, "wavelength or obstruction out of range");
+  const int sp = P / S;
+  if (sp > 8 || !(pad == 2 || pad == 4) || pad * sp > 32 || P > 1024 || cfg->batch_max > 65535)
+    return fail(PWFS_ERR_UNSUPPORTED, "Shack-Hartmann: subapertures of at most 8 pixels, pad 2 or 4, pad * s <= 32");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(PWFS_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  auto* c = new pwfs_sh_s();
+  if ((e = hipGetDevice(&c->device)) != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetDevice");
+  }
+  c->P = P;
+  c->S = S;
+  c->s = sp;
+  c->M = pad * sp;
+  c->batch_max = cfg->batch_max;
+  c->kphase = 2.0 * M_PI * 1e-9 / cfg->wavelength_m;
+  std::vector<float> amp((size_t)P * P);
+  if (pupil_amp_host) {
+    for (size_t i = 0; i < amp.size(); ++i) {
+      if (!std::isfinite(pupil_amp_host[i])) {
+        delete c;
+        return fail(PWFS_ERR_INVALID_ARG, "pupil amplitude has non-finite values");
+      }
+      amp[i] = pupil_amp_host[i];
+    }
+  } else {
+    circle_pupil(P, cfg->obstruction, amp);
+  }
+  for (int iy = 0; iy < S; ++iy)
+    for (int ix = 0; ix < S; ++ix) {
+      double f = 0.0;
+      for (int dy = 0; dy < sp; ++dy)
+        for (int dx = 0; dx < sp; ++dx) f += amp[(size_t)(iy * sp + dy) * P + ix * sp + dx];
+      if (f >= 0.5 * sp * sp) c->valid.push_back(iy * S + ix);
+    }
+  c->nv = (int)c->valid.size();
+  if (c->nv == 0) {
+    delete c;
+    return fail(PWFS_ERR_INVALID_ARG, "no valid subaperture");
+  }
+  std::vector<cpx> twm((size_t)c->M);
+  for (int k = 0; k < c->M; ++k) {
+    const double ang = -2.0 * M_PI * (double)k / (double)c->M;
+    twm[k] = cpx{(float)std::cos(ang), (float)std::sin(ang)};
+  }
+  const size_t bm = (size_t)c->batch_max;
+  struct A { void** ptr; size_t bytes; const char* what; } allocs[] = {
+      {(void**)&c->amp, amp.size() * sizeof(float), "sh amp"},
+      {(void**)&c->d_valid, (size_t)c->nv * sizeof(int), "sh valid"},
+      {(void**)&c->twm, twm.size() * sizeof(cpx), "sh twiddles"},
+      {(void**)&c->sref, (size_t)2 * c->nv * sizeof(float), "sh reference"},
+      {(void**)&c->field, bm * P * P * sizeof(cpx), "sh field"},
+      {(void**)&c->zero_opd, (size_t)P * P * sizeof(float), "sh zero opd"},
+      {(void**)&c->tmp, (size_t)2 * c->nv * sizeof(float), "sh reference scratch"},
+  };
+  for (auto& a : allocs) {
+    int st = dev_alloc(a.ptr, a.bytes, a.what);
+    if (st != PWFS_OK) {
+      free_sh(c);
+      return st;
+    }
+  }
+  if ((e = hipMemcpy(c->amp, amp.data(), amp.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_valid, c->valid.data(), (size_t)c->nv * sizeof(int), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(c->twm, twm.data(), twm.size() * sizeof(cpx), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(c->zero_opd, 0, (size_t)P * P * sizeof(float))) != hipSuccess ||
+      (e = hipMemset(c->sref, 0, (size_t)2 * c->nv * sizeof(float))) != hipSuccess ||
+      (e = run_sh(c, c->zero_opd, 1, nullptr, c->tmp, c->sref, nullptr)) != hipSuccess ||
+      (e = hipMemcpy(c->sref, c->tmp, (size_t)2 * c->nv * sizeof(float), hipMemcpyDeviceToDevice)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
+    free_sh(c);
+    return hip_fail(e, "Shack-Hartmann set-up");
+  }
+  *out = c;
+  return PWFS_OK;
+}
+
+int pwfs_sh_info(pwfs_sh_t c, int32_t* n_valid, int32_t* spot_side) {
+  if (!c) return fail(PWFS_ERR_INVALID_ARG, "sensor is NULL");
+  if (n_valid) *n_valid = c->nv;
+  if (spot_side) *spot_side = c->M;
+  return PWFS_OK;
+}
+
+int pwfs_sh_get_valid(pwfs_sh_t c, int32_t* idx_host) {
+  if (!c || !idx_host) return fail(PWFS_ERR_INVALID_ARG, "sensor or idx_host is NULL");
+  std::memcpy(idx_host, c->valid.data(), c->valid.size() * sizeof(int32_t));
+  return PWFS_OK;
+}
+
+int pwfs_sh_get_reference(pwfs_sh_t c, float* sref_host) {
+  if (!c || !sref_host) return fail(PWFS_ERR_INVALID_ARG, "sensor or sref_host is NULL");
+  DeviceGuard g(c->device);
+  hipError_t e = hipMemcpy(sref_host, c->sref, (size_t)2 * c->nv * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "pwfs_sh_get_reference");
+  return PWFS_OK;
+}
+
+int pwfs_sh_measure(pwfs_sh_t c, const float* d_opd_nm, int32_t B, float* d_spots, float* d_slopes, void* stream) {
+  if (!c) return fail(PWFS_ERR_INVALID_ARG, "sensor is NULL");
+  if (B < 0) return fail(PWFS_ERR_INVALID_ARG, "B must be >= 0");
+  if (B == 0 || (!d_spots && !d_slopes)) return PWFS_OK;
+  if (!d_opd_nm) return fail(PWFS_ERR_INVALID_ARG, "d_opd_nm is NULL");
+  DeviceGuard g(c->device);
+  hipError_t e = run_sh(c, d_opd_nm, B, d_spots, d_slopes, c->sref, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "pwfs_sh_measure launch");
+  return PWFS_OK;
+}
+
+void pwfs_sh_destroy(pwfs_sh_t c) {
+  if (!c) return;
+  {
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+  }
+  free_sh(c);
 }
 
 static void free_psf(pwfs_psf_s* c) {

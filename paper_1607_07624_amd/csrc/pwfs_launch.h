@@ -62,6 +62,20 @@ struct PsfArgs {
   float* strehl;       // [B] or NULL
 };
 
+// Shack-Hartmann: field, per-subaperture zero-padded spots, centroids.
+struct ShArgs {
+  int P, S, s, M, nv, B;
+  double kphase;
+  const float* opd;    // [B][P][P] nm
+  const float* amp;    // [P][P]
+  const int* valid;    // [nv] j = iy S + ix
+  const cpx* twm;      // [M] w_M^k
+  const float* sref;   // [2 nv]
+  cpx* field;          // [B][P][P]
+  float* spots;        // [B][nv][M][M] or NULL
+  float* slopes;       // [B][2 nv] or NULL
+};
+
 // ev: NULL, or four events recorded before the row pass, between the passes
 // and after the slopes kernel.
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
@@ -71,6 +85,7 @@ hipError_t launch_field(const MeasureArgs& a, hipStream_t stream);
 hipError_t launch_field_raw(const float* opd, const float* amp, double kphase, int P, int B, cpx* field,
                             hipStream_t stream);
 hipError_t launch_psf(const PsfArgs& a, hipStream_t stream);
+hipError_t launch_sh(const ShArgs& a, hipStream_t stream);
 hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t stream);
 hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t stream);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t stream);

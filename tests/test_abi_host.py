@@ -128,3 +128,18 @@ def test_psf_camera_rejects_bad_config_before_touching_a_device(over, status):
     h = ctypes.c_void_p()
     assert lib.pwfs_psf_create(ctypes.byref(c), None, ctypes.byref(h)) == status
     assert lib.pwfs_last_error().decode()
+
+
+@pytest.mark.parametrize("over,status", [
+    (dict(n_sub=7), -1), (dict(n_sub=4), -2), (dict(pad=3), -2), (dict(wavelength_m=-1.0), -1),
+    (dict(batch_max=0), -1),
+])
+def test_sh_rejects_bad_config_before_touching_a_device(over, status):
+    from paper_1607_07624_amd._lib import sh_config_struct
+    lib = pw.load_library()
+    c = sh_config_struct(160, 40, 4, 4, 750e-9, 0.0)
+    for k, v in over.items():
+        setattr(c, k, v)
+    h = ctypes.c_void_p()
+    assert lib.pwfs_sh_create(ctypes.byref(c), None, ctypes.byref(h)) == status
+    assert lib.pwfs_last_error().decode()
