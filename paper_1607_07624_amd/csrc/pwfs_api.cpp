@@ -377,10 +377,16 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   p->n_a = K / 2 + 1;
   std::vector<int> k_ia(K), k_order;
   for (int k = 0; k < K; ++k) k_ia[k] = std::min(k, K - k);
-  for (int ia = 0; ia < p->n_a; ++ia) {
-    k_order.push_back(ia);
-    if (ia != 0 && K - ia != ia && K - ia < K) k_order.push_back(K - ia);
-  }
+  // The pairs (k, K-k), which share one x tilt, come first and adjacent, so a
+  // chunk of an even number of points stages each of its x tilts once; the
+  // unpaired points (k = 0 and, for even K, k = K/2) come last.
+  for (int ia = 1; ia < p->n_a; ++ia)
+    if (K - ia != ia) {
+      k_order.push_back(ia);
+      k_order.push_back(K - ia);
+    }
+  k_order.push_back(0);
+  if (K % 2 == 0 && K / 2 != 0) k_order.push_back(K / 2);
   if ((int)k_order.size() != K) {
     delete p;
     return fail(PWFS_ERR_INVALID_ARG, "internal: modulation ordering");
