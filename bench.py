@@ -32,17 +32,19 @@ import numpy as np
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per 16-frame column-pass launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# recorded in profiles/pwfs_measure_n640_p160_k48_b16.md (scaled by the copy-kernel factors
-# 2.0 / 1.0).  Valid only for the kernel sources with these hashes and this work split
-# (x-tilt chunk, modulation chunk); reported as null otherwise.
+# HBM bytes per 16-frame column-pass launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (KiB per dispatch, scaled by the copy-kernel factors 2.0 / 1.0; summary and commands in
+# profiles/pwfs_measure_n640_p160_k48_b16.md), one entry per work split (x-tilt chunk,
+# modulation chunk).  Valid only for the sources with these hashes (the kernels and the plan's
+# modulation order); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "8c387080e72899f1fcd14e57443c71fc1844e7f4",
+    "sources_sha1": {"pwfs_kernels.hip": "3433cca61b835e38be2e35b92ff40346d29c43a0",
                      "pwfs_common.h": "05ad04b20e1339450c0fcb05421ccf490d40edbf",
-                     "pwfs_dft.h": "dc4c8d92932d722a11520e45113183e7ea3c618a"},
+                     "pwfs_dft.h": "dc4c8d92932d722a11520e45113183e7ea3c618a",
+                     "pwfs_api.cpp": "385b2a5502cc9dbe0e41cafb57495e1f2ffe1700"},
     "batch": 16,
-    "schedule": (3, 6),
-    "col_pass_bytes": (104289.2 * 2.0 + 3200.0 * 1.0) * 1024,
+    "col_pass_kib": {(3, 2): (81269.3, 9600.0), (3, 3): (107868.0, 6400.0), (3, 4): (82013.0, 4800.0),
+                     (3, 6): (81747.6, 3200.0)},
 }
 
 
@@ -53,9 +55,8 @@ def counter_traffic(batch, schedule):
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha1(f.read()).hexdigest() != h:
                 return None
-    if batch != COUNTER_TRAFFIC["batch"] or tuple(schedule) != COUNTER_TRAFFIC["schedule"]:
-        return None
-    return COUNTER_TRAFFIC["col_pass_bytes"]
+    kib = COUNTER_TRAFFIC["col_pass_kib"].get(tuple(schedule)) if batch == COUNTER_TRAFFIC["batch"] else None
+    return None if kib is None else (kib[0] * 2.0 + kib[1] * 1.0) * 1024
 
 
 def log(*a):
