@@ -170,8 +170,22 @@ def multi_source_leg(args, log):
         kernels.append({"wavelength_nm": round(cfg.wavelength_m * 1e9), "row_ms": round(kt["row_ms"] / n, 4),
                         "col_ms": round(col_ms, 4), "slopes_ms": round(kt["slopes_ms"] / n, 4),
                         "col_tflops": round(lines * line_flops16(cfg.n_pupil, True) / (col_ms * 1e-3) / 1e12, 2)})
+    for k in kernels:
+        k["col_frac_of_fp32_peak"] = round(k["col_tflops"] / PEAK_FP32_TFLOPS, 4)
+    cpu = None
+    if not args.no_cpu:
+        # The FP64 oracle on the host cores for one 650 nm frame of the same batch.
+        import oracle
+        orc = oracle.Oracle(CFG3)
+        o = ms.opd[0].cpu().numpy().astype(np.float64)
+        t0 = time.perf_counter()
+        orc.measure(o)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(1.0 / dt, 4), "unit": "sensor frames/s", "cores": len(os.sched_getaffinity(0)),
+               "kind": "oracle", "sample": "1 frame (650 nm, guide star 0), FP64 literal 2-D route"}
     out = {"workload": "40 m class: N=1920, P=480, K=64, b=5 (7232 valid); 6 guide stars at 45 arcsec, "
                        "3 layers (0/5/12 km), 650 + 850 nm",
+           "cpu_baseline": cpu,
            "sensor_frames_per_call": 2 * ns, "graph_ms": round(graph_ms, 4), "eager_ms": round(eager_ms, 4),
            "sensor_frames_per_s": round(2 * ns / (graph_ms * 1e-3), 1),
            "schedules": [{k: v for k, v in s_.items() if k in ("a_chunk", "k_chunk")} for s_ in ms.schedules],

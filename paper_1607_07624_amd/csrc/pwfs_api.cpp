@@ -183,11 +183,18 @@ void split_work(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk, int* n_
   *n_chunks = (p->K + *k_chunk - 1) / *k_chunk;
 }
 
+// Floats of one (frame, chunk) partial: the chunk's four binned images, or
+// per-column row-binned sums when the binning does not divide a long-line
+// column block.
+size_t partial_per_chunk(const pwfs_plan_s* p) {
+  return pwfs::partials_by_column(p->P, p->b) ? (size_t)4 * p->P * p->S : (size_t)4 * p->S * p->S;
+}
+
 // A schedule is usable when its chunk partials fit the plan's workspace.
 bool schedule_fits(const pwfs_plan_s* p, int B, int a_chunk, int k_chunk) {
   if (B < 1 || B > p->batch_max || a_chunk < 1 || a_chunk > p->n_a || k_chunk < 1 || k_chunk > p->K) return false;
   const size_t nc = (size_t)((p->K + k_chunk - 1) / k_chunk);
-  return (size_t)B * nc * 4 * p->S * p->S <= p->partial_cap;
+  return (size_t)B * nc * partial_per_chunk(p) <= p->partial_cap;
 }
 
 int validate(const pwfs_config_t* c) {
@@ -489,14 +496,14 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   // Device buffers.
   int bm = cfg->batch_max;
   int ac, kc, nc;
-  // Chunk partials for any schedule (up to K chunks per frame): K 4 S^2
-  // floats per frame, an eighth of the row-pass workspace per frame.
+  // Chunk partials for any schedule (up to K chunks per frame).
   size_t partial_elems = 0;
+  const size_t ppc = partial_per_chunk(p);
   for (int B = 1; B <= bm; ++B) {
     split_work(p, B, &ac, &kc, &nc);
-    partial_elems = std::max(partial_elems, (size_t)B * nc * 4 * S * S);
+    partial_elems = std::max(partial_elems, (size_t)B * nc * ppc);
   }
-  partial_elems = std::max(partial_elems, (size_t)bm * K * 4 * S * S);
+  partial_elems = std::max(partial_elems, (size_t)bm * K * ppc);
   p->partial_cap = partial_elems;
   const size_t rw_elems = (size_t)bm * p->n_a * 2 * P * P;
   struct A { void** ptr; size_t bytes; const char* what; } allocs[] = {

@@ -520,9 +520,13 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
   const int n4ss = 4 * S * S;
   // With a detector the noiseless images go to the intensity scratch and the
   // detector writes the pixels that the slopes use.
-  hipLaunchKernelGGL(pupil_reduce_kernel, dim3((n4ss + 255) / 256, a.B), dim3(256), 0, st, a.partial,
-                     a.n_chunks, n4ss, 1.0f / (float)a.K, a.det_on ? a.intensity : a.pupils);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (partials_by_column(a.P, a.n_bin)) {
+    if ((e = launch_reduce_cols(a, a.det_on ? a.intensity : a.pupils, st)) != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(pupil_reduce_kernel, dim3((n4ss + 255) / 256, a.B), dim3(256), 0, st, a.partial,
+                       a.n_chunks, n4ss, 1.0f / (float)a.K, a.det_on ? a.intensity : a.pupils);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (a.det_on) {
     if ((e = launch_detector(a.intensity, a.pupils, n4ss, a.B, a.frame0, a.det_gain, a.det_ron, a.det_seed, st)) !=
         hipSuccess)

@@ -197,10 +197,11 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
   }
 }
 
-// Column pass, long lines.  Block = CB / 2 waves = CB adjacent columns x' of
-// one frame (one 32-lane team per column) and one chunk of modulation points;
-// CB = 8, or 10 when the binning is 5 (a block must hold whole bins and
-// never straddle the two pupil windows).  The CB columns of one distinct x
+// Column pass, long lines.  Block = CB / 2 waves = CB = 8 adjacent columns x'
+// of one frame (one 32-lane team per column) and one chunk of modulation
+// points; a block never straddles the two pupil windows.  When the binning
+// divides 8 the block bins b x b itself; otherwise (b = 5) it writes
+// row-binned sums per column and a reduction kernel finishes the bins.  The CB columns of one distinct x
 // tilt are gathered from the intermediate into LDS as [y/4][column][y%4]
 // with a y-group stride of 40 values (conflict-free reads); each team
 // accumulates |E|^2 of its column over the chunk in registers, then the
@@ -297,22 +298,61 @@ __global__ __launch_bounds__(32 * CB) void col_pass16_kernel(
   });
   __syncthreads();
   const int S = P / n_bin;
-  const int nbc = CB / n_bin;
-  const int xw = X0 >= P ? 1 : 0;
-  const int ix0 = (X0 - xw * P) / n_bin;
-  float* dst = partial + (fr * (size_t)n_chunks + chunk) * (size_t)(4 * S * S);
-  for (int o = tid; o < nbc * 2 * S; o += NT) {
-    const int bc = o / (2 * S);
-    const int rem = o - bc * 2 * S;
-    const int qq = rem / S;
-    const int iy = rem - qq * S;
-    float sum = 0.f;
-    for (int dx = 0; dx < n_bin; ++dx) {
-      const float* gp = tile + ((bc * n_bin + dx) * 2 + qq) * P + iy * n_bin;
-      for (int dy = 0; dy < n_bin; ++dy) sum += gp[dy];
+  if (CB % n_bin == 0) {
+    // whole bins in the block: b x b sums straight into the chunk's pupils
+    const int nbc = CB / n_bin;
+    const int xw = X0 >= P ? 1 : 0;
+    const int ix0 = (X0 - xw * P) / n_bin;
+    float* dst = partial + (fr * (size_t)n_chunks + chunk) * (size_t)(4 * S * S);
+    for (int o = tid; o < nbc * 2 * S; o += NT) {
+      const int bc = o / (2 * S);
+      const int rem = o - bc * 2 * S;
+      const int qq = rem / S;
+      const int iy = rem - qq * S;
+      float sum = 0.f;
+      for (int dx = 0; dx < n_bin; ++dx) {
+        const float* gp = tile + ((bc * n_bin + dx) * 2 + qq) * P + iy * n_bin;
+        for (int dy = 0; dy < n_bin; ++dy) sum += gp[dy];
+      }
+      dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = sum;
     }
-    dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = sum;
+  } else {
+    // bins straddle blocks: row-binned sums per column, [qq][x'][iy], finished
+    // by pupil_reduce_cols_kernel
+    float* dst = partial + (fr * (size_t)n_chunks + chunk) * (size_t)(4 * P * S);
+    for (int o = tid; o < CB * 2 * S; o += NT) {
+      const int c = o / (2 * S);
+      const int rem = o - c * 2 * S;
+      const int qq = rem / S;
+      const int iy = rem - qq * S;
+      const float* gp = tile + (c * 2 + qq) * P + iy * n_bin;
+      float sum = 0.f;
+      for (int dy = 0; dy < n_bin; ++dy) sum += gp[dy];
+      dst[(size_t)qq * (2 * P * S) + (size_t)(X0 + c) * S + iy] = sum;
+    }
   }
+}
+
+// Pupil images from per-column partials [frame][chunk][qy][x'][iy]: pixel
+// (q, iy, ix) = (1/K) sum over chunks (in order) and the b columns of the bin.
+__global__ __launch_bounds__(256) void pupil_reduce_cols_kernel(const float* __restrict__ partial, int n_chunks,
+                                                                int P, int S, int n_bin, float inv_k,
+                                                                float* __restrict__ pupils) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const size_t fr = blockIdx.y;
+  const int SS = S * S;
+  if (i >= 4 * SS) return;
+  const int q = i / SS, rem = i - q * SS, iy = rem / S, ix = rem - iy * S;
+  const int xw = q & 1, qy = q >> 1;
+  const size_t per_chunk = (size_t)4 * P * S;
+  const float* pp = partial + fr * (size_t)n_chunks * per_chunk + (size_t)qy * (2 * P * S) +
+                    (size_t)(xw * P + ix * n_bin) * S + iy;
+  float s = 0.f;
+  for (int c = 0; c < n_chunks; ++c) {
+    const float* pc = pp + (size_t)c * per_chunk;
+    for (int dx = 0; dx < n_bin; ++dx) s += pc[(size_t)dx * S];
+  }
+  pupils[fr * 4 * (size_t)SS + i] = s * inv_k;
 }
 
 template <int E>
@@ -344,9 +384,18 @@ hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t st) {
 hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t st) {
   switch (a.P) {
     case 128: return launch_cols16_e<8, 8>(a, st);
-    case 480: return a.n_bin == 5 ? launch_cols16_e<30, 10>(a, st) : launch_cols16_e<30, 8>(a, st);
+    case 480: return launch_cols16_e<30, 8>(a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+bool partials_by_column(int P, int n_bin) { return (P == 128 || P == 480) && 8 % n_bin != 0; }
+
+hipError_t launch_reduce_cols(const MeasureArgs& a, float* out, hipStream_t st) {
+  const int S = a.P / a.n_bin;
+  hipLaunchKernelGGL(pupil_reduce_cols_kernel, dim3((4 * S * S + 255) / 256, a.B), dim3(256), 0, st, a.partial,
+                     a.n_chunks, a.P, S, a.n_bin, 1.0f / (float)a.K, out);
+  return hipGetLastError();
 }
 
 }  // namespace pwfs

@@ -37,7 +37,7 @@ struct MeasureArgs {
   // workspace
   cpx* field;          // [B][P][P]    A exp(i phi)
   cpx* Rw;             // [B][n_a][2P][P]
-  float* partial;      // [B][n_chunks][4][S][S]
+  float* partial;      // [B][n_chunks][4][S][S] (per-column [B][n_chunks][2][2P][S], see below)
   // detector (det_on == 0: the pupils are the noiseless intensity)
   int det_on;
   float det_gain, det_ron;   // electrons per unit intensity, readout noise (e- RMS)
@@ -88,6 +88,10 @@ hipError_t launch_psf(const PsfArgs& a, hipStream_t stream);
 hipError_t launch_sh(const ShArgs& a, hipStream_t stream);
 hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t stream);
 hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t stream);
+// Long lines with a binning that does not divide 8 columns: the column pass
+// writes per-column partials [B][n_chunks][2][2P][S], finished here.
+bool partials_by_column(int P, int n_bin);
+hipError_t launch_reduce_cols(const MeasureArgs& a, float* pupils, hipStream_t stream);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t stream);
 hipError_t launch_detector(const float* intensity, float* pixels, int npix, int B, uint64_t frame0, float gain,
                            float ron, uint64_t seed, hipStream_t stream);
