@@ -146,12 +146,11 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
     constexpr int NW = 4 * P;
     constexpr int NPT = (NW + 255) / 256;
     const uint4* src = reinterpret_cast<const uint4*>(fieldg + (fr * (size_t)P + yb) * (size_t)P);
+    // The tail's surplus lanes load word NW - 1 again and store nothing: every
+    // element of w is defined, so w stays in registers.
     uint4 w[NPT];
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int e = tid + 256 * i;
-      if (e < NW) w[i] = src[e];
-    }
+    for (int i = 0; i < NPT; ++i) w[i] = src[min(tid + 256 * i, NW - 1)];
     fence();
 #pragma unroll
     for (int i = 0; i < NPT; ++i) {
@@ -207,7 +206,7 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
 // accumulates |E|^2 of its column over the chunk in registers, then the
 // block bins b x b through LDS and writes its part of the chunk's pupils.
 template <int E, int CB>
-__global__ __launch_bounds__(32 * CB) void col_pass16_kernel(
+__global__ __launch_bounds__(32 * CB, 2) void col_pass16_kernel(
     const cpx* __restrict__ Rw, const cpx* __restrict__ in_b, const cpx* __restrict__ f_b,
     const int* __restrict__ k_order, const int* __restrict__ k_ia, const cpx* __restrict__ mid,
     const cpx* __restrict__ tw, const cpx* __restrict__ outw, float* __restrict__ partial, int n_a, int K,
@@ -259,11 +258,9 @@ __global__ __launch_bounds__(32 * CB) void col_pass16_kernel(
       uint4 w[NPT];
 #pragma unroll
       for (int i = 0; i < NPT; ++i) {
-        const int u = tid + NT * i;
-        if (u < NW) {
-          const int g = u / (2 * CB), rem = u - g * (2 * CB), cc = rem >> 1, h = rem & 1;
-          w[i] = *reinterpret_cast<const uint4*>(src + rw_index(X0 + cc, 4 * g, P) + 2 * h);
-        }
+        const int u = min(tid + NT * i, NW - 1);   // tail lanes reload the last word
+        const int g = u / (2 * CB), rem = u - g * (2 * CB), cc = rem >> 1, h = rem & 1;
+        w[i] = *reinterpret_cast<const uint4*>(src + rw_index(X0 + cc, 4 * g, P) + 2 * h);
       }
       fence();
 #pragma unroll

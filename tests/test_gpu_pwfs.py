@@ -234,6 +234,33 @@ def test_cfg3_frame_and_reference():
     _check_batch(CFG3, opd, batch_max=1)
 
 
+def test_cfg3_binning5_schedules():
+    """Binning 5 does not divide the column pass's 8-column blocks, so each
+    block writes row-binned sums per column and a second kernel finishes the
+    bins over the chunks: ragged modulation chunks (64 = 9 x 7 + 1), one point
+    per chunk, and one chunk for all points reorder only the FP32 sum, on both
+    pupil windows of two frames."""
+    import paper_1607_07624_amd as pw
+    torch = torch_cuda()
+    B = 2
+    opd, _ = open_loop_batch(CFG3, ATMO3, [34, 35])
+    plan = pw.Plan(CFG3, batch_max=B)
+    orc = orc_for(CFG3)
+    i = 1
+    p_o, s_o = orc.measure(opd[i].astype(np.float64))
+    d = torch.from_numpy(np.ascontiguousarray(opd)).cuda()
+    n_a = CFG3.n_mod // 2 + 1
+    for sch in ((5, 7), (n_a, 1), (1, CFG3.n_mod)):
+        plan.set_schedule(B, *sch)
+        pup, s = plan.measure(d)
+        torch.cuda.synchronize()
+        e_s = rel_l2(s.cpu().numpy()[i], s_o)
+        e_p = rel_l2(pup.cpu().numpy()[i], p_o)
+        say(f"[gpu] cfg3 schedule {sch}: frame {i} slope rel err {e_s:.3e}  pupil rel err {e_p:.3e}")
+        assert e_s <= SLOPE_TOL and e_p <= PUPIL_TOL
+    plan.close()
+
+
 CFG_K1 = SensorConfig(name="p32_k1_r0_unmodulated", n_fft=128, n_pupil=32, n_bin=2, n_mod=1,
                       mod_radius_lod=0.0, wavelength_m=750e-9, diameter_m=8.0)
 CFG_K2 = SensorConfig(name="p32_k2_r3", n_fft=128, n_pupil=32, n_bin=2, n_mod=2,
