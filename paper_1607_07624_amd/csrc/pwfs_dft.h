@@ -2,7 +2,8 @@
 //
 // Every transform here is fully unrolled at compile time: the data live in
 // registers of one lane, all twiddles are compile-time FP64 values rounded
-// to FP32, and trivial twiddles (1, -1, +-i) are never multiplied.
+// to FP32, trivial twiddles (1, -1, +-i) are never multiplied, and lengths
+// with coprime factors use the twiddle-free prime-factor split.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -191,14 +192,65 @@ constexpr int first_radix(int n) {
   return n;
 }
 
-// Composite length: decimation in time, E = R * Q.
+// Largest power of the smallest prime factor of n, or 0 when n is itself a
+// prime power (no split into coprime factors).
+constexpr int coprime_part(int n) {
+  for (int p = 2; p <= n; ++p) {
+    if (n % p == 0) {
+      int q = p;
+      while (n % (q * p) == 0) q *= p;
+      return q == n ? 0 : q;
+    }
+  }
+  return 0;
+}
+// a^{-1} mod m for gcd(a, m) = 1, m > 1.
+constexpr int inverse_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 0;
+}
+
+// Composite length E.  With coprime factors E = N1 N2 the prime-factor
+// (Good-Thomas) split needs no twiddles: input n = (N2 n1 + N1 n2) mod E,
+// output k = (N2 u k1 + N1 v k2) mod E with u = N2^{-1} mod N1 and
+// v = N1^{-1} mod N2, since then w_E^{nk} = w_N1^{n1 k1} w_N2^{n2 k2}.
+// Prime powers use decimation in time, E = R * Q:
 //   X[k1 + Q k2] = sum_r w_E^{r k1} w_R^{r k2} DFT_Q(x[R q + r])[k1]
 template <int E, int DIR>
 struct Dft {
+  static constexpr int N1 = coprime_part(E);
   static constexpr int R = first_radix(E);
   static constexpr int Q = E / R;
   __device__ __forceinline__ static void run(cpx (&x)[E]) {
-    if constexpr (Q == 1) {
+    if constexpr (N1 > 0) {
+      constexpr int N2 = E / N1;
+      constexpr int U = inverse_mod(N2 % N1, N1);
+      constexpr int V = inverse_mod(N1 % N2, N2);
+      static_assert((N2 * U) % N1 == 1 && (N1 * V) % N2 == 1, "factors not coprime");
+      cpx t[N1][N2];
+      static_for<0, N1>([&](auto n1_) {
+        constexpr int n1 = decltype(n1_)::value;
+        static_for<0, N2>([&](auto n2_) {
+          constexpr int n2 = decltype(n2_)::value;
+          t[n1][n2] = x[(N2 * n1 + N1 * n2) % E];
+        });
+        Dft<N2, DIR>::run(t[n1]);
+      });
+      static_for<0, N2>([&](auto k2_) {
+        constexpr int k2 = decltype(k2_)::value;
+        cpx u[N1];
+        static_for<0, N1>([&](auto n1_) {
+          constexpr int n1 = decltype(n1_)::value;
+          u[n1] = t[n1][k2];
+        });
+        Dft<N1, DIR>::run(u);
+        static_for<0, N1>([&](auto k1_) {
+          constexpr int k1 = decltype(k1_)::value;
+          x[(N2 * U * k1 + N1 * V * k2) % E] = u[k1];
+        });
+      });
+    } else if constexpr (Q == 1) {
       Radix<R, DIR>::run(x);
     } else {
       cpx t[R][Q];
