@@ -398,8 +398,9 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
     delete p;
     return fail(PWFS_ERR_INVALID_ARG, "internal: modulation ordering");
   }
-  // Tilt ramps r(x) = exp(i 2 pi t (x - xc) / N) (FP64), alone and times the
-  // twist w_N^{(2q+1) x} of the two quads.
+  // Tilt ramps r(x) = exp(i 2 pi t (x - xc) / N) (FP64), negated (the line
+  // operator finishes the low face as y_H - f = -y_L, whose intensity is that
+  // of y_L) and times the twist w_N^{(2q+1) x} of the two quads.
   const double xc = 0.5 * (P - 1);
   const bool t32 = (cfg->flags & 1) != 0;   // precision study: FP32-generated tables
   std::vector<std::complex<double>> tw(2 * (size_t)P);
@@ -429,7 +430,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
     const double a = rho * std::cos(2.0 * M_PI * (double)ia / (double)K);
     for (int x = 0; x < P; ++x) {
       const std::complex<double> r = ramp(a, x);
-      f_a[(size_t)ia * P + x] = to32(r);
+      f_a[(size_t)ia * P + x] = to32(-r);
       for (int q = 0; q < 2; ++q) in_a[((size_t)ia * 2 + q) * P + x] = to32(r * tw[(size_t)q * P + x]);
     }
   }
@@ -437,7 +438,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
     const double bk = rho * std::sin(2.0 * M_PI * (double)k / (double)K);
     for (int y = 0; y < P; ++y) {
       const std::complex<double> r = ramp(bk, y);
-      f_b[(size_t)k * P + y] = to32(r);
+      f_b[(size_t)k * P + y] = to32(-r);
       for (int q = 0; q < 2; ++q) in_b[((size_t)k * 2 + q) * P + y] = to32(r * tw[(size_t)q * P + y]);
     }
   }

@@ -67,11 +67,14 @@ __device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ m
 // Full 1-D pyramid operator for one line.
 //   load_in(m)  = f(x) w_N^{(2q+1) x} at x = l + 4 m (tilted input times this
 //                 quad's twist, one complex product from a combined table);
-//   load_f(m)   = f(l + 4 m) (needed by quad 0 for y_L = f - y_H);
+//   load_x(m), load_t(m): the untilted sample at x = l + 4 m and this quad's
+//                 finishing factor, minus the tilt for quad 0 and zero for
+//                 quad 1, so that y_H + x t is y_H - f = -y_L or y_H;
 //   outw[q * P + j] = (4/N) w_N^{-(2q+1) j}  (2/N times the 2 the half-band step leaves out).
-// On return quad 0 holds y_L(l + 4 m) and quad 1 holds y_H(l + 4 m) in v[m].
-template <int E, typename LoadIn, typename LoadF>
-__device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadF&& load_f,
+// On return quad 0 holds -y_L(l + 4 m) and quad 1 holds y_H(l + 4 m) in v[m]
+// (the sign of a whole pupil window drops out of every intensity).
+template <int E, typename LoadIn, typename LoadX, typename LoadT>
+__device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadX&& load_x, LoadT&& load_t,
                                         const cpx* __restrict__ mid, const cpx* __restrict__ outw,
                                         int q, int l) {
   constexpr int P = 4 * E;
@@ -83,16 +86,13 @@ __device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadF&& l
   fence();
   half_band<E>(v, mid, l);
   const cpx* ow = outw + q * TabLds<E>::QO + l;
-  const float keep = (q == 0) ? 1.f : 0.f;   // quad 0 adds f back (y_L = f - y_H)
-  const float sgn = (q == 0) ? -1.f : 1.f;
   static_for<0, E>([&](auto m_) {
     constexpr int m = decltype(m_)::value;
     if constexpr (m % 8 == 0 && m > 0) fence();
     cpx w = cmul(v[m], ow[4 * m]);
     w.re += swap_quads(w.re);
     w.im += swap_quads(w.im);
-    const cpx f = load_f(m);
-    v[m] = {fmaf(sgn, w.re, keep * f.re), fmaf(sgn, w.im, keep * f.im)};
+    v[m] = cfma(load_x(m), load_t(m), w);
   });
 }
 

@@ -22,6 +22,10 @@ __device__ __forceinline__ cpx csub(cpx a, cpx b) { return {a.re - b.re, a.im - 
 __device__ __forceinline__ cpx cmul(cpx a, cpx b) {
   return {fmaf(a.re, b.re, -a.im * b.im), fmaf(a.re, b.im, a.im * b.re)};
 }
+// a * b + c (four FMAs)
+__device__ __forceinline__ cpx cfma(cpx a, cpx b, cpx c) {
+  return {fmaf(a.re, b.re, fmaf(-a.im, b.im, c.re)), fmaf(a.re, b.im, fmaf(a.im, b.re, c.im))};
+}
 // a * conj(b)
 __device__ __forceinline__ cpx cmulc(cpx a, cpx b) {
   return {fmaf(a.re, b.re, a.im * b.im), fmaf(a.im, b.re, -a.re * b.im)};

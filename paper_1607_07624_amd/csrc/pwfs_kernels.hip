@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
   constexpr int LDP = P + 4;
   __shared__ __align__(16) cpx field[32 * LDP];
   __shared__ __align__(16) cpx s_in[2 * P + 4];
-  __shared__ __align__(16) cpx s_f[P];
+  __shared__ __align__(16) cpx s_f[2 * TabLds<E>::QO];   // [quad 0: -tilt | quad 1: 0]
   __shared__ __align__(16) cpx s_mid[4 * TabLds<E>::MS];
   __shared__ __align__(16) cpx s_out[2 * P + 4];
   const int tid = threadIdx.x;
@@ -109,6 +109,7 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
   }
   stage_mid<E>(s_mid, mid, tid);
   stage_quads<E>(s_out, outw, tid);
+  for (int i = tid; i < P; i += 256) s_f[TabLds<E>::QO + i] = cpx{0.f, 0.f};
   const int a1 = min(a0 + a_chunk, n_a);
   const int r = wave * 8 + t;                     // row within the block
   const cpx* frow = field + r * LDP + l;
@@ -119,10 +120,10 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
     copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
     __syncthreads();
     const cpx* tin = s_in + q * TabLds<E>::QO + l;
-    const cpx* tf = s_f + l;
+    const cpx* tf = s_f + q * TabLds<E>::QO + l;
     cpx v[E];
-    line_op<E>(v, [&](int m) { return cmul(frow[4 * m], tin[4 * m]); },
-               [&](int m) { return cmul(frow[4 * m], tf[4 * m]); }, s_mid, s_out, q, l);
+    line_op<E>(v, [&](int m) { return cmul(frow[4 * m], tin[4 * m]); }, [&](int m) { return frow[4 * m]; },
+               [&](int m) { return tf[4 * m]; }, s_mid, s_out, q, l);
     // Element (x' = qP + l + 4m, y) sits at base + (m >> 1) 8P + (m & 1) 16
     // (see rw_index); each address is formed just before its store so the
     // compiler does not keep E 64-bit addresses live across the transforms.
@@ -159,7 +160,7 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   constexpr int NA = QB ? E / 4 : E;            // accumulators per lane
   __shared__ __align__(16) cpx s_col[32 * P];
   __shared__ __align__(16) cpx s_in[2 * P + 4];
-  __shared__ __align__(16) cpx s_f[P];
+  __shared__ __align__(16) cpx s_f[2 * TabLds<E>::QO];   // [quad 0: -tilt | quad 1: 0]
   __shared__ __align__(16) cpx s_mid[4 * TabLds<E>::MS];
   __shared__ __align__(16) cpx s_out[2 * P + 4];
   const int tid = threadIdx.x;
@@ -172,13 +173,14 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   static_for<0, NA>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
   stage_mid<E>(s_mid, mid, tid);
   stage_quads<E>(s_out, outw, tid);
+  for (int i = tid; i < P; i += 256) s_f[TabLds<E>::QO + i] = cpx{0.f, 0.f};
   const int kb = chunk * k_chunk;
   const int ke = min(kb + k_chunk, K);
   const cpx* frame = Rw + fr * (size_t)n_a * (size_t)(2 * P * P) + (size_t)(X0 >> 3) * (size_t)(8 * P);
   const int c = wave * 8 + t;                      // column within the block
   const cpx* col = s_col + wave * 8 * P + t * 4 + l;   // element (x' = X0 + c, y = l + 4m) at col[32 m]
   const cpx* tin = s_in + q * TabLds<E>::QO + l;
-  const cpx* tf = s_f + l;
+  const cpx* tf = s_f + q * TabLds<E>::QO + l;
   // With QB, lane l keeps the row groups m = 4 i + l: one FMA with a 0/1 mask
   // per group instead of a select and an add.
   float keepm[4];
@@ -196,8 +198,8 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
     copy16(s_f, f_b + (size_t)k * P, P / 2, tid, 256);
     __syncthreads();
     cpx v[E];
-    line_op<E>(v, [&](int m) { return cmul(col[32 * m], tin[4 * m]); },
-               [&](int m) { return cmul(col[32 * m], tf[4 * m]); }, s_mid, s_out, q, l);
+    line_op<E>(v, [&](int m) { return cmul(col[32 * m], tin[4 * m]); }, [&](int m) { return col[32 * m]; },
+               [&](int m) { return tf[4 * m]; }, s_mid, s_out, q, l);
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
       float e = fmaf(v[m].re, v[m].re, v[m].im * v[m].im);

@@ -92,13 +92,14 @@ __device__ __forceinline__ void half_band16(cpx (&v)[E], const cpx* __restrict__
 }
 
 // Full 1-D pyramid operator of one line held by a 32-lane team.
-//   load_in(m) = f(x) w_N^{(2q+1) x}, load_f(m) = f(x) at x = l1 + 4 l2 + 16 m;
-//   ow = outw + q QO + l1 + 4 l2.
-// On return projection 0 holds y_L(x) and projection 1 holds y_H(x) in v[m].
-template <int E, typename LoadIn, typename LoadF>
-__device__ __forceinline__ void line_op16(cpx (&v)[E], LoadIn&& load_in, LoadF&& load_f, const cpx* __restrict__ ml,
-                                          const cpx* __restrict__ tl, const cpx* __restrict__ ow, int q, float sA,
-                                          float sB, bool l3) {
+//   load_in(m) = f(x) w_N^{(2q+1) x} at x = l1 + 4 l2 + 16 m; load_x(m), load_t(m):
+//   the untilted sample and this projection's finishing factor (minus the tilt
+//   for projection 0, zero for projection 1); ow = outw + q QO + l1 + 4 l2.
+// On return projection 0 holds -y_L(x) and projection 1 holds y_H(x) in v[m].
+template <int E, typename LoadIn, typename LoadX, typename LoadT>
+__device__ __forceinline__ void line_op16(cpx (&v)[E], LoadIn&& load_in, LoadX&& load_x, LoadT&& load_t,
+                                          const cpx* __restrict__ ml, const cpx* __restrict__ tl,
+                                          const cpx* __restrict__ ow, float sA, float sB, bool l3) {
   static_for<0, E>([&](auto m_) {
     constexpr int m = decltype(m_)::value;
     if constexpr (m % 8 == 0 && m > 0) fence();
@@ -106,16 +107,13 @@ __device__ __forceinline__ void line_op16(cpx (&v)[E], LoadIn&& load_in, LoadF&&
   });
   fence();
   half_band16<E>(v, ml, tl, sA, sB, l3);
-  const float keep = (q == 0) ? 1.f : 0.f;
-  const float sgn = (q == 0) ? -1.f : 1.f;
   static_for<0, E>([&](auto m_) {
     constexpr int m = decltype(m_)::value;
     if constexpr (m % 8 == 0 && m > 0) fence();
     cpx w = cmul(v[m], ow[16 * m]);
     w.re += swap_halves(w.re);
     w.im += swap_halves(w.im);
-    const cpx f = load_f(m);
-    v[m] = {fmaf(sgn, w.re, keep * f.re), fmaf(sgn, w.im, keep * f.im)};
+    v[m] = cfma(load_x(m), load_t(m), w);
   });
 }
 
@@ -130,7 +128,7 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
   constexpr int P = T::P;
   __shared__ __align__(16) cpx field[8 * T::LDP];
   __shared__ __align__(16) cpx s_in[2 * T::QO];
-  __shared__ __align__(16) cpx s_f[P];
+  __shared__ __align__(16) cpx s_f[2 * T::QO];   // [projection 0: -tilt | projection 1: 0]
   __shared__ __align__(16) cpx s_mid[16 * T::MS];
   __shared__ __align__(16) cpx s_tw[4 * T::TS];
   __shared__ __align__(16) cpx s_out[2 * T::QO];
@@ -162,6 +160,7 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
     }
   }
   stage_tables16<E>(s_mid, s_tw, s_out, mid, tw, outw, tid, 256);
+  for (int i = tid; i < P; i += 256) s_f[T::QO + i] = cpx{0.f, 0.f};
   const int a1 = min(a0 + a_chunk, n_a);
   const int r = wave * 2 + team;                  // row within the block
   const int y = yb + r;
@@ -171,7 +170,7 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
   const cpx* tl = s_tw + l2 * T::TS;
   const cpx* ow = s_out + q * T::QO + xl;
   const cpx* tin = s_in + q * T::QO + xl;
-  const cpx* tf = s_f + xl;
+  const cpx* tf = s_f + q * T::QO + xl;
   const float sA = (l2 & 2) ? -1.f : 1.f, sB = (l2 & 1) ? -1.f : 1.f;
   const bool l3 = l2 == 3;
   for (int ia = a0; ia < a1; ++ia) {
@@ -181,8 +180,8 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
     copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
     __syncthreads();
     cpx v[E];
-    line_op16<E>(v, [&](int m) { return cmul(frow[16 * m], tin[16 * m]); },
-                 [&](int m) { return cmul(frow[16 * m], tf[16 * m]); }, ml, tl, ow, q, sA, sB, l3);
+    line_op16<E>(v, [&](int m) { return cmul(frow[16 * m], tin[16 * m]); }, [&](int m) { return frow[16 * m]; },
+                 [&](int m) { return tf[16 * m]; }, ml, tl, ow, sA, sB, l3);
     // Element (x' = qP + xl + 16 m, y): consecutive m are 16 P apart in the
     // intermediate layout (two 8-column groups); addresses formed just in time.
     cpx* out = Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P) + rw_index(q * P + xl, y, P);
@@ -218,7 +217,7 @@ __global__ __launch_bounds__(32 * CB, 2) void col_pass16_kernel(
   static_assert(4 * CB <= T::GS, "staged columns exceed the y-group stride");
   __shared__ __align__(16) cpx s_col[G * T::GS];
   __shared__ __align__(16) cpx s_in[2 * T::QO];
-  __shared__ __align__(16) cpx s_f[P];
+  __shared__ __align__(16) cpx s_f[2 * T::QO];   // [projection 0: -tilt | projection 1: 0]
   __shared__ __align__(16) cpx s_mid[16 * T::MS];
   __shared__ __align__(16) cpx s_tw[4 * T::TS];
   __shared__ __align__(16) cpx s_out[2 * T::QO];
@@ -231,6 +230,7 @@ __global__ __launch_bounds__(32 * CB, 2) void col_pass16_kernel(
   float acc[E];
   static_for<0, E>([&](auto m_) { acc[decltype(m_)::value] = 0.f; });
   stage_tables16<E>(s_mid, s_tw, s_out, mid, tw, outw, tid, NT);
+  for (int i = tid; i < P; i += NT) s_f[T::QO + i] = cpx{0.f, 0.f};
   const int kb = chunk * k_chunk;
   const int ke = min(kb + k_chunk, K);
   const cpx* frame = Rw + fr * (size_t)n_a * (size_t)(2 * P * P);
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(32 * CB, 2) void col_pass16_kernel(
   const cpx* tl = s_tw + l2 * T::TS;
   const cpx* ow = s_out + q * T::QO + xl;
   const cpx* tin = s_in + q * T::QO + xl;
-  const cpx* tf = s_f + xl;
+  const cpx* tf = s_f + q * T::QO + xl;
   const float sA = (l2 & 2) ? -1.f : 1.f, sB = (l2 & 1) ? -1.f : 1.f;
   const bool l3 = l2 == 3;
   int cur_ia = -1;
@@ -279,7 +279,8 @@ __global__ __launch_bounds__(32 * CB, 2) void col_pass16_kernel(
     __syncthreads();
     cpx v[E];
     line_op16<E>(v, [&](int m) { return cmul(colp[4 * m * T::GS], tin[16 * m]); },
-                 [&](int m) { return cmul(colp[4 * m * T::GS], tf[16 * m]); }, ml, tl, ow, q, sA, sB, l3);
+                 [&](int m) { return colp[4 * m * T::GS]; }, [&](int m) { return tf[16 * m]; }, ml, tl, ow, sA, sB,
+                 l3);
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
       acc[m] += fmaf(v[m].re, v[m].re, v[m].im * v[m].im);

@@ -24,9 +24,9 @@ struct MeasureArgs {
   // plan tables
   const float* amp;
   const cpx* in_a;     // [n_a][2][P]  r_a(x) w_N^{(2q+1)x}
-  const cpx* f_a;      // [n_a][P]     r_a(x)
+  const cpx* f_a;      // [n_a][P]     -r_a(x) (finishing factor of the low-face projection)
   const cpx* in_b;     // [K][2][P]    r_b(y) w_N^{(2q+1)y}
-  const cpx* f_b;      // [K][P]       r_b(y)
+  const cpx* f_b;      // [K][P]       -r_b(y)
   const cpx* mid;      // [4][P/4][2] folded mix coefficients (A/2, B/2) per lane; P = 16 E: [16][E][2]
   const cpx* tw16;     // P = 16 E only: [4][E] subgroup twiddles w_{4E}^{l2 k1}
   const cpx* outw;     // [2][P]
