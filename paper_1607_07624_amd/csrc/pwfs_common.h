@@ -46,18 +46,7 @@ __device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ m
   static_for<0, E>([&](auto k_) {
     constexpr int k = decltype(k_)::value;
     if constexpr (k % 8 == 0 && k > 0) fence();
-    const cpx a = ml[2 * k], b = ml[2 * k + 1];
-    const float pr = quad_perm<0x39>(v[k].re), pim = quad_perm<0x39>(v[k].im);  // lane l+1
-    const float nr = quad_perm<0x93>(v[k].re), nim = quad_perm<0x93>(v[k].im);  // lane l-1
-    float re = fmaf(a.re, pr, v[k].re);
-    re = fmaf(-a.im, pim, re);
-    re = fmaf(b.re, nr, re);
-    re = fmaf(-b.im, nim, re);
-    float im = fmaf(a.re, pim, v[k].im);
-    im = fmaf(a.im, pr, im);
-    im = fmaf(b.re, nim, im);
-    im = fmaf(b.im, nr, im);
-    v[k] = {re, im};
+    v[k] = mix3_quad(v[k], ml[2 * k], ml[2 * k + 1]);   // lanes l + 1, l - 1
   });
   fence();
   Dft<E, -1>::run(v);

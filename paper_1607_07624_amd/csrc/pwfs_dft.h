@@ -303,18 +303,48 @@ __device__ __forceinline__ float swap_quads(float v) {
   return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
 }
 
-// DPP row rotations inside each 16-lane row: lane i reads lane (i + 4) mod 16
-// (row_ror:12) or lane (i - 4) mod 16 (row_ror:4).
-__device__ __forceinline__ float row_from_plus4(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x12C, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float row_from_minus4(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x124, 0xF, 0xF, true));
-}
 // Lane i reads lane i ^ 16 (partner projection of a 32-lane team), ds_swizzle bit mode.
 __device__ __forceinline__ float swap_halves(float v) {
   return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
 }
+
+// Three-tap lane mix V = v + a v' + b v'', with v' and v'' the values of v on
+// the lanes that the DPP controls PL and MI select.  Each neighbour value is
+// read through the DPP operand of the multiply-add itself instead of a
+// separate DPP move (ten VALU instructions instead of twelve).  The leading
+// s_nop 1 gives the two wait states a DPP read needs after a VALU write of
+// its source; inside the block no DPP source is written, and every lane is
+// active wherever this is used.
+#define PWFS_MIX3_ASM(PL, MI)                                                  \
+  "s_nop 1\n\t"                                                                \
+  "v_mul_f32_dpp %0, %2, %4 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"   \
+  "v_mul_f32_dpp %1, %3, %4 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"   \
+  "v_fmac_f32_dpp %0, -%3, %5 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+  "v_fmac_f32_dpp %1, %2, %5 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %0, %2, %6 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %1, %3, %6 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %0, -%3, %7 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+  "v_fmac_f32_dpp %1, %2, %7 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_add_f32_e32 %0, %2, %0\n\t"                                               \
+  "v_add_f32_e32 %1, %3, %1"
+
+// Quad form: v' from lane l + 1, v'' from lane l - 1 (mod 4).
+__device__ __forceinline__ cpx mix3_quad(cpx v, cpx a, cpx b) {
+  cpx r;
+  asm(PWFS_MIX3_ASM("quad_perm:[1,2,3,0]", "quad_perm:[3,0,1,2]")
+      : "=&v"(r.re), "=&v"(r.im)
+      : "v"(v.re), "v"(v.im), "v"(a.re), "v"(a.im), "v"(b.re), "v"(b.im));
+  return r;
+}
+// Row form: v' from lane i + 4, v'' from lane i - 4 (mod 16, inside each row of 16).
+__device__ __forceinline__ cpx mix3_row4(cpx v, cpx a, cpx b) {
+  cpx r;
+  asm(PWFS_MIX3_ASM("row_ror:12", "row_ror:4")
+      : "=&v"(r.re), "=&v"(r.im)
+      : "v"(v.re), "v"(v.im), "v"(a.re), "v"(a.im), "v"(b.re), "v"(b.im));
+  return r;
+}
+#undef PWFS_MIX3_ASM
 
 // Radix-2 butterfly between the lanes of a quad paired by the DPP pattern PERM
 // (0x4E: lane ^ 2, 0xB1: lane ^ 1): self + partner on the lane whose pair bit

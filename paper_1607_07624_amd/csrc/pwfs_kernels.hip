@@ -144,20 +144,23 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
 // 32 columns form one contiguous block of 32P complex values, staged in LDS
 // once per distinct x tilt (k and K-k are adjacent in the modulation order
 // and share it).  Each team accumulates |E|^2 of its column over the chunk
-// in registers.  With QB (binning a multiple of 4) the four rows 4m..4m+3,
-// held by the four lanes of a quad, are summed by a DPP quad reduction as
-// they are accumulated, and lane l keeps the row groups m = 4i + l.  The
+// in registers.  With G = 4 (binning a multiple of 4) the four rows
+// 4m..4m+3, held by the four lanes of a quad, are summed by a DPP quad
+// reduction as they are accumulated and lane l keeps the row groups
+// m = 4i + l; with G = 2 (even binning) lane pairs sum rows 4m + {0, 1} and
+// 4m + {2, 3} and each lane keeps every other m; G = 1 keeps every row.  The
 // block then finishes the b x b binning through LDS and writes its part of
 // the chunk's four pupil images.
-//   in_b[k][q][y] = r_b(y) w_N^{(2q+1) y},  f_b[k][y] = r_b(y).
-template <int E, bool QB>
+//   in_b[k][q][y] = r_b(y) w_N^{(2q+1) y},  f_b[k][y] = -r_b(y).
+template <int E, int G>
 __global__ __launch_bounds__(256) void col_pass_kernel(
     const cpx* __restrict__ Rw, const cpx* __restrict__ in_b, const cpx* __restrict__ f_b,
     const int* __restrict__ k_order, const int* __restrict__ k_ia, const cpx* __restrict__ mid,
     const cpx* __restrict__ outw, float* __restrict__ partial, int n_a, int K, int k_chunk,
     int n_chunks, int n_bin) {
   constexpr int P = 4 * E;
-  constexpr int NA = QB ? E / 4 : E;            // accumulators per lane
+  static_assert(G == 1 || G == 2 || G == 4, "row groups of 1, 2 or 4 lanes");
+  constexpr int NA = E / G;                      // accumulators per lane
   __shared__ __align__(16) cpx s_col[32 * P];
   __shared__ __align__(16) cpx s_in[2 * P + 4];
   __shared__ __align__(16) cpx s_f[2 * TabLds<E>::QO];   // [quad 0: -tilt | quad 1: 0]
@@ -181,10 +184,10 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   const cpx* col = s_col + wave * 8 * P + t * 4 + l;   // element (x' = X0 + c, y = l + 4m) at col[32 m]
   const cpx* tin = s_in + q * TabLds<E>::QO + l;
   const cpx* tf = s_f + q * TabLds<E>::QO + l;
-  // With QB, lane l keeps the row groups m = 4 i + l: one FMA with a 0/1 mask
-  // per group instead of a select and an add.
-  float keepm[4];
-  static_for<0, 4>([&](auto j_) { keepm[decltype(j_)::value] = (l == decltype(j_)::value) ? 1.f : 0.f; });
+  // Lane l keeps the groups m = G i + (l mod G): one FMA with a 0/1 mask per
+  // group instead of a select and an add.
+  float keepm[G];
+  static_for<0, G>([&](auto j_) { keepm[decltype(j_)::value] = ((l & (G - 1)) == decltype(j_)::value) ? 1.f : 0.f; });
   int cur_ia = -1;
   for (int kk = kb; kk < ke; ++kk) {
     const int k = k_order[kk];
@@ -203,10 +206,13 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
       float e = fmaf(v[m].re, v[m].re, v[m].im * v[m].im);
-      if constexpr (QB) {
+      if constexpr (G == 4) {
         e += quad_perm<0xB1>(e);                   // lanes (0,1), (2,3)
         e += quad_perm<0x4E>(e);                   // lanes (0,2), (1,3)
         acc[m >> 2] = fmaf(keepm[m & 3], e, acc[m >> 2]);
+      } else if constexpr (G == 2) {
+        e += quad_perm<0xB1>(e);                   // lanes (0,1), (2,3)
+        acc[m >> 1] = fmaf(keepm[m & 1], e, acc[m >> 1]);
       } else {
         acc[m] += e;
       }
@@ -219,15 +225,17 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
   const int xw = X0 >= P ? 1 : 0;
   const int ix0 = (X0 - xw * P) / n_bin;
   float* dst = partial + (fr * (size_t)n_chunks + chunk) * (size_t)(4 * S * S);
-  if constexpr (QB) {
-    // tile[c][q][g]: sum over rows 4g..4g+3 of column c, window q.
-    float* my = tile + (c * 2 + q) * (P / 4) + l;
+  if constexpr (G > 1) {
+    // tile[c][q][g]: sum over rows G g .. G g + G - 1 of column c, window q;
+    // lane l holds the groups g = 4 i + slot.
+    const int slot = G == 4 ? l : 2 * (l & 1) + (l >> 1);
+    float* my = tile + (c * 2 + q) * (P / G) + slot;
     static_for<0, NA>([&](auto i_) {
       constexpr int i = decltype(i_)::value;
       my[4 * i] = acc[i];
     });
     __syncthreads();
-    const int gpb = n_bin / 4;                     // row groups per bin
+    const int gpb = n_bin / G;                     // row groups per bin
     for (int o = tid; o < nbc * 2 * S; o += 256) {
       const int bc = o / (2 * S);
       const int rem = o - bc * 2 * S;
@@ -235,7 +243,7 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
       const int iy = rem - qq * S;
       float sum = 0.f;
       for (int dx = 0; dx < n_bin; ++dx) {
-        const float* g = tile + ((bc * n_bin + dx) * 2 + qq) * (P / 4) + iy * gpb;
+        const float* g = tile + ((bc * n_bin + dx) * 2 + qq) * (P / G) + iy * gpb;
         for (int dg = 0; dg < gpb; ++dg) sum += g[dg];
       }
       dst[(size_t)(xw + 2 * qq) * S * S + (size_t)iy * S + ix0 + bc] = sum;
@@ -487,10 +495,13 @@ template <int E>
 static hipError_t launch_cols(const MeasureArgs& a, hipStream_t st) {
   dim3 grid(2 * a.P / 32, a.n_chunks, a.B);
   if (a.n_bin % 4 == 0)
-    hipLaunchKernelGGL((col_pass_kernel<E, true>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
+    hipLaunchKernelGGL((col_pass_kernel<E, 4>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
+                       a.k_ia, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
+  else if (a.n_bin % 2 == 0)
+    hipLaunchKernelGGL((col_pass_kernel<E, 2>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
                        a.k_ia, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
   else
-    hipLaunchKernelGGL((col_pass_kernel<E, false>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
+    hipLaunchKernelGGL((col_pass_kernel<E, 1>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
                        a.k_ia, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
   return hipGetLastError();
 }

@@ -67,18 +67,7 @@ __device__ __forceinline__ void half_band16(cpx (&v)[E], const cpx* __restrict__
   static_for<0, E>([&](auto k_) {
     constexpr int k = decltype(k_)::value;
     if constexpr (k % 8 == 0 && k > 0) fence();
-    const cpx a = ml[2 * k], b = ml[2 * k + 1];
-    const float pr = row_from_plus4(v[k].re), pim = row_from_plus4(v[k].im);     // outer lane l1 + 1
-    const float nr = row_from_minus4(v[k].re), nim = row_from_minus4(v[k].im);   // outer lane l1 - 1
-    float re = fmaf(a.re, pr, v[k].re);
-    re = fmaf(-a.im, pim, re);
-    re = fmaf(b.re, nr, re);
-    re = fmaf(-b.im, nim, re);
-    float im = fmaf(a.re, pim, v[k].im);
-    im = fmaf(a.im, pr, im);
-    im = fmaf(b.re, nim, im);
-    im = fmaf(b.im, nr, im);
-    v[k] = {re, im};
+    v[k] = mix3_row4(v[k], ml[2 * k], ml[2 * k + 1]);   // outer lanes l1 + 1, l1 - 1
   });
   fence();
   static_for<0, E>([&](auto k_) {
