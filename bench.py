@@ -38,13 +38,13 @@ PEAK_HBM_GBS = 8000.0
 # modulation chunk).  Valid only for the sources with these hashes (the kernels and the plan's
 # modulation order); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "3433cca61b835e38be2e35b92ff40346d29c43a0",
-                     "pwfs_common.h": "05ad04b20e1339450c0fcb05421ccf490d40edbf",
-                     "pwfs_dft.h": "dc4c8d92932d722a11520e45113183e7ea3c618a",
-                     "pwfs_api.cpp": "385b2a5502cc9dbe0e41cafb57495e1f2ffe1700"},
+    "sources_sha1": {"pwfs_kernels.hip": "7c292e3589dfbf0ca31749618d366ca7aceefb7d",
+                     "pwfs_common.h": "50d6264b0088e9585ba397ee39d86f4e88d42bd9",
+                     "pwfs_dft.h": "c25e60bc82b746d087c11d9741edc141a2bed7c1",
+                     "pwfs_api.cpp": "4b5b5298bbf091c2a7c4bc2e8dad321e9154a7fa"},
     "batch": 16,
-    "col_pass_kib": {(3, 2): (81269.3, 9600.0), (3, 3): (107868.0, 6400.0), (3, 4): (82013.0, 4800.0),
-                     (3, 6): (81747.6, 3200.0)},
+    "col_pass_kib": {(3, 2): (81256.4, 9600.0), (3, 3): (107718.6, 6400.1), (3, 4): (81807.4, 4800.0),
+                     (3, 6): (81640.3, 3200.0)},
 }
 
 
@@ -76,8 +76,24 @@ def _first_radix(n):
     return n
 
 
+def _coprime_part(n):
+    for p in range(2, n + 1):
+        if n % p == 0:
+            q = p
+            while n % (q * p) == 0:
+                q *= p
+            return 0 if q == n else q
+    return 0
+
+
 def dft_flops(E: int) -> int:
-    """Real flops of the in-register mixed-radix DFT of length E (trivial twiddles free)."""
+    """Real flops of the in-register DFT of length E: the twiddle-free
+    prime-factor split E = N1 N2 for coprime factors, else mixed-radix
+    decimation in time (trivial twiddles free)."""
+    N1 = _coprime_part(E)
+    if N1:
+        N2 = E // N1
+        return N1 * dft_flops(N2) + N2 * dft_flops(N1)
     R = _first_radix(E)
     Q = E // R
     if Q == 1:
@@ -91,7 +107,7 @@ def line_flops(P: int, intensity: bool) -> int:
     length P in four-step form, input twist, output twiddles, y_L = f - y_H,
     plus |E|^2 accumulation in the column pass)."""
     E = P // 4
-    projection = 4 * (2 * dft_flops(E) + 20 * E)     # 4 lanes: DFT_E, twiddle + 3-tap mix + conj twiddle, IDFT_E
+    projection = 4 * (2 * dft_flops(E) + 16 * E)     # 4 lanes: DFT_E, 3-tap mix (two complex MACs + v), IDFT_E
     f = 6 * P                                         # tilt ramp times input
     twist = 2 * 6 * P
     out = 2 * 6 * P + 2 * P + 2 * P                   # output twiddles, sum of the two halves, f - y_H
@@ -331,7 +347,7 @@ def main():
                 "traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 counters)",
                 "hbm_frac_of_peak": (round(traffic / (col_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
                                      if traffic else None),
-                "kernel": "col_pass_kernel<40>", "kernel_ms": round(col_ms, 4),
+                "kernel": "col_pass_kernel<40, 4>", "kernel_ms": round(col_ms, 4),
                 "flop_per_launch": int(fl_col),
                 "convention_5NlogN_tflops": round(conv / (col_ms * 1e-3) / 1e12, 2)}
     extra = {"row_pass_ms": round(row_ms, 4), "row_pass_tflops": round(fl_row / (row_ms * 1e-3) / 1e12, 2),

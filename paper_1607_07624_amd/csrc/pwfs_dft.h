@@ -336,15 +336,30 @@ __device__ __forceinline__ cpx mix3_quad(cpx v, cpx a, cpx b) {
       : "v"(v.re), "v"(v.im), "v"(a.re), "v"(a.im), "v"(b.re), "v"(b.im));
   return r;
 }
-// Row form: v' from lane i + 4, v'' from lane i - 4 (mod 16, inside each row of 16).
-__device__ __forceinline__ cpx mix3_row4(cpx v, cpx a, cpx b) {
-  cpx r;
-  asm(PWFS_MIX3_ASM("row_ror:12", "row_ror:4")
-      : "=&v"(r.re), "=&v"(r.im)
-      : "v"(v.re), "v"(v.im), "v"(a.re), "v"(a.im), "v"(b.re), "v"(b.im));
-  return r;
-}
 #undef PWFS_MIX3_ASM
+
+// Row form: v' from lane i + 4 (row_ror:12), v'' from lane i - 4 (row_ror:4),
+// mod 16 inside each row of 16 lanes.  Plain DPP moves and FMAs: the long-line
+// column pass runs at the 256-register limit, where the early-clobber outputs
+// of the DPP-operand form above make the compiler spill.
+__device__ __forceinline__ cpx mix3_row4(cpx v, cpx a, cpx b) {
+  auto rot = [](float x, auto ctrl) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), decltype(ctrl)::value, 0xF, 0xF, true));
+  };
+  using P4 = std::integral_constant<int, 0x12C>;
+  using M4 = std::integral_constant<int, 0x124>;
+  const float pr = rot(v.re, P4{}), pim = rot(v.im, P4{});
+  const float nr = rot(v.re, M4{}), nim = rot(v.im, M4{});
+  float re = fmaf(a.re, pr, v.re);
+  re = fmaf(-a.im, pim, re);
+  re = fmaf(b.re, nr, re);
+  re = fmaf(-b.im, nim, re);
+  float im = fmaf(a.re, pim, v.im);
+  im = fmaf(a.im, pr, im);
+  im = fmaf(b.re, nim, im);
+  im = fmaf(b.im, nr, im);
+  return {re, im};
+}
 
 // Radix-2 butterfly between the lanes of a quad paired by the DPP pattern PERM
 // (0x4E: lane ^ 2, 0xB1: lane ^ 1): self + partner on the lane whose pair bit
