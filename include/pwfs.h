@@ -23,9 +23,14 @@
  *   - pyramid mask exp(-2 pi i Delta (|u| + |v|) / N) on signed frequency
  *     indices, apex on frequency bin 0, Delta = N / 4;
  *   - pupil q = (x side +) + 2 (y side +), each binned b x b to S x S,
- *     S = P / b, stored [q][iy][ix] row-major;
- *   - valid subapertures: pupil fill fraction of the b x b block >= 0.5,
- *     listed as j = iy * S + ix in ascending order;
+ *     S = P / b, stored [q][iy][ix] row-major; or, with det_window = S > 0
+ *     (and b = 1), each P x P window resampled to S x S detector pixels of
+ *     pitch P / S pupil pixels (a non-integer rebin: detector pixel (j, i)
+ *     integrates the piecewise-constant window over
+ *     [j P/S, (j+1) P/S) x [i P/S, (i+1) P/S), in pixel-area units);
+ *   - valid subapertures: pupil fill fraction of the b x b block (of the
+ *     detector pixel's footprint with det_window) >= 0.5, listed as
+ *     j = iy * S + ix in ascending order (pwfs_set_valid replaces the list);
  *   - slopes: sx = [(I1 + I3) - (I0 + I2)] / n, sy = [(I2 + I3) - (I0 + I1)] / n
  *     with n the mean total flux over valid subapertures of the same frame
  *     (norm_mode 0) or each subaperture's own total flux (norm_mode 1);
@@ -63,8 +68,8 @@ enum {
 
 typedef struct {
   int32_t n_fft;      /* N: FFT grid side.  Must equal 4 * n_pupil.                        */
-  int32_t n_pupil;    /* P: pupil diameter in pixels: 32, 64 or 160.                       */
-  int32_t n_bin;      /* b: detector binning, P % b == 0, b in {1, 2, 4, 8}.              */
+  int32_t n_pupil;    /* P: pupil window in pixels: 32, 64, 128, 160 or 480.               */
+  int32_t n_bin;      /* b: detector binning, P % b == 0, b in {1, 2, 4, 8} (or 5, P 480). */
   int32_t n_mod;      /* K: modulation points, 1 <= K <= 1024.                            */
   int32_t face_shift; /* Delta in pixels; 0 selects N / 4 (the only supported value).     */
   int32_t norm_mode;  /* 0: global mean flux over valid subapertures; 1: per subaperture. */
@@ -78,6 +83,14 @@ typedef struct {
   double wavelength_m;    /* lambda                                                       */
   double mod_radius_lod;  /* r_mod in lambda / D, >= 0                                    */
   double obstruction;     /* central obstruction, fraction of D, 0 <= eps < 1              */
+  int32_t det_window;     /* 0: integer binning by n_bin.  S > 0: each pupil window of P   */
+                          /* pixels is resampled to S detector pixels (2 <= S <= P, n_bin */
+                          /* must be 1).  The paper's detector (output_resolution 80,     */
+                          /* pupils of pup_diam 30 pixels whose centres are pup_dist 36   */
+                          /* apart) is S = pup_dist = 36 with a pupil of diameter         */
+                          /* P pup_diam / pup_dist pupil pixels: the four windows fill    */
+                          /* the central 72 x 72 pixels of the 80 x 80 frame.             */
+  int32_t reserved;       /* must be 0                                                    */
 } pwfs_config_t;
 
 /* Build a plan: validates cfg, generates the FP64 tables (tilt ramps,
@@ -95,6 +108,16 @@ int pwfs_plan_info(pwfs_plan_t plan, int32_t* n_valid, int32_t* n_sub, size_t* w
 /* Copy the valid-subaperture list (n_valid int32, ascending j = iy*S+ix)
  * into host memory. */
 int pwfs_get_valid(pwfs_plan_t plan, int32_t* idx_host);
+
+/* Replace the valid-subaperture list with n host indices (strictly
+ * ascending, each in [0, S * S)), e.g. from a pupil acquisition on a
+ * detector frame (the paper's calibration: a flat-wavefront frame taken with
+ * a large modulation radius, thresholded).  Reallocates the list and the
+ * reference, then measures the reference slopes of a flat wavefront again
+ * (noiseless, detector bypassed).  Synchronises the device; must not overlap
+ * any other call on this plan.  PWFS_ERR_INVALID_ARG for an empty, unsorted
+ * or out-of-range list (the plan keeps its previous list). */
+int pwfs_set_valid(pwfs_plan_t plan, const int32_t* idx_host, int32_t n);
 
 /* Copy the current reference slopes (2 * n_valid floats) into host memory. */
 int pwfs_get_reference(pwfs_plan_t plan, float* sref_host);

@@ -16,7 +16,9 @@ model implemented here is the textbook modulated pyramid, with every
 convention the paper leaves open fixed as documented in each function.
 """
 from .pwfs import (pupil_amplitude, valid_subapertures, modulation_offsets,
-                   pyramid_mask, intensity, pupil_images, slopes, Oracle)
+                   pyramid_mask, intensity, pupil_images, slopes, Oracle,
+                   overlap_matrix, rebin, acquire_valid)
 
 __all__ = ["pupil_amplitude", "valid_subapertures", "modulation_offsets",
-           "pyramid_mask", "intensity", "pupil_images", "slopes", "Oracle"]
+           "pyramid_mask", "intensity", "pupil_images", "slopes", "Oracle",
+           "overlap_matrix", "rebin", "acquire_valid"]

@@ -24,8 +24,15 @@ Conventions (the paper is silent on all of them):
     signed frequency indices in [-N/2, N/2) (apex on bin 0);
   * back to the pupil: inverse FFT with 1/N^2; intensity = mean over k;
   * pupil q = (sx > 0) + 2 (sy > 0) is the window at rows o + sy Delta,
-    cols o + sx Delta (sx, sy = -1/+1), summed b x b;
-  * valid subaperture: pupil fill fraction of its b x b block >= 0.5;
+    cols o + sx Delta (sx, sy = -1/+1), summed b x b; or, with a detector
+    window S (the detector's output resolution, Tab. 1 "pyramid":
+    output_resolution, pup_diam, pup_dist), resampled to S x S detector
+    pixels of pitch P / S: each detector pixel integrates the
+    piecewise-constant window over its footprint (a non-integer rebin);
+  * valid subaperture: pupil fill fraction of its b x b block (of the
+    detector pixel's footprint) >= 0.5; or the paper's pupil acquisition
+    (Sec. 4 calibration script): a flat-wavefront frame taken with the
+    modulation radius raised to 20 lambda/D, thresholded;
   * slopes: sx = [(I1 + I3) - (I0 + I2)] / n, sy = [(I2 + I3) - (I0 + I1)] / n,
     n = mean total flux over valid subapertures (norm_mode 0) or each
     subaperture's own total flux (norm_mode 1); ordering [sx over V; sy over V]
@@ -52,13 +59,47 @@ def pupil_amplitude(P: int, obstruction: float = 0.0) -> np.ndarray:
     return inside.astype(np.float64)
 
 
-def valid_subapertures(A: np.ndarray, b: int) -> np.ndarray:
+def overlap_matrix(P: int, S: int) -> np.ndarray:
+    """W [S, P]: length of [y, y + 1) inside [j P / S, (j + 1) P / S) in
+    pupil pixels (exact: both ends are multiples of 1 / S)."""
+    W = np.zeros((S, P))
+    for j in range(S):
+        for y in range(P):
+            ov = min((y + 1) * S, (j + 1) * P) - max(y * S, j * P)
+            if ov > 0:
+                W[j, y] = ov / S
+    return W
+
+
+def rebin(win: np.ndarray, S: int) -> np.ndarray:
+    """Detector pixels [S, S] of a P x P window: the integral of the
+    piecewise-constant image over each pixel's footprint (pupil-pixel area
+    units), out[j, i] = sum_y,x W[j, y] W[i, x] win[y, x]."""
+    W = overlap_matrix(win.shape[0], S)
+    return W @ win @ W.T
+
+
+def valid_subapertures(A: np.ndarray, b: int, det_window: int = 0) -> np.ndarray:
     """Indices j = iy * S + ix (ascending) of subapertures whose b x b block
-    of the pupil is at least half filled."""
+    of the pupil (detector pixel footprint with a detector window) is at
+    least half filled."""
     P = A.shape[0]
-    S = P // b
-    fill = A.reshape(S, b, S, b).mean(axis=(1, 3))
+    if det_window:
+        S = det_window
+        fill = rebin(A, S) / (P / S) ** 2
+    else:
+        S = P // b
+        fill = A.reshape(S, b, S, b).mean(axis=(1, 3))
     return np.flatnonzero(fill.ravel() >= 0.5).astype(np.int64)
+
+
+def acquire_valid(pupils: np.ndarray, thr: float) -> np.ndarray:
+    """Pupil acquisition on a detector frame [4, S, S] (the paper's
+    calibration thresholds a flat-wavefront frame taken with a large
+    modulation radius; its thresholds are not given): subapertures where the
+    sum of the four pupil images reaches thr times its maximum."""
+    tot = pupils.sum(axis=0).ravel()
+    return np.flatnonzero(tot >= thr * tot.max()).astype(np.int64)
 
 
 def modulation_offsets(cfg) -> tuple[np.ndarray, np.ndarray]:
@@ -111,7 +152,8 @@ def intensity(cfg, opd_nm: np.ndarray, A: np.ndarray | None = None,
 def pupil_images(cfg, I: np.ndarray) -> np.ndarray:
     """Four binned pupil images [4, S, S] cut from the N x N intensity."""
     N, P, b = cfg.n_fft, cfg.n_pupil, cfg.n_bin
-    S = P // b
+    dw = getattr(cfg, "det_window", 0)
+    S = dw if dw else P // b
     o = (N - P) // 2
     d = cfg.delta
     out = np.empty((4, S, S))
@@ -120,7 +162,7 @@ def pupil_images(cfg, I: np.ndarray) -> np.ndarray:
         sy = 1 if q & 2 else -1
         r0, c0 = o + sy * d, o + sx * d
         win = I[r0:r0 + P, c0:c0 + P]
-        out[q] = win.reshape(S, b, S, b).sum(axis=(1, 3))
+        out[q] = rebin(win, S) if dw else win.reshape(S, b, S, b).sum(axis=(1, 3))
     return out
 
 
@@ -137,10 +179,11 @@ def slopes(pupils: np.ndarray, valid: np.ndarray, norm_mode: int = 0) -> np.ndar
 class Oracle:
     """One sensor: pupil, valid list and reference slopes fixed at construction."""
 
-    def __init__(self, cfg, A: np.ndarray | None = None):
+    def __init__(self, cfg, A: np.ndarray | None = None, valid: np.ndarray | None = None):
         self.cfg = cfg
         self.A = pupil_amplitude(cfg.n_pupil, cfg.obstruction) if A is None else np.asarray(A, np.float64)
-        self.valid = valid_subapertures(self.A, cfg.n_bin)
+        self.valid = (valid_subapertures(self.A, cfg.n_bin, getattr(cfg, "det_window", 0)) if valid is None
+                      else np.asarray(valid, np.int64))
         flat = np.zeros((cfg.n_pupil, cfg.n_pupil))
         self.ref_pupils = pupil_images(cfg, intensity(cfg, flat, self.A))
         self.s_ref = slopes(self.ref_pupils, self.valid, cfg.norm_mode)

@@ -43,7 +43,8 @@ class config_struct(ctypes.Structure):
                 ("n_mod", ctypes.c_int32), ("face_shift", ctypes.c_int32), ("norm_mode", ctypes.c_int32),
                 ("batch_max", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("diameter_m", ctypes.c_double), ("wavelength_m", ctypes.c_double),
-                ("mod_radius_lod", ctypes.c_double), ("obstruction", ctypes.c_double)]
+                ("mod_radius_lod", ctypes.c_double), ("obstruction", ctypes.c_double),
+                ("det_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def library_path() -> str:
@@ -63,6 +64,7 @@ def load_library():
     lib.pwfs_plan.argtypes = [ctypes.POINTER(config_struct), vp, ctypes.POINTER(vp)]
     lib.pwfs_plan_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz)]
     lib.pwfs_get_valid.argtypes = [vp, vp]
+    lib.pwfs_set_valid.argtypes = [vp, vp, i32]
     lib.pwfs_get_reference.argtypes = [vp, vp]
     lib.pwfs_set_reference.argtypes = [vp, vp, vp]
     lib.pwfs_measure.argtypes = [vp, vp, i32, vp, vp, vp]
@@ -97,7 +99,7 @@ def load_library():
     lib.pwfs_strerror.restype = ctypes.c_char_p
     lib.pwfs_last_error.argtypes = []
     lib.pwfs_last_error.restype = ctypes.c_char_p
-    for name in ("pwfs_plan", "pwfs_plan_info", "pwfs_get_valid", "pwfs_get_reference",
+    for name in ("pwfs_plan", "pwfs_plan_info", "pwfs_get_valid", "pwfs_set_valid", "pwfs_get_reference",
                  "pwfs_set_reference", "pwfs_measure", "recon_apply", "pwfs_get_pupil",
                  "pwfs_timing_enable", "pwfs_timing_read", "pwfs_get_schedule", "pwfs_set_schedule",
                  "pwfs_autotune", "pwfs_set_detector", "pwfs_get_detector", "pwfs_set_frame_counter",
@@ -136,7 +138,8 @@ def make_config(cfg, batch_max: int, flags: int = 0) -> config_struct:
     return config_struct(n_fft=cfg.n_fft, n_pupil=cfg.n_pupil, n_bin=cfg.n_bin, n_mod=cfg.n_mod,
                          face_shift=cfg.face_shift, norm_mode=cfg.norm_mode, batch_max=batch_max,
                          flags=flags, diameter_m=cfg.diameter_m, wavelength_m=cfg.wavelength_m,
-                         mod_radius_lod=cfg.mod_radius_lod, obstruction=cfg.obstruction)
+                         mod_radius_lod=cfg.mod_radius_lod, obstruction=cfg.obstruction,
+                         det_window=getattr(cfg, "det_window", 0), reserved=0)
 
 
 class Plan:
@@ -169,6 +172,16 @@ class Plan:
         out = np.empty(self.n_valid, np.int32)
         _check(self.lib.pwfs_get_valid(self.handle, out.ctypes.data), "pwfs_get_valid")
         return out
+
+    def set_valid(self, idx) -> None:
+        """Replace the valid-subaperture list (pwfs_set_valid); the reference
+        slopes are measured again."""
+        a = np.ascontiguousarray(idx, dtype=np.int32)
+        _check(self.lib.pwfs_set_valid(self.handle, a.ctypes.data, int(a.size)), "pwfs_set_valid")
+        nv, ns, ws = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+        _check(self.lib.pwfs_plan_info(self.handle, ctypes.byref(nv), ctypes.byref(ns), ctypes.byref(ws)),
+               "pwfs_plan_info")
+        self.n_valid, self.workspace_bytes = nv.value, ws.value
 
     @property
     def s_ref(self) -> np.ndarray:

@@ -117,6 +117,8 @@ struct pwfs_plan_s {
   pwfs_config_t cfg{};
   int device = 0;
   int N = 0, P = 0, E = 0, S = 0, b = 0, K = 0, n_a = 0, nv = 0, batch_max = 0;
+  int Sb = 0;                                   // column-pass images: P / b (S unless det_window)
+  int Sd = 0;                                   // det_window (0: integer binning)
   double kphase = 0.0;
   std::vector<int> valid;
   // device tables
@@ -136,6 +138,7 @@ struct pwfs_plan_s {
   cpx* Rw = nullptr;
   float* partial = nullptr;
   float* pupils = nullptr;
+  float* fullres = nullptr;                     // [batch_max][4][P][P] with det_window
   cpx* field = nullptr;
   float* zero_opd = nullptr;
   float* tmp_slopes = nullptr;
@@ -187,7 +190,7 @@ void split_work(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk, int* n_
 // per-column row-binned sums when the binning does not divide a long-line
 // column block.
 size_t partial_per_chunk(const pwfs_plan_s* p) {
-  return pwfs::partials_by_column(p->P, p->b) ? (size_t)4 * p->P * p->S : (size_t)4 * p->S * p->S;
+  return pwfs::partials_by_column(p->P, p->b) ? (size_t)4 * p->P * p->Sb : (size_t)4 * p->Sb * p->Sb;
 }
 
 // A schedule is usable when its chunk partials fit the plan's workspace.
@@ -219,6 +222,12 @@ int validate(const pwfs_config_t* c) {
   if (!(b_pow2 || (long_lines(P) && c->n_bin == 5 && P % 10 == 0)))
     return fail(PWFS_ERR_UNSUPPORTED, "n_bin must be 1, 2, 4 or 8 (or 5 with n_pupil 480)");
   if (c->batch_max > 65535) return fail(PWFS_ERR_UNSUPPORTED, "batch_max > 65535");
+  if (c->reserved != 0) return fail(PWFS_ERR_INVALID_ARG, "reserved must be 0");
+  if (c->det_window != 0) {
+    if (c->det_window < 2 || c->det_window > P)
+      return fail(PWFS_ERR_INVALID_ARG, "det_window must be 0 or in [2, n_pupil]");
+    if (c->n_bin != 1) return fail(PWFS_ERR_INVALID_ARG, "det_window needs n_bin 1");
+  }
   return PWFS_OK;
 }
 
@@ -227,7 +236,7 @@ void free_plan(pwfs_plan_s* p) {
   DeviceGuard g(p->device);
   void* ptrs[] = {p->amp, p->in_a, p->f_a, p->in_b, p->f_b, p->mid, p->tw16, p->outw, p->k_order, p->k_ia,
                   p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->pixels, p->field, p->zero_opd,
-                  p->tmp_slopes};
+                  p->tmp_slopes, p->fullres};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto* pool : {&p->ev_used, &p->ev_free})
@@ -273,6 +282,8 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
   a.Rw = p->Rw;
   a.field = p->field;
   a.partial = p->partial;
+  a.det_window = p->Sd;
+  a.fullres = p->fullres;
   return a;
 }
 
@@ -345,7 +356,9 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   p->P = P;
   p->E = P / 4;
   p->b = b;
-  p->S = P / b;
+  p->Sb = P / b;
+  p->Sd = cfg->det_window;
+  p->S = p->Sd > 0 ? p->Sd : p->Sb;
   p->K = K;
   p->batch_max = cfg->batch_max;
   p->kphase = 2.0 * M_PI * 1e-9 / cfg->wavelength_m;
@@ -363,15 +376,30 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   } else {
     circle_pupil(P, cfg->obstruction, amp);
   }
-  // Valid subapertures: block fill fraction >= 0.5.
+  // Valid subapertures: fill fraction of the b x b block (of the detector
+  // pixel's footprint with det_window, overlaps in units of 1 / S) >= 0.5.
   const int S = p->S;
-  for (int iy = 0; iy < S; ++iy)
-    for (int ix = 0; ix < S; ++ix) {
-      double s = 0.0;
-      for (int dy = 0; dy < b; ++dy)
-        for (int dx = 0; dx < b; ++dx) s += amp[(size_t)(iy * b + dy) * P + ix * b + dx];
-      if (s >= 0.5 * b * b) p->valid.push_back(iy * S + ix);
-    }
+  if (p->Sd > 0) {
+    auto ov = [&](int j, int y) {
+      return (double)(std::min((y + 1) * S, (j + 1) * P) - std::max(y * S, j * P));
+    };
+    for (int iy = 0; iy < S; ++iy)
+      for (int ix = 0; ix < S; ++ix) {
+        double s = 0.0;
+        for (int y = (iy * P) / S; y < ((iy + 1) * P + S - 1) / S; ++y)
+          for (int x = (ix * P) / S; x < ((ix + 1) * P + S - 1) / S; ++x)
+            s += ov(iy, y) * ov(ix, x) * (double)amp[(size_t)y * P + x];
+        if (s >= 0.5 * (double)P * P) p->valid.push_back(iy * S + ix);   // area P^2 / S^2 in units 1/S^2
+      }
+  } else {
+    for (int iy = 0; iy < S; ++iy)
+      for (int ix = 0; ix < S; ++ix) {
+        double s = 0.0;
+        for (int dy = 0; dy < b; ++dy)
+          for (int dx = 0; dx < b; ++dx) s += amp[(size_t)(iy * b + dy) * P + ix * b + dx];
+        if (s >= 0.5 * b * b) p->valid.push_back(iy * S + ix);
+      }
+  }
   p->nv = (int)p->valid.size();
   p->amp_host = amp;
   if (p->nv == 0) {
@@ -524,6 +552,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {(void**)&p->partial, partial_elems * sizeof(float), "pupil partials"},
       {(void**)&p->pupils, (size_t)bm * 4 * S * S * sizeof(float), "pupil scratch"},
       {(void**)&p->pixels, (size_t)bm * 4 * S * S * sizeof(float), "detector scratch"},
+      {(void**)&p->fullres, p->Sd > 0 ? (size_t)bm * 4 * P * P * sizeof(float) : 0, "full-resolution images"},
       {(void**)&p->field, (size_t)bm * P * P * sizeof(cpx), "pupil field"},
       {(void**)&p->zero_opd, (size_t)P * P * sizeof(float), "zero opd"},
       {(void**)&p->tmp_slopes, (size_t)2 * p->nv * sizeof(float), "reference scratch"},
@@ -1099,6 +1128,56 @@ int pwfs_plan_info(pwfs_plan_t p, int32_t* n_valid, int32_t* n_sub, size_t* work
 int pwfs_get_valid(pwfs_plan_t p, int32_t* idx_host) {
   if (!p || !idx_host) return fail(PWFS_ERR_INVALID_ARG, "plan or idx_host is NULL");
   std::memcpy(idx_host, p->valid.data(), p->valid.size() * sizeof(int32_t));
+  return PWFS_OK;
+}
+
+int pwfs_set_valid(pwfs_plan_t p, const int32_t* idx_host, int32_t n) {
+  if (!p || !idx_host) return fail(PWFS_ERR_INVALID_ARG, "plan or idx_host is NULL");
+  if (n < 1) return fail(PWFS_ERR_INVALID_ARG, "the valid list must not be empty");
+  const int S = p->S;
+  for (int32_t i = 0; i < n; ++i) {
+    if (idx_host[i] < 0 || idx_host[i] >= S * S) return fail(PWFS_ERR_INVALID_ARG, "valid index out of range");
+    if (i > 0 && idx_host[i] <= idx_host[i - 1])
+      return fail(PWFS_ERR_INVALID_ARG, "valid indices must be strictly ascending");
+  }
+  DeviceGuard g(p->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "pwfs_set_valid");
+  int* dv = nullptr;
+  float *sr = nullptr, *ts = nullptr;
+  int st = dev_alloc((void**)&dv, (size_t)n * sizeof(int), "valid");
+  if (st == PWFS_OK) st = dev_alloc((void**)&sr, (size_t)2 * n * sizeof(float), "sref");
+  if (st == PWFS_OK) st = dev_alloc((void**)&ts, (size_t)2 * n * sizeof(float), "reference scratch");
+  if (st == PWFS_OK) {
+    if ((e = hipMemcpy(dv, idx_host, (size_t)n * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(sr, 0, (size_t)2 * n * sizeof(float))) != hipSuccess)
+      st = hip_fail(e, "pwfs_set_valid upload");
+  }
+  if (st != PWFS_OK) {
+    for (void* q : {(void*)dv, (void*)sr, (void*)ts})
+      if (q) (void)hipFree(q);
+    return st;
+  }
+  for (void* q : {(void*)p->d_valid, (void*)p->sref, (void*)p->tmp_slopes})
+    if (q) (void)hipFree(q);
+  p->ws_bytes -= (size_t)p->nv * sizeof(int) + (size_t)4 * p->nv * sizeof(float);
+  p->d_valid = dv;
+  p->sref = sr;
+  p->tmp_slopes = ts;
+  p->valid.assign(idx_host, idx_host + n);
+  p->nv = n;
+  p->ws_bytes += (size_t)n * sizeof(int) + (size_t)4 * n * sizeof(float);
+  // Noiseless flat-wavefront reference with the new list (detector bypassed,
+  // frame counter untouched).
+  const bool det = p->det_on;
+  p->det_on = false;
+  st = run_measure(p, p->zero_opd, 1, nullptr, p->tmp_slopes, p->sref, nullptr);
+  p->det_on = det;
+  if (st != PWFS_OK) return st;
+  if ((e = hipMemcpy(p->sref, p->tmp_slopes, (size_t)2 * n * sizeof(float), hipMemcpyDeviceToDevice)) !=
+          hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess)
+    return hip_fail(e, "pwfs_set_valid reference");
   return PWFS_OK;
 }
 

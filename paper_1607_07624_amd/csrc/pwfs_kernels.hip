@@ -506,6 +506,34 @@ static hipError_t launch_cols(const MeasureArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Non-integer detector rebin: each P x P window [B][4][P][P] to S x S pixels
+// of pitch P / S.  Positions in units of 1 / S: pupil pixel y spans
+// [y S, (y + 1) S), detector pixel j spans [j P, (j + 1) P); their overlap is
+// an exact integer, and pixel (j, i) = sum_y,x ov_y ov_x img[y][x] / S^2, the
+// integral of the piecewise-constant window over the pixel in pupil-pixel
+// area units.
+__global__ __launch_bounds__(256) void rebin_kernel(const float* __restrict__ in, int P, int S,
+                                                    float* __restrict__ out) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  const size_t fr = blockIdx.y;
+  if (o >= 4 * S * S) return;
+  const int q = o / (S * S), rem = o - q * S * S, j = rem / S, i = rem - j * S;
+  const float* img = in + (fr * 4 + q) * (size_t)P * P;
+  const int y0 = (j * P) / S, y1 = ((j + 1) * P + S - 1) / S;
+  const int x0 = (i * P) / S, x1 = ((i + 1) * P + S - 1) / S;
+  float acc = 0.f;
+  for (int y = y0; y < y1; ++y) {
+    const int wy = min((y + 1) * S, (j + 1) * P) - max(y * S, j * P);
+    float row = 0.f;
+    for (int x = x0; x < x1; ++x) {
+      const int wx = min((x + 1) * S, (i + 1) * P) - max(x * S, i * P);
+      row = fmaf((float)wx, img[(size_t)y * P + x], row);
+    }
+    acc = fmaf((float)wy, row, acc);
+  }
+  out[fr * 4 * (size_t)S * S + o] = acc / (float)(S * S);
+}
+
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) {
   hipError_t e = hipSuccess;
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
@@ -529,15 +557,23 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
   }
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-  const int S = a.P / a.n_bin;
+  const int Sb = a.P / a.n_bin;                  // images of the column pass
+  const int S = a.det_window > 0 ? a.det_window : Sb;
   const int n4ss = 4 * S * S;
   // With a detector the noiseless images go to the intensity scratch and the
   // detector writes the pixels that the slopes use.
+  float* images = a.det_on ? a.intensity : a.pupils;
+  float* reduced = a.det_window > 0 ? a.fullres : images;
   if (partials_by_column(a.P, a.n_bin)) {
-    if ((e = launch_reduce_cols(a, a.det_on ? a.intensity : a.pupils, st)) != hipSuccess) return e;
+    if ((e = launch_reduce_cols(a, reduced, st)) != hipSuccess) return e;
   } else {
-    hipLaunchKernelGGL(pupil_reduce_kernel, dim3((n4ss + 255) / 256, a.B), dim3(256), 0, st, a.partial,
-                       a.n_chunks, n4ss, 1.0f / (float)a.K, a.det_on ? a.intensity : a.pupils);
+    const int n4bb = 4 * Sb * Sb;
+    hipLaunchKernelGGL(pupil_reduce_kernel, dim3((n4bb + 255) / 256, a.B), dim3(256), 0, st, a.partial,
+                       a.n_chunks, n4bb, 1.0f / (float)a.K, reduced);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (a.det_window > 0) {
+    hipLaunchKernelGGL(rebin_kernel, dim3((n4ss + 255) / 256, a.B), dim3(256), 0, st, a.fullres, a.P, S, images);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (a.det_on) {

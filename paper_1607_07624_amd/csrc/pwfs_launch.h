@@ -43,6 +43,10 @@ struct MeasureArgs {
   float det_gain, det_ron;   // electrons per unit intensity, readout noise (e- RMS)
   uint64_t det_seed, frame0; // Philox key, frame index of the slice's first frame
   float* intensity;          // [B][4][S][S] scratch for the noiseless images when det_on
+  // non-integer detector rebin (det_window = S > 0, n_bin = 1): the chunk sum
+  // goes to fullres [B][4][P][P], then each window is resampled to S x S
+  int det_window;
+  float* fullres;
 };
 
 // PSF camera: field at the science wavelength, zero-padded 2-D transform,

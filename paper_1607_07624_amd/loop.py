@@ -60,6 +60,28 @@ def calibrate(plan, modes, eps_nm: float, device="cuda"):
     return torch.from_numpy(R.astype(np.float32)).to(device).contiguous(), IM, sig
 
 
+def acquire_valid(cfg, pupil_amp=None, thr: float = 0.5, mod_radius_lod: float = 20.0, n_mod: int = 128,
+                  device="cuda") -> np.ndarray:
+    """Pupil acquisition (the paper's Sec. 4 calibration script): a flat
+    wavefront measured through the library with the modulation radius raised
+    (20 lambda/D), then thresholded on the host: the subapertures where the
+    sum of the four pupil images reaches thr times its maximum (the paper's
+    thresholds are not given; one relative threshold is used).  Returns the
+    ascending index list for Plan.set_valid."""
+    import dataclasses
+    import torch
+    from ._lib import Plan
+    acq = Plan(dataclasses.replace(cfg, mod_radius_lod=float(mod_radius_lod), n_mod=int(n_mod)), batch_max=1,
+               pupil_amp=pupil_amp)
+    try:
+        P = cfg.n_pupil
+        pupils, _ = acq.measure(torch.zeros((1, P, P), dtype=torch.float32, device=device))
+        tot = pupils[0].double().sum(dim=0).cpu().numpy().ravel()
+    finally:
+        acq.close()
+    return np.flatnonzero(tot >= thr * tot.max()).astype(np.int32)
+
+
 class ClosedLoop:
     """Integrator loop of one sensor plan (batch 1) with a modal DM.
 

@@ -26,6 +26,9 @@ class SensorConfig:
     n_fft       N: side of the square FFT grid (pupil plane == focal plane grid).
     n_pupil     P: pupil diameter in pupil-plane pixels.
     n_bin       b: detector binning; S = P / b subapertures across.
+    det_window  S > 0: instead of binning, each P-pixel pupil window is
+                resampled to S detector pixels of pitch P / S (non-integer
+                rebin; needs n_bin 1); S subapertures across.
     n_mod       K: modulation points on the circle.
     face_shift  Delta: pupil-image displacement in pixels produced by each
                 pyramid face; 0 selects N / 4.
@@ -48,10 +51,11 @@ class SensorConfig:
     obstruction: float = 0.0
     face_shift: int = 0
     norm_mode: int = 0
+    det_window: int = 0
 
     @property
     def n_sub(self) -> int:
-        return self.n_pupil // self.n_bin
+        return self.det_window if self.det_window else self.n_pupil // self.n_bin
 
     @property
     def delta(self) -> int:
@@ -96,6 +100,28 @@ CFG2 = SensorConfig(name="cfg2_n640_p160_k48", n_fft=640, n_pupil=160, n_bin=4,
                     n_mod=48, mod_radius_lod=3.0, wavelength_m=750e-9,
                     diameter_m=8.4)
 ATMO2 = AtmoConfig(r0_m=0.12, L0_m=40.0, wind_m_s=15.0, frame_rate_hz=1000.0)
+
+# The paper's detector geometry (Tab. 1 "pyramid": output_resolution 80,
+# pupils pup_diam 30 pixels across with centres pup_dist 36 apart; 3 lambda/D
+# modulation at 750 nm).  Each P = 160 pupil window is resampled to 36
+# detector pixels (pitch 4.44 pupil pixels); the window spans 36 / 30 pupil
+# diameters, so the pupil is 133.3 pixels across (paper_pupil) and the
+# window-relative diameter and modulation radius carry that factor.
+PAPER_PUP_DIAM, PAPER_PUP_DIST, PAPER_DET_PX = 30, 36, 80
+CFG_PAPER_DET = SensorConfig(name="paper_det80_n640_p160_k48", n_fft=640, n_pupil=160, n_bin=1,
+                             n_mod=48, mod_radius_lod=3.0 * 36 / 30, wavelength_m=750e-9,
+                             diameter_m=8.4 * 36 / 30, det_window=36)
+
+
+def paper_pupil(P: int, pup_diam: int = PAPER_PUP_DIAM, pup_dist: int = PAPER_PUP_DIST):
+    """Binary circular pupil of diameter P pup_diam / pup_dist pixels centred
+    in the P x P window (float32)."""
+    import numpy as np
+    c = (P - 1) / 2.0
+    y, x = np.mgrid[0:P, 0:P]
+    r = P * pup_diam / pup_dist / 2.0
+    return (((x - c) ** 2 + (y - c) ** 2) <= r * r).astype(np.float32)
+
 
 # Precision study on the same shapes: 16 independent screens with
 # r0 drawn uniformly in [0.08, 0.2] m (L0 as in the closed loop).

@@ -58,6 +58,8 @@ def _plan_status(**over):
     (dict(n_bin=5), -2), (dict(n_mod=2000), -2),
     (dict(n_pupil=480, n_fft=1920, n_bin=3), -2), (dict(n_pupil=480, n_fft=1920, n_bin=6), -2),
     (dict(n_pupil=128, n_fft=512, n_bin=5), -1), (dict(n_pupil=320, n_fft=1280), -2),
+    (dict(det_window=36), -1), (dict(n_bin=1, det_window=1), -1), (dict(n_bin=1, det_window=161), -1),
+    (dict(n_bin=1, det_window=-2), -1), (dict(reserved=1), -1),
 ])
 def test_plan_rejects_bad_config_before_touching_a_device(over, status):
     st, msg = _plan_status(**over)
@@ -72,6 +74,7 @@ def test_null_arguments_rejected():
     assert lib.pwfs_measure(None, None, 1, None, None, None) == -1
     assert lib.pwfs_plan_info(None, None, None, None) == -1
     assert lib.pwfs_get_valid(None, None) == -1
+    assert lib.pwfs_set_valid(None, None, 1) == -1
     assert lib.recon_apply(None, 0, 10, None, 1, 1.0, 0.0, None, None) == -1
     assert lib.recon_apply(None, 10, 10, None, -1, 1.0, 0.0, None, None) == -1
     # B == 0 is an empty batch: nothing to do, nothing dereferenced.
