@@ -375,6 +375,34 @@ def main():
     torch.cuda.synchronize()
     extra["b1_frames_per_s"] = round(n1 / (ev0.elapsed_time(ev1) / 1e3), 1)
 
+    # The paper's detector geometry (80 x 80 frame, pupils 30 px across and 36
+    # apart: each P = 160 window rebinned to 36 px), valid list from the pupil
+    # acquisition on a flat frame at 20 lambda/D; same batch, same path.
+    if not args.random_R:
+        from synth.configs import CFG_PAPER_DET, paper_pupil
+        from paper_1607_07624_amd.loop import acquire_valid
+        pamp = paper_pupil(CFG_PAPER_DET.n_pupil)
+        pplan = pw.Plan(CFG_PAPER_DET, batch_max=B, pupil_amp=pamp)
+        n_fill = pplan.n_valid
+        pplan.set_valid(acquire_valid(CFG_PAPER_DET, pamp))
+        if not args.no_autotune and not args.schedule:
+            pplan.autotune(B, reps=3)
+        popd = torch.from_numpy(open_loop_batch(CFG_PAPER_DET, ATMO2, list(range(B)), r0_range=CFG4_R0_RANGE)[0]).to(dev)
+        ps = torch.empty((B, 2 * pplan.n_valid), device=dev)
+        for _ in range(5):
+            pplan.measure_into(popd, None, ps)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(50):
+            pplan.measure_into(popd, None, ps)
+        ev1.record()
+        torch.cuda.synchronize()
+        extra["paper_detector"] = {"geometry": "80 x 80 px, pupils 30 px across 36 apart (160-px windows to 36 px)",
+                                   "n_valid_acquired": pplan.n_valid, "n_valid_fill_rule": n_fill,
+                                   "frames_per_s": round(B * 50 / (ev0.elapsed_time(ev1) / 1e3), 1)}
+        log(f"paper detector geometry {extra['paper_detector']}")
+        pplan.close()
+
     # Closed loop on the GPU (frozen flow, 1 kHz, 15 m/s).
     loop = None
     if not args.no_loop:
