@@ -21,7 +21,8 @@
  *   - K modulation points at angles 2 pi k / K, radius r_mod N / P focal
  *     pixels; intensity is the mean over the K points;
  *   - pyramid mask exp(-2 pi i Delta (|u| + |v|) / N) on signed frequency
- *     indices, apex on frequency bin 0, Delta = N / 4;
+ *     indices, apex on frequency bin 0, Delta = N / 4; optionally times a
+ *     circular field stop (field_stop_lod);
  *   - pupil q = (x side +) + 2 (y side +), each binned b x b to S x S,
  *     S = P / b, stored [q][iy][ix] row-major; or, with det_window = S > 0
  *     (and b = 1), each P x P window resampled to S x S detector pixels of
@@ -91,6 +92,13 @@ typedef struct {
                           /* P pup_diam / pup_dist pupil pixels: the four windows fill    */
                           /* the central 72 x 72 pixels of the 80 x 80 frame.             */
   int32_t reserved;       /* must be 0                                                    */
+  double field_stop_lod;  /* 0: no field stop.  > 0: diameter, in lambda / D (the unit of  */
+                          /* mod_radius_lod), of a circular focal-plane stop: the field is */
+                          /* kept where u_s^2 + v_s^2 <= R^2, R = field_stop_lod N / (2P)  */
+                          /* focal pixels (the paper's pyramid "fov").  The disc is not    */
+                          /* separable, so such a plan runs a general 2-D path (three      */
+                          /* pruned transform passes per modulation point, about 5 x the   */
+                          /* work); n_pupil must be 32, 64 or 160; fixed work split.       */
 } pwfs_config_t;
 
 /* Build a plan: validates cfg, generates the FP64 tables (tilt ramps,

@@ -17,8 +17,8 @@ convention the paper leaves open fixed as documented in each function.
 """
 from .pwfs import (pupil_amplitude, valid_subapertures, modulation_offsets,
                    pyramid_mask, intensity, pupil_images, slopes, Oracle,
-                   overlap_matrix, rebin, acquire_valid)
+                   overlap_matrix, rebin, acquire_valid, field_stop_mask, sensor_mask)
 
 __all__ = ["pupil_amplitude", "valid_subapertures", "modulation_offsets",
            "pyramid_mask", "intensity", "pupil_images", "slopes", "Oracle",
-           "overlap_matrix", "rebin", "acquire_valid"]
+           "overlap_matrix", "rebin", "acquire_valid", "field_stop_mask", "sensor_mask"]

@@ -21,7 +21,9 @@ Conventions (the paper is silent on all of them):
     applied as exp(i 2 pi (a_k (x - xc) + b_k (y - xc)) / N), xc = (N-1)/2;
   * focal plane: unnormalised forward FFT; pyramid mask
     M(u, v) = exp(-2 pi i Delta (|u_s| + |v_s|) / N) with u_s, v_s the
-    signed frequency indices in [-N/2, N/2) (apex on bin 0);
+    signed frequency indices in [-N/2, N/2) (apex on bin 0); optionally
+    times a circular field stop (Tab. 1 "pyramid": fov), kept where
+    u_s^2 + v_s^2 <= R^2, R = (stop diameter in lambda/D) N / (2 P);
   * back to the pupil: inverse FFT with 1/N^2; intensity = mean over k;
   * pupil q = (sx > 0) + 2 (sy > 0) is the window at rows o + sy Delta,
     cols o + sx Delta (sx, sy = -1/+1), summed b x b; or, with a detector
@@ -116,6 +118,21 @@ def pyramid_mask(N: int, delta: int) -> np.ndarray:
     return np.exp(-2j * np.pi * delta * (us[None, :] + us[:, None]) / N)
 
 
+def field_stop_mask(N: int, P: int, diameter_lod: float) -> np.ndarray:
+    """Circular focal-plane stop of the given diameter (lambda/D units of the
+    modulation radius) on the unshifted N x N grid (float64 0/1)."""
+    us = np.fft.fftfreq(N, 1.0 / N)
+    R = 0.5 * diameter_lod * N / P
+    return ((us[None, :] ** 2 + us[:, None] ** 2) <= R * R).astype(np.float64)
+
+
+def sensor_mask(cfg) -> np.ndarray:
+    """Pyramid mask, times the field stop when the configuration has one."""
+    M = pyramid_mask(cfg.n_fft, cfg.delta)
+    fs = getattr(cfg, "field_stop_lod", 0.0)
+    return M * field_stop_mask(cfg.n_fft, cfg.n_pupil, fs) if fs > 0 else M
+
+
 def _field(cfg, opd_nm: np.ndarray, A: np.ndarray) -> np.ndarray:
     N, P = cfg.n_fft, cfg.n_pupil
     o = (N - P) // 2
@@ -136,7 +153,7 @@ def intensity(cfg, opd_nm: np.ndarray, A: np.ndarray | None = None,
     if A is None:
         A = pupil_amplitude(cfg.n_pupil, cfg.obstruction)
     if mask is None:
-        mask = pyramid_mask(N, cfg.delta)
+        mask = sensor_mask(cfg)
     a, b = modulation_offsets(cfg) if offsets is None else offsets
     E = _field(cfg, opd_nm, A)
     g = np.arange(N) - (N - 1) / 2.0

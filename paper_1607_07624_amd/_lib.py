@@ -44,7 +44,8 @@ class config_struct(ctypes.Structure):
                 ("batch_max", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("diameter_m", ctypes.c_double), ("wavelength_m", ctypes.c_double),
                 ("mod_radius_lod", ctypes.c_double), ("obstruction", ctypes.c_double),
-                ("det_window", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("det_window", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("field_stop_lod", ctypes.c_double)]
 
 
 def library_path() -> str:
@@ -139,7 +140,8 @@ def make_config(cfg, batch_max: int, flags: int = 0) -> config_struct:
                          face_shift=cfg.face_shift, norm_mode=cfg.norm_mode, batch_max=batch_max,
                          flags=flags, diameter_m=cfg.diameter_m, wavelength_m=cfg.wavelength_m,
                          mod_radius_lod=cfg.mod_radius_lod, obstruction=cfg.obstruction,
-                         det_window=getattr(cfg, "det_window", 0), reserved=0)
+                         det_window=getattr(cfg, "det_window", 0), reserved=0,
+                         field_stop_lod=getattr(cfg, "field_stop_lod", 0.0))
 
 
 class Plan:

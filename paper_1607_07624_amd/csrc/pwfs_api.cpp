@@ -119,6 +119,10 @@ struct pwfs_plan_s {
   int N = 0, P = 0, E = 0, S = 0, b = 0, K = 0, n_a = 0, nv = 0, batch_max = 0;
   int Sb = 0;                                   // column-pass images: P / b (S unless det_window)
   int Sd = 0;                                   // det_window (0: integer binning)
+  bool fs_on = false;                           // circular field stop: general 2-D path
+  int fs_r2max = 0;                             // stop: inside iff u_s^2 + v_s^2 <= fs_r2max
+  cpx *fs_rx = nullptr, *fs_ry = nullptr, *fs_tw4n = nullptr, *fs_twp = nullptr, *fs_twi = nullptr,
+      *fs_py = nullptr, *fs_Z = nullptr, *fs_W = nullptr;
   double kphase = 0.0;
   std::vector<int> valid;
   // device tables
@@ -223,6 +227,10 @@ int validate(const pwfs_config_t* c) {
     return fail(PWFS_ERR_UNSUPPORTED, "n_bin must be 1, 2, 4 or 8 (or 5 with n_pupil 480)");
   if (c->batch_max > 65535) return fail(PWFS_ERR_UNSUPPORTED, "batch_max > 65535");
   if (c->reserved != 0) return fail(PWFS_ERR_INVALID_ARG, "reserved must be 0");
+  if (!(c->field_stop_lod >= 0.0) || !std::isfinite(c->field_stop_lod))
+    return fail(PWFS_ERR_INVALID_ARG, "field_stop_lod must be finite and >= 0");
+  if (c->field_stop_lod > 0.0 && !(P == 32 || P == 64 || P == 160))
+    return fail(PWFS_ERR_UNSUPPORTED, "a field stop needs n_pupil 32, 64 or 160");
   if (c->det_window != 0) {
     if (c->det_window < 2 || c->det_window > P)
       return fail(PWFS_ERR_INVALID_ARG, "det_window must be 0 or in [2, n_pupil]");
@@ -236,7 +244,8 @@ void free_plan(pwfs_plan_s* p) {
   DeviceGuard g(p->device);
   void* ptrs[] = {p->amp, p->in_a, p->f_a, p->in_b, p->f_b, p->mid, p->tw16, p->outw, p->k_order, p->k_ia,
                   p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->pixels, p->field, p->zero_opd,
-                  p->tmp_slopes, p->fullres};
+                  p->tmp_slopes, p->fullres, p->fs_rx, p->fs_ry, p->fs_tw4n, p->fs_twp, p->fs_twi, p->fs_py,
+                  p->fs_Z, p->fs_W};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto* pool : {&p->ev_used, &p->ev_free})
@@ -282,8 +291,25 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
   a.Rw = p->Rw;
   a.field = p->field;
   a.partial = p->partial;
-  a.det_window = p->Sd;
   a.fullres = p->fullres;
+  a.rebin_S = (p->Sd > 0 || p->fs_on) ? p->S : 0;
+  if (p->fs_on) {
+    // Output pass of the field-stop path: modulation chunks for ~2048 blocks.
+    const long rows = 2L * p->P / 16 * Bs;
+    int nc = (int)std::max<long>(1, std::min<long>(p->K, (2048 + rows - 1) / rows));
+    a.k_chunk = (p->K + nc - 1) / nc;
+    a.n_chunks = (p->K + a.k_chunk - 1) / a.k_chunk;
+    a.fs_on = 1;
+    a.fs_r2max = p->fs_r2max;
+    a.fs_rx = p->fs_rx;
+    a.fs_ry = p->fs_ry;
+    a.fs_tw4n = p->fs_tw4n;
+    a.fs_twp = p->fs_twp;
+    a.fs_twi = p->fs_twi;
+    a.fs_py = p->fs_py;
+    a.fs_Z = p->fs_Z;
+    a.fs_W = p->fs_W;
+  }
   return a;
 }
 
@@ -356,9 +382,10 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
   p->P = P;
   p->E = P / 4;
   p->b = b;
-  p->Sb = P / b;
+  p->fs_on = cfg->field_stop_lod > 0.0;
+  p->Sb = p->fs_on ? P : P / b;
   p->Sd = cfg->det_window;
-  p->S = p->Sd > 0 ? p->Sd : p->Sb;
+  p->S = p->Sd > 0 ? p->Sd : P / b;
   p->K = K;
   p->batch_max = cfg->batch_max;
   p->kphase = 2.0 * M_PI * 1e-9 / cfg->wavelength_m;
@@ -522,6 +549,51 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       }
   }
 
+  // Field-stop path tables (pwfs_fstop.hip): ramps alone (not negated), the
+  // residue twists of the zero-padded transforms w_N^{r x}, the inverse ones
+  // with the window phase and 1/N, (-i)^r w_N^{-r x} / N, the quad twiddles
+  // w_P^{l k1} and the pyramid factor of one axis; the stop is the disc
+  // u_s^2 + v_s^2 <= R^2 of radius R = field_stop_lod N / (2P) focal pixels.
+  std::vector<cpx> fs_rx, fs_ry, fs_tw4n, fs_twp, fs_twi, fs_py;
+  if (p->fs_on) {
+    fs_rx.resize((size_t)K * P);
+    fs_ry.resize((size_t)K * P);
+    for (int k = 0; k < K; ++k) {
+      const double ak = rho * std::cos(2.0 * M_PI * (double)k / (double)K);
+      const double bk = rho * std::sin(2.0 * M_PI * (double)k / (double)K);
+      for (int x = 0; x < P; ++x) {
+        fs_rx[(size_t)k * P + x] = to32(ramp(ak, x));
+        fs_ry[(size_t)k * P + x] = to32(ramp(bk, x));
+      }
+    }
+    fs_tw4n.resize(4 * (size_t)P);
+    fs_twi.resize(4 * (size_t)P);
+    for (int r = 0; r < 4; ++r)
+      for (int x = 0; x < P; ++x) {
+        const long n = ((long)r * x) % N;
+        const double ang = -2.0 * M_PI * (double)n / (double)N;
+        fs_tw4n[(size_t)r * P + x] = cpx{(float)std::cos(ang), (float)std::sin(ang)};
+        const double angi = -0.5 * M_PI * (double)r - ang;
+        fs_twi[(size_t)r * P + x] = cpx{(float)(std::cos(angi) / N), (float)(std::sin(angi) / N)};
+      }
+    fs_twp.resize(4 * (size_t)p->E);
+    for (int l = 0; l < 4; ++l)
+      for (int k1 = 0; k1 < p->E; ++k1) {
+        const double ang = -2.0 * M_PI * (double)(((long)l * k1) % P) / (double)P;
+        fs_twp[(size_t)l * p->E + k1] = cpx{(float)std::cos(ang), (float)std::sin(ang)};
+      }
+    fs_py.resize(N);
+    const int delta = N / 4;
+    for (int v = 0; v < N; ++v) {
+      const long vs = v < N / 2 ? v : v - N;
+      const double ang = -2.0 * M_PI * (double)(((long)delta * std::labs(vs)) % N) / (double)N;
+      fs_py[v] = cpx{(float)std::cos(ang), (float)std::sin(ang)};
+    }
+    const double R = 0.5 * cfg->field_stop_lod * (double)N / (double)P;
+    const double lim = 2.0 * (N / 2) * (N / 2);
+    p->fs_r2max = R * R >= lim ? (int)lim : (int)std::floor(R * R);
+  }
+
   // Device buffers.
   int bm = cfg->batch_max;
   int ac, kc, nc;
@@ -548,11 +620,20 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {(void**)&p->k_ia, (size_t)K * sizeof(int), "k_ia"},
       {(void**)&p->d_valid, (size_t)p->nv * sizeof(int), "valid"},
       {(void**)&p->sref, (size_t)2 * p->nv * sizeof(float), "sref"},
-      {(void**)&p->Rw, rw_elems * sizeof(cpx), "row-pass workspace"},
+      {(void**)&p->Rw, p->fs_on ? 0 : rw_elems * sizeof(cpx), "row-pass workspace"},
       {(void**)&p->partial, partial_elems * sizeof(float), "pupil partials"},
       {(void**)&p->pupils, (size_t)bm * 4 * S * S * sizeof(float), "pupil scratch"},
       {(void**)&p->pixels, (size_t)bm * 4 * S * S * sizeof(float), "detector scratch"},
-      {(void**)&p->fullres, p->Sd > 0 ? (size_t)bm * 4 * P * P * sizeof(float) : 0, "full-resolution images"},
+      {(void**)&p->fullres, (p->Sd > 0 || p->fs_on) ? (size_t)bm * 4 * P * P * sizeof(float) : 0,
+       "full-resolution images"},
+      {(void**)&p->fs_rx, fs_rx.size() * sizeof(cpx), "fs_rx"},
+      {(void**)&p->fs_ry, fs_ry.size() * sizeof(cpx), "fs_ry"},
+      {(void**)&p->fs_tw4n, fs_tw4n.size() * sizeof(cpx), "fs_tw4n"},
+      {(void**)&p->fs_twp, fs_twp.size() * sizeof(cpx), "fs_twp"},
+      {(void**)&p->fs_twi, fs_twi.size() * sizeof(cpx), "fs_twi"},
+      {(void**)&p->fs_py, fs_py.size() * sizeof(cpx), "fs_py"},
+      {(void**)&p->fs_Z, p->fs_on ? (size_t)bm * K * N * P * sizeof(cpx) : 0, "field-stop row transforms"},
+      {(void**)&p->fs_W, p->fs_on ? (size_t)bm * K * 2 * P * N * sizeof(cpx) : 0, "field-stop column transforms"},
       {(void**)&p->field, (size_t)bm * P * P * sizeof(cpx), "pupil field"},
       {(void**)&p->zero_opd, (size_t)P * P * sizeof(float), "zero opd"},
       {(void**)&p->tmp_slopes, (size_t)2 * p->nv * sizeof(float), "reference scratch"},
@@ -577,8 +658,15 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {p->k_order, k_order.data(), (size_t)K * sizeof(int)},
       {p->k_ia, k_ia.data(), (size_t)K * sizeof(int)},
       {p->d_valid, p->valid.data(), (size_t)p->nv * sizeof(int)},
+      {p->fs_rx, fs_rx.data(), fs_rx.size() * sizeof(cpx)},
+      {p->fs_ry, fs_ry.data(), fs_ry.size() * sizeof(cpx)},
+      {p->fs_tw4n, fs_tw4n.data(), fs_tw4n.size() * sizeof(cpx)},
+      {p->fs_twp, fs_twp.data(), fs_twp.size() * sizeof(cpx)},
+      {p->fs_twi, fs_twi.data(), fs_twi.size() * sizeof(cpx)},
+      {p->fs_py, fs_py.data(), fs_py.size() * sizeof(cpx)},
   };
   for (auto& c : copies) {
+    if (c.bytes == 0) continue;
     if ((e = hipMemcpy(c.dst, c.src, c.bytes, hipMemcpyHostToDevice)) != hipSuccess) {
       free_plan(p);
       return hip_fail(e, "table upload");
@@ -1019,6 +1107,7 @@ int pwfs_get_schedule(pwfs_plan_t p, int32_t B, int32_t* a_chunk, int32_t* k_chu
 
 int pwfs_set_schedule(pwfs_plan_t p, int32_t B, int32_t a_chunk, int32_t k_chunk) {
   if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (p->fs_on) return fail(PWFS_ERR_UNSUPPORTED, "field-stop plans have a fixed work split");
   if (B < 1 || B > p->batch_max) return fail(PWFS_ERR_INVALID_ARG, "B outside [1, batch_max]");
   if (a_chunk == 0 && k_chunk == 0) {
     p->sched.erase(B);
@@ -1032,6 +1121,7 @@ int pwfs_set_schedule(pwfs_plan_t p, int32_t B, int32_t a_chunk, int32_t k_chunk
 
 int pwfs_autotune(pwfs_plan_t p, int32_t B, int32_t reps, void* stream, double* ms_default, double* ms_tuned) {
   if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (p->fs_on) return fail(PWFS_ERR_UNSUPPORTED, "field-stop plans have a fixed work split");
   if (B < 1 || B > p->batch_max) return fail(PWFS_ERR_INVALID_ARG, "B outside [1, batch_max]");
   if (reps < 1 || reps > 1000) return fail(PWFS_ERR_INVALID_ARG, "reps outside [1, 1000]");
   DeviceGuard g(p->device);

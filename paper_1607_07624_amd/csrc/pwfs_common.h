@@ -85,6 +85,37 @@ __device__ __forceinline__ void line_op(cpx (&v)[E], LoadIn&& load_in, LoadX&& l
   });
 }
 
+// DFT_P (P = 4E) held by a quad, lane l holding x = l + 4 m (m < E): in-lane
+// DFT_E, twiddle twl[k1] = w_P^{l k1}, DFT_4 across the quad (two DPP
+// butterflies); afterwards lane l holds u = k1 + E rev(l), rev = (0, 2, 1, 3).
+template <int E>
+__device__ __forceinline__ void dft_quad(cpx (&v)[E], const cpx* __restrict__ twl, float sA, float sB, bool l3) {
+  Dft<E, +1>::run(v);
+  fence();
+  static_for<0, E>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    if constexpr (k % 8 == 0 && k > 0) fence();
+    v[k] = quad_dft4_fwd(cmul(v[k], twl[k]), sA, sB, l3);
+  });
+}
+
+__device__ __forceinline__ int rev2(int l) { return l == 1 ? 2 : (l == 2 ? 1 : l); }
+
+// Inverse of dft_quad's steps: from lane l holding X[k1 + E rev(l)] in
+// register k1 to lane l holding sum_u X[u] w_P^{-u t} at t = l + 4 m in
+// register m (unnormalised): DFT_4^-1 across the quad, conjugate twiddle,
+// in-lane inverse DFT_E.
+template <int E>
+__device__ __forceinline__ void idft_quad(cpx (&v)[E], const cpx* __restrict__ twl, float sA, float sB, bool l3) {
+  static_for<0, E>([&](auto k_) {
+    constexpr int k = decltype(k_)::value;
+    if constexpr (k % 8 == 0 && k > 0) fence();
+    v[k] = cmulc(quad_dft4_inv(v[k], sA, sB, l3), twl[k]);
+  });
+  fence();
+  Dft<E, -1>::run(v);
+}
+
 __device__ __forceinline__ size_t rw_index(int xp, int y, int P) {
   return ((size_t)(xp >> 3) * (size_t)(P >> 2) + (size_t)(y >> 2)) * 32u + (size_t)((xp & 7) * 4 + (y & 3));
 }

@@ -506,6 +506,8 @@ static hipError_t launch_cols(const MeasureArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_finish(const MeasureArgs& a, int Sb, hipStream_t st, hipEvent_t* ev);
+
 // Non-integer detector rebin: each P x P window [B][4][P][P] to S x S pixels
 // of pitch P / S.  Positions in units of 1 / S: pupil pixel y spans
 // [y S, (y + 1) S), detector pixel j spans [j P, (j + 1) P); their overlap is
@@ -537,6 +539,12 @@ __global__ __launch_bounds__(256) void rebin_kernel(const float* __restrict__ in
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) {
   hipError_t e = hipSuccess;
   if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
+  if (a.fs_on) {
+    if ((e = launch_field(a, st)) != hipSuccess) return e;
+    if ((e = launch_fstop_passes(a, st, ev)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
+    return launch_finish(a, a.P, st, ev);
+  }
   switch (a.P) {
     case 32: e = launch_rows<8>(a, st); break;
     case 64: e = launch_rows<16>(a, st); break;
@@ -557,14 +565,20 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
   }
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-  const int Sb = a.P / a.n_bin;                  // images of the column pass
-  const int S = a.det_window > 0 ? a.det_window : Sb;
+  return launch_finish(a, a.P / a.n_bin, st, ev);
+}
+
+// After the passes: chunk sum of the partial images (Sb x Sb per window),
+// optional rebin, detector and slopes.
+hipError_t launch_finish(const MeasureArgs& a, int Sb, hipStream_t st, hipEvent_t* ev) {
+  hipError_t e = hipSuccess;
+  const int S = a.rebin_S > 0 ? a.rebin_S : Sb;
   const int n4ss = 4 * S * S;
   // With a detector the noiseless images go to the intensity scratch and the
   // detector writes the pixels that the slopes use.
   float* images = a.det_on ? a.intensity : a.pupils;
-  float* reduced = a.det_window > 0 ? a.fullres : images;
-  if (partials_by_column(a.P, a.n_bin)) {
+  float* reduced = a.rebin_S > 0 ? a.fullres : images;
+  if (!a.fs_on && partials_by_column(a.P, a.n_bin)) {
     if ((e = launch_reduce_cols(a, reduced, st)) != hipSuccess) return e;
   } else {
     const int n4bb = 4 * Sb * Sb;
@@ -572,7 +586,7 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
                        a.n_chunks, n4bb, 1.0f / (float)a.K, reduced);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (a.det_window > 0) {
+  if (a.rebin_S > 0) {
     hipLaunchKernelGGL(rebin_kernel, dim3((n4ss + 255) / 256, a.B), dim3(256), 0, st, a.fullres, a.P, S, images);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

@@ -43,10 +43,20 @@ struct MeasureArgs {
   float det_gain, det_ron;   // electrons per unit intensity, readout noise (e- RMS)
   uint64_t det_seed, frame0; // Philox key, frame index of the slice's first frame
   float* intensity;          // [B][4][S][S] scratch for the noiseless images when det_on
-  // non-integer detector rebin (det_window = S > 0, n_bin = 1): the chunk sum
-  // goes to fullres [B][4][P][P], then each window is resampled to S x S
-  int det_window;
+  // rebin_S > 0 (detector window, or the field-stop path): the chunk sum goes
+  // to fullres [B][4][P][P], then each window is resampled to rebin_S pixels
   float* fullres;
+  // circular field stop (fs_on): general 2-D path of pwfs_fstop.hip; the
+  // modulation chunks of its output pass reuse k_chunk / n_chunks
+  int fs_on, fs_r2max, rebin_S;
+  const cpx* fs_rx;    // [K][P]  r_a(x)
+  const cpx* fs_ry;    // [K][P]  r_b(y)
+  const cpx* fs_tw4n;  // [4][P]  w_N^{u1 x}
+  const cpx* fs_twp;   // [4][E]  w_P^{l k1}
+  const cpx* fs_twi;   // [4][P]  (-i)^{v1} w_N^{-v1 t} / N
+  const cpx* fs_py;    // [N]     exp(-2 pi i Delta |v_s| / N)
+  cpx* fs_Z;           // [B][K][N][P]
+  cpx* fs_W;           // [B][K][2P][N]
 };
 
 // PSF camera: field at the science wavelength, zero-padded 2-D transform,
@@ -83,6 +93,9 @@ struct ShArgs {
 // ev: NULL, or four events recorded before the row pass, between the passes
 // and after the slopes kernel.
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
+// The three passes of the field-stop path (pwfs_fstop.hip), after the field;
+// records ev[1] after the row pass when ev is given.
+hipError_t launch_fstop_passes(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
 // Pieces of launch_measure: the pupil field (one frame slice), and the row and
 // column passes of the long-line kernels (P = 128, 480).
 hipError_t launch_field(const MeasureArgs& a, hipStream_t stream);

@@ -22,19 +22,6 @@
 
 namespace pwfs {
 
-template <int E>
-__device__ __forceinline__ void dft_quad(cpx (&v)[E], const cpx* __restrict__ twl, float sA, float sB, bool l3) {
-  Dft<E, +1>::run(v);
-  fence();
-  static_for<0, E>([&](auto k_) {
-    constexpr int k = decltype(k_)::value;
-    if constexpr (k % 8 == 0 && k > 0) fence();
-    v[k] = quad_dft4_fwd(cmul(v[k], twl[k]), sA, sB, l3);
-  });
-}
-
-__device__ __forceinline__ int rev2(int l) { return l == 1 ? 2 : (l == 2 ? 1 : l); }
-
 // twpad [pad][P] = w_N^{u1 x};  twp [4][E] = w_P^{l k1}.
 template <int E>
 __global__ __launch_bounds__(256) void psf_row_kernel(const cpx* __restrict__ field, const cpx* __restrict__ twpad,

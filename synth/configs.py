@@ -29,6 +29,8 @@ class SensorConfig:
     det_window  S > 0: instead of binning, each P-pixel pupil window is
                 resampled to S detector pixels of pitch P / S (non-integer
                 rebin; needs n_bin 1); S subapertures across.
+    field_stop_lod  diameter of a circular focal-plane field stop in the
+                units of mod_radius_lod (0: none).
     n_mod       K: modulation points on the circle.
     face_shift  Delta: pupil-image displacement in pixels produced by each
                 pyramid face; 0 selects N / 4.
@@ -52,6 +54,7 @@ class SensorConfig:
     face_shift: int = 0
     norm_mode: int = 0
     det_window: int = 0
+    field_stop_lod: float = 0.0
 
     @property
     def n_sub(self) -> int:

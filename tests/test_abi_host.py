@@ -60,6 +60,8 @@ def _plan_status(**over):
     (dict(n_pupil=128, n_fft=512, n_bin=5), -1), (dict(n_pupil=320, n_fft=1280), -2),
     (dict(det_window=36), -1), (dict(n_bin=1, det_window=1), -1), (dict(n_bin=1, det_window=161), -1),
     (dict(n_bin=1, det_window=-2), -1), (dict(reserved=1), -1),
+    (dict(field_stop_lod=-1.0), -1), (dict(field_stop_lod=float("nan")), -1),
+    (dict(n_pupil=480, n_fft=1920, n_bin=5, field_stop_lod=100.0), -2),
 ])
 def test_plan_rejects_bad_config_before_touching_a_device(over, status):
     st, msg = _plan_status(**over)

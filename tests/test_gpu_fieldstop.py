@@ -1,0 +1,98 @@
+"""The pyramid with a circular field stop through the C ABI (the general 2-D
+path: pruned row, column and output transforms per modulation point) against
+the FP64 oracle.  Gates as in test_gpu_pwfs."""
+import numpy as np
+import pytest
+
+from synth.configs import CFG2, CFG_PAPER_DET, ATMO1, ATMO2, SensorConfig, paper_pupil
+from synth.screens import open_loop_batch
+import oracle
+from tests.gpu_common import torch_cuda, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+SLOPE_TOL = 1e-5
+PUPIL_TOL = 2e-6
+# The paper's fov of 2 arcsec at 750 nm on the 8.4 m pupil: 2 / (206265 x 750e-9 / 8.4) = 108.6 lambda/D.
+FOV_LOD = 2.0 / (206264.806 * 750e-9 / 8.4)
+
+CFG2_FS = CFG2.with_(name="cfg2_fov2arcsec", field_stop_lod=FOV_LOD)
+CFG_SMALL_FS = SensorConfig(name="p32_k12_stop8_obs_norm1", n_fft=128, n_pupil=32, n_bin=2, n_mod=12,
+                            mod_radius_lod=2.5, wavelength_m=750e-9, diameter_m=8.0, obstruction=0.2,
+                            norm_mode=1, field_stop_lod=8.0)
+CFG_P64_FS = SensorConfig(name="p64_det14_k16_stop20", n_fft=256, n_pupil=64, n_bin=1, n_mod=16,
+                          mod_radius_lod=3.6, wavelength_m=750e-9, diameter_m=9.6, det_window=14,
+                          field_stop_lod=20.0)
+
+
+def _check(cfg, A, opd, batch_max):
+    import paper_1607_07624_amd as pw
+    torch = torch_cuda()
+    plan = pw.Plan(cfg, batch_max=batch_max, pupil_amp=A)
+    orc = oracle.Oracle(cfg, None if A is None else A.astype(np.float64))
+    assert np.array_equal(plan.valid, orc.valid)
+    e = float(np.abs(plan.s_ref.astype(np.float64) - orc.s_ref).max())
+    say(f"[gpu] {cfg.name}: {plan.n_valid} valid, reference slope max abs err {e:.3e}")
+    assert e <= 1e-6
+    pup, s = plan.measure(torch.from_numpy(np.ascontiguousarray(opd)).cuda())
+    torch.cuda.synchronize()
+    pup, s = pup.cpu().numpy(), s.cpu().numpy()
+    for i in range(len(opd)):
+        p_o, s_o = orc.measure(opd[i].astype(np.float64))
+        e_s, e_p = rel_l2(s[i], s_o), rel_l2(pup[i], p_o)
+        say(f"[gpu]   frame {i}: slope rel err {e_s:.3e}  pupil rel err {e_p:.3e}")
+        assert e_s <= SLOPE_TOL and e_p <= PUPIL_TOL
+    plan.close()
+
+
+def test_small_tight_stop_ragged_slices():
+    """P = 32, a stop of 8 lambda/D (it cuts deep into the modulated PSF),
+    obstruction, per-subaperture normalisation, binning 2, three frames in
+    slices of two."""
+    opd, _ = open_loop_batch(CFG_SMALL_FS, ATMO1, [70, 71, 72], screen_n=64)
+    _check(CFG_SMALL_FS, None, opd, batch_max=2)
+
+
+def test_stop_with_the_detector_window():
+    """P = 64 with a 20 lambda/D stop and the non-integer rebin to 14 pixels."""
+    opd, _ = open_loop_batch(CFG_P64_FS, ATMO2, [73, 74], screen_n=256)
+    _check(CFG_P64_FS, paper_pupil(64), opd, batch_max=2)
+
+
+def test_lbt_like_geometry_with_the_papers_fov():
+    opd, _ = open_loop_batch(CFG2_FS, ATMO2, [75, 76])
+    _check(CFG2_FS, None, opd, batch_max=2)
+
+
+def test_papers_sensor_stop_and_detector():
+    """The paper's pyramid: 80 x 80 detector with pupils 30 px across and 36
+    apart, and its 2 arcsec field stop (in the window's lambda/D: x 36/30)."""
+    cfg = CFG_PAPER_DET.with_(name="paper_det80_fov2", field_stop_lod=FOV_LOD * 36 / 30)
+    opd, _ = open_loop_batch(cfg, ATMO2, [77])
+    _check(cfg, paper_pupil(160), opd, batch_max=1)
+
+
+def test_open_stop_matches_the_separable_path_and_schedules_are_fixed():
+    """A stop larger than the focal grid leaves the general path with the
+    separable path's result; field-stop plans refuse work-split changes."""
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd._lib import PwfsError
+    torch = torch_cuda()
+    cfg = CFG2.with_(name="cfg2_open_stop", field_stop_lod=1.0e4)
+    opd, _ = open_loop_batch(cfg, ATMO2, [78, 79, 80])
+    d = torch.from_numpy(opd).cuda()
+    gen = pw.Plan(cfg, batch_max=3)
+    sep = pw.Plan(CFG2, batch_max=3)
+    pg, sg = gen.measure(d)
+    ps, ss = sep.measure(d)
+    torch.cuda.synchronize()
+    for i in range(3):
+        e = rel_l2(sg[i].cpu().numpy(), ss[i].cpu().numpy())
+        say(f"[gpu] open stop vs separable, frame {i}: slope rel diff {e:.3e}")
+        assert e <= SLOPE_TOL and rel_l2(pg[i].cpu().numpy(), ps[i].cpu().numpy()) <= PUPIL_TOL
+    with pytest.raises(PwfsError):
+        gen.set_schedule(3, 1, 1)
+    with pytest.raises(PwfsError):
+        gen.autotune(3)
+    gen.close()
+    sep.close()
