@@ -400,7 +400,27 @@ def main():
         extra["paper_detector"] = {"geometry": "80 x 80 px, pupils 30 px across 36 apart (160-px windows to 36 px)",
                                    "n_valid_acquired": pplan.n_valid, "n_valid_fill_rule": n_fill,
                                    "frames_per_s": round(B * 50 / (ev0.elapsed_time(ev1) / 1e3), 1)}
+        # The same sensor with the paper's 2 arcsec field stop: the general 2-D path.
+        fov_lod = 2.0 / (206264.806 * CFG_PAPER_DET.wavelength_m / 8.4) * 36 / 30
+        fplan = pw.Plan(CFG_PAPER_DET.with_(field_stop_lod=fov_lod), batch_max=B, pupil_amp=pamp)
+        fplan.set_valid(pplan.valid)
+        fs_ = torch.empty((B, 2 * fplan.n_valid), device=dev)
+        for _ in range(3):
+            fplan.measure_into(popd, None, fs_)
+        torch.cuda.synchronize()
+        fplan.timing_enable(True)
+        ev0.record()
+        for _ in range(10):
+            fplan.measure_into(popd, None, fs_)
+        ev1.record()
+        torch.cuda.synchronize()
+        kt = fplan.timing_read()
+        fplan.timing_enable(False)
+        extra["paper_detector"]["with_field_stop"] = {
+            "fov_lambda_over_d": round(fov_lod * 30 / 36, 1), "frames_per_s": round(B * 10 / (ev0.elapsed_time(ev1) / 1e3), 1),
+            "rows_ms": round(kt["row_ms"] / kt["slices"], 4), "columns_and_output_ms": round(kt["col_ms"] / kt["slices"], 4)}
         log(f"paper detector geometry {extra['paper_detector']}")
+        fplan.close()
         pplan.close()
 
     # Closed loop on the GPU (frozen flow, 1 kHz, 15 m/s).
