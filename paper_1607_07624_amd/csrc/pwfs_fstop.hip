@@ -45,7 +45,8 @@ __device__ __forceinline__ cpx sum_quads(cpx a) {   // sum over the four quads o
 template <int E>
 __global__ __launch_bounds__(256) void fs_rows_kernel(const cpx* __restrict__ field, const cpx* __restrict__ rx,
                                                       const cpx* __restrict__ ry, const cpx* __restrict__ tw4n,
-                                                      const cpx* __restrict__ twp, int K, cpx* __restrict__ Z) {
+                                                      const cpx* __restrict__ twp, int r2max, int K,
+                                                      cpx* __restrict__ Z) {
   constexpr int P = 4 * E, N = 4 * P;
   const int tid = threadIdx.x, l = tid & 3;
   const int g = blockIdx.x * 64 + (tid >> 2);
@@ -68,14 +69,17 @@ __global__ __launch_bounds__(256) void fs_rows_kernel(const cpx* __restrict__ fi
   const int ub = 4 * E * rev2(l) + u1;               // u = 4 (k1 + E rev(l)) + u1
   static_for<0, E>([&](auto k_) {
     constexpr int k1 = decltype(k_)::value;
-    zc[(size_t)(ub + 4 * k1) * P] = cmul(v[k1], rb);
+    const int uu = ub + 4 * k1;
+    const int uus = uu < N / 2 ? uu : uu - N;
+    if (uus * uus <= r2max) zc[(size_t)uu * P] = cmul(v[k1], rb);   // columns the stop blocks are never read
   });
 }
 
 // Columns: a block holds 16 adjacent columns (4 per wave, four quads v1 per
 // column); grid (N / 16, K, B).  Output W[fk][w][t][u], w = 0 for the rows
 // of side -, staged through LDS so that each row segment of 16 columns is
-// written at once.
+// written at once.  A column the stop blocks entirely (u_s^2 > R^2) is zero
+// and is neither read nor transformed.
 template <int E>
 __global__ __launch_bounds__(256) void fs_cols_kernel(const cpx* __restrict__ Z, const cpx* __restrict__ tw4n,
                                                       const cpx* __restrict__ twp, const cpx* __restrict__ twi,
@@ -83,51 +87,70 @@ __global__ __launch_bounds__(256) void fs_cols_kernel(const cpx* __restrict__ Z,
                                                       cpx* __restrict__ W) {
   constexpr int P = 4 * E, N = 4 * P;
   __shared__ __align__(16) cpx tile[2 * P * 16];
+  __shared__ __align__(16) cpx s_twp[4 * E];
+  __shared__ __align__(16) cpx s_tw4n[4 * P];
+  __shared__ __align__(16) cpx s_twi[4 * P];
+  __shared__ __align__(16) cpx s_py[N];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l = lane & 3;
+  for (int i = tid; i < 4 * E; i += 256) s_twp[i] = twp[i];
+  for (int i = tid; i < 4 * P; i += 256) {
+    s_tw4n[i] = tw4n[i];
+    s_twi[i] = twi[i];
+  }
+  for (int i = tid; i < N; i += 256) s_py[i] = py[i];
+  __syncthreads();
   const int qd = lane >> 2;
   const int c16 = wave * 4 + (qd >> 2);
   const int v1 = qd & 3;
   const int u = blockIdx.x * 16 + c16;
   const size_t fk = (size_t)blockIdx.z * K + blockIdx.y;
-  const cpx* zc = Z + (fk * N + u) * (size_t)P + l;
-  const cpx* tw = tw4n + (size_t)v1 * P + l;
-  cpx v[E];
-  static_for<0, E>([&](auto m_) {
-    constexpr int m = decltype(m_)::value;
-    v[m] = cmul(zc[4 * m], tw[4 * m]);
-  });
-  fence();
-  const float sA = (l & 2) ? -1.f : 1.f, sB = (l & 1) ? -1.f : 1.f;
-  const bool l3 = l == 3;
-  dft_quad<E>(v, twp + l * E, sA, sB, l3);
-  // lane l, register k1: v = 4 (k1 + E rev(l)) + v1
   const int us = u < N / 2 ? u : u - N;
-  const cpx pu = py[u];
-  const int vb = 4 * E * rev2(l) + v1;
-  static_for<0, E>([&](auto k_) {
-    constexpr int k1 = decltype(k_)::value;
-    if constexpr (k1 % 8 == 0 && k1 > 0) fence();
-    const int vv = vb + 4 * k1;
-    const int vs = vv < N / 2 ? vv : vv - N;
-    const float in = (us * us + vs * vs <= r2max) ? 1.f : 0.f;
-    const cpx mk = cmul(py[vv], pu);
-    const cpx g = cmul(v[k1], mk);
-    v[k1] = {in * g.re, in * g.im};
-  });
-  fence();
-  idft_quad<E>(v, twp + l * E, sA, sB, l3);
-  // lane l, register m: t = l + 4 m
-  const cpx* ti = twi + (size_t)v1 * P + l;
-  const float s1 = (v1 & 1) ? -1.f : 1.f;
   const int w = v1 & 1, msel = v1 >> 1;
-  static_for<0, E>([&](auto m_) {
-    constexpr int m = decltype(m_)::value;
-    if constexpr (m % 8 == 0 && m > 0) fence();
-    const cpx d = cmul(v[m], ti[4 * m]);
-    const cpx a = sum_quads(d);
-    const cpx b = sum_quads(cpx{s1 * d.re, s1 * d.im});
-    if ((m & 1) == msel) tile[(w * P + l + 4 * m) * 16 + c16] = w ? b : a;
-  });
+  if (us * us > r2max) {
+    // The stop blocks this whole column (the same for its four quads).
+    static_for<0, E>([&](auto m_) {
+      constexpr int m = decltype(m_)::value;
+      if ((m & 1) == msel) tile[(w * P + l + 4 * m) * 16 + c16] = cpx{0.f, 0.f};
+    });
+  } else {
+    const cpx* zc = Z + (fk * N + u) * (size_t)P + l;
+    const cpx* tw = s_tw4n + v1 * P + l;
+    cpx v[E];
+    static_for<0, E>([&](auto m_) {
+      constexpr int m = decltype(m_)::value;
+      v[m] = cmul(zc[4 * m], tw[4 * m]);
+    });
+    fence();
+    const float sA = (l & 2) ? -1.f : 1.f, sB = (l & 1) ? -1.f : 1.f;
+    const bool l3 = l == 3;
+    dft_quad<E>(v, s_twp + l * E, sA, sB, l3);
+    // lane l, register k1: v = 4 (k1 + E rev(l)) + v1
+    const cpx pu = s_py[u];
+    const int vb = 4 * E * rev2(l) + v1;
+    static_for<0, E>([&](auto k_) {
+      constexpr int k1 = decltype(k_)::value;
+      if constexpr (k1 % 8 == 0 && k1 > 0) fence();
+      const int vv = vb + 4 * k1;
+      const int vs = vv < N / 2 ? vv : vv - N;
+      const float in = (us * us + vs * vs <= r2max) ? 1.f : 0.f;
+      const cpx g = cmul(v[k1], cmul(s_py[vv], pu));
+      v[k1] = {in * g.re, in * g.im};
+    });
+    fence();
+    asm volatile("" ::: "memory");   // the quad twiddles are read again from LDS, not kept in registers
+    idft_quad<E>(v, s_twp + l * E, sA, sB, l3);
+    // lane l, register m: t = l + 4 m
+    const cpx* ti = s_twi + v1 * P + l;
+    const float s1 = (v1 & 1) ? -1.f : 1.f;
+    static_for<0, E>([&](auto m_) {
+      constexpr int m = decltype(m_)::value;
+      if constexpr (m % 8 == 0 && m > 0) fence();
+      const cpx d = cmul(v[m], ti[4 * m]);
+      const cpx a = sum_quads(d);
+      const cpx b = sum_quads(cpx{s1 * d.re, s1 * d.im});
+      if ((m & 1) == msel) tile[(w * P + l + 4 * m) * 16 + c16] = w ? b : a;
+    });
+  }
   __syncthreads();
   cpx* wb = W + fk * (size_t)(2 * P) * N + (size_t)blockIdx.x * 16;
   for (int i = tid; i < 2 * P * 16; i += 256) wb[(size_t)(i >> 4) * N + (i & 15)] = tile[i];
@@ -142,7 +165,12 @@ __global__ __launch_bounds__(256) void fs_out_kernel(const cpx* __restrict__ W, 
                                                      const cpx* __restrict__ twi, int K, int k_chunk, int n_chunks,
                                                      float* __restrict__ partial) {
   constexpr int P = 4 * E, N = 4 * P;
+  __shared__ __align__(16) cpx s_twp[4 * E];
+  __shared__ __align__(16) cpx s_twi[4 * P];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l = lane & 3;
+  for (int i = tid; i < 4 * E; i += 256) s_twp[i] = twp[i];
+  for (int i = tid; i < 4 * P; i += 256) s_twi[i] = twi[i];
+  __syncthreads();
   const int qd = lane >> 2;
   const int r = blockIdx.x * 16 + wave * 4 + (qd >> 2);
   const int u1 = qd & 3;
@@ -153,10 +181,12 @@ __global__ __launch_bounds__(256) void fs_out_kernel(const cpx* __restrict__ W, 
   const bool l3 = l == 3;
   const float s1 = (u1 & 1) ? -1.f : 1.f;
   const int xw = u1 & 1, msel = u1 >> 1;             // this quad keeps side xw, registers k1 = 2 j + msel
-  const cpx* ti = twi + (size_t)u1 * P + E * rev2(l);   // t = k1 + E rev(l)
+  const cpx* ti = s_twi + u1 * P + E * rev2(l);       // t = k1 + E rev(l)
   float acc[E / 2];
   static_for<0, E / 2>([&](auto j_) { acc[decltype(j_)::value] = 0.f; });
   for (int k = kb; k < ke; ++k) {
+    // Tables are read from LDS in every iteration (kept out of registers).
+    asm volatile("" ::: "memory");
     const cpx* row = W + ((fr * K + k) * (size_t)(2 * P) + r) * N + 4 * l + u1;   // u = 16 m + 4 l + u1
     cpx v[E];
     static_for<0, E>([&](auto m_) {
@@ -165,7 +195,7 @@ __global__ __launch_bounds__(256) void fs_out_kernel(const cpx* __restrict__ W, 
       v[m] = cpx{c.re, -c.im};
     });
     fence();
-    dft_quad<E>(v, twp + l * E, sA, sB, l3);
+    dft_quad<E>(v, s_twp + l * E, sA, sB, l3);
     static_for<0, E / 2>([&](auto j_) {
       constexpr int j = decltype(j_)::value;
       if constexpr (j % 4 == 0 && j > 0) fence();
@@ -193,7 +223,7 @@ static hipError_t launch_fs_e(const MeasureArgs& a, hipStream_t st, hipEvent_t* 
   constexpr int P = 4 * E, N = 4 * P;
   hipError_t e;
   hipLaunchKernelGGL(fs_rows_kernel<E>, dim3(P / 16, a.K, a.B), dim3(256), 0, st, a.field, a.fs_rx, a.fs_ry,
-                     a.fs_tw4n, a.fs_twp, a.K, a.fs_Z);
+                     a.fs_tw4n, a.fs_twp, a.fs_r2max, a.K, a.fs_Z);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   hipLaunchKernelGGL(fs_cols_kernel<E>, dim3(N / 16, a.K, a.B), dim3(256), 0, st, a.fs_Z, a.fs_tw4n, a.fs_twp,
