@@ -432,15 +432,27 @@ def main():
         cl = ClosedLoop(plan1, modes_dev, R, LOOP_GAIN, LOOP_DELAY)
         torch.cuda.synchronize()
         ev0.record()
-        res, _ = cl.run(seq)
+        res_eager, _ = cl.run(seq)
+        ev1.record()
+        torch.cuda.synchronize()
+        eager_ms = ev0.elapsed_time(ev1)
+        # The same loop with each step replayed from one captured HIP graph
+        # (same residuals bit for bit; reported beside the eager rate).
+        ev0.record()
+        res, _ = cl.run_graph(seq)
         ev1.record()
         torch.cuda.synchronize()
         loop_ms = ev0.elapsed_time(ev1)
+        graph_ms = loop_ms
+        graph_same = bool(torch.equal(res, res_eager))
+        res, loop_ms = res_eager, eager_ms
         per_step = residual_rms_nm(res.cpu().numpy(), amp)
         ol = residual_rms_nm(seq.cpu().numpy().reshape(T, -1), amp)
         loop = {"steps": T, "residual_nm_rms": round(float(np.sqrt(np.mean(per_step[LOOP_SETTLE_STEPS:] ** 2))), 2),
                 "open_loop_nm_rms": round(float(np.sqrt(np.mean(ol[LOOP_SETTLE_STEPS:] ** 2))), 2),
-                "steps_per_s": round(T / (loop_ms / 1e3), 1), "gain": LOOP_GAIN, "delay": LOOP_DELAY,
+                "steps_per_s": round(T / (loop_ms / 1e3), 1),
+                "graph_replay": {"steps_per_s": round(T / (graph_ms / 1e3), 1), "equals_eager": graph_same},
+                "gain": LOOP_GAIN, "delay": LOOP_DELAY,
                 "reconstructor": "linear (KL 600, push-pull IM, full-SVD pinv)"}
         cam = pw.PsfCamera(P, 8, 1.65e-6, batch_max=B)
         loop.update(strehl_stats(cam, res, P, LOOP_SETTLE_STEPS))

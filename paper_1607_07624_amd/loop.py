@@ -198,6 +198,60 @@ class ClosedLoop:
         return res, hist[d:]
 
 
+    def run_graph(self, opd_seq_dev, residuals_dev=None):
+        """run() for the linear reconstructor with each step replayed from one
+        captured HIP graph (torch.cuda.CUDAGraph): the same library calls in
+        the same order on static buffers, so the same results bit for bit.
+        Per step: one copy in, the replay, two copies out.  The delay line is
+        a ring of `delay` static command buffers, ring[j] = c(t - 1 - j),
+        shifted inside the graph.  Needs delay >= 1 and a noiseless sensor (a
+        detector's frame counter would be frozen into the graph)."""
+        import torch
+        if self.net is not None:
+            raise ValueError("graph replay runs the linear reconstructor only")
+        if self.delay < 1:
+            raise ValueError("graph replay needs delay >= 1")
+        det = getattr(self.plan, "detector", None)
+        if det is not None and det()["gain"] > 0.0:
+            raise ValueError("graph replay needs a noiseless sensor")
+        T = opd_seq_dev.shape[0]
+        P, M, d = self.P, self.M, self.delay
+        dev = opd_seq_dev.device
+        res = residuals_dev if residuals_dev is not None else torch.empty((T, P * P), device=dev)
+        hist = torch.empty((T, M), device=dev)
+        opd_in = torch.zeros((1, P * P), device=dev)
+        r = torch.zeros((1, P * P), device=dev)
+        ring = [torch.zeros((1, M), device=dev) for _ in range(d)]
+        cn = torch.zeros((1, M), device=dev)
+
+        def step():
+            r.copy_(opd_in)
+            recon_apply(self.BKL, ring[d - 1], -1.0, 1.0, r)          # u(t) = c(t - d)
+            cn.copy_(ring[0])
+            self.plan.measure_into(r.view(1, P, P), None, self.s)
+            recon_apply(self.R, self.s, self.gain, 1.0, cn)           # c(t) = c(t-1) + g R s(t)
+            for j in range(d - 1, 0, -1):
+                ring[j].copy_(ring[j - 1])
+            ring[0].copy_(cn)
+
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            step()                                                    # warm-up outside the capture
+        torch.cuda.current_stream(dev).wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for b in ring:
+            b.zero_()
+        for t in range(T):
+            opd_in.copy_(opd_seq_dev[t].reshape(1, -1))
+            graph.replay()
+            res[t].copy_(r[0])
+            hist[t].copy_(cn[0])
+        return res, hist
+
+
 class BatchedLoop:
     """B independent integrator loops (Monte-Carlo realisations: different
     screens, same sensor, reconstructor and controller) advanced together,

@@ -125,3 +125,35 @@ def test_batched_loops_match_oracle_cfg1():
             f"worst per-step rel diff {worst:.3e}")
         assert worst <= 1e-3
         assert abs(tot_g - tot_o) <= 1e-4 * tot_o
+
+
+def test_graph_replayed_loop_equals_eager():
+    """The linear loop replayed step by step from one captured HIP graph gives
+    the eager loop's residuals and commands bit for bit, for delays 2 and 3,
+    on two sequences with eager work and synchronisations between the runs;
+    a sensor with a detector is refused (its frame counter would be frozen)."""
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd.loop import calibrate, ClosedLoop
+    torch = torch_cuda()
+    T = 120
+    modes, A = _modes(CFG1, 25.0, 60)
+    atmo = AtmoConfig(r0_m=0.5, L0_m=25.0, wind_m_s=15.0)
+    plan_cal = pw.Plan(CFG1, batch_max=16)
+    R_g, _, _ = calibrate(plan_cal, modes, PUSH_PULL_NM)
+    plan = pw.Plan(CFG1, batch_max=1)
+    modes_dev = torch.from_numpy(modes).cuda()
+    for delay, seed in ((LOOP_DELAY, 11), (3, 12)):
+        seq = torch.from_numpy(frozen_flow_sequence(CFG1, atmo, T, seed=seed, screen_n=256)).cuda()
+        cl = ClosedLoop(plan, modes_dev, R_g, LOOP_GAIN, delay)
+        res_e, c_e = cl.run(seq)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 16, device="cuda").sum()         # eager work between the runs
+        res_g, c_g = cl.run_graph(seq)
+        torch.cuda.synchronize()
+        say(f"[gpu] graph loop, delay {delay}: residual equal {torch.equal(res_g, res_e)}, "
+            f"commands equal {torch.equal(c_g, c_e)} ({float(junk):.1f})")
+        assert torch.equal(res_g, res_e) and torch.equal(c_g, c_e)
+    plan.set_detector(1.0e5, 1.0, seed=3)
+    with pytest.raises(ValueError):
+        ClosedLoop(plan, modes_dev, R_g, LOOP_GAIN, LOOP_DELAY).run_graph(seq)
+    plan.close()
