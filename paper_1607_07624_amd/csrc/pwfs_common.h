@@ -1,5 +1,5 @@
 // pwfs_common.h -- device helpers shared by the pyramid line kernels (gfx950):
-// scheduling fences, pointer laundering, the quad-lane half-band projection
+// scheduling fences, the quad DFT and its inverse, the quad-lane half-band projection
 // and line operator, the row-pass intermediate index and LDS staging copies.
 #pragma once
 
@@ -12,14 +12,6 @@ namespace pwfs {
 // Scheduling fence: keeps the machine scheduler from hoisting the table and
 // field loads of later phases over the register-resident transforms.
 __device__ __forceinline__ void fence() { __builtin_amdgcn_sched_barrier(0); }
-
-// Opaque copy of a wave-uniform pointer: stops loop-invariant code motion
-// from hoisting whole tables out of the modulation loop into registers.
-template <typename T>
-__device__ __forceinline__ const T* opaque(const T* p) {
-  asm volatile("" : "+s"(p));
-  return p;
-}
 
 // LDS copies of the pyramid tables are padded so that a ds_read of a quad's
 // four lanes (mix table, rows of 2E values) or of a team's two quads (input
