@@ -286,12 +286,24 @@ void pwfs_psf_destroy(pwfs_psf_t cam);
 int pwfs_get_schedule(pwfs_plan_t plan, int32_t B, int32_t* a_chunk, int32_t* k_chunk);
 int pwfs_set_schedule(pwfs_plan_t plan, int32_t B, int32_t a_chunk, int32_t k_chunk);
 
+/* Lane form of the line kernels for slices of B frames: 8 (a line on two
+ * 4-lane quads, one per half-band projection, P/4 samples per lane) or 32 (a
+ * line on two 16-lane rows, P/16 samples per lane, the quad DFT_4 steps done
+ * across lanes).  n_pupil 128 and 480 always use 32; 32, 64 use 8; at 160
+ * both exist (8 by default; 32 keeps more waves busy for a few frames).  Only
+ * the FP32 rounding differs.  PWFS_ERR_UNSUPPORTED for a form the geometry
+ * does not have or a field-stop plan, PWFS_ERR_INVALID_ARG for lanes other
+ * than 8 or 32. */
+int pwfs_get_schedule_lanes(pwfs_plan_t plan, int32_t B, int32_t* lanes);
+int pwfs_set_schedule_lanes(pwfs_plan_t plan, int32_t B, int32_t lanes);
+
 /* Autotuner: times the row pass for every distinct number of x-tilt chunks
  * and then the column pass (with the chunk reduction and the slopes) for
  * every distinct number of modulation chunks that fits the workspace, on B
  * flat frames, best of `reps` launches each (1..1000), and keeps the
  * fastest schedule for slices of B frames (a candidate must beat the best
- * so far by 2 %).  It allocates and frees a temporary input and output of
+ * so far by 2 %); at n_pupil 160 it does so for both lane forms and keeps
+ * the faster.  It allocates and frees a temporary input and output of
  * B frames and waits for `stream`: a set-up call, not for the hot path.
  * ms_default / ms_tuned (may be NULL) receive the measured time of one
  * B-frame call with the default and with the chosen schedule. */

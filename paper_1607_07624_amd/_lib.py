@@ -76,6 +76,8 @@ def load_library():
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.pwfs_get_schedule.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pwfs_set_schedule.argtypes = [vp, i32, i32, i32]
+    lib.pwfs_get_schedule_lanes.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.pwfs_set_schedule_lanes.argtypes = [vp, i32, i32]
     lib.pwfs_autotune.argtypes = [vp, i32, i32, vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
     lib.pwfs_set_detector.argtypes = [vp, ctypes.POINTER(detector_struct)]
@@ -103,6 +105,7 @@ def load_library():
     for name in ("pwfs_plan", "pwfs_plan_info", "pwfs_get_valid", "pwfs_set_valid", "pwfs_get_reference",
                  "pwfs_set_reference", "pwfs_measure", "recon_apply", "pwfs_get_pupil",
                  "pwfs_timing_enable", "pwfs_timing_read", "pwfs_get_schedule", "pwfs_set_schedule",
+                 "pwfs_get_schedule_lanes", "pwfs_set_schedule_lanes",
                  "pwfs_autotune", "pwfs_set_detector", "pwfs_get_detector", "pwfs_set_frame_counter",
                  "pwfs_detect", "pwfs_psf_create", "pwfs_psf_info", "pwfs_psf_compute", "pwfs_sh_create",
                  "pwfs_sh_info", "pwfs_sh_get_valid", "pwfs_sh_get_reference", "pwfs_sh_measure"):
@@ -249,7 +252,17 @@ class Plan:
         _check(self.lib.pwfs_autotune(self.handle, int(B), int(reps), _stream_handle(self._torch, self.device),
                                        ctypes.byref(d0), ctypes.byref(d1)), "pwfs_autotune")
         a, k = self.get_schedule(B)
-        return {"B": int(B), "a_chunk": a, "k_chunk": k, "ms_default": d0.value, "ms_tuned": d1.value}
+        return {"B": int(B), "a_chunk": a, "k_chunk": k, "lanes": self.get_lanes(B), "ms_default": d0.value,
+                "ms_tuned": d1.value}
+
+    def get_lanes(self, B: int) -> int:
+        """Lane form (8 or 32 lanes per line) pwfs_measure uses for slices of B frames."""
+        n = ctypes.c_int32()
+        _check(self.lib.pwfs_get_schedule_lanes(self.handle, int(B), ctypes.byref(n)), "pwfs_get_schedule_lanes")
+        return n.value
+
+    def set_lanes(self, B: int, lanes: int):
+        _check(self.lib.pwfs_set_schedule_lanes(self.handle, int(B), int(lanes)), "pwfs_set_schedule_lanes")
 
     def set_reference(self, sref=None):
         t = self._torch

@@ -155,6 +155,8 @@ struct pwfs_plan_s {
   float det_gain = 0.f;
   float* pixels = nullptr;                      // [batch_max][4][S][S] detector output scratch
   std::map<int, std::array<int, 2>> sched;      // slice size -> {a_chunk, k_chunk}
+  std::map<int, int> teams32;                   // slice size -> 1: 32-lane teams at P = 160
+  cpx* mid16 = nullptr;                         // P = 160: mix table of the 32-lane form
   std::vector<float> amp_host;
   // per-kernel timing
   bool timing = false;
@@ -163,12 +165,22 @@ struct pwfs_plan_s {
 
 namespace {
 
+// Lane form of a slice of B frames: 32-lane teams always for P = 128 and 480,
+// at P = 160 when chosen (pwfs_set_schedule_lanes or the autotuner), else
+// 8-lane teams (quads).
+bool teams32(const pwfs_plan_s* p, int B) {
+  if (long_lines(p->P)) return true;
+  if (p->P != 160) return false;
+  auto it = p->teams32.find(B);
+  return it != p->teams32.end() && it->second != 0;
+}
+
 // Default work split for a slice of B frames: enough waves per pass to keep
 // several in flight on every SIMD of the 256-CU chip.  A wave holds 8 lines
-// (8-lane teams) or 2 lines (32-lane teams, P = 128 and 480).
+// (8-lane teams) or 2 lines (32-lane teams).
 void default_split(const pwfs_plan_s* p, int B, int* a_chunk, int* k_chunk) {
   const long target = 2048;
-  const long lines_per_wave = long_lines(p->P) ? 2 : 8;
+  const long lines_per_wave = teams32(p, B) ? 2 : 8;
   const long row_waves = (long)p->P / lines_per_wave * p->n_a * B;
   int ac = (int)std::max<long>(1, row_waves / target);
   *a_chunk = std::min(ac, p->n_a);
@@ -244,7 +256,7 @@ void free_plan(pwfs_plan_s* p) {
   DeviceGuard g(p->device);
   void* ptrs[] = {p->amp, p->in_a, p->f_a, p->in_b, p->f_b, p->mid, p->tw16, p->outw, p->k_order, p->k_ia,
                   p->d_valid, p->sref, p->Rw, p->partial, p->pupils, p->pixels, p->field, p->zero_opd,
-                  p->tmp_slopes, p->fullres, p->fs_rx, p->fs_ry, p->fs_tw4n, p->fs_twp, p->fs_twi, p->fs_py,
+                  p->tmp_slopes, p->fullres, p->mid16, p->fs_rx, p->fs_ry, p->fs_tw4n, p->fs_twp, p->fs_twi, p->fs_py,
                   p->fs_Z, p->fs_W};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -265,6 +277,7 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
   a.norm_mode = p->cfg.norm_mode;
   a.B = Bs;
   split_work(p, Bs, &a.a_chunk, &a.k_chunk, &a.n_chunks);
+  a.lines16 = teams32(p, Bs) ? 1 : 0;
   a.kphase = p->kphase;
   a.fp32_phase = (p->cfg.flags & 2) != 0;
   a.opd = opd + (size_t)b0 * p->P * p->P;
@@ -281,7 +294,7 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
   a.f_a = p->f_a;
   a.in_b = p->in_b;
   a.f_b = p->f_b;
-  a.mid = p->mid;
+  a.mid = (p->P == 160 && a.lines16) ? p->mid16 : p->mid;
   a.tw16 = p->tw16;
   a.outw = p->outw;
   a.k_order = p->k_order;
@@ -524,18 +537,21 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
     dst[1] = to32(std::complex<double>(0.5, 0.5) * std::conj(wlk(l, k)) * wlk((l + 3) & 3, k));
   };
   const bool lines32 = long_lines(P);
+  const bool have32 = lines32 || P == 160;       // tables of the 32-lane form
   const int E16 = P / 16;
-  std::vector<cpx> tw16(lines32 ? 4 * (size_t)E16 : 1);
+  std::vector<cpx> tw16(have32 ? 4 * (size_t)E16 : 1), mid16(P == 160 ? 8 * (size_t)p->E : 0);
   if (!lines32) {
     for (int l = 0; l < 4; ++l)
       for (int k = 0; k < p->E; ++k) mix(l, k, &mid[((size_t)l * p->E + k) * 2]);
-  } else {
+  }
+  if (have32) {
     // Lane 4 l1 + l2 of a 16-lane row holds in-lane frequency k1 of outer
     // lane l1 at t' = k1 + E16 rev(l2) after the subgroup DFT_4; its
     // twiddle before that DFT is w_{4 E16}^{l2 k1}.
+    std::vector<cpx>& m16 = lines32 ? mid : mid16;
     const int rev2[4] = {0, 2, 1, 3};
     for (int l16 = 0; l16 < 16; ++l16)
-      for (int k1 = 0; k1 < E16; ++k1) mix(l16 >> 2, k1 + E16 * rev2[l16 & 3], &mid[((size_t)l16 * E16 + k1) * 2]);
+      for (int k1 = 0; k1 < E16; ++k1) mix(l16 >> 2, k1 + E16 * rev2[l16 & 3], &m16[((size_t)l16 * E16 + k1) * 2]);
     for (int l2 = 0; l2 < 4; ++l2)
       for (int k1 = 0; k1 < E16; ++k1) {
         const long n = (long)l2 * k1;
@@ -615,6 +631,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {(void**)&p->f_b, f_b.size() * sizeof(cpx), "f_b"},
       {(void**)&p->mid, mid.size() * sizeof(cpx), "mid"},
       {(void**)&p->tw16, tw16.size() * sizeof(cpx), "tw16"},
+      {(void**)&p->mid16, mid16.size() * sizeof(cpx), "mid16"},
       {(void**)&p->outw, outw.size() * sizeof(cpx), "outw"},
       {(void**)&p->k_order, (size_t)K * sizeof(int), "k_order"},
       {(void**)&p->k_ia, (size_t)K * sizeof(int), "k_ia"},
@@ -654,6 +671,7 @@ int pwfs_plan(const pwfs_config_t* cfg, const float* pupil_amp_host, pwfs_plan_t
       {p->f_b, f_b.data(), f_b.size() * sizeof(cpx)},
       {p->mid, mid.data(), mid.size() * sizeof(cpx)},
       {p->tw16, tw16.data(), tw16.size() * sizeof(cpx)},
+      {p->mid16, mid16.data(), mid16.size() * sizeof(cpx)},
       {p->outw, outw.data(), outw.size() * sizeof(cpx)},
       {p->k_order, k_order.data(), (size_t)K * sizeof(int)},
       {p->k_ia, k_ia.data(), (size_t)K * sizeof(int)},
@@ -1119,6 +1137,30 @@ int pwfs_set_schedule(pwfs_plan_t p, int32_t B, int32_t a_chunk, int32_t k_chunk
   return PWFS_OK;
 }
 
+int pwfs_get_schedule_lanes(pwfs_plan_t p, int32_t B, int32_t* lanes) {
+  if (!p || !lanes) return fail(PWFS_ERR_INVALID_ARG, "plan or lanes is NULL");
+  if (B < 1 || B > p->batch_max) return fail(PWFS_ERR_INVALID_ARG, "B outside [1, batch_max]");
+  *lanes = teams32(p, B) ? 32 : 8;
+  return PWFS_OK;
+}
+
+int pwfs_set_schedule_lanes(pwfs_plan_t p, int32_t B, int32_t lanes) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (p->fs_on) return fail(PWFS_ERR_UNSUPPORTED, "field-stop plans have a fixed work split");
+  if (B < 1 || B > p->batch_max) return fail(PWFS_ERR_INVALID_ARG, "B outside [1, batch_max]");
+  if (lanes != 8 && lanes != 32) return fail(PWFS_ERR_INVALID_ARG, "lanes must be 8 or 32");
+  if (long_lines(p->P)) {
+    if (lanes != 32) return fail(PWFS_ERR_UNSUPPORTED, "n_pupil 128 and 480 run 32-lane teams only");
+    return PWFS_OK;
+  }
+  if (p->P != 160) {
+    if (lanes != 8) return fail(PWFS_ERR_UNSUPPORTED, "32-lane teams need n_pupil 128, 160 or 480");
+    return PWFS_OK;
+  }
+  p->teams32[B] = lanes == 32 ? 1 : 0;
+  return PWFS_OK;
+}
+
 int pwfs_autotune(pwfs_plan_t p, int32_t B, int32_t reps, void* stream, double* ms_default, double* ms_tuned) {
   if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
   if (p->fs_on) return fail(PWFS_ERR_UNSUPPORTED, "field-stop plans have a fixed work split");
@@ -1170,39 +1212,73 @@ int pwfs_autotune(pwfs_plan_t p, int32_t B, int32_t reps, void* stream, double* 
     }
     return le;
   };
-  int a0, k0;
-  default_split(p, B, &a0, &k0);
-  double row0, col0;
-  e = time_schedule(a0, k0, &row0, &col0);
-  int best_a = a0, best_k = k0;
-  double best_row = row0, best_col = col0;
-  // Row pass: one candidate per distinct number of x-tilt chunks.
-  for (int a = 1; a <= p->n_a && e == hipSuccess; ++a) {
-    if (a > 1 && (p->n_a + a - 1) / a == (p->n_a + a - 2) / (a - 1)) continue;
-    if (a == a0 || !schedule_fits(p, B, a, k0)) continue;
-    double r, c;
-    e = time_schedule(a, k0, &r, &c);
-    if (e == hipSuccess && r < 0.98 * best_row) {
-      best_row = r;
-      best_a = a;
+  // One search per lane form (both at P = 160): the default split, then the
+  // row pass over the distinct numbers of x-tilt chunks, then the column pass
+  // over the distinct numbers of modulation chunks.
+  const bool had_form = p->teams32.count(B) != 0;
+  const int old_form = had_form ? p->teams32[B] : 0;
+  auto search = [&](int form, int* ba, int* bk, double* brow, double* bcol, double* dflt) -> hipError_t {
+    if (p->P == 160) p->teams32[B] = form;
+    int a0, k0;
+    default_split(p, B, &a0, &k0);
+    double row0, col0;
+    hipError_t le = time_schedule(a0, k0, &row0, &col0);
+    *ba = a0;
+    *bk = k0;
+    *brow = row0;
+    *bcol = col0;
+    *dflt = row0 + col0;
+    for (int a = 1; a <= p->n_a && le == hipSuccess; ++a) {
+      if (a > 1 && (p->n_a + a - 1) / a == (p->n_a + a - 2) / (a - 1)) continue;
+      if (a == a0 || !schedule_fits(p, B, a, k0)) continue;
+      double r, c;
+      le = time_schedule(a, k0, &r, &c);
+      if (le == hipSuccess && r < 0.98 * *brow) {
+        *brow = r;
+        *ba = a;
+      }
     }
-  }
-  // Column pass: one candidate per distinct number of modulation chunks.
-  for (int k = 1; k <= p->K && e == hipSuccess; ++k) {
-    if (k > 1 && (p->K + k - 1) / k == (p->K + k - 2) / (k - 1)) continue;
-    if (k == k0 || !schedule_fits(p, B, best_a, k)) continue;
-    double r, c;
-    e = time_schedule(best_a, k, &r, &c);
-    if (e == hipSuccess && c < 0.98 * best_col) {
-      best_col = c;
-      best_k = k;
+    for (int k = 1; k <= p->K && le == hipSuccess; ++k) {
+      if (k > 1 && (p->K + k - 1) / k == (p->K + k - 2) / (k - 1)) continue;
+      if (k == k0 || !schedule_fits(p, B, *ba, k)) continue;
+      double r, c;
+      le = time_schedule(*ba, k, &r, &c);
+      if (le == hipSuccess && c < 0.98 * *bcol) {
+        *bcol = c;
+        *bk = k;
+      }
+    }
+    return le;
+  };
+  int best_a = 0, best_k = 0, best_form = 0;
+  double best_row = 0.0, best_col = 0.0, dflt8 = 0.0;
+  e = search(0, &best_a, &best_k, &best_row, &best_col, &dflt8);
+  if (e == hipSuccess && p->P == 160) {
+    int a2, k2;
+    double r2, c2, d2;
+    e = search(1, &a2, &k2, &r2, &c2, &d2);
+    if (e == hipSuccess && r2 + c2 < 0.98 * (best_row + best_col)) {
+      best_a = a2;
+      best_k = k2;
+      best_row = r2;
+      best_col = c2;
+      best_form = 1;
     }
   }
   if (e != hipSuccess) status = hip_fail(e, "autotune launch");
   cleanup();
-  if (status != PWFS_OK) return status;
+  if (status != PWFS_OK) {
+    if (p->P == 160) {
+      if (had_form)
+        p->teams32[B] = old_form;
+      else
+        p->teams32.erase(B);
+    }
+    return status;
+  }
   p->sched[B] = {best_a, best_k};
-  if (ms_default) *ms_default = row0 + col0;
+  if (p->P == 160) p->teams32[B] = best_form;
+  if (ms_default) *ms_default = dflt8;   // 8-lane teams (32-lane at P = 128, 480), default split
   if (ms_tuned) *ms_tuned = best_row + best_col;
   return PWFS_OK;
 }

@@ -545,23 +545,27 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
     if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
     return launch_finish(a, a.P, st, ev);
   }
-  switch (a.P) {
-    case 32: e = launch_rows<8>(a, st); break;
-    case 64: e = launch_rows<16>(a, st); break;
-    case 160: e = launch_rows<40>(a, st); break;
-    case 128:
-    case 480: e = launch_rows_long(a, st); break;
-    default: return hipErrorInvalidValue;
+  if (a.lines16) {
+    e = launch_rows_long(a, st);
+  } else {
+    switch (a.P) {
+      case 32: e = launch_rows<8>(a, st); break;
+      case 64: e = launch_rows<16>(a, st); break;
+      case 160: e = launch_rows<40>(a, st); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-  switch (a.P) {
-    case 32: e = launch_cols<8>(a, st); break;
-    case 64: e = launch_cols<16>(a, st); break;
-    case 160: e = launch_cols<40>(a, st); break;
-    case 128:
-    case 480: e = launch_cols_long(a, st); break;
-    default: return hipErrorInvalidValue;
+  if (a.lines16) {
+    e = launch_cols_long(a, st);
+  } else {
+    switch (a.P) {
+      case 32: e = launch_cols<8>(a, st); break;
+      case 64: e = launch_cols<16>(a, st); break;
+      case 160: e = launch_cols<40>(a, st); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;

@@ -8,7 +8,8 @@
 namespace pwfs {
 
 // ===========================================================================
-// Long lines, P = 16 E (P = 128, 480).  The four lanes of the quad form above
+// Long lines, P = 16 E (P = 128, 480; at P = 160 an alternative to the quad
+// form for small batches).  The four lanes of the quad form above
 // become four 4-lane subgroups: a projection is held by a row of 16 lanes,
 // lane 4 l1 + l2 holding the samples x = l1 + 4 l2 + 16 m (m < E), so that
 // "outer lane" l1 holds x = l1 + 4 m' with m' = l2 + 4 m as before.  Its
@@ -363,6 +364,7 @@ static hipError_t launch_cols16_e(const MeasureArgs& a, hipStream_t st) {
 hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t st) {
   switch (a.P) {
     case 128: return launch_rows16_e<8>(a, st);
+    case 160: return launch_rows16_e<10>(a, st);
     case 480: return launch_rows16_e<30>(a, st);
     default: return hipErrorInvalidValue;
   }
@@ -371,6 +373,7 @@ hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t st) {
 hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t st) {
   switch (a.P) {
     case 128: return launch_cols16_e<8, 8>(a, st);
+    case 160: return launch_cols16_e<10, 8>(a, st);
     case 480: return launch_cols16_e<30, 8>(a, st);
     default: return hipErrorInvalidValue;
   }

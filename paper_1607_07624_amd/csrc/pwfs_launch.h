@@ -17,6 +17,7 @@ struct MeasureArgs {
   int B, a_chunk, k_chunk, n_chunks;
   double kphase;  // 2 pi 1e-9 / lambda
   int fp32_phase; // precision study: form and reduce the phase in FP32
+  int lines16;    // 32-lane teams (16-lane projections): always for P = 128, 480; optional at P = 160
   // inputs / outputs
   const float* opd;
   float* pupils;       // [B][4][S][S]: the caller's buffer or the plan's scratch
@@ -27,8 +28,8 @@ struct MeasureArgs {
   const cpx* f_a;      // [n_a][P]     -r_a(x) (finishing factor of the low-face projection)
   const cpx* in_b;     // [K][2][P]    r_b(y) w_N^{(2q+1)y}
   const cpx* f_b;      // [K][P]       -r_b(y)
-  const cpx* mid;      // [4][P/4][2] folded mix coefficients (A/2, B/2) per lane; P = 16 E: [16][E][2]
-  const cpx* tw16;     // P = 16 E only: [4][E] subgroup twiddles w_{4E}^{l2 k1}
+  const cpx* mid;      // [4][P/4][2] folded mix coefficients (A/2, B/2) per lane; 32-lane teams: [16][E][2]
+  const cpx* tw16;     // 32-lane teams only: [4][E] subgroup twiddles w_{4E}^{l2 k1}
   const cpx* outw;     // [2][P]
   const int* k_order;  // [K]
   const int* k_ia;     // [K]

@@ -188,6 +188,44 @@ def test_schedules_change_only_rounding_cfg2():
     plan.close()
 
 
+def test_cfg2_32_lane_form():
+    """At P = 160 both lane forms exist: 32-lane teams (16-lane projections,
+    10 samples per lane) meet the oracle gates like the default 8-lane quads,
+    for one frame and for a batch, and the form is a per-slice-size choice."""
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd._lib import PwfsError
+    torch = torch_cuda()
+    B = 3
+    opd, _ = open_loop_batch(CFG2, ATMO2, [44, 45, 46], r0_range=CFG4_R0_RANGE)
+    plan = pw.Plan(CFG2, batch_max=B)
+    orc = orc_for(CFG2)
+    assert plan.get_lanes(1) == 8 and plan.get_lanes(B) == 8
+    plan.set_lanes(1, 32)
+    plan.set_lanes(B, 32)
+    assert plan.get_lanes(1) == 32 and plan.get_lanes(2) == 8
+    d = torch.from_numpy(np.ascontiguousarray(opd)).cuda()
+    for sl in (d[:1], d):
+        pup, s = plan.measure(sl.contiguous())
+        torch.cuda.synchronize()
+        pup, s = pup.cpu().numpy(), s.cpu().numpy()
+        for i in range(sl.shape[0]):
+            p_o, s_o = orc.measure(opd[i].astype(np.float64))
+            e_s, e_p = rel_l2(s[i], s_o), rel_l2(pup[i], p_o)
+            say(f"[gpu] cfg2 32-lane, B={sl.shape[0]}, frame {i}: slope rel err {e_s:.3e}  pupil rel err {e_p:.3e}")
+            assert e_s <= SLOPE_TOL and e_p <= PUPIL_TOL
+    for bad in (16, 0):
+        with pytest.raises(PwfsError):
+            plan.set_lanes(1, bad)
+    tuned = plan.autotune(1, reps=3)
+    say(f"[gpu] cfg2 B=1 autotune over both forms: {tuned}")
+    assert tuned["lanes"] in (8, 32)
+    plan.close()
+    p64 = pw.Plan(CFG_P64, batch_max=1)
+    with pytest.raises(PwfsError):
+        p64.set_lanes(1, 32)
+    p64.close()
+
+
 def test_schedule_outside_workspace_is_rejected():
     import paper_1607_07624_amd as pw
     from paper_1607_07624_amd._lib import PwfsError
