@@ -236,7 +236,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures a single GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by independent frames with no exchange, see the design notes)",
+              "(the path would shard by independent frames, sources or modulation points with no exchange)",
               file=sys.stderr, flush=True)
         sys.exit(2)
 
