@@ -38,13 +38,13 @@ PEAK_HBM_GBS = 8000.0
 # modulation chunk).  Valid only for the sources with these hashes (the kernels and the plan's
 # modulation order); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "7c292e3589dfbf0ca31749618d366ca7aceefb7d",
-                     "pwfs_common.h": "50d6264b0088e9585ba397ee39d86f4e88d42bd9",
+    "sources_sha1": {"pwfs_kernels.hip": "2528947de5f5910e5488ebf2f3071ab5b5a37a5f",
+                     "pwfs_common.h": "00efe5b82f0650c0dcede32a37c16456f6dce4cb",
                      "pwfs_dft.h": "c25e60bc82b746d087c11d9741edc141a2bed7c1",
-                     "pwfs_api.cpp": "4b5b5298bbf091c2a7c4bc2e8dad321e9154a7fa"},
+                     "pwfs_api.cpp": "f542d00cc1f94bd016e044515fbcac83e0c3f3bc"},
     "batch": 16,
-    "col_pass_kib": {(3, 2): (81256.4, 9600.0), (3, 3): (107718.6, 6400.1), (3, 4): (81807.4, 4800.0),
-                     (3, 6): (81640.3, 3200.0)},
+    "col_pass_kib": {(3, 2): (81251.7, 9600.0), (3, 3): (107714.2, 6400.0), (3, 4): (81808.0, 4800.0),
+                     (3, 6): (81639.1, 3200.0)},
 }
 
 
