@@ -331,78 +331,88 @@ __global__ __launch_bounds__(1024) void slopes_kernel(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// m = alpha R s + beta m.  A block of 4 waves handles RW (4 / WPR) rows; each
-// group of RW rows is split over WPR waves (long rows) whose lanes stride it
-// with float4 (or scalar) loads, each lane keeping RW x BT accumulators, so
-// one load of a slope vector feeds RW rows.  Butterfly reduction inside each
-// wave, then the WPR wave partials are added in wave order through LDS: a
-// fixed summation order, bitwise reproducible.  Rows and frames past the
-// ends are clamped to the last one for loading (in bounds, never stored).
-template <int BT, int VEC, int RW>
-__global__ __launch_bounds__(256) void recon_kernel(const float* __restrict__ R, int M, int ns,
-                                                     const float* __restrict__ s, int B, float alpha,
-                                                     float beta, float* __restrict__ m, int wpr) {
-  __shared__ float part[4][RW * BT];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int groups_per_block = 4 / wpr;
-  const int i0 = (blockIdx.x * groups_per_block + wave / wpr) * RW;
-  const int slice = wave % wpr;
+// m = alpha R s + beta m for B <= 16.  Block = W <= 10 waves over RW rows of
+// R and BT slope vectors; thread t of the block takes the float4 (or scalar)
+// columns j = t, t + 64 W, ... (one pass when the row has at most 640 of
+// them), loads the RW row pieces and the BT vector pieces of a column before
+// any product, and keeps the RW x BT partial sums (NV of them, a power of two
+// <= 64).  Each wave then sums its 64 lanes by recursive halving: at the step
+// of distance o a lane keeps one half of its sums (the upper half when lane
+// bit o is set), adds the partner's copy of that half and hands over the
+// other, so after log2 NV steps lane l holds sum number l >> (6 - log2 NV) of
+// its group of 64 / NV lanes, and a butterfly over the group completes it
+// (63 exchanges for NV = 64 instead of 6 x 64).  The W wave sums are added in
+// wave order through LDS: a fixed summation order, bitwise reproducible.
+// Rows and vectors past the ends are clamped to the last one for loading (in
+// bounds, never stored).
+constexpr int kReconMaxWaves = 10;
+
+template <int BT, int RW, int VEC>
+__global__ __launch_bounds__(64 * kReconMaxWaves) void recon_kernel(const float* __restrict__ R, int M, int ns,
+                                                                    const float* __restrict__ s, int B,
+                                                                    float alpha, float beta,
+                                                                    float* __restrict__ m) {
+  constexpr int NV = RW * BT;
+  static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "RW x BT sums: a power of two <= 64");
+  constexpr int LOG2NV = NV >= 64 ? 6 : NV >= 32 ? 5 : NV >= 16 ? 4 : NV >= 8 ? 3 : NV >= 4 ? 2 : NV >= 2 ? 1 : 0;
+  constexpr int SH = 6 - LOG2NV;
+  using V = typename std::conditional<VEC == 4, float4, float>::type;
+  __shared__ float part[kReconMaxWaves][NV];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int W = (int)(blockDim.x >> 6);
+  const int i0 = blockIdx.x * RW;
   const int b0 = blockIdx.y * BT;
   const int nb = min(BT, B - b0);
-  float acc[RW][BT];
+  const int nv = ns / VEC;
+  float v[NV];
 #pragma unroll
-  for (int rr = 0; rr < RW; ++rr)
+  for (int e = 0; e < NV; ++e) v[e] = 0.f;
+  for (int j = tid; j < nv; j += 64 * W) {
+    V r[RW], x[BT];
 #pragma unroll
-    for (int bb = 0; bb < BT; ++bb) acc[rr][bb] = 0.f;
-  if (i0 < M) {
-    const int nv = ns / VEC;
-    using V = typename std::conditional<VEC == 4, float4, float>::type;
-    const V* sb = reinterpret_cast<const V*>(s + (size_t)b0 * ns);
-    for (int j = slice * 64 + lane; j < nv; j += 64 * wpr) {
-      // All loads are issued before the first product (the fence keeps the
-      // scheduler from interleaving load, wait and use one at a time).
-      V r[RW], x[BT];
+    for (int rr = 0; rr < RW; ++rr)
+      r[rr] = reinterpret_cast<const V*>(R + (size_t)min(i0 + rr, M - 1) * (size_t)ns)[j];
 #pragma unroll
-      for (int rr = 0; rr < RW; ++rr) r[rr] = reinterpret_cast<const V*>(R + (size_t)min(i0 + rr, M - 1) * ns)[j];
-#pragma unroll
-      for (int bb = 0; bb < BT; ++bb) x[bb] = sb[(size_t)min(bb, nb - 1) * nv + j];
-      fence();
-#pragma unroll
-      for (int rr = 0; rr < RW; ++rr)
-#pragma unroll
-        for (int bb = 0; bb < BT; ++bb) {
-          if constexpr (VEC == 4) {
-            acc[rr][bb] = fmaf(r[rr].x, x[bb].x, acc[rr][bb]);
-            acc[rr][bb] = fmaf(r[rr].y, x[bb].y, acc[rr][bb]);
-            acc[rr][bb] = fmaf(r[rr].z, x[bb].z, acc[rr][bb]);
-            acc[rr][bb] = fmaf(r[rr].w, x[bb].w, acc[rr][bb]);
-          } else {
-            acc[rr][bb] = fmaf(r[rr], x[bb], acc[rr][bb]);
-          }
-        }
-    }
-  }
-#pragma unroll
-  for (int rr = 0; rr < RW; ++rr)
-#pragma unroll
-    for (int bb = 0; bb < BT; ++bb) {
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) acc[rr][bb] += __shfl_xor(acc[rr][bb], off);
-    }
-  if (lane == 0) {
+    for (int bb = 0; bb < BT; ++bb)
+      x[bb] = reinterpret_cast<const V*>(s + (size_t)(b0 + min(bb, nb - 1)) * (size_t)ns)[j];
+    fence();
 #pragma unroll
     for (int rr = 0; rr < RW; ++rr)
 #pragma unroll
-      for (int bb = 0; bb < BT; ++bb) part[wave][rr * BT + bb] = acc[rr][bb];
+      for (int bb = 0; bb < BT; ++bb) {
+        float& acc = v[rr * BT + bb];
+        if constexpr (VEC == 4) {
+          acc = fmaf(r[rr].x, x[bb].x, acc);
+          acc = fmaf(r[rr].y, x[bb].y, acc);
+          acc = fmaf(r[rr].z, x[bb].z, acc);
+          acc = fmaf(r[rr].w, x[bb].w, acc);
+        } else {
+          acc = fmaf(r[rr], x[bb], acc);
+        }
+      }
   }
+  static_for<0, LOG2NV>([&](auto st_) {
+    constexpr int st = decltype(st_)::value;
+    constexpr int o = 32 >> st, h = NV >> (st + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int e = 0; e < h; ++e) {
+      const float keep = up ? v[e + h] : v[e];
+      const float give = up ? v[e] : v[e + h];
+      v[e] = keep + __shfl_xor(give, o);
+    }
+  });
+#pragma unroll
+  for (int o = 32 >> LOG2NV; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o);
+  if ((lane & ((1 << SH) - 1)) == 0) part[wave][lane >> SH] = v[0];
   __syncthreads();
-  if (slice == 0 && lane < nb * RW) {
-    const int rr = lane / nb, bl = lane - rr * nb;
+  if (tid < NV) {
+    const int rr = tid / BT, bb = tid - rr * BT;
     const int i = i0 + rr;
-    if (i < M) {
-      float tot = 0.f;
-      for (int w = 0; w < wpr; ++w) tot += part[wave + w][rr * BT + bl];
-      float* mm = m + (size_t)(b0 + bl) * M + i;
+    if (i < M && bb < nb) {
+      float tot = part[0][tid];
+      for (int w = 1; w < W; ++w) tot += part[w][tid];
+      float* mm = m + (size_t)(b0 + bb) * M + i;
       *mm = beta != 0.f ? fmaf(alpha, tot, beta * *mm) : alpha * tot;
     }
   }
@@ -625,13 +635,12 @@ static void launch_recon_bt(const float* R, int M, int ns, const float* s, int B
                             float* m, hipStream_t st) {
   const bool vec = (ns % 4 == 0) && ((uintptr_t)R % 16 == 0) && ((uintptr_t)s % 16 == 0);
   const int nv = vec ? ns / 4 : ns;
-  const int wpr = nv >= 384 ? 4 : (nv >= 192 ? 2 : 1);
-  const int rpb = RW * (4 / wpr);
-  dim3 grid((M + rpb - 1) / rpb, (B + BT - 1) / BT);
+  const int waves = std::max(1, std::min(kReconMaxWaves, (nv + 63) / 64));
+  dim3 grid((M + RW - 1) / RW, (B + BT - 1) / BT);
   if (vec)
-    hipLaunchKernelGGL((recon_kernel<BT, 4, RW>), grid, dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m, wpr);
+    hipLaunchKernelGGL((recon_kernel<BT, RW, 4>), grid, dim3(64 * waves), 0, st, R, M, ns, s, B, alpha, beta, m);
   else
-    hipLaunchKernelGGL((recon_kernel<BT, 1, RW>), grid, dim3(256), 0, st, R, M, ns, s, B, alpha, beta, m, wpr);
+    hipLaunchKernelGGL((recon_kernel<BT, RW, 1>), grid, dim3(64 * waves), 0, st, R, M, ns, s, B, alpha, beta, m);
 }
 
 hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, float alpha,
@@ -641,14 +650,16 @@ hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, fl
                        alpha, beta, m);
     return hipGetLastError();
   }
+  // Four rows per block at every batch size: the block's 4 x BT sums come
+  // out of the halving steps in one pass.
   if (B <= 1)
-    launch_recon_bt<1, 1>(R, M, ns, s, B, alpha, beta, m, st);
+    launch_recon_bt<1, 4>(R, M, ns, s, B, alpha, beta, m, st);
   else if (B <= 4)
-    launch_recon_bt<4, 1>(R, M, ns, s, B, alpha, beta, m, st);
+    launch_recon_bt<4, 4>(R, M, ns, s, B, alpha, beta, m, st);
   else if (B <= 8)
-    launch_recon_bt<8, 2>(R, M, ns, s, B, alpha, beta, m, st);
+    launch_recon_bt<8, 4>(R, M, ns, s, B, alpha, beta, m, st);
   else
-    launch_recon_bt<16, 2>(R, M, ns, s, B, alpha, beta, m, st);
+    launch_recon_bt<16, 4>(R, M, ns, s, B, alpha, beta, m, st);
   return hipGetLastError();
 }
 

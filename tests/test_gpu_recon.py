@@ -8,7 +8,9 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("M,ns,B", [(600, 2544, 1), (600, 2544, 16), (37, 101, 3), (25600, 600, 1),
-                                    (5, 70, 9), (600, 2544, 17), (600, 25600, 256), (70, 33, 100)])
+                                    (5, 70, 9), (600, 2544, 8), (602, 2545, 16), (1001, 14464, 16),
+                                    (3, 4, 2), (2, 1, 1),
+                                    (600, 2544, 17), (600, 25600, 256), (70, 33, 100)])
 @pytest.mark.parametrize("alpha,beta", [(1.0, 0.0), (0.4, 1.0), (-1.0, 1.0)])
 def test_recon_apply_matches_fp64(M, ns, B, alpha, beta):
     import paper_1607_07624_amd as pw
