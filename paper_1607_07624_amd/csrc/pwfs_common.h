@@ -13,6 +13,15 @@ namespace pwfs {
 // field loads of later phases over the register-resident transforms.
 __device__ __forceinline__ void fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// Global-address-space views (builtin vector types, which copy across address
+// spaces) for pointers that pass an empty asm: a pointer laundered that way
+// in the generic space would give flat accesses, and one pending flat access
+// turns every later wait into a full drain of the memory counter.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
+typedef __attribute__((address_space(1))) f32x2 g_f32x2;
+
 // LDS copies of the pyramid tables are padded so that a ds_read of a quad's
 // four lanes (mix table, rows of 2E values) or of a team's two quads (input
 // and output tables, halves of P values) spreads over distinct banks: both

@@ -91,6 +91,24 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
   const int yb = blockIdx.x * 32;
   const int a0 = blockIdx.y * a_chunk;
   const size_t fr = blockIdx.z;
+  // Tilt tables, 3 P / 2 16-byte words (in_a quad 0 half, in_a quad 1 half,
+  // f_a), loaded one x tilt ahead so that the load latency hides behind the
+  // current tilt's transforms.  Thread t moves word t mod 3 P / 2 (threads
+  // past the table repeat a word: same value, same address), and the last
+  // tilt reloads itself, so there is no branch and the wait before the LDS
+  // write covers that one load, not the stores of the previous tilt.
+  constexpr int H = P / 2;
+  const int tw = tid % (3 * H);
+  const int tab_part = tw / H, tab_w = tw - (tw / H) * H;
+  u32x4* const tab_dst = reinterpret_cast<u32x4*>(
+      tab_part == 0 ? s_in : (tab_part == 1 ? s_in + TabLds<E>::QO : s_f)) + tab_w;
+  auto tab_src = [&](int ia) {
+    const cpx* base = tab_part < 2 ? in_a + (size_t)ia * 2 * P + tab_part * P : f_a + (size_t)ia * P;
+    return (g_u32x4*)base + tab_w;
+  };
+  // First tilt's word: issued before the field rows, whose wait covers it
+  // (a0 < n_a for every block of the grid).
+  u32x4 tab_next = *tab_src(a0);
   // 32 field rows (contiguous in HBM) -> LDS rows of stride LDP, 16 bytes per move.
   // 32 P / 2 = 256 (P / 16) words per block, all loads issued before the LDS writes.
   const uint4* src = reinterpret_cast<const uint4*>(fieldg + (fr * (size_t)P + yb) * (size_t)P);
@@ -114,10 +132,14 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
   const int r = wave * 8 + t;                     // row within the block
   const cpx* frow = field + r * LDP + l;
   const int y = yb + r;
+  auto tab_ptr = tab_src(min(a0 + 1, a1 - 1));   // global address space: global loads
+  // The first word is consumed here, on every path into the loop, so the
+  // loop's own wait counts only the one load in flight across its stores.
+  asm volatile("" ::"v"(tab_next.x), "v"(tab_next.y), "v"(tab_next.z), "v"(tab_next.w));
   for (int ia = a0; ia < a1; ++ia) {
     __syncthreads();
-    stage_quads<E>(s_in, in_a + (size_t)ia * 2 * P, tid);
-    copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
+    *tab_dst = tab_next;
+    tab_next = *tab_ptr;
     __syncthreads();
     const cpx* tin = s_in + q * TabLds<E>::QO + l;
     const cpx* tf = s_f + q * TabLds<E>::QO + l;
@@ -127,13 +149,20 @@ __global__ __launch_bounds__(256) void row_pass_kernel(
     // Element (x' = qP + l + 4m, y) sits at base + (m >> 1) 8P + (m & 1) 16
     // (see rw_index); each address is formed just before its store so the
     // compiler does not keep E 64-bit addresses live across the transforms.
-    cpx* out = Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P) + rw_index(q * P + l, y, P);
+    // The pointer is in the global address space before it passes the asm,
+    // so the stores are global, not flat: a pending flat access would turn
+    // the wait for the next tilt's table load into a wait for these stores.
+    g_f32x2* out = (g_f32x2*)Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P) + rw_index(q * P + l, y, P);
+    // Next tilt's table address, formed before the stores: registers written
+    // after them could be ones a store still reads, which costs a full wait.
+    tab_ptr = tab_src(min(ia + 2, a1 - 1));
+    asm volatile("" : "+v"(tab_ptr));
     fence();
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
-      cpx* o = out + (size_t)((m >> 1) * 8 * P + (m & 1) * 16);
+      g_f32x2* o = out + (size_t)((m >> 1) * 8 * P + (m & 1) * 16);
       asm volatile("" : "+v"(o));
-      *o = v[m];
+      *o = f32x2{v[m].re, v[m].im};
     });
   }
 }
@@ -493,6 +522,7 @@ hipError_t launch_field(const MeasureArgs& a, hipStream_t st) {
 
 template <int E>
 static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
+  if (a.a_chunk < 1 || a.n_a < 1) return hipErrorInvalidValue;   // every block needs a0 < n_a
   hipError_t e = launch_field(a, st);
   if (e != hipSuccess) return e;
   dim3 grid(a.P / 32, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);

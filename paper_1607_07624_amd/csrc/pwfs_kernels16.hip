@@ -128,6 +128,24 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
   const int yb = blockIdx.x * 8;
   const int a0 = blockIdx.y * a_chunk;
   const size_t fr = blockIdx.z;
+  // Up to n_pupil 170 the tilt tables (3 P / 2 16-byte words) take one word
+  // per thread and are loaded one x tilt ahead, as in the 8-lane row pass;
+  // at n_pupil 480 the extra registers would cost a wave per SIMD, so those
+  // tables are copied at the top of each tilt.
+  constexpr int H = P / 2;
+  constexpr bool kPrefetch = 3 * H <= 256;
+  const int tw3 = tid % (3 * H);
+  const int tab_part = tw3 / H, tab_w = tw3 - (tw3 / H) * H;
+  u32x4* const tab_dst = reinterpret_cast<u32x4*>(
+      tab_part == 0 ? s_in : (tab_part == 1 ? s_in + T::QO : s_f)) + tab_w;
+  auto tab_src = [&](int ia) {
+    const cpx* base = tab_part < 2 ? in_a + (size_t)ia * 2 * P + tab_part * P : f_a + (size_t)ia * P;
+    return (g_u32x4*)base + tab_w;
+  };
+  u32x4 tab_next = {0u, 0u, 0u, 0u};
+  // First tilt's word: issued before the field rows, whose wait covers it
+  // (a0 < n_a for every block of the grid).
+  if constexpr (kPrefetch) tab_next = *tab_src(a0);
   // 8 field rows (contiguous in HBM, 4 P 16-byte words) -> LDS rows of stride
   // LDP; every load is issued before the first LDS write.
   {
@@ -163,24 +181,41 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
   const cpx* tf = s_f + q * T::QO + xl;
   const float sA = (l2 & 2) ? -1.f : 1.f, sB = (l2 & 1) ? -1.f : 1.f;
   const bool l3 = l2 == 3;
+  auto tab_ptr = tab_src(min(a0 + 1, a1 - 1));   // global address space: global loads
+  // The first word is consumed here, on every path into the loop, so the
+  // loop's own wait counts only the one load in flight across its stores.
+  if constexpr (kPrefetch) asm volatile("" ::"v"(tab_next.x), "v"(tab_next.y), "v"(tab_next.z), "v"(tab_next.w));
   for (int ia = a0; ia < a1; ++ia) {
     __syncthreads();
-    copy16(s_in, in_a + (size_t)ia * 2 * P, P / 2, tid, 256);
-    copy16(s_in + T::QO, in_a + (size_t)ia * 2 * P + P, P / 2, tid, 256);
-    copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
+    if constexpr (kPrefetch) {
+      *tab_dst = tab_next;
+      tab_next = *tab_ptr;
+    } else {
+      copy16(s_in, in_a + (size_t)ia * 2 * P, P / 2, tid, 256);
+      copy16(s_in + T::QO, in_a + (size_t)ia * 2 * P + P, P / 2, tid, 256);
+      copy16(s_f, f_a + (size_t)ia * P, P / 2, tid, 256);
+    }
     __syncthreads();
     cpx v[E];
     line_op16<E>(v, [&](int m) { return cmul(frow[16 * m], tin[16 * m]); }, [&](int m) { return frow[16 * m]; },
                  [&](int m) { return tf[16 * m]; }, ml, tl, ow, sA, sB, l3);
     // Element (x' = qP + xl + 16 m, y): consecutive m are 16 P apart in the
     // intermediate layout (two 8-column groups); addresses formed just in time.
-    cpx* out = Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P) + rw_index(q * P + xl, y, P);
+    // Global (not flat) stores: the pointer is in the global address space
+    // before it passes the asm.
+    g_f32x2* out = (g_f32x2*)Rw + (fr * (size_t)n_a + ia) * (size_t)(2 * P * P) + rw_index(q * P + xl, y, P);
+    // Next tilt's table address, formed before the stores (registers written
+    // after them could be ones a store still reads, which costs a full wait).
+    if constexpr (kPrefetch) {
+      tab_ptr = tab_src(min(ia + 2, a1 - 1));
+      asm volatile("" : "+v"(tab_ptr));
+    }
     fence();
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
-      cpx* o = out + (size_t)m * 16 * P;
+      g_f32x2* o = out + (size_t)m * 16 * P;
       asm volatile("" : "+v"(o));
-      *o = v[m];
+      *o = f32x2{v[m].re, v[m].im};
     });
   }
 }
@@ -347,6 +382,7 @@ template <int E>
 static hipError_t launch_rows16_e(const MeasureArgs& a, hipStream_t st) {
   hipError_t e = launch_field(a, st);
   if (e != hipSuccess) return e;
+  if (a.a_chunk < 1 || a.n_a < 1) return hipErrorInvalidValue;   // every block needs a0 < n_a
   dim3 grid(a.P / 8, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
   hipLaunchKernelGGL(row_pass16_kernel<E>, grid, dim3(256), 0, st, a.field, a.in_a, a.f_a, a.mid, a.tw16, a.outw,
                      a.Rw, a.n_a, a.a_chunk);
