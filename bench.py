@@ -38,13 +38,13 @@ PEAK_HBM_GBS = 8000.0
 # modulation chunk).  Valid only for the sources with these hashes (the kernels and the plan's
 # modulation order); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "2528947de5f5910e5488ebf2f3071ab5b5a37a5f",
-                     "pwfs_common.h": "00efe5b82f0650c0dcede32a37c16456f6dce4cb",
+    "sources_sha1": {"pwfs_kernels.hip": "8842f9529f29361814f6a008bace05cb0ab18819",
+                     "pwfs_common.h": "025f50a7adaee45f6fb1b6cf1add932e493ee268",
                      "pwfs_dft.h": "c25e60bc82b746d087c11d9741edc141a2bed7c1",
                      "pwfs_api.cpp": "f542d00cc1f94bd016e044515fbcac83e0c3f3bc"},
     "batch": 16,
-    "col_pass_kib": {(3, 2): (81251.7, 9600.0), (3, 3): (107714.2, 6400.0), (3, 4): (81808.0, 4800.0),
-                     (3, 6): (81639.1, 3200.0)},
+    "col_pass_kib": {(3, 2): (81243.2, 9600.0), (3, 3): (107711.8, 6400.0), (3, 4): (81795.7, 4800.0),
+                     (3, 6): (81638.2, 3200.0)},
 }
 
 
