@@ -188,6 +188,37 @@ def test_schedules_change_only_rounding_cfg2():
     plan.close()
 
 
+@pytest.mark.parametrize("cfg,lanes", [(CFG1, 8), (CFG2, 8), (CFG2, 32), (CFG_P128, 32), (CFG_P480B8, 32)],
+                         ids=["p32", "p160_quads", "p160_teams32", "p128", "p480"])
+def test_row_pass_chunking_is_bit_exact(cfg, lanes):
+    """Each x tilt's row transform is computed on its own, so the number of
+    x tilts per row-pass block (with the tilt tables loaded one tilt ahead,
+    the last tilt of a block reloading itself) must not change a single bit
+    of the result: every a_chunk, with the column split fixed, gives the
+    slopes of a_chunk = 1 exactly."""
+    import paper_1607_07624_amd as pw
+    torch = torch_cuda()
+    B = 2
+    atmo = ATMO3 if cfg.n_pupil == 480 else ATMO2
+    opd, _ = open_loop_batch(cfg, atmo, [60, 61], r0_range=CFG4_R0_RANGE if cfg is CFG2 else None)
+    plan = pw.Plan(cfg, batch_max=B)
+    if lanes == 32 and cfg.n_pupil == 160:
+        plan.set_lanes(B, 32)
+    d = torch.from_numpy(np.ascontiguousarray(opd)).cuda()
+    n_a = cfg.n_mod // 2 + 1
+    k_chunk = 2 if cfg.n_mod >= 2 else 1
+    plan.set_schedule(B, 1, k_chunk)
+    ref = _slopes_with(plan, d)
+    for a in sorted({2, 3, 4, 7, n_a - 1, n_a} - {0, 1}):
+        if a > n_a:
+            continue
+        plan.set_schedule(B, a, k_chunk)
+        got = _slopes_with(plan, d)
+        say(f"[gpu] {cfg.name} lanes {lanes}: a_chunk {a} of {n_a} bit-exact {np.array_equal(got, ref)}")
+        assert np.array_equal(got, ref)
+    plan.close()
+
+
 def test_cfg2_32_lane_form():
     """At P = 160 both lane forms exist: 32-lane teams (16-lane projections,
     10 samples per lane) meet the oracle gates like the default 8-lane quads,
