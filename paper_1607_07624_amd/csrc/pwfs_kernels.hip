@@ -36,6 +36,7 @@
 // so that both the row pass's stores and the column pass's loads touch
 // 128-256 contiguous bytes per instruction.
 #include "pwfs_common.h"
+#include "pwfs_field.h"
 #include "pwfs_launch.h"
 
 #include <algorithm>
@@ -45,28 +46,12 @@
 namespace pwfs {
 
 // ---------------------------------------------------------------------------
-// Pupil field A exp(i phi), phi = 2 pi opd 1e-9 / lambda formed and reduced
-// modulo 2 pi in FP64, then FP32 sincos; once per frame.
-// (fp32_phase, precision study only: phase formed in FP32 and passed to
-// sincosf unreduced.)
+// Pupil field A exp(i phi) of every pixel (pupil_field); once per frame.
 __global__ __launch_bounds__(256) void field_kernel(const float* __restrict__ opd, const float* __restrict__ amp,
                                                     double kphase, int fp32_phase, int PP, size_t n,
                                                     cpx* __restrict__ field) {
-  constexpr double two_pi = 6.283185307179586476925286766559;
-  constexpr double inv_two_pi = 0.15915494309189533576888376337251;
-  const float kphase_f = (float)kphase;
-  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    float sn, cs;
-    if (fp32_phase) {
-      sincosf(opd[i] * kphase_f, &sn, &cs);
-    } else {
-      const double th = (double)opd[i] * kphase;
-      const double red = fma(-rint(th * inv_two_pi), two_pi, th);
-      sincosf((float)red, &sn, &cs);
-    }
-    const float A = amp[i % PP];
-    field[i] = {A * cs, A * sn};
-  }
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    field[i] = pupil_field(opd[i], amp[i % PP], kphase, fp32_phase);
 }
 
 // Row pass.  Block = 4 waves = 32 pupil rows of one frame (8 rows per wave),

@@ -1,5 +1,6 @@
 // pwfs_kernels16.hip -- pyramid line kernels for long lines, P = 16 E (P = 128, 480), gfx950.
 #include "pwfs_common.h"
+#include "pwfs_field.h"
 #include "pwfs_launch.h"
 
 #include <algorithm>
@@ -108,12 +109,17 @@ __device__ __forceinline__ void line_op16(cpx (&v)[E], LoadIn&& load_in, LoadX&&
 }
 
 // Row pass, long lines.  Block = 4 waves = 8 pupil rows of one frame (two
-// 32-lane teams per wave), looping over a chunk of distinct x tilts.
-template <int E>
+// 32-lane teams per wave), looping over a chunk of distinct x tilts.  With
+// kField the block forms the field of its 8 rows from the OPD and the
+// amplitude itself (pupil_field, the arithmetic of field_kernel) instead of
+// reading it from a field pass: at n_pupil 128 and 160 the 1,024-1,280
+// sincos per block cost less than a separate launch, which matters for the
+// single-frame calls this form serves; at 480 the field pass stays.
+template <int E, bool kField>
 __global__ __launch_bounds__(256) void row_pass16_kernel(
-    const cpx* __restrict__ fieldg, const cpx* __restrict__ in_a, const cpx* __restrict__ f_a,
-    const cpx* __restrict__ mid, const cpx* __restrict__ tw, const cpx* __restrict__ outw, cpx* __restrict__ Rw,
-    int n_a, int a_chunk) {
+    const cpx* __restrict__ fieldg, const float* __restrict__ opd, const float* __restrict__ amp, double kphase,
+    int fp32_phase, const cpx* __restrict__ in_a, const cpx* __restrict__ f_a, const cpx* __restrict__ mid,
+    const cpx* __restrict__ tw, const cpx* __restrict__ outw, cpx* __restrict__ Rw, int n_a, int a_chunk) {
   using T = Tab16<E>;
   constexpr int P = T::P;
   __shared__ __align__(16) cpx field[8 * T::LDP];
@@ -151,19 +157,45 @@ __global__ __launch_bounds__(256) void row_pass16_kernel(
   {
     constexpr int NW = 4 * P;
     constexpr int NPT = (NW + 255) / 256;
-    const uint4* src = reinterpret_cast<const uint4*>(fieldg + (fr * (size_t)P + yb) * (size_t)P);
     // The tail's surplus lanes load word NW - 1 again and store nothing: every
     // element of w is defined, so w stays in registers.
-    uint4 w[NPT];
+    if constexpr (kField) {
+      // Word e = pixels 2 e and 2 e + 1 of the 8 rows (row e / (P / 2)).
+      const float* po = opd + (fr * (size_t)P + yb) * (size_t)P;
+      const float* pa = amp + (size_t)yb * P;
+      float o[NPT][2], am[NPT][2];
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) w[i] = src[min(tid + 256 * i, NW - 1)];
-    fence();
+      for (int i = 0; i < NPT; ++i) {
+        const int e = min(tid + 256 * i, NW - 1);
+        o[i][0] = po[2 * e];
+        o[i][1] = po[2 * e + 1];
+        am[i][0] = pa[2 * e];
+        am[i][1] = pa[2 * e + 1];
+      }
+      fence();
 #pragma unroll
-    for (int i = 0; i < NPT; ++i) {
-      const int e = tid + 256 * i;
-      if (e < NW) {
-        const int r = e / (P / 2), c2 = e - r * (P / 2);
-        *reinterpret_cast<uint4*>(field + r * T::LDP + 2 * c2) = w[i];
+      for (int i = 0; i < NPT; ++i) {
+        const int e = tid + 256 * i;
+        if (e < NW) {
+          const int r = e / (P / 2), c2 = e - r * (P / 2);
+          cpx* f = field + r * T::LDP + 2 * c2;
+          f[0] = pupil_field(o[i][0], am[i][0], kphase, fp32_phase);
+          f[1] = pupil_field(o[i][1], am[i][1], kphase, fp32_phase);
+        }
+      }
+    } else {
+      const uint4* src = reinterpret_cast<const uint4*>(fieldg + (fr * (size_t)P + yb) * (size_t)P);
+      uint4 w[NPT];
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) w[i] = src[min(tid + 256 * i, NW - 1)];
+      fence();
+#pragma unroll
+      for (int i = 0; i < NPT; ++i) {
+        const int e = tid + 256 * i;
+        if (e < NW) {
+          const int r = e / (P / 2), c2 = e - r * (P / 2);
+          *reinterpret_cast<uint4*>(field + r * T::LDP + 2 * c2) = w[i];
+        }
       }
     }
   }
@@ -380,12 +412,15 @@ __global__ __launch_bounds__(256) void pupil_reduce_cols_kernel(const float* __r
 
 template <int E>
 static hipError_t launch_rows16_e(const MeasureArgs& a, hipStream_t st) {
-  hipError_t e = launch_field(a, st);
-  if (e != hipSuccess) return e;
+  constexpr bool kField = E <= 10;                // the field formed in the row pass (n_pupil 128, 160)
   if (a.a_chunk < 1 || a.n_a < 1) return hipErrorInvalidValue;   // every block needs a0 < n_a
+  if constexpr (!kField) {
+    hipError_t e = launch_field(a, st);
+    if (e != hipSuccess) return e;
+  }
   dim3 grid(a.P / 8, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
-  hipLaunchKernelGGL(row_pass16_kernel<E>, grid, dim3(256), 0, st, a.field, a.in_a, a.f_a, a.mid, a.tw16, a.outw,
-                     a.Rw, a.n_a, a.a_chunk);
+  hipLaunchKernelGGL((row_pass16_kernel<E, kField>), grid, dim3(256), 0, st, a.field, a.opd, a.amp, a.kphase,
+                     a.fp32_phase, a.in_a, a.f_a, a.mid, a.tw16, a.outw, a.Rw, a.n_a, a.a_chunk);
   return hipGetLastError();
 }
 
