@@ -311,18 +311,33 @@ __global__ __launch_bounds__(256) void pupil_reduce_kernel(const float* __restri
 
 // Slopes.  One block of 1024 threads per frame: mean total flux over the
 // valid subapertures (fixed-order tree), then reference-subtracted slopes.
+// The four intensities of a thread's first two subapertures (all of them up
+// to 2048 valid ones) stay in registers between the two passes, so the
+// second pass does not repeat the dependent index-then-pixel loads.
 __global__ __launch_bounds__(1024) void slopes_kernel(const float* __restrict__ pupils, int S,
                                                       const int* __restrict__ valid, int nv,
                                                       const float* __restrict__ sref, int norm_mode,
                                                       float* __restrict__ slopes) {
+  constexpr int KEEP = 2;
   __shared__ float red[1024];
   const int tid = threadIdx.x;
   const size_t fr = blockIdx.x;
   const size_t SS = (size_t)S * S;
   const float* pp = pupils + fr * 4 * SS;
+  float ik[KEEP][4];
+#pragma unroll
+  for (int r = 0; r < KEEP; ++r) {
+    const int v = tid + 1024 * r;
+    const size_t j = (size_t)valid[min(v, nv - 1)];   // clamped for loading, used only when v < nv
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ik[r][c] = pp[c * SS + j];
+  }
   float loc = 0.f;
   if (norm_mode == 0) {
-    for (int v = tid; v < nv; v += 1024) {
+#pragma unroll
+    for (int r = 0; r < KEEP; ++r)
+      if (tid + 1024 * r < nv) loc += (ik[r][0] + ik[r][1]) + (ik[r][2] + ik[r][3]);
+    for (int v = tid + 1024 * KEEP; v < nv; v += 1024) {
       const size_t j = (size_t)valid[v];
       loc += (pp[j] + pp[SS + j]) + (pp[2 * SS + j] + pp[3 * SS + j]);
     }
@@ -335,12 +350,17 @@ __global__ __launch_bounds__(1024) void slopes_kernel(const float* __restrict__ 
   }
   const float mean_flux = red[0] / (float)nv;
   float* so = slopes + fr * 2 * (size_t)nv;
-  for (int v = tid; v < nv; v += 1024) {
-    const size_t j = (size_t)valid[v];
-    const float i0 = pp[j], i1 = pp[SS + j], i2 = pp[2 * SS + j], i3 = pp[3 * SS + j];
+  auto emit = [&](int v, float i0, float i1, float i2, float i3) {
     const float n = norm_mode ? ((i0 + i1) + (i2 + i3)) : mean_flux;
     so[v] = ((i1 + i3) - (i0 + i2)) / n - sref[v];
     so[nv + v] = ((i2 + i3) - (i0 + i1)) / n - sref[nv + v];
+  };
+#pragma unroll
+  for (int r = 0; r < KEEP; ++r)
+    if (tid + 1024 * r < nv) emit(tid + 1024 * r, ik[r][0], ik[r][1], ik[r][2], ik[r][3]);
+  for (int v = tid + 1024 * KEEP; v < nv; v += 1024) {
+    const size_t j = (size_t)valid[v];
+    emit(v, pp[j], pp[SS + j], pp[2 * SS + j], pp[3 * SS + j]);
   }
 }
 
