@@ -38,13 +38,14 @@ PEAK_HBM_GBS = 8000.0
 # modulation chunk).  Valid only for the sources with these hashes (the kernels and the plan's
 # modulation order); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "8842f9529f29361814f6a008bace05cb0ab18819",
+    "sources_sha1": {"pwfs_kernels.hip": "32dc90cebc32d673e0456210789f733fec7330b5",
+                     "pwfs_field.h": "bc1faa09406794b7ad671c337fa21b1f47710d8a",
                      "pwfs_common.h": "025f50a7adaee45f6fb1b6cf1add932e493ee268",
                      "pwfs_dft.h": "c25e60bc82b746d087c11d9741edc141a2bed7c1",
                      "pwfs_api.cpp": "f542d00cc1f94bd016e044515fbcac83e0c3f3bc"},
     "batch": 16,
-    "col_pass_kib": {(3, 2): (81243.2, 9600.0), (3, 3): (107711.8, 6400.0), (3, 4): (81795.7, 4800.0),
-                     (3, 6): (81638.2, 3200.0)},
+    "col_pass_kib": {(3, 2): (81250.1, 9600.0), (3, 3): (107704.2, 6400.0), (3, 4): (81809.8, 4800.0),
+                     (3, 6): (81642.0, 3200.0)},
 }
 
 
