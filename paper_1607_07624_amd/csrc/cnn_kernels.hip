@@ -93,6 +93,102 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int kc, floa
   }
 }
 
+// Small-M products (M <= 16 rows of A, both operands contiguous in k: the
+// fully connected layers at the loop's batch sizes), C(i, j) = sum_k
+// A[i][k] B[j][k].  Block = W <= 8 waves over RW = 4 columns j and BT rows
+// i; thread t takes the 8-element (16-byte) k groups t, t + 64 W, ..., loads
+// the RW weight rows' and the BT activation rows' groups before any product,
+// and keeps the RW x BT sums.  Each wave adds its 64 lanes by recursive
+// halving (a lane keeps half of its sums and trades the other half at each
+// step), the W wave sums are added in wave order through LDS (fixed order),
+// then the epilogue of gemm_bf16_kernel.  Columns and rows past the ends are
+// clamped to the last one for loading (in bounds, never stored).  The
+// weights stream from HBM once, instead of through 64 x 64 MFMA tiles that
+// are 1 / 64 full at one row and need a split-K pass to fill the GPU.
+constexpr int kGemvMaxWaves = 8;
+
+template <int BT>
+__global__ __launch_bounds__(64 * kGemvMaxWaves) void gemv_bf16_kernel(GemmArgs g) {
+  constexpr int RW = 4;
+  constexpr int NV = RW * BT;
+  constexpr int LOG2NV = NV >= 64 ? 6 : NV >= 32 ? 5 : NV >= 16 ? 4 : NV >= 8 ? 3 : NV >= 4 ? 2 : NV >= 2 ? 1 : 0;
+  constexpr int SH = 6 - LOG2NV;
+  static_assert((NV & (NV - 1)) == 0 && NV <= 64, "RW x BT sums: a power of two <= 64");
+  __shared__ float wsum[kGemvMaxWaves][NV];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int W = (int)(blockDim.x >> 6);
+  const int j0 = blockIdx.x * RW, i0 = blockIdx.y * BT;
+  const int ng = g.K / 8;
+  float v[NV];
+#pragma unroll
+  for (int e = 0; e < NV; ++e) v[e] = 0.f;
+  for (int q = tid; q < ng; q += 64 * W) {
+    uint4 wr[RW], ar[BT];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+      wr[r] = reinterpret_cast<const uint4*>(g.B + (long)min(j0 + r, g.N - 1) * g.sbn)[q];
+#pragma unroll
+    for (int b = 0; b < BT; ++b)
+      ar[b] = reinterpret_cast<const uint4*>(g.A + (long)min(i0 + b, g.M - 1) * g.sam)[q];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      float wl[RW], wh[RW], al[BT], ah[BT];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        const uint32_t u = h == 0 ? wr[r].x : h == 1 ? wr[r].y : h == 2 ? wr[r].z : wr[r].w;
+        wl[r] = __uint_as_float(u << 16);
+        wh[r] = __uint_as_float(u & 0xffff0000u);
+      }
+#pragma unroll
+      for (int b = 0; b < BT; ++b) {
+        const uint32_t u = h == 0 ? ar[b].x : h == 1 ? ar[b].y : h == 2 ? ar[b].z : ar[b].w;
+        al[b] = __uint_as_float(u << 16);
+        ah[b] = __uint_as_float(u & 0xffff0000u);
+      }
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int b = 0; b < BT; ++b) {
+          float& acc = v[r * BT + b];
+          acc = fmaf(wl[r], al[b], acc);
+          acc = fmaf(wh[r], ah[b], acc);
+        }
+    }
+  }
+#pragma unroll
+  for (int st = 0; st < LOG2NV; ++st) {
+    const int o = 32 >> st, hh = NV >> (st + 1);
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int e = 0; e < NV / 2; ++e) {
+      if (e < hh) {
+        const float keep = up ? v[e + hh] : v[e];
+        const float give = up ? v[e] : v[e + hh];
+        v[e] = keep + __shfl_xor(give, o);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32 >> LOG2NV; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o);
+  if ((lane & ((1 << SH) - 1)) == 0) wsum[wave][lane >> SH] = v[0];
+  __syncthreads();
+  if (tid < NV) {
+    const int r = tid / BT, b = tid - r * BT;
+    const int i = i0 + b, j = j0 + r;
+    if (i < g.M && j < g.N) {
+      float x = wsum[0][tid];
+      for (int w = 1; w < W; ++w) x += wsum[w][tid];
+      if (g.bias) x += g.bias[j];
+      x *= g.alpha;
+      if (g.C && g.beta != 0.f) x = fmaf(g.beta, g.C[(long)i * g.ldc + j], x);
+      if (g.relu) x = fmaxf(x, 0.f);
+      if (g.C) g.C[(long)i * g.ldc + j] = x;
+      if (g.Cb) g.Cb[(long)i * g.ldcb + j] = f2bf(x);
+    }
+  }
+}
+
 // Sum of split-K partials in split order, then the epilogue.
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int splits, const float* __restrict__ part) {
   const size_t idx = blockIdx.x * (size_t)256 + threadIdx.x;
@@ -283,8 +379,26 @@ __global__ __launch_bounds__(256) void prepare_kernel(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 static unsigned grid_for(size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 8192); }
 
+template <int BT>
+static hipError_t launch_gemv(const GemmArgs& g, hipStream_t st) {
+  const int ng = g.K / 8;
+  const int waves = std::max(1, std::min(kGemvMaxWaves, (ng + 63) / 64));
+  hipLaunchKernelGGL(gemv_bf16_kernel<BT>, dim3((g.N + 3) / 4, (g.M + BT - 1) / BT), dim3(64 * waves), 0, st, g);
+  return hipGetLastError();
+}
+
 hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
+  // Up to 16 rows with both operands contiguous in k in 16-byte groups: the
+  // matrix-vector kernel.
+  const bool gemv = g.M <= 16 && g.sak == 1 && g.sbk == 1 && g.K % 8 == 0 && g.sam % 8 == 0 && g.sbn % 8 == 0 &&
+                    (uintptr_t)g.A % 16 == 0 && (uintptr_t)g.B % 16 == 0;
+  if (gemv) {
+    if (g.M == 1) return launch_gemv<1>(g, st);
+    if (g.M <= 4) return launch_gemv<4>(g, st);
+    if (g.M <= 8) return launch_gemv<8>(g, st);
+    return launch_gemv<16>(g, st);
+  }
   const int bx = (g.N + 63) / 64, by = (g.M + 63) / 64;
   const long blocks = (long)bx * by;
   int splits = 1;
