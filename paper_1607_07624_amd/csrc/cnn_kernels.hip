@@ -93,10 +93,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int kc, floa
   }
 }
 
-// Small-M products (M <= 16 rows of A, both operands contiguous in k: the
-// fully connected layers at the loop's batch sizes), C(i, j) = sum_k
-// A[i][k] B[j][k].  Block = W <= 8 waves over RW = 4 columns j and BT rows
-// i; thread t takes the 8-element (16-byte) k groups t, t + 64 W, ..., loads
+// Small-M products (at most 128 rows of A, both operands contiguous in k:
+// the fully connected layers at the loop's batch sizes, the later
+// convolutions of one frame), C(i, j) = sum_k A[i][k] B[j][k].  Block =
+// W <= 8 waves over RW = 4 columns j and BT <= 16 rows i (grid over both); thread t takes the 8-element (16-byte) k groups t, t + 64 W, ..., loads
 // the RW weight rows' and the BT activation rows' groups before any product,
 // and keeps the RW x BT sums.  Each wave adds its 64 lanes by recursive
 // halving (a lane keeps half of its sums and trades the other half at each
@@ -389,9 +389,10 @@ static hipError_t launch_gemv(const GemmArgs& g, hipStream_t st) {
 
 hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
-  // Up to 16 rows with both operands contiguous in k in 16-byte groups: the
-  // matrix-vector kernel.
-  const bool gemv = g.M <= 16 && g.sak == 1 && g.sbk == 1 && g.K % 8 == 0 && g.sam % 8 == 0 && g.sbn % 8 == 0 &&
+  // Up to 128 rows with both operands contiguous in k in 16-byte groups (the
+  // fully connected layers, and the second and third convolutions of a single
+  // frame): the matrix-vector kernel, one launch and no split-K pass.
+  const bool gemv = g.M <= 128 && g.sak == 1 && g.sbk == 1 && g.K % 8 == 0 && g.sam % 8 == 0 && g.sbn % 8 == 0 &&
                     (uintptr_t)g.A % 16 == 0 && (uintptr_t)g.B % 16 == 0;
   if (gemv) {
     if (g.M == 1) return launch_gemv<1>(g, st);
