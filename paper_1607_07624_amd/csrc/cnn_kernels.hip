@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "cnn_launch.h"
 
@@ -93,9 +94,9 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int kc, floa
   }
 }
 
-// Small-M products (at most 128 rows of A, both operands contiguous in k:
-// the fully connected layers at the loop's batch sizes, the later
-// convolutions of one frame), C(i, j) = sum_k A[i][k] B[j][k].  Block =
+// Small-M products (at most 512 rows of A, both operands contiguous in k:
+// the fully connected layers at the loop's batch sizes, the convolutions of
+// one frame), C(i, j) = sum_k A[i][k] B[j][k].  Block =
 // W <= 8 waves over RW = 4 columns j and BT <= 16 rows i (grid over both); thread t takes the 8-element (16-byte) k groups t, t + 64 W, ..., loads
 // the RW weight rows' and the BT activation rows' groups before any product,
 // and keeps the RW x BT sums.  Each wave adds its 64 lanes by recursive
@@ -107,7 +108,15 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int kc, floa
 // are 1 / 64 full at one row and need a split-K pass to fill the GPU.
 constexpr int kGemvMaxWaves = 8;
 
-template <int BT>
+template <class V>
+__device__ __forceinline__ uint32_t vword(const V& v, int h) {
+  if constexpr (sizeof(V) == 16) return h == 0 ? v.x : h == 1 ? v.y : h == 2 ? v.z : v.w;
+  else return h == 0 ? v.x : v.y;
+}
+
+// GW: k elements per load (8: 16-byte groups; 4: 8-byte groups, for K a
+// multiple of 4 only, such as the first convolution's 36).
+template <int BT, int GW>
 __global__ __launch_bounds__(64 * kGemvMaxWaves) void gemv_bf16_kernel(GemmArgs g) {
   constexpr int RW = 4;
   constexpr int NV = RW * BT;
@@ -118,31 +127,32 @@ __global__ __launch_bounds__(64 * kGemvMaxWaves) void gemv_bf16_kernel(GemmArgs 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int W = (int)(blockDim.x >> 6);
   const int j0 = blockIdx.x * RW, i0 = blockIdx.y * BT;
-  const int ng = g.K / 8;
+  using V = typename std::conditional<GW == 8, uint4, uint2>::type;
+  const int ng = g.K / GW;
   float v[NV];
 #pragma unroll
   for (int e = 0; e < NV; ++e) v[e] = 0.f;
   for (int q = tid; q < ng; q += 64 * W) {
-    uint4 wr[RW], ar[BT];
+    V wr[RW], ar[BT];
 #pragma unroll
     for (int r = 0; r < RW; ++r)
-      wr[r] = reinterpret_cast<const uint4*>(g.B + (long)min(j0 + r, g.N - 1) * g.sbn)[q];
+      wr[r] = reinterpret_cast<const V*>(g.B + (long)min(j0 + r, g.N - 1) * g.sbn)[q];
 #pragma unroll
     for (int b = 0; b < BT; ++b)
-      ar[b] = reinterpret_cast<const uint4*>(g.A + (long)min(i0 + b, g.M - 1) * g.sam)[q];
+      ar[b] = reinterpret_cast<const V*>(g.A + (long)min(i0 + b, g.M - 1) * g.sam)[q];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
+    for (int h = 0; h < GW / 2; ++h) {
       float wl[RW], wh[RW], al[BT], ah[BT];
 #pragma unroll
       for (int r = 0; r < RW; ++r) {
-        const uint32_t u = h == 0 ? wr[r].x : h == 1 ? wr[r].y : h == 2 ? wr[r].z : wr[r].w;
+        const uint32_t u = vword(wr[r], h);
         wl[r] = __uint_as_float(u << 16);
         wh[r] = __uint_as_float(u & 0xffff0000u);
       }
 #pragma unroll
       for (int b = 0; b < BT; ++b) {
-        const uint32_t u = h == 0 ? ar[b].x : h == 1 ? ar[b].y : h == 2 ? ar[b].z : ar[b].w;
+        const uint32_t u = vword(ar[b], h);
         al[b] = __uint_as_float(u << 16);
         ah[b] = __uint_as_float(u & 0xffff0000u);
       }
@@ -379,26 +389,34 @@ __global__ __launch_bounds__(256) void prepare_kernel(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 static unsigned grid_for(size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 8192); }
 
-template <int BT>
+template <int BT, int GW>
 static hipError_t launch_gemv(const GemmArgs& g, hipStream_t st) {
-  const int ng = g.K / 8;
+  const int ng = g.K / GW;
   const int waves = std::max(1, std::min(kGemvMaxWaves, (ng + 63) / 64));
-  hipLaunchKernelGGL(gemv_bf16_kernel<BT>, dim3((g.N + 3) / 4, (g.M + BT - 1) / BT), dim3(64 * waves), 0, st, g);
+  hipLaunchKernelGGL((gemv_bf16_kernel<BT, GW>), dim3((g.N + 3) / 4, (g.M + BT - 1) / BT), dim3(64 * waves), 0, st,
+                     g);
   return hipGetLastError();
+}
+
+template <int GW>
+static hipError_t launch_gemv_gw(const GemmArgs& g, hipStream_t st) {
+  if (g.M == 1) return launch_gemv<1, GW>(g, st);
+  if (g.M <= 4) return launch_gemv<4, GW>(g, st);
+  if (g.M <= 8) return launch_gemv<8, GW>(g, st);
+  return launch_gemv<16, GW>(g, st);
 }
 
 hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
-  // Up to 128 rows with both operands contiguous in k in 16-byte groups (the
-  // fully connected layers, and the second and third convolutions of a single
-  // frame): the matrix-vector kernel, one launch and no split-K pass.
-  const bool gemv = g.M <= 128 && g.sak == 1 && g.sbk == 1 && g.K % 8 == 0 && g.sam % 8 == 0 && g.sbn % 8 == 0 &&
-                    (uintptr_t)g.A % 16 == 0 && (uintptr_t)g.B % 16 == 0;
-  if (gemv) {
-    if (g.M == 1) return launch_gemv<1>(g, st);
-    if (g.M <= 4) return launch_gemv<4>(g, st);
-    if (g.M <= 8) return launch_gemv<8>(g, st);
-    return launch_gemv<16>(g, st);
+  // Up to 512 rows with both operands contiguous in k (the fully connected
+  // layers, and the convolutions of a single frame): the matrix-vector kernel,
+  // one launch and no split-K pass (measured faster than the MFMA tiles up to
+  // 16 frames; at 64 frames every convolution has more rows and keeps them).
+  if (g.M <= 512 && g.sak == 1 && g.sbk == 1) {
+    if (g.K % 8 == 0 && g.sam % 8 == 0 && g.sbn % 8 == 0 && (uintptr_t)g.A % 16 == 0 && (uintptr_t)g.B % 16 == 0)
+      return launch_gemv_gw<8>(g, st);
+    if (g.K % 4 == 0 && g.sam % 4 == 0 && g.sbn % 4 == 0 && (uintptr_t)g.A % 8 == 0 && (uintptr_t)g.B % 8 == 0)
+      return launch_gemv_gw<4>(g, st);
   }
   const int bx = (g.N + 63) / 64, by = (g.M + 63) / 64;
   const long blocks = (long)bx * by;
