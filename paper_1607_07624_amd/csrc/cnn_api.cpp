@@ -56,7 +56,7 @@ struct pwfs_cnn_s {
   float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
   uint16_t* wb = nullptr;
   // activations (bf16) and FP32 work buffers
-  uint16_t *xb = nullptr, *cols1 = nullptr, *a1 = nullptr, *cols2 = nullptr, *a2 = nullptr, *cols3 = nullptr,
+  uint16_t *cols1 = nullptr, *a1 = nullptr, *cols2 = nullptr, *a2 = nullptr, *cols3 = nullptr,
            *a3 = nullptr, *h = nullptr, *doutb = nullptr, *dzb = nullptr;
   float *out = nullptr, *dout = nullptr, *gtmp = nullptr, *dz = nullptr, *part = nullptr, *loss = nullptr;
   size_t part_elems = 0;
@@ -69,7 +69,7 @@ void free_net(pwfs_cnn_s* n) {
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(n->device);
-  void* ptrs[] = {n->w, n->m, n->v, n->g, n->wb, n->xb, n->cols1, n->a1, n->cols2, n->a2, n->cols3, n->a3,
+  void* ptrs[] = {n->w, n->m, n->v, n->g, n->wb, n->cols1, n->a1, n->cols2, n->a2, n->cols3, n->a3,
                   n->h, n->doutb, n->dzb, n->out, n->dout, n->gtmp, n->dz, n->part, n->loss};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -128,11 +128,9 @@ GemmArgs dgrad_args(const uint16_t* dY, const uint16_t* W, int R, int N, int K, 
 // `out` (NULL: the internal output buffer, alpha 1, beta 0).
 int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out = nullptr,
                 float out_alpha = 1.f, float out_beta = 0.f) {
-  const size_t in_elems = (size_t)B * n->S * n->S * 4;
-  CK(pwfs::cnn::to_bf16(x, in_elems, n->xb, st));
   const float* W = n->w;
   const uint16_t* Wb = n->wb;
-  CK(pwfs::cnn::im2col(n->xb, B, n->S, n->S, 4, n->cols1, st));
+  CK(pwfs::cnn::im2col_f32(x, B, n->S, n->S, 4, n->cols1, st));   // input rounded to bf16 on the way
   CK(pwfs::cnn::gemm(fwd_args(n->cols1, Wb + n->off[0], W + n->off[1], B * n->S1 * n->S1, n->c1, 36, true,
                               nullptr, n->a1), n->part, n->part_elems, st));
   CK(pwfs::cnn::im2col(n->a1, B, n->S1, n->S1, n->c1, n->cols2, st));
@@ -247,7 +245,7 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
       {(void**)&n->w, n->n_params * 4, "params"}, {(void**)&n->m, n->n_params * 4, "adam m"},
       {(void**)&n->v, n->n_params * 4, "adam v"}, {(void**)&n->g, n->n_params * 4, "grads"},
       {(void**)&n->wb, n->n_params * 2, "bf16 params"},
-      {(void**)&n->xb, B * n->S * n->S * 4 * 2, "input"}, {(void**)&n->cols1, R1 * 36 * 2, "cols1"},
+      {(void**)&n->cols1, R1 * 36 * 2, "cols1"},
       {(void**)&n->a1, R1 * n->c1 * 2, "a1"}, {(void**)&n->cols2, R2 * n->c1 * 9 * 2, "cols2"},
       {(void**)&n->a2, R2 * n->c2 * 2, "a2"}, {(void**)&n->cols3, R3 * n->c2 * 9 * 2, "cols3"},
       {(void**)&n->a3, R3 * n->c3 * 2, "a3"}, {(void**)&n->h, B * n->hidden * 2, "hidden"},

@@ -218,7 +218,13 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int splits
 // ---------------------------------------------------------------------------
 // im2col for a 3x3 stride-2 pad-1 convolution, NHWC input:
 // cols[(b, yo, xo)][c * 9 + ky * 3 + kx] = act[b][2 yo + ky - 1][2 xo + kx - 1][c] (0 outside).
-__global__ __launch_bounds__(256) void im2col_kernel(const uint16_t* __restrict__ act, int B, int H, int W,
+// (Also from an FP32 input, rounded to bf16 as to_bf16_kernel rounds it: the
+// network input's conversion and its im2col in one pass.)
+__device__ __forceinline__ uint16_t as_bf16(uint16_t h) { return h; }
+__device__ __forceinline__ uint16_t as_bf16(float f) { return f2bf(f); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void im2col_kernel(const T* __restrict__ act, int B, int H, int W,
                                                      int C, uint16_t* __restrict__ cols) {
   const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
   const size_t K9 = (size_t)C * 9;
@@ -231,7 +237,8 @@ __global__ __launch_bounds__(256) void im2col_kernel(const uint16_t* __restrict_
     const int rem = (int)(row - (size_t)b * Ho * Wo);
     const int yo = rem / Wo, xo = rem - yo * Wo;
     const int y = 2 * yo + ky - 1, x = 2 * xo + kx - 1;
-    cols[idx] = (y >= 0 && y < H && x >= 0 && x < W) ? act[(((size_t)b * H + y) * W + x) * C + c] : (uint16_t)0;
+    cols[idx] = (y >= 0 && y < H && x >= 0 && x < W) ? as_bf16(act[(((size_t)b * H + y) * W + x) * C + c])
+                                                      : (uint16_t)0;
   }
 }
 
@@ -442,7 +449,13 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
 
 hipError_t im2col(const uint16_t* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st) {
   const size_t total = (size_t)B * ((H + 1) / 2) * ((W + 1) / 2) * C * 9;
-  hipLaunchKernelGGL(im2col_kernel, dim3(grid_for(total)), dim3(256), 0, st, act, B, H, W, C, cols);
+  hipLaunchKernelGGL(im2col_kernel<uint16_t>, dim3(grid_for(total)), dim3(256), 0, st, act, B, H, W, C, cols);
+  return hipGetLastError();
+}
+
+hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st) {
+  const size_t total = (size_t)B * ((H + 1) / 2) * ((W + 1) / 2) * C * 9;
+  hipLaunchKernelGGL(im2col_kernel<float>, dim3(grid_for(total)), dim3(256), 0, st, act, B, H, W, C, cols);
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ struct GemmArgs {
 // part: split-K partial buffer of part_elems floats (NULL disables split-K).
 hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t st);
 hipError_t im2col(const uint16_t* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st);
+// The same from an FP32 input, each value rounded to bf16 (round to nearest even).
+hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st);
 hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, float* dz,
                        uint16_t* dzb, hipStream_t st);
 hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, float* dz, uint16_t* dzb, hipStream_t st);
