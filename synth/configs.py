@@ -130,6 +130,14 @@ def paper_pupil(P: int, pup_diam: int = PAPER_PUP_DIAM, pup_dist: int = PAPER_PU
 # r0 drawn uniformly in [0.08, 0.2] m (L0 as in the closed loop).
 CFG4_R0_RANGE = (0.08, 0.2)
 CFG4_SEEDS = tuple(range(16))
+# Closed loops of the precision study: frozen-flow sequences whose r0 is the
+# one drawn for the same seed's open-loop screen (first draw of the seed's
+# generator), 500 steps each; the sequence itself uses seed 10000 + seed.
+CFG4_LOOP_SEEDS = (0, 1, 2, 3, 4, 5)
+CFG4_LOOP_STEPS = 500
+# The LBT-like loop of the benchmark: r0 0.12 m, 1000 steps, sequence seed.
+CFG2_LOOP_SEED = 2024
+CFG2_LOOP_STEPS = 1000
 
 # 40 m class multi-source sensor: six guide stars on a 45 arcsec ring seen
 # through a three-layer atmosphere, sensed at 650 and 850 nm.  The

@@ -11,7 +11,11 @@ covariance depends only on the pixel offset, so it is applied by FFT
 convolution on a 2P x 2P grid; the leading eigenvectors are found by block
 subspace iteration followed by a Rayleigh-Ritz step.  Each mode is zero
 outside the pupil, has zero mean over it and unit RMS (1 nm) over it, and
-modes are mutually orthogonal over the pupil.
+modes are mutually orthogonal over the pupil.  The sign of each mode is
+fixed by a convention (its inner product with a seeded Gaussian field over
+the pupil pixels is positive), so the basis does not depend on the sign
+choices of the linear-algebra library: results computed with it on one
+machine (stored expected values) refer to the same modes on another.
 """
 from __future__ import annotations
 
@@ -37,13 +41,19 @@ def _cov_kernel(P: int, pixel_m: float, L0_m: float) -> np.ndarray:
     return sfft.rfft2(c)
 
 
+def sign_probe(npix: int) -> np.ndarray:
+    """Seeded Gaussian field over the pupil pixels that fixes the modes' signs."""
+    return np.random.default_rng(20161607).standard_normal(npix)
+
+
 def kl_modes(A: np.ndarray, pixel_m: float, L0_m: float, n_modes: int,
              iters: int = 8, oversample: int = 64, seed: int = 12345,
              cache: bool = True) -> np.ndarray:
     """[n_modes, P, P] float64 KL modes (unit RMS in nm over the pupil)."""
     P = A.shape[0]
     key = hashlib.sha1(np.packbits(A.astype(bool)).tobytes()
-                       + repr((P, pixel_m, L0_m, n_modes, iters, oversample, seed)).encode()).hexdigest()[:16]
+                       + repr((P, pixel_m, L0_m, n_modes, iters, oversample, seed,
+                               "sign-v1")).encode()).hexdigest()[:16]
     cdir = os.environ.get("PWFS_CACHE_DIR", os.path.join(os.path.expanduser("~"), ".cache", "pwfs_kl"))
     path = os.path.join(cdir, f"kl_{key}.npy")
     if cache and os.path.exists(path):
@@ -78,6 +88,7 @@ def kl_modes(A: np.ndarray, pixel_m: float, L0_m: float, n_modes: int,
     U = X @ V[:, order]                          # orthonormal columns, piston-free
     U -= U.mean(axis=0, keepdims=True)
     U, _ = np.linalg.qr(U)
+    U *= np.where(sign_probe(npix) @ U < 0.0, -1.0, 1.0)[None, :]
     modes = np.zeros((n_modes, P * P))
     modes[:, pix] = U.T * np.sqrt(npix)
     modes = modes.reshape(n_modes, P, P)

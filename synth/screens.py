@@ -87,6 +87,18 @@ def frozen_flow_sequence(cfg: SensorConfig, atmo: AtmoConfig, n_steps: int, seed
     return out
 
 
+def cfg4_loop_sequence(cfg: SensorConfig, atmo: AtmoConfig, seed: int, n_steps: int,
+                       r0_range=(0.08, 0.2)) -> tuple[np.ndarray, float]:
+    """Frozen-flow sequence of one precision-study loop: r0 is the first
+    uniform draw of default_rng(seed) in r0_range (the r0 of that seed's
+    open-loop screen), the screen and its motion those of
+    frozen_flow_sequence with seed 10000 + seed.  Returns (seq, r0)."""
+    r0 = float(np.random.default_rng(int(seed)).uniform(*r0_range))
+    at = AtmoConfig(r0_m=r0, L0_m=atmo.L0_m, r0_wavelength_m=atmo.r0_wavelength_m,
+                    wind_m_s=atmo.wind_m_s, frame_rate_hz=atmo.frame_rate_hz)
+    return frozen_flow_sequence(cfg, at, n_steps, seed=10000 + int(seed)), r0
+
+
 def tilt_opd_nm(P: int, alpha_lod: float, wavelength_m: float, axis: str = "x") -> np.ndarray:
     """Pure tilt of alpha lambda/D across the pupil: phase 2 pi alpha x / P.
 

@@ -9,7 +9,7 @@ import pytest
 from synth.configs import CFG_PAPER_DET, ATMO1, ATMO2, SensorConfig, paper_pupil
 from synth.screens import open_loop_batch
 import oracle
-from tests.gpu_common import torch_cuda, rel_l2, say
+from tests.gpu_common import torch_cuda, rel_l2, say, check_frame
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +39,7 @@ def _check(cfg, A, opd, batch_max, plan=None, orc=None):
     pup, s = pup.cpu().numpy(), s.cpu().numpy()
     for i in range(len(opd)):
         p_o, s_o = orc.measure(opd[i].astype(np.float64))
-        e_s, e_p = rel_l2(s[i], s_o), rel_l2(pup[i], p_o)
-        say(f"[gpu]   frame {i}: slope rel err {e_s:.3e}  pupil rel err {e_p:.3e}")
-        assert e_s <= SLOPE_TOL and e_p <= PUPIL_TOL
+        check_frame(f"frame {i}", s[i], s_o, pup[i], p_o)
     if own:
         plan.close()
 

@@ -7,7 +7,7 @@ import pytest
 from synth.configs import CFG2, CFG_PAPER_DET, ATMO1, ATMO2, SensorConfig, paper_pupil
 from synth.screens import open_loop_batch
 import oracle
-from tests.gpu_common import torch_cuda, rel_l2, say
+from tests.gpu_common import torch_cuda, rel_l2, say, check_frame
 
 pytestmark = pytest.mark.gpu
 
@@ -39,9 +39,7 @@ def _check(cfg, A, opd, batch_max):
     pup, s = pup.cpu().numpy(), s.cpu().numpy()
     for i in range(len(opd)):
         p_o, s_o = orc.measure(opd[i].astype(np.float64))
-        e_s, e_p = rel_l2(s[i], s_o), rel_l2(pup[i], p_o)
-        say(f"[gpu]   frame {i}: slope rel err {e_s:.3e}  pupil rel err {e_p:.3e}")
-        assert e_s <= SLOPE_TOL and e_p <= PUPIL_TOL
+        check_frame(f"frame {i}", s[i], s_o, pup[i], p_o)
     plan.close()
 
 
@@ -87,9 +85,8 @@ def test_open_stop_matches_the_separable_path_and_schedules_are_fixed():
     ps, ss = sep.measure(d)
     torch.cuda.synchronize()
     for i in range(3):
-        e = rel_l2(sg[i].cpu().numpy(), ss[i].cpu().numpy())
-        say(f"[gpu] open stop vs separable, frame {i}: slope rel diff {e:.3e}")
-        assert e <= SLOPE_TOL and rel_l2(pg[i].cpu().numpy(), ps[i].cpu().numpy()) <= PUPIL_TOL
+        check_frame(f"open stop vs separable, frame {i}", sg[i].cpu().numpy(), ss[i].cpu().numpy(),
+                    pg[i].cpu().numpy(), ps[i].cpu().numpy())
     with pytest.raises(PwfsError):
         gen.set_schedule(3, 1, 1)
     with pytest.raises(PwfsError):
