@@ -94,20 +94,13 @@ def bf16_round(a: np.ndarray) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def forward(p: dict, x: np.ndarray, act_round=None):
-    """(prediction [B, n_out], cache) for NHWC input x.
-
-    act_round (default None: exact FP64) is applied to every hidden
-    activation after its ReLU, i.e. to the operands of the next layer's
-    products; with bf16_round it models a network whose activations are
-    stored in bf16 (bf16 weights, FP32 accumulation).  The backward pass then
-    differentiates through the stored (rounded) activations."""
-    r = act_round if act_round is not None else (lambda a: a)
-    a1 = r(np.maximum(conv_forward(x, p["w1"], p["b1"]), 0.0))
-    a2 = r(np.maximum(conv_forward(a1, p["w2"], p["b2"]), 0.0))
-    a3 = r(np.maximum(conv_forward(a2, p["w3"], p["b3"]), 0.0))
+def forward(p: dict, x: np.ndarray):
+    """(prediction [B, n_out], cache) for NHWC input x, exact FP64."""
+    a1 = np.maximum(conv_forward(x, p["w1"], p["b1"]), 0.0)
+    a2 = np.maximum(conv_forward(a1, p["w2"], p["b2"]), 0.0)
+    a3 = np.maximum(conv_forward(a2, p["w3"], p["b3"]), 0.0)
     f = a3.reshape(a3.shape[0], -1)
-    h = r(np.maximum(f @ p["fw1"].T + p["fb1"], 0.0))
+    h = np.maximum(f @ p["fw1"].T + p["fb1"], 0.0)
     out = h @ p["fw2"].T + p["fb2"]
     return out, (x, a1, a2, a3, f, h)
 
@@ -137,8 +130,8 @@ def backward(p: dict, cache, dout: np.ndarray) -> dict:
     return g
 
 
-def loss_and_grads(p: dict, x: np.ndarray, target: np.ndarray, act_round=None, weights=None):
-    pred, cache = forward(p, x, act_round)
+def loss_and_grads(p: dict, x: np.ndarray, target: np.ndarray, weights=None):
+    pred, cache = forward(p, x)
     loss, dout = mse(pred, target, weights)
     return loss, backward(p, cache, dout), pred
 

@@ -55,10 +55,11 @@ struct pwfs_cnn_s {
   // parameters
   float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
   uint16_t* wb = nullptr;
-  // activations (bf16) and FP32 work buffers
+  // activations as bf16 pairs (lo plane after the hi plane; cols1, the
+  // bf16-rounded input's im2col, is one plane) and FP32 work buffers
   uint16_t *cols1 = nullptr, *a1 = nullptr, *cols2 = nullptr, *a2 = nullptr, *cols3 = nullptr,
            *a3 = nullptr, *h = nullptr, *doutb = nullptr, *dzb = nullptr;
-  float *out = nullptr, *dout = nullptr, *gtmp = nullptr, *dz = nullptr, *part = nullptr, *loss = nullptr;
+  float *out = nullptr, *gtmp = nullptr, *part = nullptr, *loss = nullptr, *mse_part = nullptr;
   size_t part_elems = 0;
 };
 
@@ -70,7 +71,7 @@ void free_net(pwfs_cnn_s* n) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(n->device);
   void* ptrs[] = {n->w, n->m, n->v, n->g, n->wb, n->cols1, n->a1, n->cols2, n->a2, n->cols3, n->a3,
-                  n->h, n->doutb, n->dzb, n->out, n->dout, n->gtmp, n->dz, n->part, n->loss};
+                  n->h, n->doutb, n->dzb, n->out, n->gtmp, n->part, n->loss, n->mse_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (prev >= 0) (void)hipSetDevice(prev);
@@ -95,29 +96,32 @@ struct DevGuard {
     if (e_ != hipSuccess) return hip_fail(e_, #expr); \
   } while (0)
 
-// Y = X W^T + bias (ReLU), X [M][K] bf16, W [N][K] bf16.
-GemmArgs fwd_args(const uint16_t* X, const uint16_t* W, const float* bias, int M, int N, int K, bool relu,
-                  float* C, uint16_t* Cb) {
+// Y = X W^T + bias (ReLU), X [M][K] bf16 (a pair when x_split: lo plane M K
+// elements on), W [N][K] bf16; Y to C (FP32) and/or Cb (a bf16 pair, lo
+// plane M N elements on).
+GemmArgs fwd_args(const uint16_t* X, bool x_split, const uint16_t* W, const float* bias, int M, int N, int K,
+                  bool relu, float* C, uint16_t* Cb) {
   GemmArgs a{};
-  a.A = X; a.sam = K; a.sak = 1;
+  a.A = X; a.sam = K; a.sak = 1; a.a_lo = x_split ? (long)M * K : 0;
   a.B = W; a.sbk = 1; a.sbn = K;
-  a.C = C; a.ldc = N; a.Cb = Cb; a.ldcb = N;
+  a.C = C; a.ldc = N; a.Cb = Cb; a.ldcb = N; a.cb_lo = Cb ? (long)M * N : 0;
   a.bias = bias; a.M = M; a.N = N; a.K = K; a.alpha = 1.f; a.beta = 0.f; a.relu = relu ? 1 : 0;
   return a;
 }
-// dW [N][K] = dY^T X, dY [R][N] bf16, X [R][K] bf16.
-GemmArgs wgrad_args(const uint16_t* dY, const uint16_t* X, int R, int N, int K, float* dW) {
+// dW [N][K] = dY^T X and db [N] = column sums of dY; dY [R][N] a bf16 pair
+// (lo plane R N elements on), X [R][K] bf16 (a pair when x_split).
+GemmArgs wgrad_args(const uint16_t* dY, const uint16_t* X, bool x_split, int R, int N, int K, float* dW, float* db) {
   GemmArgs a{};
-  a.A = dY; a.sam = 1; a.sak = N;
-  a.B = X; a.sbk = K; a.sbn = 1;
-  a.C = dW; a.ldc = K;
+  a.A = dY; a.sam = 1; a.sak = N; a.a_lo = (long)R * N;
+  a.B = X; a.sbk = K; a.sbn = 1; a.b_lo = x_split ? (long)R * K : 0;
+  a.C = dW; a.ldc = K; a.bias_grad = db;
   a.M = N; a.N = K; a.K = R; a.alpha = 1.f;
   return a;
 }
-// dX [R][K] = dY W, dY [R][N] bf16, W [N][K] bf16.
+// dX [R][K] = dY W, dY [R][N] a bf16 pair, W [N][K] bf16.
 GemmArgs dgrad_args(const uint16_t* dY, const uint16_t* W, int R, int N, int K, float* dX) {
   GemmArgs a{};
-  a.A = dY; a.sam = N; a.sak = 1;
+  a.A = dY; a.sam = N; a.sak = 1; a.a_lo = (long)R * N;
   a.B = W; a.sbk = K; a.sbn = 1;
   a.C = dX; a.ldc = K;
   a.M = R; a.N = K; a.K = N; a.alpha = 1.f;
@@ -130,18 +134,19 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
                 float out_alpha = 1.f, float out_beta = 0.f) {
   const float* W = n->w;
   const uint16_t* Wb = n->wb;
+  const int R1 = B * n->S1 * n->S1, R2 = B * n->S2 * n->S2, R3 = B * n->S3 * n->S3;
   CK(pwfs::cnn::im2col_f32(x, B, n->S, n->S, 4, n->cols1, st));   // input rounded to bf16 on the way
-  CK(pwfs::cnn::gemm(fwd_args(n->cols1, Wb + n->off[0], W + n->off[1], B * n->S1 * n->S1, n->c1, 36, true,
-                              nullptr, n->a1), n->part, n->part_elems, st));
-  CK(pwfs::cnn::im2col(n->a1, B, n->S1, n->S1, n->c1, n->cols2, st));
-  CK(pwfs::cnn::gemm(fwd_args(n->cols2, Wb + n->off[2], W + n->off[3], B * n->S2 * n->S2, n->c2, n->c1 * 9, true,
-                              nullptr, n->a2), n->part, n->part_elems, st));
-  CK(pwfs::cnn::im2col(n->a2, B, n->S2, n->S2, n->c2, n->cols3, st));
-  CK(pwfs::cnn::gemm(fwd_args(n->cols3, Wb + n->off[4], W + n->off[5], B * n->S3 * n->S3, n->c3, n->c2 * 9, true,
-                              nullptr, n->a3), n->part, n->part_elems, st));
-  CK(pwfs::cnn::gemm(fwd_args(n->a3, Wb + n->off[6], W + n->off[7], B, n->hidden, n->flat, true, nullptr, n->h),
+  CK(pwfs::cnn::gemm(fwd_args(n->cols1, false, Wb + n->off[0], W + n->off[1], R1, n->c1, 36, true, nullptr, n->a1),
                      n->part, n->part_elems, st));
-  GemmArgs last = fwd_args(n->h, Wb + n->off[8], W + n->off[9], B, n->nout, n->hidden, false,
+  CK(pwfs::cnn::im2col(n->a1, B, n->S1, n->S1, n->c1, n->cols2, st));
+  CK(pwfs::cnn::gemm(fwd_args(n->cols2, true, Wb + n->off[2], W + n->off[3], R2, n->c2, n->c1 * 9, true, nullptr,
+                              n->a2), n->part, n->part_elems, st));
+  CK(pwfs::cnn::im2col(n->a2, B, n->S2, n->S2, n->c2, n->cols3, st));
+  CK(pwfs::cnn::gemm(fwd_args(n->cols3, true, Wb + n->off[4], W + n->off[5], R3, n->c3, n->c2 * 9, true, nullptr,
+                              n->a3), n->part, n->part_elems, st));
+  CK(pwfs::cnn::gemm(fwd_args(n->a3, true, Wb + n->off[6], W + n->off[7], B, n->hidden, n->flat, true, nullptr, n->h),
+                     n->part, n->part_elems, st));
+  GemmArgs last = fwd_args(n->h, true, Wb + n->off[8], W + n->off[9], B, n->nout, n->hidden, false,
                            out ? out : n->out, nullptr);
   if (out) {
     last.alpha = out_alpha;
@@ -151,45 +156,35 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
   return 0;
 }
 
-// Product with an upstream-gradient operand A held as bf16 hi/lo pairs (lo at
-// A + a_lo_off): C = A_hi B, then C += A_lo B.
-hipError_t gemm_hilo(GemmArgs a, size_t a_lo_off, pwfs_cnn_s* n, hipStream_t st) {
-  hipError_t e = pwfs::cnn::gemm(a, n->part, n->part_elems, st);
-  if (e != hipSuccess) return e;
-  a.A += a_lo_off;
-  a.beta = 1.f;
-  return pwfs::cnn::gemm(a, n->part, n->part_elems, st);
-}
-
 int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B, float* loss, hipStream_t st) {
   const uint16_t* Wb = n->wb;
   float* G = n->g;
-  CK(pwfs::cnn::mse(n->out, target, weights, B * n->nout, n->nout, n->dout, n->doutb, loss, st));
+  const size_t P = (size_t)n->part_elems;
+  CK(pwfs::cnn::mse(n->out, target, weights, B * n->nout, n->nout, n->doutb, loss, n->mse_part, st));
   // fc2
-  const size_t lo_out = (size_t)B * n->nout;
-  CK(gemm_hilo(wgrad_args(n->doutb, n->h, B, n->nout, n->hidden, G + n->off[8]), lo_out, n, st));
-  CK(pwfs::cnn::colsum(n->dout, B, n->nout, G + n->off[9], st));
-  CK(gemm_hilo(dgrad_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->gtmp), lo_out, n, st));
-  CK(pwfs::cnn::relu_mask(n->gtmp, n->h, (size_t)B * n->hidden, n->dz, n->dzb, st));
+  CK(pwfs::cnn::gemm(wgrad_args(n->doutb, n->h, true, B, n->nout, n->hidden, G + n->off[8], G + n->off[9]),
+                     n->part, P, st));
+  CK(pwfs::cnn::gemm(dgrad_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->gtmp), n->part, P, st));
+  CK(pwfs::cnn::relu_mask(n->gtmp, n->h, (size_t)B * n->hidden, n->dzb, st));
   // fc1
-  CK(gemm_hilo(wgrad_args(n->dzb, n->a3, B, n->hidden, n->flat, G + n->off[6]), (size_t)B * n->hidden, n, st));
-  CK(pwfs::cnn::colsum(n->dz, B, n->hidden, G + n->off[7], st));
-  CK(gemm_hilo(dgrad_args(n->dzb, Wb + n->off[6], B, n->hidden, n->flat, n->gtmp), (size_t)B * n->hidden, n, st));
-  CK(pwfs::cnn::relu_mask(n->gtmp, n->a3, (size_t)B * n->flat, n->dz, n->dzb, st));
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->a3, true, B, n->hidden, n->flat, G + n->off[6], G + n->off[7]),
+                     n->part, P, st));
+  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[6], B, n->hidden, n->flat, n->gtmp), n->part, P, st));
+  CK(pwfs::cnn::relu_mask(n->gtmp, n->a3, (size_t)B * n->flat, n->dzb, st));
   // conv3
   const int R3 = B * n->S3 * n->S3, R2 = B * n->S2 * n->S2, R1 = B * n->S1 * n->S1;
-  CK(gemm_hilo(wgrad_args(n->dzb, n->cols3, R3, n->c3, n->c2 * 9, G + n->off[4]), (size_t)R3 * n->c3, n, st));
-  CK(pwfs::cnn::colsum(n->dz, R3, n->c3, G + n->off[5], st));
-  CK(gemm_hilo(dgrad_args(n->dzb, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), (size_t)R3 * n->c3, n, st));
-  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S2, n->S2, n->c2, n->a2, n->dz, n->dzb, st));
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols3, true, R3, n->c3, n->c2 * 9, G + n->off[4], G + n->off[5]),
+                     n->part, P, st));
+  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), n->part, P, st));
+  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S2, n->S2, n->c2, n->a2, n->dzb, st));
   // conv2
-  CK(gemm_hilo(wgrad_args(n->dzb, n->cols2, R2, n->c2, n->c1 * 9, G + n->off[2]), (size_t)R2 * n->c2, n, st));
-  CK(pwfs::cnn::colsum(n->dz, R2, n->c2, G + n->off[3], st));
-  CK(gemm_hilo(dgrad_args(n->dzb, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), (size_t)R2 * n->c2, n, st));
-  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dz, n->dzb, st));
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols2, true, R2, n->c2, n->c1 * 9, G + n->off[2], G + n->off[3]),
+                     n->part, P, st));
+  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, P, st));
+  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dzb, st));
   // conv1
-  CK(gemm_hilo(wgrad_args(n->dzb, n->cols1, R1, n->c1, 36, G + n->off[0]), (size_t)R1 * n->c1, n, st));
-  CK(pwfs::cnn::colsum(n->dz, R1, n->c1, G + n->off[1], st));
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols1, false, R1, n->c1, 36, G + n->off[0], G + n->off[1]),
+                     n->part, P, st));
   return 0;
 }
 
@@ -238,7 +233,7 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
   const size_t B = (size_t)n->bm;
   const size_t R1 = B * n->S1 * n->S1, R2 = B * n->S2 * n->S2, R3 = B * n->S3 * n->S3;
   const size_t gtmp = std::max({B * n->hidden, B * n->flat, R3 * n->c2 * 9, R2 * n->c1 * 9});
-  const size_t dz = std::max({B * n->hidden, B * n->flat, R2 * n->c2, R1 * n->c1});
+  const size_t dz = std::max({B * n->nout, B * n->hidden, B * n->flat, R3 * n->c3, R2 * n->c2, R1 * n->c1});
   n->part_elems = std::max<size_t>({(size_t)4 << 20, (size_t)64 * n->c1 * 36, (size_t)64 * n->c2 * n->c1 * 9,
                                     (size_t)64 * n->c3 * n->c2 * 9});
   struct A { void** p; size_t bytes; const char* what; } al[] = {
@@ -246,13 +241,14 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
       {(void**)&n->v, n->n_params * 4, "adam v"}, {(void**)&n->g, n->n_params * 4, "grads"},
       {(void**)&n->wb, n->n_params * 2, "bf16 params"},
       {(void**)&n->cols1, R1 * 36 * 2, "cols1"},
-      {(void**)&n->a1, R1 * n->c1 * 2, "a1"}, {(void**)&n->cols2, R2 * n->c1 * 9 * 2, "cols2"},
-      {(void**)&n->a2, R2 * n->c2 * 2, "a2"}, {(void**)&n->cols3, R3 * n->c2 * 9 * 2, "cols3"},
-      {(void**)&n->a3, R3 * n->c3 * 2, "a3"}, {(void**)&n->h, B * n->hidden * 2, "hidden"},
-      {(void**)&n->doutb, B * n->nout * 2 * 2, "dout bf16 hi/lo"}, {(void**)&n->dzb, dz * 2 * 2, "dz bf16 hi/lo"},
-      {(void**)&n->out, B * n->nout * 4, "out"}, {(void**)&n->dout, B * n->nout * 4, "dout"},
-      {(void**)&n->gtmp, gtmp * 4, "data gradients"}, {(void**)&n->dz, dz * 4, "dz"},
+      {(void**)&n->a1, R1 * n->c1 * 2 * 2, "a1 pair"}, {(void**)&n->cols2, R2 * n->c1 * 9 * 2 * 2, "cols2 pair"},
+      {(void**)&n->a2, R2 * n->c2 * 2 * 2, "a2 pair"}, {(void**)&n->cols3, R3 * n->c2 * 9 * 2 * 2, "cols3 pair"},
+      {(void**)&n->a3, R3 * n->c3 * 2 * 2, "a3 pair"}, {(void**)&n->h, B * n->hidden * 2 * 2, "hidden pair"},
+      {(void**)&n->doutb, B * n->nout * 2 * 2, "dout pair"}, {(void**)&n->dzb, dz * 2 * 2, "dz pair"},
+      {(void**)&n->out, B * n->nout * 4, "out"},
+      {(void**)&n->gtmp, gtmp * 4, "data gradients"},
       {(void**)&n->part, n->part_elems * 4, "split-K partials"}, {(void**)&n->loss, 4, "loss"},
+      {(void**)&n->mse_part, pwfs::cnn::mse_partials((int)(B * n->nout)) * 4, "loss partials"},
   };
   for (auto& a : al) {
     int s = dev_alloc(a.p, a.bytes, a.what);

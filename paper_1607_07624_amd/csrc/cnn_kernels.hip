@@ -1,14 +1,20 @@
 // cnn_kernels.hip -- kernels of the learned modal reconstructor (gfx950).
 //
-// Every product (convolutions as im2col GEMMs, fully connected layers,
-// their data and weight gradients) runs on one strided bf16 GEMM built on
-// v_mfma_f32_32x32x8bf16_1k with FP32 accumulation, with an optional
-// deterministic split-K (fixed-order reduction of per-split partials) and a
-// fused epilogue (bias, ReLU, beta * C, FP32 and/or bf16 output).  The other
-// kernels are gathers and elementwise passes: im2col, col2im in gather form
-// (each input element sums its own contributions in a fixed order, no
-// atomics), ReLU masks, bias-gradient column sums, the MSE loss, Adam and
-// the network-input preparation from binned pupil images.
+// Every product (convolutions as im2col products, fully connected layers,
+// their data and weight gradients) runs on one tiled bf16 GEMM built on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation: operands staged through
+// a double-buffered LDS tile by 16-byte loads, an optional deterministic
+// split-K (partials added in split order), and a fused epilogue (bias,
+// ReLU, beta * C, FP32 and/or bf16 output).  Activations and upstream
+// gradients are carried as bf16 pairs hi + lo (~16 significant bits), so a
+// product keeps the precision of FP32 operands to ~2^-17 while every
+// multiply runs on the bf16 matrix cores.  Bias gradients come out of the
+// weight-gradient product as one extra output column (a column of ones in
+// the activation operand).  Small products (a few rows) run on a
+// matrix-vector kernel that streams the weights once.  The other kernels
+// are gathers and elementwise passes: im2col, col2im in gather form (each
+// input element sums its own contributions in a fixed order, no atomics),
+// ReLU masks, the MSE loss, Adam and the network-input preparation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,7 +26,7 @@
 namespace pwfs {
 namespace cnn {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -31,81 +37,331 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ bool bf_pos(uint16_t h) { return h != 0 && !(h & 0x8000u); }
-__device__ __forceinline__ void split_bf(float v, uint16_t* hi, uint16_t* lo, size_t i);
 
-// ---------------------------------------------------------------------------
-// GEMM: C(i, j) = sum_k A(i, k) B(k, j), A(i, k) = A[i sam + k sak],
-// B(k, j) = B[k sbk + j sbn].  Block = 4 waves, tile 64 x 64, K step 32;
-// wave (wm, wn) owns the 32 x 32 sub-tile.  MFMA 32x32x8 operand layout:
-// lane l holds A rows (l % 32), k = 4 (l / 32) .. +3, B columns (l % 32),
-// same k; accumulator v of lane l is C(8 (v / 4) + 4 (l / 32) + v % 4, l % 32).
-// With gridDim.z > 1 each z handles K range [z kc, (z+1) kc) and writes raw
-// partials to part[z][M][N] (epilogue applied by gemm_reduce_kernel).
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g, int kc, float* __restrict__ part) {
-  __shared__ __align__(16) uint16_t As[64][40];
-  __shared__ __align__(16) uint16_t Bs[64][40];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  const int kbeg = blockIdx.z * kc;
-  const int kend = min(g.K, kbeg + kc);
-  f32x16 acc;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    for (int e = tid; e < 2048; e += 256) {
-      int ii, kk;
-      if (g.sak == 1) { ii = e >> 5; kk = e & 31; } else { kk = e >> 6; ii = e & 63; }
-      const int gi = i0 + ii, gk = k0 + kk;
-      As[ii][kk] = (gi < g.M && gk < kend) ? g.A[(long)gi * g.sam + (long)gk * g.sak] : (uint16_t)0;
-    }
-    for (int e = tid; e < 2048; e += 256) {
-      int jj, kk;
-      if (g.sbk == 1) { jj = e >> 5; kk = e & 31; } else { kk = e >> 6; jj = e & 63; }
-      const int gj = j0 + jj, gk = k0 + kk;
-      Bs[jj][kk] = (gj < g.N && gk < kend) ? g.B[(long)gk * g.sbk + (long)gj * g.sbn] : (uint16_t)0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 32; kk += 8) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[wm * 32 + (lane & 31)][kk + 4 * (lane >> 5)]);
-      const bf16x4 b = *reinterpret_cast<const bf16x4*>(&Bs[wn * 32 + (lane & 31)][kk + 4 * (lane >> 5)]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-    }
-    __syncthreads();
+// Split of an FP32 value into bf16 hi + lo (hi = bf16(v), lo = bf16(v - hi)).
+__device__ __forceinline__ void split_bf(float v, uint16_t* hi, uint16_t* lo, size_t i) {
+  const uint16_t h = f2bf(v);
+  hi[i] = h;
+  lo[i] = f2bf(v - bf2f(h));
+}
+
+// Epilogue of one output element (i, j); j == N is the bias-gradient column.
+__device__ __forceinline__ void epilogue(const GemmArgs& g, int i, int j, float x) {
+  if (j == g.N) {
+    g.bias_grad[i] = x;
+    return;
   }
-  const int j = j0 + wn * 32 + (lane & 31);
-  if (j >= g.N) return;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int i = i0 + wm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    if (i >= g.M) continue;
-    float x = acc[v];
-    if (part) {
-      part[((size_t)blockIdx.z * g.M + i) * g.N + j] = x;
-      continue;
-    }
-    if (g.bias) x += g.bias[j];
-    x *= g.alpha;
-    if (g.C && g.beta != 0.f) x = fmaf(g.beta, g.C[(long)i * g.ldc + j], x);
-    if (g.relu) x = fmaxf(x, 0.f);
-    if (g.C) g.C[(long)i * g.ldc + j] = x;
-    if (g.Cb) g.Cb[(long)i * g.ldcb + j] = f2bf(x);
+  if (g.bias) x += g.bias[j];
+  x *= g.alpha;
+  if (g.C && g.beta != 0.f) x = fmaf(g.beta, g.C[(long)i * g.ldc + j], x);
+  if (g.relu) x = fmaxf(x, 0.f);
+  if (g.C) g.C[(long)i * g.ldc + j] = x;
+  if (g.Cb) {
+    const long o = (long)i * g.ldcb + j;
+    const uint16_t h = f2bf(x);
+    g.Cb[o] = h;
+    if (g.cb_lo) g.Cb[o + g.cb_lo] = f2bf(x - bf2f(h));
   }
 }
 
-// Small-M products (at most 512 rows of A, both operands contiguous in k:
-// the fully connected layers at the loop's batch sizes, the convolutions of
-// one frame), C(i, j) = sum_k A[i][k] B[j][k].  Block =
-// W <= 8 waves over RW = 4 columns j and BT <= 16 rows i (grid over both); thread t takes the 8-element (16-byte) k groups t, t + 64 W, ..., loads
-// the RW weight rows' and the BT activation rows' groups before any product,
-// and keeps the RW x BT sums.  Each wave adds its 64 lanes by recursive
-// halving (a lane keeps half of its sums and trades the other half at each
-// step), the W wave sums are added in wave order through LDS (fixed order),
-// then the epilogue of gemm_bf16_kernel.  Columns and rows past the ends are
-// clamped to the last one for loading (in bounds, never stored).  The
-// weights stream from HBM once, instead of through 64 x 64 MFMA tiles that
-// are 1 / 64 full at one row and need a split-K pass to fill the GPU.
+// ---------------------------------------------------------------------------
+// Tiled MFMA GEMM.  Block = 4 waves in a WM x WN arrangement, each wave
+// owning TM x TN blocks of 32 x 32 outputs: a BM x BN tile, BM = 32 WM TM,
+// BN = 32 WN TN.  K advances 32 at a time through two LDS stages (the next
+// stage's global loads are in flight while the current stage is multiplied;
+// one barrier per step).  LDS holds every operand tile as [row][k] with k
+// contiguous and a row pitch of 40 bf16 (80 bytes), so an MFMA operand is
+// one 16-byte read per lane: v_mfma_f32_32x32x16_bf16 takes, in lane l, the
+// 8 consecutive k of row (l mod 32) starting at 8 (l / 32); its 16
+// accumulators of lane l are C(8 (v / 4) + 4 (l / 32) + v mod 4, l mod 32).
+//
+// Operand views.  A tile of R rows (rows = i for A, j for B) by 32 k comes
+// from global memory in one of two layouts:
+//  * k-contiguous (stride 1 along k): chunk = 8 k of one row, one 16-byte
+//    load (vw 8), two 8-byte loads (vw 4) or 8 element loads (vw 1);
+//  * row-contiguous (stride 1 along rows): quad-chunk = 8 rows x 4 k, four
+//    loads of 8 rows each, transposed in registers into 8 rows x 4 k and
+//    written as 8-byte LDS stores.
+// vw (16-, 8- or 2-byte groups) is decided on the host from the strides,
+// extents and alignment, uniform per launch.  Elements past the extents are
+// zero; the bias-gradient column (B row N) is 1 in the hi plane.
+constexpr int kBK = 32;
+constexpr int kPitch = 40;
+
+struct OpView {
+  const uint16_t* p;
+  long s_row, s_k;     // element strides along the tile's rows and along k
+  int rows;            // extent of rows holding data
+  int ones_row;        // a row of ones at this index (hi plane), -1: none
+  int vw;              // 8, 4 or 1 elements per load along the contiguous dimension
+};
+
+struct Chunk8 { uint32_t w[4]; };
+
+__device__ __forceinline__ uint32_t ld_u16(const uint16_t* p) { return *p; }
+
+// 8 elements along the contiguous dimension starting at `e` (element index
+// along it), `lim` the extent there; q: address of element 0.
+__device__ __forceinline__ Chunk8 load8(const uint16_t* q, int e, int lim, int vw) {
+  Chunk8 c;
+  if (vw == 8) {
+    if (e < lim) {
+      const uint4 v = *reinterpret_cast<const uint4*>(q);
+      c.w[0] = v.x; c.w[1] = v.y; c.w[2] = v.z; c.w[3] = v.w;
+    } else {
+      c.w[0] = c.w[1] = c.w[2] = c.w[3] = 0u;
+    }
+  } else if (vw == 4) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (e + 4 * h < lim) {
+        const uint2 v = *reinterpret_cast<const uint2*>(q + 4 * h);
+        c.w[2 * h] = v.x; c.w[2 * h + 1] = v.y;
+      } else {
+        c.w[2 * h] = c.w[2 * h + 1] = 0u;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const uint32_t lo = (e + 2 * h < lim) ? ld_u16(q + 2 * h) : 0u;
+      const uint32_t hi = (e + 2 * h + 1 < lim) ? ld_u16(q + 2 * h + 1) : 0u;
+      c.w[h] = lo | (hi << 16);
+    }
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint32_t half_of(const Chunk8& c, int r) {
+  return (c.w[r >> 1] >> ((r & 1) * 16)) & 0xffffu;
+}
+__device__ __forceinline__ void set_half(Chunk8& c, int r, uint32_t v) {
+  const int s = (r & 1) * 16;
+  c.w[r >> 1] = (c.w[r >> 1] & ~(0xffffu << s)) | (v << s);
+}
+
+// Staged global data of one operand plane for one k step: up to 2 chunks
+// (k-contiguous) or one quad-chunk of 4 loads (row-contiguous) per thread.
+struct Stage {
+  Chunk8 c[4];
+};
+
+template <bool KC, int R>
+__device__ __forceinline__ void op_load(const OpView& v, long lo, int r0, int k0, int K, Stage& s, int tid) {
+  const uint16_t* p = v.p + lo;
+  if constexpr (KC) {
+    // R rows x 4 chunks; thread t takes chunks t and t + 256
+#pragma unroll
+    for (int t = 0; t < (R * 4 + 255) / 256; ++t) {
+      const int c = tid + 256 * t;
+      if (c < R * 4) {
+        const int row = c >> 2, kk = (c & 3) * 8;
+        const int gr = r0 + row;
+        const bool in = gr < v.rows;
+        const int gk = k0 + kk;
+        if (in) {
+          s.c[t] = load8(p + (long)gr * v.s_row + gk, gk, K, v.vw);
+        } else {
+          s.c[t].w[0] = s.c[t].w[1] = s.c[t].w[2] = s.c[t].w[3] = 0u;
+        }
+        if (gr == v.ones_row && lo == 0) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) set_half(s.c[t], e, gk + e < K ? 0x3f80u : 0u);
+        }
+      }
+    }
+  } else {
+    // quad-chunks: (R / 8) row groups x 8 k groups; thread t < R
+    if (tid < R) {
+      const int rg = tid % (R / 8), kg = tid / (R / 8);
+      const int gr = r0 + rg * 8;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int gk = k0 + kg * 4 + t;
+        if (gk < K) {
+          s.c[t] = load8(p + (long)gk * v.s_k + gr, gr, v.rows, v.vw);
+        } else {
+          s.c[t].w[0] = s.c[t].w[1] = s.c[t].w[2] = s.c[t].w[3] = 0u;
+        }
+        if (lo == 0) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r)
+            if (v.ones_row == gr + r) set_half(s.c[t], r, gk < K ? 0x3f80u : 0u);
+        }
+      }
+    }
+  }
+}
+
+template <bool KC, int R>
+__device__ __forceinline__ void op_store(uint16_t* lds, const Stage& s, int tid) {
+  if constexpr (KC) {
+#pragma unroll
+    for (int t = 0; t < (R * 4 + 255) / 256; ++t) {
+      const int c = tid + 256 * t;
+      if (c < R * 4) {
+        const int row = c >> 2, kk = (c & 3) * 8;
+        *reinterpret_cast<uint4*>(lds + row * kPitch + kk) = make_uint4(s.c[t].w[0], s.c[t].w[1], s.c[t].w[2], s.c[t].w[3]);
+      }
+    }
+  } else {
+    if (tid < R) {
+      const int rg = tid % (R / 8), kg = tid / (R / 8);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const uint32_t w0 = half_of(s.c[0], r) | (half_of(s.c[1], r) << 16);
+        const uint32_t w1 = half_of(s.c[2], r) | (half_of(s.c[3], r) << 16);
+        *reinterpret_cast<uint2*>(lds + (rg * 8 + r) * kPitch + kg * 4) = make_uint2(w0, w1);
+      }
+    }
+  }
+}
+
+template <int WM, int WN, int TM, int TN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, OpView vb, int kc,
+                                                        float* __restrict__ part) {
+  constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN;
+  extern __shared__ __align__(16) uint16_t lds[];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / WN, wn = wave % WN;
+  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * kc;
+  const int kend = min(g.K, kbeg + kc);
+  const bool alo = g.a_lo != 0, blo = g.b_lo != 0;
+  // LDS stage: A_hi [BM], A_lo [BM] (if any), B_hi [BN], B_lo [BN] (if any), rows of kPitch
+  const int stage_rows = BM * (alo ? 2 : 1) + BN * (blo ? 2 : 1);
+  uint16_t* st0 = lds;
+  uint16_t* st1 = lds + stage_rows * kPitch;
+  auto a_hi = [&](uint16_t* s) { return s; };
+  auto a_lo = [&](uint16_t* s) { return s + BM * kPitch; };
+  auto b_hi = [&](uint16_t* s) { return s + BM * (alo ? 2 : 1) * kPitch; };
+  auto b_lo = [&](uint16_t* s) { return s + (BM * (alo ? 2 : 1) + BN) * kPitch; };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+  Stage sa, sal, sb, sbl;
+  // prologue
+  op_load<AKC, BM>(va, 0, i0, kbeg, kend, sa, tid);
+  if (alo) op_load<AKC, BM>(va, g.a_lo, i0, kbeg, kend, sal, tid);
+  op_load<BKC, BN>(vb, 0, j0, kbeg, kend, sb, tid);
+  if (blo) op_load<BKC, BN>(vb, g.b_lo, j0, kbeg, kend, sbl, tid);
+  op_store<AKC, BM>(a_hi(st0), sa, tid);
+  if (alo) op_store<AKC, BM>(a_lo(st0), sal, tid);
+  op_store<BKC, BN>(b_hi(st0), sb, tid);
+  if (blo) op_store<BKC, BN>(b_lo(st0), sbl, tid);
+  __syncthreads();
+
+  int it = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += kBK, ++it) {
+    uint16_t* cur = (it & 1) ? st1 : st0;
+    uint16_t* nxt = (it & 1) ? st0 : st1;
+    const bool more = k0 + kBK < kend;
+    if (more) {
+      op_load<AKC, BM>(va, 0, i0, k0 + kBK, kend, sa, tid);
+      if (alo) op_load<AKC, BM>(va, g.a_lo, i0, k0 + kBK, kend, sal, tid);
+      op_load<BKC, BN>(vb, 0, j0, k0 + kBK, kend, sb, tid);
+      if (blo) op_load<BKC, BN>(vb, g.b_lo, j0, k0 + kBK, kend, sbl, tid);
+    }
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+      const int kof = sub * 16 + 8 * (lane >> 5);
+      bf16x8 fa[TM], fb[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+        fa[a] = *reinterpret_cast<const bf16x8*>(a_hi(cur) + (wm * TM * 32 + a * 32 + (lane & 31)) * kPitch + kof);
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        fb[b] = *reinterpret_cast<const bf16x8*>(b_hi(cur) + (wn * TN * 32 + b * 32 + (lane & 31)) * kPitch + kof);
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+      if (alo) {
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+          const bf16x8 fl =
+              *reinterpret_cast<const bf16x8*>(a_lo(cur) + (wm * TM * 32 + a * 32 + (lane & 31)) * kPitch + kof);
+#pragma unroll
+          for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl, fb[b], acc[a][b], 0, 0, 0);
+        }
+      }
+      if (blo) {
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const bf16x8 fl =
+              *reinterpret_cast<const bf16x8*>(b_lo(cur) + (wn * TN * 32 + b * 32 + (lane & 31)) * kPitch + kof);
+#pragma unroll
+          for (int a = 0; a < TM; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fl, acc[a][b], 0, 0, 0);
+        }
+      }
+    }
+    if (more) {
+      op_store<AKC, BM>(a_hi(nxt), sa, tid);
+      if (alo) op_store<AKC, BM>(a_lo(nxt), sal, tid);
+      op_store<BKC, BN>(b_hi(nxt), sb, tid);
+      if (blo) op_store<BKC, BN>(b_lo(nxt), sbl, tid);
+    }
+    __syncthreads();
+  }
+
+  const int Nc = g.N + (g.bias_grad ? 1 : 0);
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int j = j0 + wn * TN * 32 + b * 32 + (lane & 31);
+      if (j >= Nc) continue;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = i0 + wm * TM * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (i >= g.M) continue;
+        if (part)
+          part[((size_t)blockIdx.z * g.M + i) * Nc + j] = acc[a][b][v];
+        else
+          epilogue(g, i, j, acc[a][b][v]);
+      }
+    }
+}
+
+// Sum of split-K partials in split order, then the epilogue.  Block = 64
+// elements x 4 split groups: group q adds splits q, q + 4, ... in order,
+// then the four group sums are added in group order (fixed order overall).
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int splits, const float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int Nc = g.N + (g.bias_grad ? 1 : 0);
+  const size_t MN = (size_t)g.M * Nc;
+  const size_t idx = blockIdx.x * (size_t)64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
+  float x = 0.f;
+  if (idx < MN)
+    for (int z = q; z < splits; z += 4) x += part[(size_t)z * MN + idx];
+  red[q][threadIdx.x & 63] = x;
+  __syncthreads();
+  if (q == 0 && idx < MN) {
+    const float s = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    epilogue(g, (int)(idx / Nc), (int)(idx % Nc), s);
+  }
+}
+
+// Small-M products C(i, j) = sum_k A[i][k] B[j][k] (both operands
+// contiguous in k; a few rows of activations against a weight matrix).
+// Block = W <= 8 waves over RW = 4 columns j and BT <= 16 rows i (grid over
+// both); thread t takes the 8-element (16-byte) k groups t, t + 64 W, ...,
+// loads the RW weight rows' and the BT activation rows' groups before any
+// product, and keeps the RW x BT sums; with a split activation operand the
+// lo plane's groups follow the hi plane's against the same weight groups.
+// Each wave adds its 64 lanes by recursive halving (a lane keeps half of
+// its sums and trades the other half at each step), the W wave sums are
+// added in wave order through LDS (fixed order), then the epilogue.
+// Columns and rows past the ends are clamped to the last one for loading
+// (in bounds, never stored).  The weights stream from HBM once.
 constexpr int kGemvMaxWaves = 8;
 
 template <class V>
@@ -129,41 +385,45 @@ __global__ __launch_bounds__(64 * kGemvMaxWaves) void gemv_bf16_kernel(GemmArgs 
   const int j0 = blockIdx.x * RW, i0 = blockIdx.y * BT;
   using V = typename std::conditional<GW == 8, uint4, uint2>::type;
   const int ng = g.K / GW;
+  const int planes = g.a_lo ? 2 : 1;
   float v[NV];
 #pragma unroll
   for (int e = 0; e < NV; ++e) v[e] = 0.f;
   for (int q = tid; q < ng; q += 64 * W) {
-    V wr[RW], ar[BT];
+    V wr[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r)
       wr[r] = reinterpret_cast<const V*>(g.B + (long)min(j0 + r, g.N - 1) * g.sbn)[q];
+    for (int pl = 0; pl < planes; ++pl) {
+      V ar[BT];
+      const uint16_t* Ap = g.A + (pl ? g.a_lo : 0);
 #pragma unroll
-    for (int b = 0; b < BT; ++b)
-      ar[b] = reinterpret_cast<const V*>(g.A + (long)min(i0 + b, g.M - 1) * g.sam)[q];
-    __builtin_amdgcn_sched_barrier(0);
+      for (int b = 0; b < BT; ++b) ar[b] = reinterpret_cast<const V*>(Ap + (long)min(i0 + b, g.M - 1) * g.sam)[q];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int h = 0; h < GW / 2; ++h) {
-      float wl[RW], wh[RW], al[BT], ah[BT];
+      for (int h = 0; h < GW / 2; ++h) {
+        float wl[RW], wh[RW], al[BT], ah[BT];
 #pragma unroll
-      for (int r = 0; r < RW; ++r) {
-        const uint32_t u = vword(wr[r], h);
-        wl[r] = __uint_as_float(u << 16);
-        wh[r] = __uint_as_float(u & 0xffff0000u);
-      }
-#pragma unroll
-      for (int b = 0; b < BT; ++b) {
-        const uint32_t u = vword(ar[b], h);
-        al[b] = __uint_as_float(u << 16);
-        ah[b] = __uint_as_float(u & 0xffff0000u);
-      }
-#pragma unroll
-      for (int r = 0; r < RW; ++r)
+        for (int r = 0; r < RW; ++r) {
+          const uint32_t u = vword(wr[r], h);
+          wl[r] = __uint_as_float(u << 16);
+          wh[r] = __uint_as_float(u & 0xffff0000u);
+        }
 #pragma unroll
         for (int b = 0; b < BT; ++b) {
-          float& acc = v[r * BT + b];
-          acc = fmaf(wl[r], al[b], acc);
-          acc = fmaf(wh[r], ah[b], acc);
+          const uint32_t u = vword(ar[b], h);
+          al[b] = __uint_as_float(u << 16);
+          ah[b] = __uint_as_float(u & 0xffff0000u);
         }
+#pragma unroll
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+          for (int b = 0; b < BT; ++b) {
+            float& acc = v[r * BT + b];
+            acc = fmaf(wl[r], al[b], acc);
+            acc = fmaf(wh[r], ah[b], acc);
+          }
+      }
     }
   }
 #pragma unroll
@@ -189,46 +449,25 @@ __global__ __launch_bounds__(64 * kGemvMaxWaves) void gemv_bf16_kernel(GemmArgs 
     if (i < g.M && j < g.N) {
       float x = wsum[0][tid];
       for (int w = 1; w < W; ++w) x += wsum[w][tid];
-      if (g.bias) x += g.bias[j];
-      x *= g.alpha;
-      if (g.C && g.beta != 0.f) x = fmaf(g.beta, g.C[(long)i * g.ldc + j], x);
-      if (g.relu) x = fmaxf(x, 0.f);
-      if (g.C) g.C[(long)i * g.ldc + j] = x;
-      if (g.Cb) g.Cb[(long)i * g.ldcb + j] = f2bf(x);
+      epilogue(g, i, j, x);
     }
   }
-}
-
-// Sum of split-K partials in split order, then the epilogue.
-__global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int splits, const float* __restrict__ part) {
-  const size_t idx = blockIdx.x * (size_t)256 + threadIdx.x;
-  const size_t MN = (size_t)g.M * g.N;
-  if (idx >= MN) return;
-  const int i = (int)(idx / g.N), j = (int)(idx % g.N);
-  float x = 0.f;
-  for (int z = 0; z < splits; ++z) x += part[(size_t)z * MN + idx];
-  if (g.bias) x += g.bias[j];
-  x *= g.alpha;
-  if (g.C && g.beta != 0.f) x = fmaf(g.beta, g.C[(long)i * g.ldc + j], x);
-  if (g.relu) x = fmaxf(x, 0.f);
-  if (g.C) g.C[(long)i * g.ldc + j] = x;
-  if (g.Cb) g.Cb[(long)i * g.ldcb + j] = f2bf(x);
 }
 
 // ---------------------------------------------------------------------------
 // im2col for a 3x3 stride-2 pad-1 convolution, NHWC input:
 // cols[(b, yo, xo)][c * 9 + ky * 3 + kx] = act[b][2 yo + ky - 1][2 xo + kx - 1][c] (0 outside).
-// (Also from an FP32 input, rounded to bf16 as to_bf16_kernel rounds it: the
-// network input's conversion and its im2col in one pass.)
-__device__ __forceinline__ uint16_t as_bf16(uint16_t h) { return h; }
-__device__ __forceinline__ uint16_t as_bf16(float f) { return f2bf(f); }
-
+// From a bf16 pair input (lo plane n_in elements after the hi plane) both
+// planes are gathered (the lo plane of cols n_out elements after its hi
+// plane); from an FP32 input each value is rounded to bf16 (one plane): the
+// network input's conversion and its im2col in one pass.
 template <typename T>
 __global__ __launch_bounds__(256) void im2col_kernel(const T* __restrict__ act, int B, int H, int W,
                                                      int C, uint16_t* __restrict__ cols) {
   const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
   const size_t K9 = (size_t)C * 9;
   const size_t total = (size_t)B * Ho * Wo * K9;
+  const size_t n_in = (size_t)B * H * W * C;
   for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
     const size_t row = idx / K9;
     const int col = (int)(idx - row * K9);
@@ -237,18 +476,24 @@ __global__ __launch_bounds__(256) void im2col_kernel(const T* __restrict__ act, 
     const int rem = (int)(row - (size_t)b * Ho * Wo);
     const int yo = rem / Wo, xo = rem - yo * Wo;
     const int y = 2 * yo + ky - 1, x = 2 * xo + kx - 1;
-    cols[idx] = (y >= 0 && y < H && x >= 0 && x < W) ? as_bf16(act[(((size_t)b * H + y) * W + x) * C + c])
-                                                      : (uint16_t)0;
+    const bool in = y >= 0 && y < H && x >= 0 && x < W;
+    const size_t src = (((size_t)b * H + y) * W + x) * C + c;
+    if constexpr (std::is_same<T, float>::value) {
+      cols[idx] = in ? f2bf(act[src]) : (uint16_t)0;
+    } else {
+      cols[idx] = in ? act[src] : (uint16_t)0;
+      cols[idx + total] = in ? act[src + n_in] : (uint16_t)0;
+    }
   }
 }
 
 // Gradient of im2col (gather form) fused with the ReLU mask of the layer's
-// forward output act: dz[b][y][x][c] = (act > 0) * sum over the (ky, kx)
-// whose output pixel (yo, xo) = ((y + 1 - ky) / 2, (x + 1 - kx) / 2) exists,
-// in ky-major order.  Writes FP32 and bf16 hi/lo (lo at dzb + B H W C).
+// forward output act (hi plane): dz[b][y][x][c] = (act > 0) * sum over the
+// (ky, kx) whose output pixel (yo, xo) = ((y + 1 - ky) / 2, (x + 1 - kx) / 2)
+// exists, in ky-major order.  Writes the bf16 pair (lo at dzb + B H W C).
 __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restrict__ dcols, int B, int H, int W,
                                                           int C, const uint16_t* __restrict__ act,
-                                                          float* __restrict__ dz, uint16_t* __restrict__ dzb) {
+                                                          uint16_t* __restrict__ dzb) {
   const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
   const size_t total = (size_t)B * H * W * C;
   for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
@@ -268,76 +513,65 @@ __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restric
         s += dcols[(((size_t)b * Ho + (yy >> 1)) * Wo + (xx >> 1)) * (size_t)(C * 9) + c * 9 + ky * 3 + kx];
       }
     }
-    const float gv = bf_pos(act[idx]) ? s : 0.f;
-    dz[idx] = gv;
-    split_bf(gv, dzb, dzb + total, idx);
+    split_bf(bf_pos(act[idx]) ? s : 0.f, dzb, dzb + total, idx);
   }
 }
 
-// Split of an FP32 value into bf16 hi + lo (hi = bf16(v), lo = bf16(v - hi)):
-// a product on the pair keeps ~16 significant bits of v.
-__device__ __forceinline__ void split_bf(float v, uint16_t* hi, uint16_t* lo, size_t i) {
-  const uint16_t h = f2bf(v);
-  hi[i] = h;
-  lo[i] = f2bf(v - bf2f(h));
-}
-
-// dz = (act > 0) * g, FP32 and bf16 hi/lo (lo written at dzb + n).
+// dz = (act > 0) * g as a bf16 pair (lo written at dzb + n).
 __global__ __launch_bounds__(256) void relu_mask_kernel(const float* __restrict__ g, const uint16_t* __restrict__ act,
-                                                        size_t n, float* __restrict__ dz, uint16_t* __restrict__ dzb) {
-  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-    const float v = bf_pos(act[i]) ? g[i] : 0.f;
-    dz[i] = v;
-    split_bf(v, dzb, dzb + n, i);
-  }
+                                                        size_t n, uint16_t* __restrict__ dzb) {
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    split_bf(bf_pos(act[i]) ? g[i] : 0.f, dzb, dzb + n, i);
 }
 
 __global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ x, size_t n, uint16_t* __restrict__ y) {
   for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) y[i] = f2bf(x[i]);
 }
 
-// Column sums of dz [rows][N] (bias gradient): one block per column, fixed
-// per-thread strides then a fixed tree.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ dz, int rows, int N, float* __restrict__ out) {
+// Weighted MSE: gradient 2 w (p - t) / n as a bf16 pair (lo at doutb + n)
+// and per-block partial sums of w (p - t)^2 (block b: elements
+// [b 1024, (b + 1) 1024), fixed tree); mse_sum_kernel adds the partials in
+// block order and divides by n.
+constexpr int kMseBlock = 1024;
+
+__global__ __launch_bounds__(256) void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
+                                                  const float* __restrict__ weights, int n, int n_out,
+                                                  uint16_t* __restrict__ doutb, float* __restrict__ part) {
   __shared__ float red[256];
-  const int j = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  const float inv = 1.f / (float)n;
   float s = 0.f;
-  for (int r = tid; r < rows; r += 256) s += dz[(size_t)r * N + j];
+  for (int t = 0; t < kMseBlock / 256; ++t) {
+    const int i = blockIdx.x * kMseBlock + t * 256 + tid;
+    if (i < n) {
+      const float d = pred[i] - target[i];
+      const float w = weights ? weights[i / n_out] : 1.f;
+      s = fmaf(w * d, d, s);
+      split_bf(2.f * w * d * inv, doutb, doutb + n, i);
+    }
+  }
   red[tid] = s;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
     if (tid < st) red[tid] += red[tid + st];
     __syncthreads();
   }
-  if (tid == 0) out[j] = red[0];
+  if (tid == 0) part[blockIdx.x] = red[0];
 }
 
-// Weighted MSE loss (one block): loss = sum_i w[i / n_out] (p_i - t_i)^2 / n,
-// gradient 2 w (p - t) / n in FP32 and bf16 hi/lo (lo at doutb + n); w = 1
-// when weights is NULL.
-__global__ __launch_bounds__(1024) void mse_kernel(const float* __restrict__ pred, const float* __restrict__ target,
-                                                   const float* __restrict__ weights, int n, int n_out,
-                                                   float* __restrict__ dout, uint16_t* __restrict__ doutb,
-                                                   float* __restrict__ loss) {
-  __shared__ float red[1024];
+__global__ __launch_bounds__(256) void mse_sum_kernel(const float* __restrict__ part, int nb, int n,
+                                                      float* __restrict__ loss) {
+  __shared__ float red[256];
   const int tid = threadIdx.x;
-  const float inv = 1.f / (float)n;
   float s = 0.f;
-  for (int i = tid; i < n; i += 1024) {
-    const float d = pred[i] - target[i];
-    const float w = weights ? weights[i / n_out] : 1.f;
-    s = fmaf(w * d, d, s);
-    const float gv = 2.f * w * d * inv;
-    dout[i] = gv;
-    split_bf(gv, doutb, doutb + n, i);
-  }
+  for (int b = tid; b < nb; b += 256) s += part[b];
   red[tid] = s;
   __syncthreads();
-  for (int st = 512; st > 0; st >>= 1) {
+  for (int st = 128; st > 0; st >>= 1) {
     if (tid < st) red[tid] += red[tid + st];
     __syncthreads();
   }
-  if (tid == 0 && loss) *loss = red[0] * inv;
+  if (tid == 0) *loss = red[0] / (float)n;
 }
 
 // Adam on the FP32 master weights; refreshes the bf16 copy.
@@ -413,36 +647,87 @@ static hipError_t launch_gemv_gw(const GemmArgs& g, hipStream_t st) {
   return launch_gemv<16, GW>(g, st);
 }
 
+// Widest load group (8, 4 or 1 elements) along the contiguous dimension of
+// an operand: its extent and the other stride must be multiples, the base
+// (and lo plane) aligned.
+static int vec_width(const uint16_t* p, long lo, long other_stride, int extent) {
+  for (int w : {8, 4}) {
+    const uintptr_t al = (uintptr_t)w * 2;
+    if (extent % w == 0 && other_stride % w == 0 && lo % w == 0 && (uintptr_t)p % al == 0) return w;
+  }
+  return 1;
+}
+
+template <int WM, int WN, int TM, int TN, bool AKC, bool BKC>
+static hipError_t launch_tile(const GemmArgs& g, const OpView& va, const OpView& vb, int splits, int kc, float* part,
+                              hipStream_t st) {
+  constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN;
+  const int Nc = g.N + (g.bias_grad ? 1 : 0);
+  const size_t lds = (size_t)2 * (BM * (g.a_lo ? 2 : 1) + BN * (g.b_lo ? 2 : 1)) * kPitch * sizeof(uint16_t);
+  hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, TM, TN, AKC, BKC>), dim3((Nc + BN - 1) / BN, (g.M + BM - 1) / BM, splits),
+                     dim3(256), lds, st, g, va, vb, kc, splits > 1 ? part : (float*)nullptr);
+  return hipGetLastError();
+}
+
+template <int WM, int WN, int TM, int TN>
+static hipError_t launch_layout(const GemmArgs& g, const OpView& va, const OpView& vb, bool akc, bool bkc, int splits,
+                                int kc, float* part, hipStream_t st) {
+  if (akc && bkc) return launch_tile<WM, WN, TM, TN, true, true>(g, va, vb, splits, kc, part, st);
+  if (akc) return launch_tile<WM, WN, TM, TN, true, false>(g, va, vb, splits, kc, part, st);
+  if (bkc) return launch_tile<WM, WN, TM, TN, false, true>(g, va, vb, splits, kc, part, st);
+  return launch_tile<WM, WN, TM, TN, false, false>(g, va, vb, splits, kc, part, st);
+}
+
 hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
-  // Up to 512 rows with both operands contiguous in k (the fully connected
-  // layers, and the convolutions of a single frame): the matrix-vector kernel,
-  // one launch and no split-K pass (measured faster than the MFMA tiles up to
-  // 16 frames; at 64 frames every convolution has more rows and keeps them).
-  if (g.M <= 512 && g.sak == 1 && g.sbk == 1) {
-    if (g.K % 8 == 0 && g.sam % 8 == 0 && g.sbn % 8 == 0 && (uintptr_t)g.A % 16 == 0 && (uintptr_t)g.B % 16 == 0)
+  // A few rows with both operands contiguous in k (the layers of one or a
+  // few frames): the matrix-vector kernel, which streams the weights once.
+  if (!g.bias_grad && g.b_lo == 0 && g.sak == 1 && g.sbk == 1 &&
+      (g.M <= 16 || (g.M <= 512 && (long)g.N * g.K <= 65536))) {
+    if (g.K % 8 == 0 && g.sam % 8 == 0 && g.sbn % 8 == 0 && g.a_lo % 8 == 0 && (uintptr_t)g.A % 16 == 0 &&
+        (uintptr_t)g.B % 16 == 0)
       return launch_gemv_gw<8>(g, st);
-    if (g.K % 4 == 0 && g.sam % 4 == 0 && g.sbn % 4 == 0 && (uintptr_t)g.A % 8 == 0 && (uintptr_t)g.B % 8 == 0)
+    if (g.K % 4 == 0 && g.sam % 4 == 0 && g.sbn % 4 == 0 && g.a_lo % 4 == 0 && (uintptr_t)g.A % 8 == 0 &&
+        (uintptr_t)g.B % 8 == 0)
       return launch_gemv_gw<4>(g, st);
   }
-  const int bx = (g.N + 63) / 64, by = (g.M + 63) / 64;
-  const long blocks = (long)bx * by;
+  const int Nc = g.N + (g.bias_grad ? 1 : 0);
+  // Operand views: A rows = i, B rows = j.
+  const bool akc = g.sak == 1, bkc = g.sbk == 1;
+  if (!akc && g.sam != 1) return hipErrorInvalidValue;
+  if (!bkc && g.sbn != 1) return hipErrorInvalidValue;
+  OpView va{g.A, g.sam, g.sak, g.M, -1, 1};
+  OpView vb{g.B, g.sbn, g.sbk, g.N, g.bias_grad ? g.N : -1, 1};
+  va.vw = akc ? vec_width(g.A, g.a_lo, g.sam, g.K) : vec_width(g.A, g.a_lo, g.sak, g.M);
+  vb.vw = bkc ? vec_width(g.B, g.b_lo, g.sbn, g.K) : vec_width(g.B, g.b_lo, g.sbk, g.N);
+  // Tile: the N extent picks the width; tall products take 128 rows.
+  int tile;   // 0: 128 x 32, 1: 128 x 64, 2: 128 x 128, 3: 64 x 64
+  if (Nc <= 32) tile = 0;
+  else if (Nc <= 64) tile = 1;
+  else if (g.M >= 512 && !(g.a_lo && g.b_lo)) tile = 2;   // (both split: 64 x 64, LDS <= 64 KB)
+  else tile = 3;
+  const int BM = tile == 3 ? 64 : 128;
+  const int BN = tile == 0 ? 32 : tile == 1 ? 64 : tile == 2 ? 128 : 64;
+  const long tiles = (long)((Nc + BN - 1) / BN) * ((g.M + BM - 1) / BM);
+  // Split K while the tiles leave the GPU's 256 CUs short of two blocks each
+  // and every split keeps at least 4 k steps; partials must fit `part`.
   int splits = 1;
-  if (part && blocks < 512 && g.K >= 256) {
-    splits = (int)std::min<long>((512 + blocks - 1) / blocks, (g.K + 127) / 128);
-    while (splits > 1 && (size_t)splits * g.M * g.N > part_elems) --splits;
+  if (part && tiles < 512) {
+    splits = (int)std::min<long>((512 + tiles - 1) / tiles, std::max(1, g.K / (4 * kBK)));
+    while (splits > 1 && (size_t)splits * g.M * Nc > part_elems) --splits;
   }
-  const int kc = ((g.K + splits - 1) / splits + 31) / 32 * 32;
+  const int kc = ((g.K + splits - 1) / splits + kBK - 1) / kBK * kBK;
   splits = (g.K + kc - 1) / kc;
-  if (splits <= 1) {
-    hipLaunchKernelGGL(gemm_bf16_kernel, dim3(bx, by, 1), dim3(256), 0, st, g, g.K, (float*)nullptr);
-    return hipGetLastError();
+  hipError_t e;
+  switch (tile) {
+    case 0: e = launch_layout<4, 1, 1, 1>(g, va, vb, akc, bkc, splits, kc, part, st); break;
+    case 1: e = launch_layout<2, 2, 2, 1>(g, va, vb, akc, bkc, splits, kc, part, st); break;
+    case 2: e = launch_layout<2, 2, 2, 2>(g, va, vb, akc, bkc, splits, kc, part, st); break;
+    default: e = launch_layout<2, 2, 1, 1>(g, va, vb, akc, bkc, splits, kc, part, st); break;
   }
-  hipLaunchKernelGGL(gemm_bf16_kernel, dim3(bx, by, splits), dim3(256), 0, st, g, kc, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const size_t MN = (size_t)g.M * g.N;
-  hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, g, splits,
+  if (e != hipSuccess || splits <= 1) return e;
+  const size_t MN = (size_t)g.M * Nc;
+  hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((MN + 63) / 64)), dim3(256), 0, st, g, splits,
                      (const float*)part);
   return hipGetLastError();
 }
@@ -459,15 +744,15 @@ hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* co
   return hipGetLastError();
 }
 
-hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, float* dz,
-                       uint16_t* dzb, hipStream_t st) {
+hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, uint16_t* dzb,
+                       hipStream_t st) {
   const size_t total = (size_t)B * H * W * C;
-  hipLaunchKernelGGL(col2im_mask_kernel, dim3(grid_for(total)), dim3(256), 0, st, dcols, B, H, W, C, act, dz, dzb);
+  hipLaunchKernelGGL(col2im_mask_kernel, dim3(grid_for(total)), dim3(256), 0, st, dcols, B, H, W, C, act, dzb);
   return hipGetLastError();
 }
 
-hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, float* dz, uint16_t* dzb, hipStream_t st) {
-  hipLaunchKernelGGL(relu_mask_kernel, dim3(grid_for(n)), dim3(256), 0, st, g, act, n, dz, dzb);
+hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, uint16_t* dzb, hipStream_t st) {
+  hipLaunchKernelGGL(relu_mask_kernel, dim3(grid_for(n)), dim3(256), 0, st, g, act, n, dzb);
   return hipGetLastError();
 }
 
@@ -476,14 +761,15 @@ hipError_t to_bf16(const float* x, size_t n, uint16_t* y, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t colsum(const float* dz, int rows, int N, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(colsum_kernel, dim3(N), dim3(256), 0, st, dz, rows, N, out);
-  return hipGetLastError();
-}
+size_t mse_partials(int n) { return (size_t)(n + kMseBlock - 1) / kMseBlock; }
 
-hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, float* dout,
-               uint16_t* doutb, float* loss, hipStream_t st) {
-  hipLaunchKernelGGL(mse_kernel, dim3(1), dim3(1024), 0, st, pred, target, weights, n, n_out, dout, doutb, loss);
+hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, uint16_t* doutb,
+               float* loss, float* part, hipStream_t st) {
+  const int nb = (int)mse_partials(n);
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, pred, target, weights, n, n_out, doutb, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !loss) return e;
+  hipLaunchKernelGGL(mse_sum_kernel, dim3(1), dim3(256), 0, st, (const float*)part, nb, n, loss);
   return hipGetLastError();
 }
 

@@ -11,6 +11,14 @@ namespace cnn {
 
 // C(i, j) = alpha (sum_k A(i, k) B(k, j) [+ bias[j]]) [+ beta C(i, j)] [ReLU], bf16
 // operands, FP32 accumulation; outputs FP32 (C) and/or bf16 (Cb).
+// A(i, k) = A[i sam + k sak], B(k, j) = B[k sbk + j sbn].
+// Split operands: with a_lo != 0 the operand A is the bf16 pair hi + lo, the
+// lo plane at A + a_lo (same strides); likewise b_lo for B.  The product is
+// A_hi B_hi + A_lo B_hi + A_hi B_lo (the lo x lo term, below 2^-16 of the
+// product, is left out).  With cb_lo != 0 the bf16 output is written as a
+// pair too: Cb = bf16(x), Cb[. + cb_lo] = bf16(x - Cb).
+// bias_grad: an extra output column j = N with B(k, N) = 1 (hi plane; 0 in
+// the lo plane), i.e. bias_grad[i] = sum_k A(i, k), written raw.
 struct GemmArgs {
   const uint16_t* A;
   long sam, sak;
@@ -25,20 +33,27 @@ struct GemmArgs {
   float alpha;
   float beta;
   int relu;
+  long a_lo, b_lo, cb_lo;
+  float* bias_grad;
 };
 
 // part: split-K partial buffer of part_elems floats (NULL disables split-K).
 hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t st);
+// Activations are bf16 pairs: the lo plane of act (cols) lies n elements after
+// its hi plane, n the plane's element count.
 hipError_t im2col(const uint16_t* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st);
 // The same from an FP32 input, each value rounded to bf16 (round to nearest even).
 hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st);
-hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, float* dz,
-                       uint16_t* dzb, hipStream_t st);
-hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, float* dz, uint16_t* dzb, hipStream_t st);
+// Data gradients masked by the forward output's ReLU, written as bf16 pairs
+// (lo plane after the hi plane).
+hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, uint16_t* dzb,
+                       hipStream_t st);
+hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, uint16_t* dzb, hipStream_t st);
 hipError_t to_bf16(const float* x, size_t n, uint16_t* y, hipStream_t st);
-hipError_t colsum(const float* dz, int rows, int N, float* out, hipStream_t st);
-hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, float* dout,
-               uint16_t* doutb, float* loss, hipStream_t st);
+// part: at least mse_partials(n) floats of scratch.
+size_t mse_partials(int n);
+hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, uint16_t* doutb,
+               float* loss, float* part, hipStream_t st);
 hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, size_t n, float lr, float b1, float b2,
                 float eps, float c1, float c2, hipStream_t st);
 hipError_t fill0(float* p, size_t n, hipStream_t st);

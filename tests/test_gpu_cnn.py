@@ -1,32 +1,36 @@
 """CNN reconstructor kernels (through the C ABI) against the FP64 oracle.
 
-Both sides use the same bf16-rounded weights and inputs.  The GPU stores
-hidden activations in bf16 (the operands of the next products), carries
-upstream gradients as bf16 hi/lo pairs (~16 bits) and accumulates in FP32.
-Two gates per tensor (relative L2):
-  * against the exact FP64 oracle: <= 2e-2.  Each stored activation is
-    rounded by up to 2^-9; the first-layer weight gradient sums many terms
-    of both signs, which amplifies that relative error by ~10x;
-  * against the oracle with the same bf16 activation rounding
-    (act_round=bf16_round): <= 1e-4 on the small net, where only FP32
-    accumulation and the hi/lo gradient split remain (measured ~5e-6); on
-    the full net <= 1e-2: a pre-activation accumulated in FP32 (GPU) or FP64
-    (oracle) occasionally falls on the other side of a bf16 rounding
-    boundary (a quantisation decision the two summation orders cannot take
-    identically), and the first-layer weight gradient's cancellation
-    amplifies those flips (measured 4.8e-3 there, <= 2e-4 on the outputs).
+Both sides use the same bf16-rounded weights and inputs; the oracle is
+exact FP64 from there on.  The GPU carries every hidden activation and every
+upstream gradient as a bf16 pair hi + lo (the value to ~2^-17 relative),
+multiplies on the bf16 matrix cores and accumulates in FP32.  Gates per
+tensor, relative L2 and per element (max |error| / max |reference|):
+  * forward outputs: <= 1e-4 (pair rounding ~7.6e-6 per operand and FP32
+    accumulation over up to 2048 terms, ~1e-5 expected);
+  * parameter gradients: <= 1e-4 (the same per-operand errors, amplified by
+    the cancellation in the sums over the batch and the positions: a bias
+    or first-layer weight gradient is a small sum of many terms of both
+    signs; measured <= 1.1e-5);
+  * the loss: <= 1e-4 relative.
+The forward runs at 1, 3, 8, 16 and 21 frames, which crosses every
+batch-size form of the matrix-vector kernel (1, 4, 8, 16 rows), its limit
+on the rows of the convolutions (at most 512, reached at 16 frames by the
+last convolution only) and the tiled MFMA product at every layer (21
+frames), also with alpha and beta (the loop's accumulate form).
 Adam and input preparation are FP32 elementwise: 1e-5.
 """
 import numpy as np
 import pytest
 
 from oracle import cnn as ocnn
-from tests.gpu_common import torch_cuda, rel_l2, say
+from tests.gpu_common import torch_cuda, rel_l2, rel_max, say
 
 pytestmark = pytest.mark.gpu
 
 SMALL = dict(n_sub=9, c1=3, c2=5, c3=4, hidden=37, n_out=11)
 FULL = dict(n_sub=40, c1=32, c2=64, c3=64, hidden=2048, n_out=600)
+FWD_TOL = 1e-4
+GRAD_TOL = 1e-4
 
 
 def bf16_round(a):
@@ -64,23 +68,31 @@ def _setup(cfg, B, seed):
     return net, torch, p, po, x, bf16_round(x), tgt
 
 
-TOL_Q = {"small": 1e-4, "full": 1e-2}
+FWD_CASES = [(SMALL, 5), (FULL, 1), (FULL, 3), (FULL, 8), (FULL, 16), (FULL, 21)]
 
 
-@pytest.mark.parametrize("cfg,B", [(SMALL, 5), (FULL, 16)], ids=["small", "full"])
+@pytest.mark.parametrize("cfg,B", FWD_CASES, ids=["small-5", "full-1", "full-3", "full-8", "full-16", "full-21"])
 def test_forward_matches_oracle(cfg, B):
     net, torch, p, po, x, xb, tgt = _setup(cfg, B, 3)
     out = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     ref, _ = ocnn.forward(po, xb.astype(np.float64))
-    refq, _ = ocnn.forward(po, xb.astype(np.float64), act_round=ocnn.bf16_round)
-    e, eq = rel_l2(out, ref), rel_l2(out, refq)
-    say(f"[gpu] cnn forward {cfg['n_sub']}x{cfg['n_out']} B={B}: rel err {e:.3e} (exact), {eq:.3e} (bf16 act)")
-    assert e <= 2e-2
-    assert eq <= TOL_Q["small" if cfg is SMALL else "full"]
+    e, em = rel_l2(out, ref), rel_max(out, ref)
+    say(f"[gpu] cnn forward {cfg['n_sub']}x{cfg['n_out']} B={B}: rel err {e:.3e} (max {em:.3e})")
+    assert e <= FWD_TOL and em <= FWD_TOL
+    # accumulate form: out = alpha net(x) + beta out
+    acc0 = np.random.default_rng(B).normal(0, 1.0, out.shape).astype(np.float32)
+    acc = torch.from_numpy(acc0).cuda()
+    net.forward_acc(torch.from_numpy(x).cuda(), acc, 0.4, 0.75)
+    refa = 0.4 * ref + 0.75 * acc0.astype(np.float64)
+    ea = rel_max(acc.cpu().numpy(), refa)
+    say(f"[gpu]   accumulate form (alpha 0.4, beta 0.75): max err {ea:.3e}")
+    assert ea <= FWD_TOL
+    net.close()
 
 
-@pytest.mark.parametrize("cfg,B,weighted", [(SMALL, 5, False), (FULL, 16, False), (SMALL, 6, True)],
-                         ids=["small", "full", "small-weighted"])
+@pytest.mark.parametrize("cfg,B,weighted", [(SMALL, 5, False), (FULL, 16, False), (SMALL, 6, True),
+                                            (FULL, 3, True)],
+                         ids=["small", "full", "small-weighted", "full-3-weighted"])
 def test_gradients_match_oracle(cfg, B, weighted):
     net, torch, p, po, x, xb, tgt = _setup(cfg, B, 5)
     w = np.random.default_rng(6).uniform(0.2, 3.0, B).astype(np.float32) if weighted else None
@@ -88,23 +100,19 @@ def test_gradients_match_oracle(cfg, B, weighted):
                             None if w is None else torch.from_numpy(w).cuda())
     g = g.cpu().numpy()
     lo, go, _ = ocnn.loss_and_grads(po, xb.astype(np.float64), tgt.astype(np.float64), weights=w)
-    lq, gq, _ = ocnn.loss_and_grads(po, xb.astype(np.float64), tgt.astype(np.float64),
-                                    act_round=ocnn.bf16_round, weights=w)
-    assert abs(float(loss.cpu()) - lo) <= 2e-2 * lo
-    tq = TOL_Q["small" if cfg is SMALL else "full"]
-    assert abs(float(loss.cpu()) - lq) <= tq * lq
+    say(f"[gpu] cnn loss B={B}: {float(loss.cpu()):.6e} (oracle {lo:.6e})")
+    assert abs(float(loss.cpu()) - lo) <= FWD_TOL * lo
     off = 0
     for k in ocnn.PARAM_ORDER:
         n = int(np.prod(net.shapes[k]))
-        e = rel_l2(g[off:off + n], go[k].ravel())
-        eq = rel_l2(g[off:off + n], gq[k].ravel())
-        say(f"[gpu] cnn grad {k}: rel err {e:.3e} (exact FP64), {eq:.3e} (bf16 activations)")
-        assert e <= 2e-2, k
-        assert eq <= tq, k
+        e, em = rel_l2(g[off:off + n], go[k].ravel()), rel_max(g[off:off + n], go[k].ravel())
+        say(f"[gpu] cnn grad {k}: rel err {e:.3e} (max {em:.3e}) against exact FP64")
+        assert e <= GRAD_TOL and em <= GRAD_TOL, k
         off += n
     g2, _ = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda(),
                           None if w is None else torch.from_numpy(w).cuda())
     assert np.array_equal(g, g2.cpu().numpy())          # deterministic
+    net.close()
 
 
 def test_adam_step_matches_formula():

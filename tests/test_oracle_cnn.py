@@ -159,15 +159,3 @@ def test_bf16_round_values():
     assert cnn.bf16_round(np.array([1.0 + 2 ** -8]))[0] == 1.0                 # tie -> even (1.0)
     assert cnn.bf16_round(np.array([1.0 + 3 * 2 ** -8]))[0] == 1.0 + 2 ** -6    # tie -> even
     assert np.all(np.abs(r - v) <= 2 ** -8 * np.abs(v))
-
-
-def test_activation_rounding_is_identity_when_exact():
-    shapes = cnn.param_shapes(S=9, c_in=4, chans=(2, 3, 3), hidden=5, n_out=4)
-    rng = np.random.default_rng(12)
-    p = _rand_params(shapes, rng)
-    x = rng.normal(size=(2, 9, 9, 4))
-    a = cnn.forward(p, x)[0]
-    b = cnn.forward(p, x, act_round=lambda v: v)[0]
-    c = cnn.forward(p, x, act_round=cnn.bf16_round)[0]
-    assert np.array_equal(a, b)
-    assert 0 < np.abs(c - a).max() < 1e-2 * np.abs(a).max()
