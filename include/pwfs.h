@@ -146,6 +146,26 @@ int pwfs_set_reference(pwfs_plan_t plan, const float* d_sref, void* stream);
 int pwfs_measure(pwfs_plan_t plan, const float* d_opd_nm, int32_t B,
                  float* d_pupils, float* d_slopes, void* stream);
 
+/* pwfs_measure without allocation, for callers that cannot allocate device
+ * memory or must not touch the plan's workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, slices, schedules, kernels and results (bit for bit) as
+ * pwfs_measure; the workspace regions (row-pass intermediate, chunk
+ * partials, pupil field, internal images, detector and field-stop buffers)
+ * come from one static device array of PWFS_STATIC_SCRATCH_BYTES per GPU,
+ * held until the process ends.  A slice of min(B, batch_max) frames must
+ * fit in it (10.2 MB of intermediate per frame at n_pupil 160, i.e. one or
+ * two frames per slice; ~0.2 MB at n_pupil 32), else PWFS_ERR_UNSUPPORTED
+ * with the bytes needed in pwfs_last_error().  Calls no hipMalloc or
+ * hipFree.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, or two host threads) race and give
+ * undefined results.  No region needs to start at zero (each call writes
+ * every element it reads), so the array's contents between calls do not
+ * matter. */
+#define PWFS_STATIC_SCRATCH_BYTES (32u << 20)
+int pwfs_measure_static(pwfs_plan_t plan, const float* d_opd_nm, int32_t B,
+                        float* d_pupils, float* d_slopes, void* stream);
+
 /* Copy the pupil amplitude used by the plan (P * P floats, [y][x]) into
  * host memory. */
 int pwfs_get_pupil(pwfs_plan_t plan, float* amp_host);

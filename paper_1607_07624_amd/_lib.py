@@ -69,6 +69,7 @@ def load_library():
     lib.pwfs_get_reference.argtypes = [vp, vp]
     lib.pwfs_set_reference.argtypes = [vp, vp, vp]
     lib.pwfs_measure.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.pwfs_measure_static.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.recon_apply.argtypes = [vp, i32, i32, vp, i32, f32, f32, vp, vp]
     lib.pwfs_get_pupil.argtypes = [vp, vp]
     lib.pwfs_timing_enable.argtypes = [vp, ctypes.c_int]
@@ -283,6 +284,21 @@ class Plan:
             _need(slopes, t, t.float32, B * 2 * self.n_valid, "slopes")
         _check(self.lib.pwfs_measure(self.handle, _ptr(opd), B, _ptr(pupils), _ptr(slopes),
                                      _stream_handle(t, self.device)), "pwfs_measure")
+        return pupils, slopes
+
+    def measure_static_into(self, opd, pupils=None, slopes=None):
+        """pwfs_measure_static (no allocation: the workspace is the library's
+        static device array) on caller-owned tensors."""
+        t = self._torch
+        P, S = self.cfg.n_pupil, self.n_sub
+        B = opd.shape[0] if opd.dim() == 3 else 1
+        _need(opd, t, t.float32, B * P * P, "opd")
+        if pupils is not None:
+            _need(pupils, t, t.float32, B * 4 * S * S, "pupils")
+        if slopes is not None:
+            _need(slopes, t, t.float32, B * 2 * self.n_valid, "slopes")
+        _check(self.lib.pwfs_measure_static(self.handle, _ptr(opd), B, _ptr(pupils), _ptr(slopes),
+                                            _stream_handle(t, self.device)), "pwfs_measure_static")
         return pupils, slopes
 
     def measure(self, opd, want_pupils: bool = True):

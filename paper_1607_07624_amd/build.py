@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libpwfs.so")
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("pwfs_kernels.hip", "pwfs_kernels16.hip",
-                                                  "pwfs_detector.hip", "pwfs_psf.hip", "pwfs_sh.hip", "pwfs_fstop.hip",
+                                                  "pwfs_detector.hip", "pwfs_psf.hip", "pwfs_sh.hip", "pwfs_fstop.hip", "pwfs_static.hip",
                                                   "pwfs_api.cpp",
                                                   "cnn_kernels.hip", "cnn_api.cpp")]
 FLAGS = [

@@ -266,8 +266,25 @@ void free_plan(pwfs_plan_s* p) {
   delete p;
 }
 
+// Device memory a slice works in beyond its inputs and outputs: the plan's
+// own workspace, or a caller-supplied region (measure_in_workspace).
+struct Workspace {
+  cpx* Rw;            // row-pass intermediate
+  float* partial;     // chunk partials
+  float* pupils;      // images when the caller passes none (noiseless images with a detector)
+  float* pixels;      // detector output when the caller passes no pupils
+  float* fullres;     // full-resolution images (det_window, field stop)
+  cpx* field;         // pupil field
+  cpx* fs_Z;          // field-stop row transforms
+  cpx* fs_W;          // field-stop column transforms
+};
+
+Workspace plan_workspace(const pwfs_plan_s* p) {
+  return Workspace{p->Rw, p->partial, p->pupils, p->pixels, p->fullres, p->field, p->fs_Z, p->fs_W};
+}
+
 pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int Bs, float* pupils, float* slopes,
-                             const float* sref) {
+                             const float* sref, const Workspace& ws) {
   pwfs::MeasureArgs a{};
   a.P = p->P;
   a.n_bin = p->b;
@@ -281,13 +298,13 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
   a.kphase = p->kphase;
   a.fp32_phase = (p->cfg.flags & 2) != 0;
   a.opd = opd + (size_t)b0 * p->P * p->P;
-  a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : (p->det_on ? p->pixels : p->pupils);
+  a.pupils = pupils ? pupils + (size_t)b0 * 4 * p->S * p->S : (p->det_on ? ws.pixels : ws.pupils);
   a.det_on = p->det_on ? 1 : 0;
   a.det_gain = p->det_gain;
   a.det_ron = (float)p->det_ron;
   a.det_seed = p->det_seed;
   a.frame0 = p->frame_next + (uint64_t)b0;
-  a.intensity = p->pupils;
+  a.intensity = ws.pupils;
   a.slopes = slopes ? slopes + (size_t)b0 * 2 * p->nv : nullptr;
   a.amp = p->amp;
   a.in_a = p->in_a;
@@ -301,10 +318,10 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
   a.k_ia = p->k_ia;
   a.valid = p->d_valid;
   a.sref = sref;
-  a.Rw = p->Rw;
-  a.field = p->field;
-  a.partial = p->partial;
-  a.fullres = p->fullres;
+  a.Rw = ws.Rw;
+  a.field = ws.field;
+  a.partial = ws.partial;
+  a.fullres = ws.fullres;
   a.rebin_S = (p->Sd > 0 || p->fs_on) ? p->S : 0;
   if (p->fs_on) {
     // Output pass of the field-stop path: modulation chunks for ~2048 blocks.
@@ -320,17 +337,18 @@ pwfs::MeasureArgs slice_args(const pwfs_plan_s* p, const float* opd, int b0, int
     a.fs_twp = p->fs_twp;
     a.fs_twi = p->fs_twi;
     a.fs_py = p->fs_py;
-    a.fs_Z = p->fs_Z;
-    a.fs_W = p->fs_W;
+    a.fs_Z = ws.fs_Z;
+    a.fs_W = ws.fs_W;
   }
   return a;
 }
 
 int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* slopes,
-                const float* sref, hipStream_t st) {
+                const float* sref, hipStream_t st, const Workspace* ws_in = nullptr) {
+  const Workspace ws = ws_in ? *ws_in : plan_workspace(p);
   for (int b0 = 0; b0 < B; b0 += p->batch_max) {
     const int Bs = std::min(p->batch_max, B - b0);
-    pwfs::MeasureArgs a = slice_args(p, opd, b0, Bs, pupils, slopes, sref);
+    pwfs::MeasureArgs a = slice_args(p, opd, b0, Bs, pupils, slopes, sref, ws);
     hipEvent_t* ev = nullptr;
     if (p->timing) {
       std::array<hipEvent_t, 4> evs{};
@@ -354,6 +372,66 @@ int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* s
 }
 
 }  // namespace
+
+namespace pwfs {
+
+// Carves the regions of one slice of Bs frames out of `base` (256-byte
+// aligned regions, in the order of Workspace); returns the bytes used.
+// With base == nullptr only the size is computed.
+size_t carve_workspace(const pwfs_plan_s* p, int Bs, char* base, Workspace* ws) {
+  int ac, kc, nc;
+  split_work(p, Bs, &ac, &kc, &nc);
+  if (p->fs_on) {
+    // the field-stop output pass picks its own modulation chunks
+    pwfs::MeasureArgs a = slice_args(p, nullptr, 0, Bs, nullptr, nullptr, nullptr, Workspace{});
+    nc = a.n_chunks;
+  }
+  const size_t P = (size_t)p->P, N = 4 * P, S = (size_t)p->S, K = (size_t)p->K, B = (size_t)Bs;
+  const size_t sizes[8] = {
+      p->fs_on ? 0 : B * p->n_a * 2 * P * P * sizeof(cpx),
+      B * nc * partial_per_chunk(p) * sizeof(float),
+      B * 4 * S * S * sizeof(float),
+      p->det_on ? B * 4 * S * S * sizeof(float) : 0,
+      (p->Sd > 0 || p->fs_on) ? B * 4 * P * P * sizeof(float) : 0,
+      B * P * P * sizeof(cpx),
+      p->fs_on ? B * K * N * P * sizeof(cpx) : 0,
+      p->fs_on ? B * K * 2 * P * N * sizeof(cpx) : 0,
+  };
+  void** slots[8] = {(void**)&ws->Rw, (void**)&ws->partial, (void**)&ws->pupils, (void**)&ws->pixels,
+                     (void**)&ws->fullres, (void**)&ws->field, (void**)&ws->fs_Z, (void**)&ws->fs_W};
+  size_t off = 0;
+  for (int i = 0; i < 8; ++i) {
+    *slots[i] = (base && sizes[i]) ? (void*)(base + off) : nullptr;
+    off += (sizes[i] + 255) / 256 * 256;
+  }
+  return off;
+}
+
+// pwfs_measure with every workspace region taken from `ws_base` (ws_bytes
+// long, 256-byte aligned) instead of the plan's; the same slices, schedules
+// and kernels, so the results are those of pwfs_measure bit for bit.
+int measure_in_workspace(pwfs_plan_t p, const float* d_opd_nm, int32_t B, float* d_pupils, float* d_slopes,
+                         void* ws_base, size_t ws_bytes, void* stream) {
+  if (!p) return fail(PWFS_ERR_INVALID_ARG, "plan is NULL");
+  if (B < 0) return fail(PWFS_ERR_INVALID_ARG, "B must be >= 0");
+  if (B == 0 || (!d_pupils && !d_slopes)) return PWFS_OK;
+  if (!d_opd_nm) return fail(PWFS_ERR_INVALID_ARG, "d_opd_nm is NULL");
+  if (!ws_base || ((uintptr_t)ws_base & 255) != 0) return fail(PWFS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  const int Bs = std::min<int>(B, p->batch_max);
+  Workspace ws{};
+  const size_t need = carve_workspace(p, Bs, nullptr, &ws);
+  if (need > ws_bytes)
+    return fail(PWFS_ERR_UNSUPPORTED, "slice of " + std::to_string(Bs) + " frames needs " + std::to_string(need) +
+                                          " bytes of workspace, the static scratch holds " + std::to_string(ws_bytes) +
+                                          " (use pwfs_measure, or a plan with a smaller batch_max)");
+  carve_workspace(p, Bs, (char*)ws_base, &ws);
+  DeviceGuard g(p->device);
+  return run_measure(p, d_opd_nm, B, d_pupils, d_slopes, p->sref, (hipStream_t)stream, &ws);
+}
+
+int plan_device(pwfs_plan_t p) { return p ? p->device : -1; }
+
+}  // namespace pwfs
 
 extern "C" {
 
@@ -1195,7 +1273,7 @@ int pwfs_autotune(pwfs_plan_t p, int32_t B, int32_t reps, void* stream, double* 
   // Best of `reps` timed launches (after one untimed launch) of a schedule:
   // row pass (with the field) and column pass + chunk reduction + slopes.
   auto time_schedule = [&](int a_chunk, int k_chunk, double* row_ms, double* col_ms) -> hipError_t {
-    pwfs::MeasureArgs a = slice_args(p, d_opd, 0, B, nullptr, d_sl, p->sref);
+    pwfs::MeasureArgs a = slice_args(p, d_opd, 0, B, nullptr, d_sl, p->sref, plan_workspace(p));
     a.a_chunk = a_chunk;
     a.k_chunk = k_chunk;
     a.n_chunks = (p->K + k_chunk - 1) / k_chunk;

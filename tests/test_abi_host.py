@@ -74,6 +74,7 @@ def test_null_arguments_rejected():
     h = ctypes.c_void_p()
     assert lib.pwfs_plan(None, None, ctypes.byref(h)) == -1
     assert lib.pwfs_measure(None, None, 1, None, None, None) == -1
+    assert lib.pwfs_measure_static(None, None, 1, None, None, None) == -1
     assert lib.pwfs_plan_info(None, None, None, None) == -1
     assert lib.pwfs_get_valid(None, None) == -1
     assert lib.pwfs_set_valid(None, None, 1) == -1
