@@ -330,22 +330,28 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
     }
 }
 
-// Sum of split-K partials in split order, then the epilogue.  Block = 64
-// elements x 4 split groups: group q adds splits q, q + 4, ... in order,
-// then the four group sums are added in group order (fixed order overall).
+// Sum of split-K partials, then the epilogue.  Block = EL elements x G split
+// groups (EL G = 256): group q adds splits q, q + G, ... in order, then the G
+// group sums are added in group order (a fixed order overall).  Many splits
+// over few outputs (long-K weight gradients) take G = 16, so that each
+// thread adds only splits / G partials (G = 16 or 64).
+template <int G>
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int splits, const float* __restrict__ part) {
-  __shared__ float red[4][64];
+  constexpr int EL = 256 / G;
+  __shared__ float red[G][EL];
   const int Nc = g.N + (g.bias_grad ? 1 : 0);
   const size_t MN = (size_t)g.M * Nc;
-  const size_t idx = blockIdx.x * (size_t)64 + (threadIdx.x & 63);
-  const int q = threadIdx.x >> 6;
+  const int e = threadIdx.x % EL, q = threadIdx.x / EL;
+  const size_t idx = blockIdx.x * (size_t)EL + e;
   float x = 0.f;
   if (idx < MN)
-    for (int z = q; z < splits; z += 4) x += part[(size_t)z * MN + idx];
-  red[q][threadIdx.x & 63] = x;
+    for (int z = q; z < splits; z += G) x += part[(size_t)z * MN + idx];
+  red[q][e] = x;
   __syncthreads();
   if (q == 0 && idx < MN) {
-    const float s = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    float s = red[0][e];
+#pragma unroll
+    for (int t = 1; t < G; ++t) s += red[t][e];
     epilogue(g, (int)(idx / Nc), (int)(idx % Nc), s);
   }
 }
@@ -709,11 +715,17 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
   const int BM = tile == 3 ? 64 : 128;
   const int BN = tile == 0 ? 32 : tile == 1 ? 64 : tile == 2 ? 128 : 64;
   const long tiles = (long)((Nc + BN - 1) / BN) * ((g.M + BM - 1) / BM);
-  // Split K while the tiles leave the GPU's 256 CUs short of two blocks each
-  // and every split keeps at least 4 k steps; partials must fit `part`.
+  // Split K when the tiles leave the GPU's 256 CUs short of work.  A block's
+  // time is mostly the latency of its k steps, so more, shorter blocks win
+  // while the partials stay cheap to add: a few tiles (long-K weight
+  // gradients) split towards ~1024 blocks of at least 2 k steps, up to 511
+  // tiles towards ~512 blocks of at least 4 steps; partials must fit `part`.
   int splits = 1;
   if (part && tiles < 512) {
-    splits = (int)std::min<long>((512 + tiles - 1) / tiles, std::max(1, g.K / (4 * kBK)));
+    const bool few = tiles < 16;
+    const long target = few ? 1024 : 512;
+    const long min_steps = few ? 2 : 4;
+    splits = (int)std::max<long>(1, std::min<long>((target + tiles - 1) / tiles, g.K / (kBK * min_steps)));
     while (splits > 1 && (size_t)splits * g.M * Nc > part_elems) --splits;
   }
   const int kc = ((g.K + splits - 1) / splits + kBK - 1) / kBK * kBK;
@@ -727,8 +739,15 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
   }
   if (e != hipSuccess || splits <= 1) return e;
   const size_t MN = (size_t)g.M * Nc;
-  hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((MN + 63) / 64)), dim3(256), 0, st, g, splits,
-                     (const float*)part);
+  if (splits >= 256)
+    hipLaunchKernelGGL(gemm_reduce_kernel<64>, dim3((unsigned)((MN + 3) / 4)), dim3(256), 0, st, g, splits,
+                       (const float*)part);
+  else if (splits >= 64)
+    hipLaunchKernelGGL(gemm_reduce_kernel<16>, dim3((unsigned)((MN + 15) / 16)), dim3(256), 0, st, g, splits,
+                       (const float*)part);
+  else
+    hipLaunchKernelGGL(gemm_reduce_kernel<4>, dim3((unsigned)((MN + 63) / 64)), dim3(256), 0, st, g, splits,
+                       (const float*)part);
   return hipGetLastError();
 }
 
