@@ -11,11 +11,24 @@ covariance depends only on the pixel offset, so it is applied by FFT
 convolution on a 2P x 2P grid; the leading eigenvectors are found by block
 subspace iteration followed by a Rayleigh-Ritz step.  Each mode is zero
 outside the pupil, has zero mean over it and unit RMS (1 nm) over it, and
-modes are mutually orthogonal over the pupil.  The sign of each mode is
-fixed by a convention (its inner product with a seeded Gaussian field over
-the pupil pixels is positive), so the basis does not depend on the sign
-choices of the linear-algebra library: results computed with it on one
-machine (stored expected values) refer to the same modes on another.
+modes are mutually orthogonal over the pupil.
+
+The basis must not depend on the machine's linear-algebra rounding, so that
+results computed with it on one machine (stored expected values) refer to
+the same modes on another.  The square pixel grid gives the circular pupil
+the symmetries of the square, under which many eigenvalues are exactly
+degenerate in pairs; an eigen-solver returns an arbitrary orthonormal basis
+of such a pair's plane, chosen by rounding (and the subspace iteration,
+stopped before the tail is converged, splits such pairs by up to ~1e-6, so
+a rotation inside them is as ill-determined).  So the Ritz vectors are
+grouped into clusters of nearly equal Ritz values (relative gap below 1e-4;
+a cluster may then join two distinct modes, which only mixes two columns
+of the basis inside their common span), and
+each cluster's basis is replaced by a canonical one: the orthonormal basis
+of the same subspace whose inner products with the first seeded Gaussian
+probe fields form a lower-triangular matrix with a positive diagonal
+(Gram-Schmidt on the probes' projections).  This fixes every mode's
+direction, including its sign, before the leading modes are kept.
 """
 from __future__ import annotations
 
@@ -41,9 +54,35 @@ def _cov_kernel(P: int, pixel_m: float, L0_m: float) -> np.ndarray:
     return sfft.rfft2(c)
 
 
-def sign_probe(npix: int) -> np.ndarray:
-    """Seeded Gaussian field over the pupil pixels that fixes the modes' signs."""
-    return np.random.default_rng(20161607).standard_normal(npix)
+def probe_fields(npix: int, m: int) -> np.ndarray:
+    """[npix, m] seeded Gaussian fields over the pupil pixels that fix the
+    modes' directions within degenerate clusters."""
+    return np.random.default_rng(20161607).standard_normal((m, npix)).T
+
+
+def _canonical_clusters(w: np.ndarray, V: np.ndarray, X: np.ndarray, rel_gap: float = 1e-4) -> np.ndarray:
+    """Eigenvectors V (columns, eigenvalues w descending) with each cluster of
+    equal eigenvalues rotated to the canonical basis of its subspace: the
+    Ritz vectors U = X V of a cluster of size c are replaced by the
+    orthonormal basis Q of span(U) with probe_j . Q_i = 0 for j < i and
+    probe_i . Q_i > 0 (i, j < c)."""
+    V = V.copy()
+    n = len(w)
+    i = 0
+    while i < n:
+        j = i + 1
+        while j < n and abs(w[j - 1] - w[j]) <= rel_gap * abs(w[i]):
+            j += 1
+        c = j - i
+        W = probe_fields(X.shape[0], c)
+        G = (W.T @ X) @ V[:, i:j]                # [c probes, c vectors]
+        # rotation R with G R lower-triangular, positive diagonal: from the QR
+        # factors of G^T (G^T = Q T, so G Q = T^T is lower-triangular)
+        Q, T = np.linalg.qr(G.T)
+        Q = Q * np.where(np.diag(T) < 0.0, -1.0, 1.0)[None, :]
+        V[:, i:j] = V[:, i:j] @ Q
+        i = j
+    return V
 
 
 def kl_modes(A: np.ndarray, pixel_m: float, L0_m: float, n_modes: int,
@@ -53,7 +92,7 @@ def kl_modes(A: np.ndarray, pixel_m: float, L0_m: float, n_modes: int,
     P = A.shape[0]
     key = hashlib.sha1(np.packbits(A.astype(bool)).tobytes()
                        + repr((P, pixel_m, L0_m, n_modes, iters, oversample, seed,
-                               "sign-v1")).encode()).hexdigest()[:16]
+                               "canonical-v2")).encode()).hexdigest()[:16]
     cdir = os.environ.get("PWFS_CACHE_DIR", os.path.join(os.path.expanduser("~"), ".cache", "pwfs_kl"))
     path = os.path.join(cdir, f"kl_{key}.npy")
     if cache and os.path.exists(path):
@@ -84,11 +123,10 @@ def kl_modes(A: np.ndarray, pixel_m: float, L0_m: float, n_modes: int,
         X = np.linalg.qr(apply(X))[0]
     H = X.T @ apply(X)
     w, V = np.linalg.eigh(0.5 * (H + H.T))
-    order = np.argsort(w)[::-1][:n_modes]
-    U = X @ V[:, order]                          # orthonormal columns, piston-free
-    U -= U.mean(axis=0, keepdims=True)
-    U, _ = np.linalg.qr(U)
-    U *= np.where(sign_probe(npix) @ U < 0.0, -1.0, 1.0)[None, :]
+    order = np.argsort(w)[::-1]
+    w, V = w[order], _canonical_clusters(w[order], V[:, order], X)
+    U = X @ V[:, :n_modes]                       # orthonormal columns, piston-free
+    U -= U.mean(axis=0, keepdims=True)           # (to rounding: exactly zero mean)
     modes = np.zeros((n_modes, P * P))
     modes[:, pix] = U.T * np.sqrt(npix)
     modes = modes.reshape(n_modes, P, P)
