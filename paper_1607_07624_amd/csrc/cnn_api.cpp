@@ -51,6 +51,7 @@ struct pwfs_cnn_s {
   int S = 0, S1 = 0, S2 = 0, S3 = 0, c1 = 0, c2 = 0, c3 = 0, hidden = 0, nout = 0, flat = 0, bm = 0;
   size_t off[10] = {};   // w1 b1 w2 b2 w3 b3 fw1 fb1 fw2 fb2
   size_t n_params = 0;
+  pwfs::cnn::ConvPerm cperm{};   // convolution blocks of the bf16 product copy
   long step = 0;
   // parameters
   float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
@@ -110,8 +111,10 @@ GemmArgs fwd_args(const uint16_t* X, bool x_split, const uint16_t* W, const floa
 }
 // dW [N][K] = dY^T X and db [N] = column sums of dY; dY [R][N] a bf16 pair
 // (lo plane R N elements on), X [R][K] bf16 (a pair when x_split).
-GemmArgs wgrad_args(const uint16_t* dY, const uint16_t* X, bool x_split, int R, int N, int K, float* dW, float* db) {
+GemmArgs wgrad_args(const uint16_t* dY, const uint16_t* X, bool x_split, int R, int N, int K, float* dW, float* db,
+                    int cperm = 0) {
   GemmArgs a{};
+  a.cperm = cperm;   // convolutions: patch columns (tap, c) go to weight columns (c, tap)
   a.A = dY; a.sam = 1; a.sak = N; a.a_lo = (long)R * N;
   a.B = X; a.sbk = K; a.sbn = 1; a.b_lo = x_split ? (long)R * K : 0;
   a.C = dW; a.ldc = K; a.bias_grad = db;
@@ -173,17 +176,17 @@ int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B
   CK(pwfs::cnn::relu_mask(n->gtmp, n->a3, (size_t)B * n->flat, n->dzb, st));
   // conv3
   const int R3 = B * n->S3 * n->S3, R2 = B * n->S2 * n->S2, R1 = B * n->S1 * n->S1;
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols3, true, R3, n->c3, n->c2 * 9, G + n->off[4], G + n->off[5]),
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols3, true, R3, n->c3, n->c2 * 9, G + n->off[4], G + n->off[5], n->c2),
                      n->part, P, st));
   CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), n->part, P, st));
   CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S2, n->S2, n->c2, n->a2, n->dzb, st));
   // conv2
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols2, true, R2, n->c2, n->c1 * 9, G + n->off[2], G + n->off[3]),
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols2, true, R2, n->c2, n->c1 * 9, G + n->off[2], G + n->off[3], n->c1),
                      n->part, P, st));
   CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, P, st));
   CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dzb, st));
   // conv1
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols1, false, R1, n->c1, 36, G + n->off[0], G + n->off[1]),
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols1, false, R1, n->c1, 36, G + n->off[0], G + n->off[1], 4),
                      n->part, P, st));
   return 0;
 }
@@ -230,6 +233,7 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
     o += sizes[i];   // packed, C order
   }
   n->n_params = o;
+  n->cperm = pwfs::cnn::ConvPerm{{n->off[0], n->off[2], n->off[4]}, {4, n->c1, n->c2}, {n->c1, n->c2, n->c3}};
   const size_t B = (size_t)n->bm;
   const size_t R1 = B * n->S1 * n->S1, R2 = B * n->S2 * n->S2, R3 = B * n->S3 * n->S3;
   const size_t gtmp = std::max({B * n->hidden, B * n->flat, R3 * n->c2 * 9, R2 * n->c1 * 9});
@@ -279,7 +283,7 @@ int pwfs_cnn_set_params(pwfs_cnn_t n, const float* d, void* stream) {
   DevGuard g(n->device);
   hipStream_t st = (hipStream_t)stream;
   CK(hipMemcpyAsync(n->w, d, n->n_params * 4, hipMemcpyDeviceToDevice, st));
-  CK(pwfs::cnn::to_bf16(n->w, n->n_params, n->wb, st));
+  CK(pwfs::cnn::weights_bf16(n->w, n->n_params, n->cperm, n->wb, st));
   CK(pwfs::cnn::fill0(n->m, n->n_params, st));
   CK(pwfs::cnn::fill0(n->v, n->n_params, st));
   n->step = 0;
@@ -354,7 +358,7 @@ int pwfs_cnn_train_step(pwfs_cnn_t n, const float* d_x, const float* d_target, c
   n->step += 1;
   const float c1 = (float)(1.0 - std::pow((double)beta1, (double)n->step));
   const float c2 = (float)(1.0 - std::pow((double)beta2, (double)n->step));
-  CK(pwfs::cnn::adam(n->w, n->g, n->m, n->v, n->wb, n->n_params, lr, beta1, beta2, eps, c1, c2, st));
+  CK(pwfs::cnn::adam(n->w, n->g, n->m, n->v, n->wb, n->cperm, n->n_params, lr, beta1, beta2, eps, c1, c2, st));
   return 0;
 }
 

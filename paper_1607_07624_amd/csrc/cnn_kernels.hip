@@ -53,6 +53,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int i, int j, float 
   }
   if (g.bias) x += g.bias[j];
   x *= g.alpha;
+  if (g.cperm) j = (j % g.cperm) * 9 + j / g.cperm;   // patch column (tap, c) -> weight column (c, tap)
   if (g.C && g.beta != 0.f) x = fmaf(g.beta, g.C[(long)i * g.ldc + j], x);
   if (g.relu) x = fmaxf(x, 0.f);
   if (g.C) g.C[(long)i * g.ldc + j] = x;
@@ -461,65 +462,112 @@ __global__ __launch_bounds__(64 * kGemvMaxWaves) void gemv_bf16_kernel(GemmArgs 
 }
 
 // ---------------------------------------------------------------------------
-// im2col for a 3x3 stride-2 pad-1 convolution, NHWC input:
-// cols[(b, yo, xo)][c * 9 + ky * 3 + kx] = act[b][2 yo + ky - 1][2 xo + kx - 1][c] (0 outside).
-// From a bf16 pair input (lo plane n_in elements after the hi plane) both
-// planes are gathered (the lo plane of cols n_out elements after its hi
-// plane); from an FP32 input each value is rounded to bf16 (one plane): the
-// network input's conversion and its im2col in one pass.
-template <typename T>
-__global__ __launch_bounds__(256) void im2col_kernel(const T* __restrict__ act, int B, int H, int W,
-                                                     int C, uint16_t* __restrict__ cols) {
+// im2col for a 3x3 stride-2 pad-1 convolution, NHWC input, patch columns in
+// (ky, kx, c) order:
+// cols[(b, yo, xo)][(ky * 3 + kx) C + c] = act[b][2 yo + ky - 1][2 xo + kx - 1][c] (0 outside),
+// so that a tap's C channels are contiguous on both sides.  From a bf16 pair
+// input (lo plane n_in elements after the hi plane) both planes are gathered
+// (the lo plane of cols n_out elements after its hi plane), 8 channels per
+// 16-byte move when C is a multiple of 8; from an FP32 input each value is
+// rounded to bf16 (one plane): the network input's conversion and its
+// im2col in one pass.  One thread per (row, tap, group of V channels).
+template <int V>
+__global__ __launch_bounds__(256) void im2col_pair_kernel(const uint16_t* __restrict__ act, int B, int H, int W,
+                                                          int C, uint16_t* __restrict__ cols) {
   const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
+  const int G = C / V;                                       // channel groups per tap
   const size_t K9 = (size_t)C * 9;
-  const size_t total = (size_t)B * Ho * Wo * K9;
-  const size_t n_in = (size_t)B * H * W * C;
+  const size_t rows = (size_t)B * Ho * Wo;
+  const size_t total = rows * 9 * G;
+  const size_t n_in = (size_t)B * H * W * C, n_out = rows * K9;
   for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
-    const size_t row = idx / K9;
-    const int col = (int)(idx - row * K9);
-    const int c = col / 9, r9 = col - c * 9, ky = r9 / 3, kx = r9 - ky * 3;
+    const int cg = (int)(idx % G);
+    const size_t t2 = idx / G;
+    const int tap = (int)(t2 % 9);
+    const size_t row = t2 / 9;
+    const int ky = tap / 3, kx = tap - ky * 3;
     const int b = (int)(row / ((size_t)Ho * Wo));
     const int rem = (int)(row - (size_t)b * Ho * Wo);
     const int yo = rem / Wo, xo = rem - yo * Wo;
     const int y = 2 * yo + ky - 1, x = 2 * xo + kx - 1;
     const bool in = y >= 0 && y < H && x >= 0 && x < W;
-    const size_t src = (((size_t)b * H + y) * W + x) * C + c;
-    if constexpr (std::is_same<T, float>::value) {
-      cols[idx] = in ? f2bf(act[src]) : (uint16_t)0;
+    const size_t src = (((size_t)b * H + y) * W + x) * C + (size_t)cg * V;
+    const size_t dst = row * K9 + (size_t)tap * C + (size_t)cg * V;
+    if constexpr (V == 8) {
+      const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+      *reinterpret_cast<uint4*>(cols + dst) = in ? *reinterpret_cast<const uint4*>(act + src) : z;
+      *reinterpret_cast<uint4*>(cols + dst + n_out) = in ? *reinterpret_cast<const uint4*>(act + src + n_in) : z;
     } else {
-      cols[idx] = in ? act[src] : (uint16_t)0;
-      cols[idx + total] = in ? act[src + n_in] : (uint16_t)0;
+      cols[dst] = in ? act[src] : (uint16_t)0;
+      cols[dst + n_out] = in ? act[src + n_in] : (uint16_t)0;
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void im2col_f32_kernel(const float* __restrict__ act, int B, int H, int W, int C,
+                                                         uint16_t* __restrict__ cols) {
+  const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
+  const size_t K9 = (size_t)C * 9;
+  const size_t total = (size_t)B * Ho * Wo * 9;
+  for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
+    const int tap = (int)(idx % 9);
+    const size_t row = idx / 9;
+    const int ky = tap / 3, kx = tap - ky * 3;
+    const int b = (int)(row / ((size_t)Ho * Wo));
+    const int rem = (int)(row - (size_t)b * Ho * Wo);
+    const int yo = rem / Wo, xo = rem - yo * Wo;
+    const int y = 2 * yo + ky - 1, x = 2 * xo + kx - 1;
+    const bool in = y >= 0 && y < H && x >= 0 && x < W;
+    const float* src = act + (((size_t)b * H + y) * W + x) * C;
+    uint16_t* dst = cols + row * K9 + (size_t)tap * C;
+    for (int c = 0; c < C; ++c) dst[c] = in ? f2bf(src[c]) : (uint16_t)0;
   }
 }
 
 // Gradient of im2col (gather form) fused with the ReLU mask of the layer's
 // forward output act (hi plane): dz[b][y][x][c] = (act > 0) * sum over the
-// (ky, kx) whose output pixel (yo, xo) = ((y + 1 - ky) / 2, (x + 1 - kx) / 2)
-// exists, in ky-major order.  Writes the bf16 pair (lo at dzb + B H W C).
+// taps (ky, kx) whose output pixel (yo, xo) = ((y + 1 - ky) / 2, (x + 1 - kx) / 2)
+// exists, in tap order, of dcols[(b, yo, xo)][(ky * 3 + kx) C + c].  One
+// thread per (pixel, group of V channels); writes the bf16 pair (lo at
+// dzb + B H W C).
+template <int V>
 __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restrict__ dcols, int B, int H, int W,
                                                           int C, const uint16_t* __restrict__ act,
                                                           uint16_t* __restrict__ dzb) {
   const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
-  const size_t total = (size_t)B * H * W * C;
+  const int G = C / V;
+  const size_t n = (size_t)B * H * W * C;
+  const size_t total = (size_t)B * H * W * G;
   for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
-    const int c = (int)(idx % C);
-    const size_t pix = idx / C;
+    const int cg = (int)(idx % G);
+    const size_t pix = idx / G;
     const int x = (int)(pix % W);
     const size_t t2 = pix / W;
     const int y = (int)(t2 % H);
     const int b = (int)(t2 / H);
-    float s = 0.f;
+    float s[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) s[v] = 0.f;
     for (int ky = 0; ky < 3; ++ky) {
       const int yy = y + 1 - ky;
       if (yy < 0 || (yy & 1) || (yy >> 1) >= Ho) continue;
       for (int kx = 0; kx < 3; ++kx) {
         const int xx = x + 1 - kx;
         if (xx < 0 || (xx & 1) || (xx >> 1) >= Wo) continue;
-        s += dcols[(((size_t)b * Ho + (yy >> 1)) * Wo + (xx >> 1)) * (size_t)(C * 9) + c * 9 + ky * 3 + kx];
+        const float* d = dcols + (((size_t)b * Ho + (yy >> 1)) * Wo + (xx >> 1)) * (size_t)(C * 9) +
+                         (size_t)(ky * 3 + kx) * C + (size_t)cg * V;
+        if constexpr (V == 8) {
+          const float4 u = reinterpret_cast<const float4*>(d)[0], w = reinterpret_cast<const float4*>(d)[1];
+          s[0] += u.x; s[1] += u.y; s[2] += u.z; s[3] += u.w;
+          s[4] += w.x; s[5] += w.y; s[6] += w.z; s[7] += w.w;
+        } else {
+          s[0] += d[0];
+        }
       }
     }
-    split_bf(bf_pos(act[idx]) ? s : 0.f, dzb, dzb + total, idx);
+    const size_t o = pix * C + (size_t)cg * V;
+#pragma unroll
+    for (int v = 0; v < V; ++v) split_bf(bf_pos(act[o + v]) ? s[v] : 0.f, dzb, dzb + n, o + v);
   }
 }
 
@@ -530,8 +578,28 @@ __global__ __launch_bounds__(256) void relu_mask_kernel(const float* __restrict_
     split_bf(bf_pos(act[i]) ? g[i] : 0.f, dzb, dzb + n, i);
 }
 
-__global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ x, size_t n, uint16_t* __restrict__ y) {
-  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) y[i] = f2bf(x[i]);
+// Position in the bf16 product copy of parameter i: convolution weights
+// [Cout][Cin][3][3] are stored [Cout][3][3][Cin] there (the patch order of
+// im2col), everything else in place.
+__device__ __forceinline__ size_t wb_index(const ConvPerm& cp, size_t i) {
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const size_t len = (size_t)cp.cout[s] * cp.cin[s] * 9;
+    if (i >= cp.off[s] && i < cp.off[s] + len) {
+      const size_t l = i - cp.off[s];
+      const size_t per_o = (size_t)cp.cin[s] * 9;
+      const size_t o = l / per_o, rem = l - o * per_o;
+      const size_t c = rem / 9, tap = rem - c * 9;
+      return cp.off[s] + o * per_o + tap * cp.cin[s] + c;
+    }
+  }
+  return i;
+}
+
+__global__ __launch_bounds__(256) void weights_bf16_kernel(const float* __restrict__ x, size_t n, ConvPerm cp,
+                                                           uint16_t* __restrict__ y) {
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    y[wb_index(cp, i)] = f2bf(x[i]);
 }
 
 // Weighted MSE: gradient 2 w (p - t) / n as a bf16 pair (lo at doutb + n)
@@ -582,8 +650,9 @@ __global__ __launch_bounds__(256) void mse_sum_kernel(const float* __restrict__ 
 
 // Adam on the FP32 master weights; refreshes the bf16 copy.
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                                                   float* __restrict__ v, uint16_t* __restrict__ wb, size_t n, float lr,
-                                                   float b1, float b2, float eps, float c1, float c2) {
+                                                   float* __restrict__ v, uint16_t* __restrict__ wb, ConvPerm cp,
+                                                   size_t n, float lr, float b1, float b2, float eps, float c1,
+                                                   float c2) {
   for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const float gi = g[i];
     const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
@@ -592,7 +661,7 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const 
     v[i] = vi;
     const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     w[i] = wi;
-    wb[i] = f2bf(wi);
+    wb[wb_index(cp, i)] = f2bf(wi);
   }
 }
 
@@ -752,21 +821,29 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
 }
 
 hipError_t im2col(const uint16_t* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st) {
-  const size_t total = (size_t)B * ((H + 1) / 2) * ((W + 1) / 2) * C * 9;
-  hipLaunchKernelGGL(im2col_kernel<uint16_t>, dim3(grid_for(total)), dim3(256), 0, st, act, B, H, W, C, cols);
+  const size_t rows = (size_t)B * ((H + 1) / 2) * ((W + 1) / 2);
+  if (C % 8 == 0)
+    hipLaunchKernelGGL(im2col_pair_kernel<8>, dim3(grid_for(rows * 9 * (C / 8))), dim3(256), 0, st, act, B, H, W, C,
+                       cols);
+  else
+    hipLaunchKernelGGL(im2col_pair_kernel<1>, dim3(grid_for(rows * 9 * C)), dim3(256), 0, st, act, B, H, W, C, cols);
   return hipGetLastError();
 }
 
 hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st) {
-  const size_t total = (size_t)B * ((H + 1) / 2) * ((W + 1) / 2) * C * 9;
-  hipLaunchKernelGGL(im2col_kernel<float>, dim3(grid_for(total)), dim3(256), 0, st, act, B, H, W, C, cols);
+  const size_t total = (size_t)B * ((H + 1) / 2) * ((W + 1) / 2) * 9;
+  hipLaunchKernelGGL(im2col_f32_kernel, dim3(grid_for(total)), dim3(256), 0, st, act, B, H, W, C, cols);
   return hipGetLastError();
 }
 
 hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, uint16_t* dzb,
                        hipStream_t st) {
-  const size_t total = (size_t)B * H * W * C;
-  hipLaunchKernelGGL(col2im_mask_kernel, dim3(grid_for(total)), dim3(256), 0, st, dcols, B, H, W, C, act, dzb);
+  const size_t pix = (size_t)B * H * W;
+  if (C % 8 == 0)
+    hipLaunchKernelGGL(col2im_mask_kernel<8>, dim3(grid_for(pix * (C / 8))), dim3(256), 0, st, dcols, B, H, W, C, act,
+                       dzb);
+  else
+    hipLaunchKernelGGL(col2im_mask_kernel<1>, dim3(grid_for(pix * C)), dim3(256), 0, st, dcols, B, H, W, C, act, dzb);
   return hipGetLastError();
 }
 
@@ -775,8 +852,8 @@ hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, uint16_t* dz
   return hipGetLastError();
 }
 
-hipError_t to_bf16(const float* x, size_t n, uint16_t* y, hipStream_t st) {
-  hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, st, x, n, y);
+hipError_t weights_bf16(const float* x, size_t n, const ConvPerm& cp, uint16_t* y, hipStream_t st) {
+  hipLaunchKernelGGL(weights_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, st, x, n, cp, y);
   return hipGetLastError();
 }
 
@@ -792,9 +869,9 @@ hipError_t mse(const float* pred, const float* target, const float* weights, int
   return hipGetLastError();
 }
 
-hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, size_t n, float lr, float b1, float b2,
-                float eps, float c1, float c2, hipStream_t st) {
-  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, st, w, g, m, v, wb, n, lr, b1, b2, eps, c1, c2);
+hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, const ConvPerm& cp, size_t n, float lr,
+                float b1, float b2, float eps, float c1, float c2, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, st, w, g, m, v, wb, cp, n, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
 

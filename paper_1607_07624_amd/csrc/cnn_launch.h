@@ -35,12 +35,21 @@ struct GemmArgs {
   int relu;
   long a_lo, b_lo, cb_lo;
   float* bias_grad;
+  int cperm;          // > 0: output column j (patch order tap, c) is stored at (j mod cperm) 9 + j / cperm
+};
+
+// The three convolution weight blocks of the flat parameter vector (offset,
+// input and output channels): their bf16 product copy is stored
+// [Cout][3][3][Cin] (patch order of im2col), the FP32 weights [Cout][Cin][3][3].
+struct ConvPerm {
+  size_t off[3];
+  int cin[3], cout[3];
 };
 
 // part: split-K partial buffer of part_elems floats (NULL disables split-K).
 hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t st);
-// Activations are bf16 pairs: the lo plane of act (cols) lies n elements after
-// its hi plane, n the plane's element count.
+// Patches in (ky, kx, c) order.  Activations are bf16 pairs: the lo plane of
+// act (cols) lies n elements after its hi plane, n the plane's element count.
 hipError_t im2col(const uint16_t* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st);
 // The same from an FP32 input, each value rounded to bf16 (round to nearest even).
 hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st);
@@ -49,13 +58,14 @@ hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* co
 hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, uint16_t* dzb,
                        hipStream_t st);
 hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, uint16_t* dzb, hipStream_t st);
-hipError_t to_bf16(const float* x, size_t n, uint16_t* y, hipStream_t st);
+// bf16 product copy of the FP32 parameters (convolution weights permuted as in ConvPerm).
+hipError_t weights_bf16(const float* x, size_t n, const ConvPerm& cp, uint16_t* y, hipStream_t st);
 // part: at least mse_partials(n) floats of scratch.
 size_t mse_partials(int n);
 hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, uint16_t* doutb,
                float* loss, float* part, hipStream_t st);
-hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, size_t n, float lr, float b1, float b2,
-                float eps, float c1, float c2, hipStream_t st);
+hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, const ConvPerm& cp, size_t n, float lr,
+                float b1, float b2, float eps, float c1, float c2, hipStream_t st);
 hipError_t fill0(float* p, size_t n, hipStream_t st);
 hipError_t prepare(const float* pupils, const float* ref, const int* valid, int nv, int B, int S, float* x,
                    hipStream_t st);
