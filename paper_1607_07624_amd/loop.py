@@ -198,13 +198,18 @@ class ClosedLoop:
         return res, hist[d:]
 
 
-    def run_graph(self, opd_seq_dev, residuals_dev=None):
-        """run() for the linear reconstructor with each step replayed from one
-        captured HIP graph (torch.cuda.CUDAGraph): the same library calls in
-        the same order on static buffers, so the same results bit for bit.
-        Per step: one copy in, the replay, two copies out.  The delay line is
-        a ring of `delay` static command buffers, ring[j] = c(t - 1 - j),
-        shifted inside the graph.  Needs delay >= 1 and a noiseless sensor (a
+    def run_graph(self, opd_seq_dev, residuals_dev=None, steps_per_graph: int = 50):
+        """run() for the linear reconstructor replayed from captured HIP graphs
+        (torch.cuda.CUDAGraph) of `steps_per_graph` steps each: the same
+        library calls in the same order on static buffers, so the same results
+        bit for bit.  A graph advances a window of L steps: the window's
+        inputs are copied in once, its residuals and commands out once, and
+        the delay line is the command window itself (hist_ext[j] = c(t - d)
+        for step t = t0 + j, rows 0..d-1 carried over from the previous
+        window).  A sequence that is not a multiple of L ends with a second,
+        shorter graph on the same buffers.  The graphs and their buffers are
+        kept on the loop object: a later run with the same L replays them
+        without capturing again.  Needs delay >= 1 and a noiseless sensor (a
         detector's frame counter would be frozen into the graph)."""
         import torch
         if self.net is not None:
@@ -219,36 +224,48 @@ class ClosedLoop:
         dev = opd_seq_dev.device
         res = residuals_dev if residuals_dev is not None else torch.empty((T, P * P), device=dev)
         hist = torch.empty((T, M), device=dev)
-        opd_in = torch.zeros((1, P * P), device=dev)
-        r = torch.zeros((1, P * P), device=dev)
-        ring = [torch.zeros((1, M), device=dev) for _ in range(d)]
-        cn = torch.zeros((1, M), device=dev)
+        L = max(1, min(int(steps_per_graph), T))
+        cache = getattr(self, "_graphs", None)
+        if cache is None or cache["L"] != L or cache["device"] != dev:
+            cache = {"L": L, "device": dev, "graphs": {},
+                     "bufs": (torch.zeros((L, P * P), device=dev), torch.zeros((L, P * P), device=dev),
+                              torch.zeros((L + d, M), device=dev))}
+            self._graphs = cache
+        opd_win, res_win, hist_ext = cache["bufs"]
 
-        def step():
-            r.copy_(opd_in)
-            recon_apply(self.BKL, ring[d - 1], -1.0, 1.0, r)          # u(t) = c(t - d)
-            cn.copy_(ring[0])
-            self.plan.measure_into(r.view(1, P, P), None, self.s)
-            recon_apply(self.R, self.s, self.gain, 1.0, cn)           # c(t) = c(t-1) + g R s(t)
-            for j in range(d - 1, 0, -1):
-                ring[j].copy_(ring[j - 1])
-            ring[0].copy_(cn)
+        def window(n):
+            for j in range(n):
+                r = res_win[j:j + 1]
+                r.copy_(opd_win[j:j + 1])
+                recon_apply(self.BKL, hist_ext[j:j + 1], -1.0, 1.0, r)          # u(t) = c(t - d)
+                c = hist_ext[j + d:j + d + 1]
+                c.copy_(hist_ext[j + d - 1:j + d])                              # c(t - 1)
+                self.plan.measure_into(r.view(1, P, P), None, self.s)
+                recon_apply(self.R, self.s, self.gain, 1.0, c)                  # c(t) = c(t-1) + g R s(t)
 
-        side = torch.cuda.Stream(device=dev)
-        side.wait_stream(torch.cuda.current_stream(dev))
-        with torch.cuda.stream(side):
-            step()                                                    # warm-up outside the capture
-        torch.cuda.current_stream(dev).wait_stream(side)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            step()
-        for b in ring:
-            b.zero_()
-        for t in range(T):
-            opd_in.copy_(opd_seq_dev[t].reshape(1, -1))
-            graph.replay()
-            res[t].copy_(r[0])
-            hist[t].copy_(cn[0])
+        def capture(n):
+            side = torch.cuda.Stream(device=dev)
+            side.wait_stream(torch.cuda.current_stream(dev))
+            with torch.cuda.stream(side):
+                window(n)                                                     # warm-up outside the capture
+            torch.cuda.current_stream(dev).wait_stream(side)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                window(n)
+            return g
+
+        graphs = cache["graphs"]
+        for n in {L, T % L} - {0}:
+            if n not in graphs:
+                graphs[n] = capture(n)
+        hist_ext.zero_()
+        for t0 in range(0, T, L):
+            n = min(L, T - t0)
+            opd_win[:n].copy_(opd_seq_dev[t0:t0 + n].reshape(n, -1))
+            graphs[n].replay()
+            res[t0:t0 + n].copy_(res_win[:n])
+            hist[t0:t0 + n].copy_(hist_ext[d:d + n])
+            hist_ext[:d].copy_(hist_ext[n:n + d].clone())
         return res, hist
 
 

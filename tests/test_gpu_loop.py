@@ -169,10 +169,13 @@ def test_batched_loops_match_oracle_cfg1():
 
 
 def test_graph_replayed_loop_equals_eager():
-    """The linear loop replayed step by step from one captured HIP graph gives
-    the eager loop's residuals and commands bit for bit, for delays 2 and 3,
-    on two sequences with eager work and synchronisations between the runs;
-    a sensor with a detector is refused (its frame counter would be frozen)."""
+    """The linear loop replayed from captured HIP graphs of L steps each gives
+    the eager loop's residuals and commands bit for bit: 120 steps with
+    L = 50 (two windows and a 20-step tail graph), 7 (a 1-step tail) and 1
+    (one step per graph), delays 2 and 3, each graph replayed several times
+    with the loop's own copies between the replays and eager work and
+    synchronisations between the runs; a sensor with a detector is refused
+    (its frame counter would be frozen)."""
     import paper_1607_07624_amd as pw
     from paper_1607_07624_amd.loop import calibrate, ClosedLoop
     torch = torch_cuda()
@@ -183,15 +186,15 @@ def test_graph_replayed_loop_equals_eager():
     R_g, _, _ = calibrate(plan_cal, modes, PUSH_PULL_NM)
     plan = pw.Plan(CFG1, batch_max=1)
     modes_dev = torch.from_numpy(modes).cuda()
-    for delay, seed in ((LOOP_DELAY, 11), (3, 12)):
+    for delay, seed, L in ((LOOP_DELAY, 11, 50), (3, 12, 7), (LOOP_DELAY, 13, 1)):
         seq = torch.from_numpy(frozen_flow_sequence(CFG1, atmo, T, seed=seed, screen_n=256)).cuda()
         cl = ClosedLoop(plan, modes_dev, R_g, LOOP_GAIN, delay)
         res_e, c_e = cl.run(seq)
         torch.cuda.synchronize()
         junk = torch.randn(1 << 16, device="cuda").sum()         # eager work between the runs
-        res_g, c_g = cl.run_graph(seq)
+        res_g, c_g = cl.run_graph(seq, steps_per_graph=L)
         torch.cuda.synchronize()
-        say(f"[gpu] graph loop, delay {delay}: residual equal {torch.equal(res_g, res_e)}, "
+        say(f"[gpu] graph loop, delay {delay}, {L} steps per graph: residual equal {torch.equal(res_g, res_e)}, "
             f"commands equal {torch.equal(c_g, c_e)} ({float(junk):.1f})")
         assert torch.equal(res_g, res_e) and torch.equal(c_g, c_e)
     plan.set_detector(1.0e5, 1.0, seed=3)
