@@ -44,10 +44,11 @@ __device__ __forceinline__ void half_band(cpx (&v)[E], const cpx* __restrict__ m
   Dft<E, +1>::run(v);
   fence();
   const cpx* ml = mid + l * TabLds<E>::MS;
-  static_for<0, E>([&](auto k_) {
-    constexpr int k = decltype(k_)::value;
+  static_assert(E % 2 == 0, "mixes in pairs");
+  static_for<0, E / 2>([&](auto h_) {
+    constexpr int k = 2 * decltype(h_)::value;
     if constexpr (k % 8 == 0 && k > 0) fence();
-    v[k] = mix3_quad(v[k], ml[2 * k], ml[2 * k + 1]);   // lanes l + 1, l - 1
+    mix3_quad2(v[k], ml[2 * k], ml[2 * k + 1], v[k + 1], ml[2 * k + 2], ml[2 * k + 3]);   // lanes l + 1, l - 1
   });
   fence();
   Dft<E, -1>::run(v);

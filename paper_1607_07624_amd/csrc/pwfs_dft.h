@@ -309,34 +309,46 @@ __device__ __forceinline__ float swap_halves(float v) {
 }
 
 // Three-tap lane mix V = v + a v' + b v'', with v' and v'' the values of v on
-// the lanes that the DPP controls PL and MI select.  Each neighbour value is
-// read through the DPP operand of the multiply-add itself instead of a
-// separate DPP move (ten VALU instructions instead of twelve).  The leading
-// s_nop 1 gives the two wait states a DPP read needs after a VALU write of
-// its source; inside the block no DPP source is written, and every lane is
-// active wherever this is used.
-#define PWFS_MIX3_ASM(PL, MI)                                                  \
+// the lanes that the DPP controls PL and MI select (quad form: lanes l + 1 and
+// l - 1 mod 4), for two values v0, v1 of the same lanes in one block.  Each
+// neighbour value is read through the DPP operand of the multiply-add itself
+// instead of a separate DPP move (ten VALU instructions per mix instead of
+// twelve).  The leading s_nop 1 gives the two wait states a DPP read needs
+// after a VALU write of its source, once for both mixes; inside the block no
+// DPP source is written, and every lane is active wherever this is used.
+#define PWFS_MIX3x2_ASM(PL, MI)                                                \
   "s_nop 1\n\t"                                                                \
-  "v_mul_f32_dpp %0, %2, %4 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"   \
-  "v_mul_f32_dpp %1, %3, %4 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"   \
-  "v_fmac_f32_dpp %0, -%3, %5 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
-  "v_fmac_f32_dpp %1, %2, %5 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
-  "v_fmac_f32_dpp %0, %2, %6 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
-  "v_fmac_f32_dpp %1, %3, %6 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
-  "v_fmac_f32_dpp %0, -%3, %7 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
-  "v_fmac_f32_dpp %1, %2, %7 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
-  "v_add_f32_e32 %0, %2, %0\n\t"                                               \
-  "v_add_f32_e32 %1, %3, %1"
+  "v_mul_f32_dpp %0, %4, %6 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"   \
+  "v_mul_f32_dpp %1, %5, %6 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"   \
+  "v_mul_f32_dpp %2, %10, %12 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"   \
+  "v_mul_f32_dpp %3, %11, %12 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"   \
+  "v_fmac_f32_dpp %0, -%5, %7 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+  "v_fmac_f32_dpp %1, %4, %7 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %2, -%11, %13 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+  "v_fmac_f32_dpp %3, %10, %13 " PL " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %0, %4, %8 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %1, %5, %8 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %2, %10, %14 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %3, %11, %14 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %0, -%5, %9 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+  "v_fmac_f32_dpp %1, %4, %9 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_fmac_f32_dpp %2, -%11, %15 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t" \
+  "v_fmac_f32_dpp %3, %10, %15 " MI " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"  \
+  "v_add_f32_e32 %0, %4, %0\n\t"                                               \
+  "v_add_f32_e32 %1, %5, %1\n\t"                                               \
+  "v_add_f32_e32 %2, %10, %2\n\t"                                               \
+  "v_add_f32_e32 %3, %11, %3"
 
-// Quad form: v' from lane l + 1, v'' from lane l - 1 (mod 4).
-__device__ __forceinline__ cpx mix3_quad(cpx v, cpx a, cpx b) {
-  cpx r;
-  asm(PWFS_MIX3_ASM("quad_perm:[1,2,3,0]", "quad_perm:[3,0,1,2]")
-      : "=&v"(r.re), "=&v"(r.im)
-      : "v"(v.re), "v"(v.im), "v"(a.re), "v"(a.im), "v"(b.re), "v"(b.im));
-  return r;
+__device__ __forceinline__ void mix3_quad2(cpx& v0, cpx a0, cpx b0, cpx& v1, cpx a1, cpx b1) {
+  cpx r0, r1;
+  asm(PWFS_MIX3x2_ASM("quad_perm:[1,2,3,0]", "quad_perm:[3,0,1,2]")
+      : "=&v"(r0.re), "=&v"(r0.im), "=&v"(r1.re), "=&v"(r1.im)
+      : "v"(v0.re), "v"(v0.im), "v"(a0.re), "v"(a0.im), "v"(b0.re), "v"(b0.im),
+        "v"(v1.re), "v"(v1.im), "v"(a1.re), "v"(a1.im), "v"(b1.re), "v"(b1.im));
+  v0 = r0;
+  v1 = r1;
 }
-#undef PWFS_MIX3_ASM
+#undef PWFS_MIX3x2_ASM
 
 // Row form: v' from lane i + 4 (row_ror:12), v'' from lane i - 4 (row_ror:4),
 // mod 16 inside each row of 16 lanes.  Plain DPP moves and FMAs: the long-line
