@@ -217,19 +217,31 @@ __global__ __launch_bounds__(256) void col_pass_kernel(
     cpx v[E];
     line_op<E>(v, [&](int m) { return cmul(col[32 * m], tin[4 * m]); }, [&](int m) { return col[32 * m]; },
                [&](int m) { return tf[4 * m]; }, s_mid, s_out, q, l);
+    // |E|^2 of all E samples first, then each DPP round over all of them: a
+    // DPP read of e[m] then follows the VALU write of e[m] by many
+    // instructions, so it needs no wait states.
+    float e[E];
     static_for<0, E>([&](auto m_) {
       constexpr int m = decltype(m_)::value;
-      float e = fmaf(v[m].re, v[m].re, v[m].im * v[m].im);
-      if constexpr (G == 4) {
-        e += quad_perm<0xB1>(e);                   // lanes (0,1), (2,3)
-        e += quad_perm<0x4E>(e);                   // lanes (0,2), (1,3)
-        acc[m >> 2] = fmaf(keepm[m & 3], e, acc[m >> 2]);
-      } else if constexpr (G == 2) {
-        e += quad_perm<0xB1>(e);                   // lanes (0,1), (2,3)
-        acc[m >> 1] = fmaf(keepm[m & 1], e, acc[m >> 1]);
-      } else {
-        acc[m] += e;
-      }
+      e[m] = fmaf(v[m].re, v[m].re, v[m].im * v[m].im);
+    });
+    if constexpr (G >= 2) {
+      static_for<0, E>([&](auto m_) {
+        constexpr int m = decltype(m_)::value;
+        e[m] += quad_perm<0xB1>(e[m]);             // lanes (0,1), (2,3)
+      });
+    }
+    if constexpr (G == 4) {
+      static_for<0, E>([&](auto m_) {
+        constexpr int m = decltype(m_)::value;
+        e[m] += quad_perm<0x4E>(e[m]);             // lanes (0,2), (1,3)
+      });
+    }
+    static_for<0, E>([&](auto m_) {
+      constexpr int m = decltype(m_)::value;
+      if constexpr (G == 4) acc[m >> 2] = fmaf(keepm[m & 3], e[m], acc[m >> 2]);
+      else if constexpr (G == 2) acc[m >> 1] = fmaf(keepm[m & 1], e[m], acc[m >> 1]);
+      else acc[m] += e[m];
     });
   }
   __syncthreads();
