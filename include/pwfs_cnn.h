@@ -57,6 +57,16 @@ int pwfs_cnn_set_params(pwfs_cnn_t net, const float* d_params, void* stream);
 /* Copy the flat FP32 master parameters into device memory. */
 int pwfs_cnn_get_params(pwfs_cnn_t net, float* d_params, void* stream);
 
+/* Optimiser state, for checkpoints: the Adam moments m and v (flat FP32,
+ * the parameters' order, device memory, n_params each) and the step count
+ * (Adam's bias correction uses it).  A checkpoint is the parameters
+ * (pwfs_cnn_get_params) and this state; restoring is pwfs_cnn_set_params
+ * (which resets the state) followed by pwfs_cnn_set_optimizer, after which
+ * training continues exactly as if it had never stopped.  Stream-ordered
+ * copies; PWFS_ERR_INVALID_ARG for NULL pointers or a negative step. */
+int pwfs_cnn_get_optimizer(pwfs_cnn_t net, float* d_m, float* d_v, int64_t* step, void* stream);
+int pwfs_cnn_set_optimizer(pwfs_cnn_t net, const float* d_m, const float* d_v, int64_t step, void* stream);
+
 /* Network input from binned pupils.
  *   d_pupils [B][4][S][S], d_ref_pupils [4][S][S] (flat-wavefront pupils),
  *   d_valid [n_valid] int32 subaperture indices j = iy * S + ix.

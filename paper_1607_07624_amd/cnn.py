@@ -29,11 +29,13 @@ def _lib():
         lib.pwfs_cnn_forward_acc.argtypes = [vp, vp, i32, f32, f32, vp, vp]
         lib.pwfs_cnn_gradients.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
         lib.pwfs_cnn_train_step.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
+        lib.pwfs_cnn_get_optimizer.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
+        lib.pwfs_cnn_set_optimizer.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
         lib.pwfs_cnn_destroy.argtypes = [vp]
         lib.pwfs_cnn_destroy.restype = None
         for n in ("pwfs_cnn_create", "pwfs_cnn_num_params", "pwfs_cnn_set_params", "pwfs_cnn_get_params",
                   "pwfs_cnn_prepare", "pwfs_cnn_forward", "pwfs_cnn_forward_acc", "pwfs_cnn_gradients",
-                  "pwfs_cnn_train_step"):
+                  "pwfs_cnn_train_step", "pwfs_cnn_get_optimizer", "pwfs_cnn_set_optimizer"):
             getattr(lib, n).restype = ctypes.c_int
         lib._cnn_typed = True
     return lib
@@ -140,6 +142,41 @@ class CNN:
         _check(self.lib.pwfs_cnn_train_step(self.handle, _ptr(x), _ptr(target), _ptr(weights), B, lr, beta1, beta2,
                                             eps, _ptr(loss), self._s()), "pwfs_cnn_train_step")
         return loss
+
+    def save(self, path: str):
+        """Checkpoint: FP32 master parameters, Adam moments and step count,
+        and the architecture, to an .npz file (no pickled objects)."""
+        t = self._torch
+        m = t.empty(self.n_params, dtype=t.float32, device="cuda")
+        v = t.empty(self.n_params, dtype=t.float32, device="cuda")
+        step = ctypes.c_int64()
+        _check(self.lib.pwfs_cnn_get_optimizer(self.handle, _ptr(m), _ptr(v), ctypes.byref(step), self._s()),
+               "pwfs_cnn_get_optimizer")
+        w = self.get_params()
+        arch = np.array([self.n_sub, self.shapes["w1"][0], self.shapes["w2"][0], self.shapes["w3"][0],
+                         self.shapes["fb1"][0], self.n_out], np.int64)
+        np.savez(path, params=w.cpu().numpy(), adam_m=m.cpu().numpy(), adam_v=v.cpu().numpy(),
+                 step=np.array(step.value, np.int64), arch=arch)
+
+    def load(self, path: str):
+        """Restore a checkpoint written by save() into this network (same
+        architecture): parameters, Adam moments and step count."""
+        t = self._torch
+        with np.load(path, allow_pickle=False) as f:
+            arch = [int(a) for a in f["arch"]]
+            mine = [self.n_sub, self.shapes["w1"][0], self.shapes["w2"][0], self.shapes["w3"][0],
+                    self.shapes["fb1"][0], self.n_out]
+            if arch != mine:
+                raise ValueError(f"checkpoint architecture {arch} differs from the network's {mine}")
+            w, m, v, step = f["params"], f["adam_m"], f["adam_v"], int(f["step"])
+        self.set_params(w)
+        md = t.from_numpy(np.ascontiguousarray(m, np.float32)).cuda()
+        vd = t.from_numpy(np.ascontiguousarray(v, np.float32)).cuda()
+        _need(md, t, t.float32, self.n_params, "adam_m")
+        _need(vd, t, t.float32, self.n_params, "adam_v")
+        _check(self.lib.pwfs_cnn_set_optimizer(self.handle, _ptr(md), _ptr(vd), step, self._s()),
+               "pwfs_cnn_set_optimizer")
+        t.cuda.current_stream().synchronize()
 
     def close(self):
         if getattr(self, "handle", None):

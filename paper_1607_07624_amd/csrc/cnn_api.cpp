@@ -17,6 +17,7 @@ using pwfs::cnn::GemmArgs;
 
 namespace pwfs {
 int set_last_error(int status, const std::string& msg);   // shared with the sensor ABI (pwfs_last_error)
+bool inject_alloc_failure();                              // allocation fault hook (PWFS_FAULT_INJECT)
 }
 
 namespace {
@@ -32,8 +33,7 @@ int hip_fail(hipError_t e, const char* what) {
 int dev_alloc(void** p, size_t bytes, const char* what) {
   *p = nullptr;
   if (bytes == 0) return 0;
-  const char* fi = std::getenv("PWFS_FAULT_INJECT");
-  if (fi && std::strcmp(fi, "oom") == 0) return fail(PWFS_CNN_ERR_OOM, std::string("injected OOM: ") + what);
+  if (pwfs::inject_alloc_failure()) return fail(PWFS_CNN_ERR_OOM, std::string("injected OOM: ") + what);
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -294,6 +294,27 @@ int pwfs_cnn_get_params(pwfs_cnn_t n, float* d, void* stream) {
   if (!n || !d) return fail(PWFS_CNN_ERR_INVALID_ARG, "network or params is NULL");
   DevGuard g(n->device);
   CK(hipMemcpyAsync(d, n->w, n->n_params * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return 0;
+}
+
+int pwfs_cnn_get_optimizer(pwfs_cnn_t n, float* d_m, float* d_v, int64_t* step, void* stream) {
+  if (!n || !d_m || !d_v || !step) return fail(PWFS_CNN_ERR_INVALID_ARG, "network or output is NULL");
+  DevGuard g(n->device);
+  hipStream_t st = (hipStream_t)stream;
+  CK(hipMemcpyAsync(d_m, n->m, n->n_params * 4, hipMemcpyDeviceToDevice, st));
+  CK(hipMemcpyAsync(d_v, n->v, n->n_params * 4, hipMemcpyDeviceToDevice, st));
+  *step = (int64_t)n->step;
+  return 0;
+}
+
+int pwfs_cnn_set_optimizer(pwfs_cnn_t n, const float* d_m, const float* d_v, int64_t step, void* stream) {
+  if (!n || !d_m || !d_v) return fail(PWFS_CNN_ERR_INVALID_ARG, "network or state is NULL");
+  if (step < 0) return fail(PWFS_CNN_ERR_INVALID_ARG, "step must be >= 0");
+  DevGuard g(n->device);
+  hipStream_t st = (hipStream_t)stream;
+  CK(hipMemcpyAsync(n->m, d_m, n->n_params * 4, hipMemcpyDeviceToDevice, st));
+  CK(hipMemcpyAsync(n->v, d_v, n->n_params * 4, hipMemcpyDeviceToDevice, st));
+  n->step = (long)step;
   return 0;
 }
 

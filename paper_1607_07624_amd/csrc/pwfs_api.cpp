@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -76,15 +77,18 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(PWFS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-bool fault_inject_oom() {
-  const char* v = std::getenv("PWFS_FAULT_INJECT");
-  return v && std::strcmp(v, "oom") == 0;
+}  // namespace
+
+namespace pwfs {
+bool inject_alloc_failure();
 }
+
+namespace {
 
 int dev_alloc(void** p, size_t bytes, const char* what) {
   *p = nullptr;
   if (bytes == 0) return PWFS_OK;
-  if (fault_inject_oom()) return fail(PWFS_ERR_OUT_OF_MEMORY, std::string("injected OOM: ") + what);
+  if (pwfs::inject_alloc_failure()) return fail(PWFS_ERR_OUT_OF_MEMORY, std::string("injected OOM: ") + what);
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -111,6 +115,30 @@ struct DeviceGuard {
 
 namespace pwfs {
 int set_last_error(int status, const std::string& msg) { return fail(status, msg); }
+
+// Test hook of the device allocators (sensor and network): with the
+// environment variable PWFS_FAULT_INJECT = "oom" every allocation fails,
+// with "oom:N" the N-th allocation after the variable took that value fails
+// (and later ones succeed), so that each partial-allocation clean-up path of
+// a create call can be driven.  Unset: no effect.
+bool inject_alloc_failure() {
+  static std::mutex mu;
+  static std::string spec;
+  static long count = 0;
+  const char* v = std::getenv("PWFS_FAULT_INJECT");
+  std::lock_guard<std::mutex> lk(mu);
+  const std::string now = v ? v : "";
+  if (now != spec) {
+    spec = now;
+    count = 0;
+  }
+  if (spec == "oom") return true;
+  if (spec.rfind("oom:", 0) == 0) {
+    const long n = std::atol(spec.c_str() + 4);
+    return ++count == n;
+  }
+  return false;
+}
 }  // namespace pwfs
 
 struct pwfs_plan_s {

@@ -110,6 +110,9 @@ def test_cnn_abi_validation_and_no_device():
     assert lib.pwfs_cnn_forward(None, None, 1, None, None) == -1
     assert lib.pwfs_cnn_prepare(None, None, None, 0, 1, 40, None, None) == -1
     assert lib.pwfs_cnn_prepare(None, None, None, 10, 0, 40, None, None) == 0      # empty batch
+    step = ctypes.c_int64()
+    assert lib.pwfs_cnn_get_optimizer(None, None, None, ctypes.byref(step), None) == -1
+    assert lib.pwfs_cnn_set_optimizer(None, None, None, 0, None) == -1
     lib.pwfs_cnn_destroy(None)
     code = ("import ctypes, sys; sys.path.insert(0, %r)\n"
             "from paper_1607_07624_amd.cnn import _lib, cnn_config\n"

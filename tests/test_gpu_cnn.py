@@ -137,6 +137,41 @@ def test_training_reduces_loss_on_device():
     assert float(loss.cpu()) < 0.3 * l0
 
 
+def test_checkpoint_round_trip(tmp_path):
+    """Training resumed from a checkpoint (parameters, Adam moments, step)
+    follows the uninterrupted run bit for bit; without the optimiser state
+    (parameters only) it does not."""
+    from paper_1607_07624_amd.cnn import CNN
+    net, torch, p, po, x, xb, tgt = _setup(SMALL, 8, 13)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda()
+    for _ in range(5):
+        net.train_step(xd, td, 3e-3)
+    path = str(tmp_path / "cnn_ckpt.npz")
+    net.save(path)
+    w_ckpt = net.get_params().cpu().numpy()
+    for _ in range(7):
+        net.train_step(xd, td, 3e-3)
+    a = net.get_params().cpu().numpy()
+    net2 = CNN(batch_max=8, **SMALL)
+    net2.load(path)
+    assert np.array_equal(net2.get_params().cpu().numpy(), w_ckpt)
+    for _ in range(7):
+        net2.train_step(xd, td, 3e-3)
+    b = net2.get_params().cpu().numpy()
+    say(f"[gpu] cnn checkpoint: resumed run equal {np.array_equal(a, b)}")
+    assert np.array_equal(a, b)
+    net3 = CNN(batch_max=8, **SMALL)
+    net3.set_params(w_ckpt)                                  # parameters only: fresh Adam state
+    for _ in range(7):
+        net3.train_step(xd, td, 3e-3)
+    assert not np.array_equal(net3.get_params().cpu().numpy(), a)
+    bad = CNN(batch_max=8, **dict(SMALL, hidden=38))
+    with pytest.raises(ValueError):
+        bad.load(path)
+    for n_ in (net, net2, net3, bad):
+        n_.close()
+
+
 def test_prepare_matches_oracle():
     from paper_1607_07624_amd.cnn import prepare
     torch = torch_cuda()
