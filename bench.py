@@ -38,14 +38,13 @@ PEAK_HBM_GBS = 8000.0
 # modulation chunk).  Valid only for the sources with these hashes (the kernels and the plan's
 # modulation order); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "32dc90cebc32d673e0456210789f733fec7330b5",
+    "sources_sha1": {"pwfs_kernels.hip": "bf725d96f743f1096b8f18a439cc1a734336648c",
                      "pwfs_field.h": "bc1faa09406794b7ad671c337fa21b1f47710d8a",
-                     "pwfs_common.h": "025f50a7adaee45f6fb1b6cf1add932e493ee268",
-                     "pwfs_dft.h": "c25e60bc82b746d087c11d9741edc141a2bed7c1",
-                     "pwfs_api.cpp": "f542d00cc1f94bd016e044515fbcac83e0c3f3bc"},
+                     "pwfs_common.h": "3096fe01bd7ba8d5172249619ee3af04487ad813",
+                     "pwfs_dft.h": "2311b455e0848ccf3b2b36c948f8cf8f42218515",
+                     "pwfs_api.cpp": "2b001c80741fa12ff0301c96d357c694d2cef3e9"},
     "batch": 16,
-    "col_pass_kib": {(3, 2): (81250.1, 9600.0), (3, 3): (107704.2, 6400.0), (3, 4): (81809.8, 4800.0),
-                     (3, 6): (81642.0, 3200.0)},
+    "col_pass_kib": {(3, 2): (81203.9, 9603.5), (3, 4): (81642.4, 4800.0), (3, 6): (81722.1, 3200.0)},
 }
 
 
@@ -259,7 +258,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=6)
     ap.add_argument("--cpu-frames-1core", type=int, default=2)
     ap.add_argument("--repeat-frames", type=int, default=2000,
-                    help="frames per repeat of the median-of-5 timing (B = 16 and B = 1)")
+                    help="frames per repeat of the median-of-5 timing (B = 16 and B = 1); 0 skips it "
+                         "(counter runs: every dispatch is then instrumented)")
     ap.add_argument("--loop-steps", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
@@ -362,7 +362,7 @@ def main():
     ms_step = ms_total / args.steps
     fps = B * args.steps / (ms_total / 1e3)
     log(f"{fps:.0f} frames/s, {ms_step:.3f} ms/step (wall {wall:.2f}s) kernels {kt}")
-    repeats = median_of_repeats(step, max(1, args.repeat_frames // B), B, ev0, ev1)
+    repeats = median_of_repeats(step, max(1, args.repeat_frames // B), B, ev0, ev1) if args.repeat_frames > 0 else None
     log(f"repeats {repeats}")
 
     if args.copy_mb:
@@ -429,7 +429,8 @@ def main():
     def step1():
         plan1.measure_into(o1, None, s1)
         pw.recon_apply(R, s1, 1.0, 0.0, m1)
-    extra["b1_repeats"] = median_of_repeats(step1, args.repeat_frames, 1, ev0, ev1)
+    if args.repeat_frames > 0:
+        extra["b1_repeats"] = median_of_repeats(step1, args.repeat_frames, 1, ev0, ev1)
 
     # The paper's detector geometry (80 x 80 frame, pupils 30 px across and 36
     # apart: each P = 160 window rebinned to 36 px), valid list from the pupil
