@@ -164,39 +164,69 @@ class ClosedLoop:
         settled = [v for (tt, v) in self.judged if tt >= self.judge_settle]
         return gam < self.gain_min or gam < self.gain_drop * max(settled)
 
-    def run(self, opd_seq_dev, residuals_dev=None):
-        """Run len(opd_seq) steps; returns (residual OPD [T, P*P], commands c(t) [T, M])."""
+    def run(self, opd_seq_dev, residuals_dev=None, state=None):
+        """Run len(opd_seq) steps; returns (residual OPD [T, P*P], commands c(t) [T, M]).
+
+        Without state the loop starts at t = 0 from zero commands.  With the
+        state of an earlier run (its `state` attribute, or load_state) it
+        continues that run: the delay line c(t0 - d) ... c(t0 - 1), the
+        reconstructor in use (learned, or linear after a hand-over), the
+        judge's record and the step count t0 (which sets the judge's
+        schedule) are restored, so running T1 steps and then T2 from the
+        state equals one run of T1 + T2 steps bit for bit.  After the run,
+        `state` holds the loop's state at its end.  At a hand-over at step t
+        the integrator restarts from zero: c(t - d + 1) ... c(t - 1), still
+        in the delay line, are set to zero (so they read zero in the returned
+        commands) and c(t) = g R s(t)."""
         import torch
         T = opd_seq_dev.shape[0]
         P, M, d = self.P, self.M, self.delay
         dev = opd_seq_dev.device
         res = residuals_dev if residuals_dev is not None else torch.empty((T, P * P), device=dev)
-        hist = torch.zeros((T + d, M), device=dev)                   # c(t) is row t + d
+        hist = torch.zeros((T + d, M), device=dev)                   # c(t0 + t) is row t + d
         learned = self.net is not None
-        self.judged = []
-        self.fallback_step = None
+        t0 = 0
+        if state is None:
+            self.judged = []
+            self.fallback_step = None
+        else:
+            if d < 1:
+                raise ValueError("resuming needs delay >= 1")
+            cmd = torch.as_tensor(state["commands"], dtype=torch.float32)
+            if tuple(cmd.shape) != (d, M):
+                raise ValueError(f"state holds commands of shape {tuple(cmd.shape)}, the loop needs ({d}, {M})")
+            if state["learned"] and self.net is None:
+                raise ValueError("state of a learned loop: the loop needs the network")
+            hist[:d].copy_(cmd.to(dev))
+            learned = learned and bool(state["learned"])
+            t0 = int(state["t"])
+            self.judged = [tuple(v) for v in state["judged"]]
+            self.fallback_step = None if state["fallback_step"] < 0 else int(state["fallback_step"])
         for t in range(T):
+            ta = t0 + t
             r_t = res[t:t + 1]
             r_t.copy_(opd_seq_dev[t].reshape(1, -1))
             recon_apply(self.BKL, hist[t:t + 1], -1.0, 1.0, r_t)     # u(t) = c(t - d)
             c_next = hist[t + d:t + d + 1]
-            if t > 0:
+            if ta > 0:
                 c_next.copy_(hist[t + d - 1:t + d])
             if learned:
                 self.plan.measure_into(r_t.view(1, P, P), self.pupils, self.s)
                 recon_apply(self.R, self.s, self.gain, 1.0, c_next)
                 self._prepare(self.pupils, self.ref[0], self.valid, self.x)
                 self.net.forward_acc(self.x, c_next, self.gain, 1.0)
-                if t % self.judge_every == 0 and self._judge(t, r_t, c_next):
+                if ta % self.judge_every == 0 and self._judge(ta, r_t, c_next):
                     learned = False
-                    self.fallback_step = t
-                    hist[: t + d + 1].zero_()
+                    self.fallback_step = ta
+                    hist[t + 1:t + d + 1].zero_()                    # the delay line still to be read
                     recon_apply(self.R, self.s, self.gain, 1.0, c_next)
             else:
                 self.plan.measure_into(r_t.view(1, P, P), None, self.s)
                 recon_apply(self.R, self.s, self.gain, 1.0, c_next)
+        self.state = {"t": t0 + T, "commands": hist[T:T + d].clone(), "learned": learned,
+                      "fallback_step": -1 if self.fallback_step is None else self.fallback_step,
+                      "judged": list(self.judged)}
         return res, hist[d:]
-
 
     def run_graph(self, opd_seq_dev, residuals_dev=None, steps_per_graph: int = 50):
         """run() for the linear reconstructor replayed from captured HIP graphs
@@ -315,3 +345,25 @@ def residual_rms_nm(res_host: np.ndarray, pupil: np.ndarray) -> np.ndarray:
     v = res_host.reshape(res_host.shape[0], -1)[:, pupil.ravel() > 0].astype(np.float64)
     v = v - v.mean(axis=1, keepdims=True)
     return np.sqrt((v ** 2).mean(axis=1))
+
+
+def save_state(path: str, state: dict, meta: dict | None = None) -> None:
+    """Write a ClosedLoop state (plus free-form metadata such as the screen
+    seed and the frozen-flow offset, kept as JSON) to an .npz of plain arrays."""
+    import json
+    cmd = state["commands"]
+    cmd = cmd.detach().cpu().numpy() if hasattr(cmd, "detach") else np.asarray(cmd)
+    judged = np.asarray(state["judged"], np.float64).reshape(-1, 2)
+    np.savez(path, t=np.int64(state["t"]), commands=np.asarray(cmd, np.float32),
+             learned=np.bool_(state["learned"]), fallback_step=np.int64(state["fallback_step"]),
+             judged=judged, meta=np.array(json.dumps(meta or {}, sort_keys=True)))
+
+
+def load_state(path: str):
+    """(state, meta) from save_state's file (read without unpickling)."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        state = {"t": int(z["t"]), "commands": z["commands"].copy(), "learned": bool(z["learned"]),
+                 "fallback_step": int(z["fallback_step"]),
+                 "judged": [(int(a), float(b)) for a, b in z["judged"]]}
+        return state, json.loads(str(z["meta"]))
