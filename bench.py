@@ -346,7 +346,6 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.timing_enable(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_wall = time.perf_counter()
@@ -357,11 +356,29 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
     ms_total = ev0.elapsed_time(ev1)
-    kt = plan.timing_read()
-    plan.timing_enable(False)
     ms_step = ms_total / args.steps
     fps = B * args.steps / (ms_total / 1e3)
-    log(f"{fps:.0f} frames/s, {ms_step:.3f} ms/step (wall {wall:.2f}s) kernels {kt}")
+    # Kernel durations: the same K steps again with the library's events bound
+    # to its kernels (their start and end times).  Timed kernels cost the
+    # stream ~20 us per step, so the throughput above is taken without them.
+    plan.timing_enable(True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step_timed = ev0.elapsed_time(ev1) / args.steps
+    kt = plan.timing_read()
+    plan.timing_enable(False)
+    # recon_apply alone, K calls on the step's slopes
+    ev0.record()
+    for _ in range(args.steps):
+        pw.recon_apply(R, s_buf, 1.0, 0.0, modes_out)
+    ev1.record()
+    torch.cuda.synchronize()
+    recon_ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"{fps:.0f} frames/s, {ms_step:.3f} ms/step (wall {wall:.2f}s; with kernel timing {ms_step_timed:.3f} ms/step)"
+        f" kernels {kt}")
     repeats = median_of_repeats(step, max(1, args.repeat_frames // B), B, ev0, ev1) if args.repeat_frames > 0 else None
     log(f"repeats {repeats}")
 
@@ -403,7 +420,10 @@ def main():
              "row_pass_tflops": round(lines_row * fft_pair_flops(cfg.n_fft) / (row_ms * 1e-3) / 1e12, 2),
              "row_pass_issued_tflops": round(fl_row / (row_ms * 1e-3) / 1e12, 2),
              "slopes_ms": round(kt["slopes_ms"] / n_launch, 4),
-             "recon_ms": round(ms_step - (kt["row_ms"] + kt["col_ms"] + kt["slopes_ms"]) / n_launch, 4)}
+             "recon_ms": round(recon_ms, 4),
+             "timing": ("kernel durations from events bound to the kernels' start and end "
+                        "(hipExtLaunchKernel) over a second pass of the same K steps; "
+                        f"that pass ran at {ms_step_timed:.4f} ms/step")}
 
     # B = 1 latency (one frame per call, same path).
     plan1 = pw.Plan(cfg, batch_max=1)

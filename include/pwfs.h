@@ -171,12 +171,15 @@ int pwfs_measure_static(pwfs_plan_t plan, const float* d_opd_nm, int32_t B,
 int pwfs_get_pupil(pwfs_plan_t plan, float* amp_host);
 
 /* Per-kernel timing of pwfs_measure.  With enable != 0 every later
- * pwfs_measure on this plan records HIP events around its row-pass,
- * column-pass and slopes kernels on the caller's stream (the previous
- * record is discarded); enable == 0 stops recording.  pwfs_timing_read
- * waits for the recorded events and returns the summed kernel durations
- * in milliseconds and the number of pwfs_measure batch slices recorded.
- * Any output pointer may be NULL. */
+ * pwfs_measure on this plan binds HIP events to its kernels on the caller's
+ * stream (hipExtLaunchKernel: an event takes a kernel's own start or end
+ * time, no marker is queued between kernels): start and end of the row
+ * segment (pupil field and row pass), of the column pass (the field-stop
+ * path: its column and output passes) and of the finish (chunk sum to
+ * slopes).  The previous record is discarded; enable == 0 stops recording.
+ * pwfs_timing_read waits for the recorded events and returns the summed
+ * segment durations in milliseconds and the number of pwfs_measure batch
+ * slices recorded.  Any output pointer may be NULL. */
 int pwfs_timing_enable(pwfs_plan_t plan, int enable);
 int pwfs_timing_read(pwfs_plan_t plan, double* ms_row, double* ms_col, double* ms_slopes,
                      int64_t* n_slices);

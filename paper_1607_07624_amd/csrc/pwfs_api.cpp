@@ -188,7 +188,7 @@ struct pwfs_plan_s {
   std::vector<float> amp_host;
   // per-kernel timing
   bool timing = false;
-  std::vector<std::array<hipEvent_t, 4>> ev_used, ev_free;
+  std::vector<std::array<hipEvent_t, 6>> ev_used, ev_free;  // start/stop of row, column, finish
 };
 
 namespace {
@@ -379,7 +379,7 @@ int run_measure(pwfs_plan_s* p, const float* opd, int B, float* pupils, float* s
     pwfs::MeasureArgs a = slice_args(p, opd, b0, Bs, pupils, slopes, sref, ws);
     hipEvent_t* ev = nullptr;
     if (p->timing) {
-      std::array<hipEvent_t, 4> evs{};
+      std::array<hipEvent_t, 6> evs{};
       if (!p->ev_free.empty()) {
         evs = p->ev_free.back();
         p->ev_free.pop_back();
@@ -848,11 +848,11 @@ int pwfs_timing_read(pwfs_plan_t p, double* ms_row, double* ms_col, double* ms_s
   DeviceGuard g(p->device);
   double acc[3] = {0.0, 0.0, 0.0};
   for (auto& a : p->ev_used) {
-    hipError_t e = hipEventSynchronize(a[3]);
+    hipError_t e = hipEventSynchronize(a[5]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     for (int i = 0; i < 3; ++i) {
       float ms = 0.f;
-      e = hipEventElapsedTime(&ms, a[i], a[i + 1]);
+      e = hipEventElapsedTime(&ms, a[2 * i], a[2 * i + 1]);
       if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
       acc[i] += ms;
     }
@@ -1276,7 +1276,7 @@ int pwfs_autotune(pwfs_plan_t p, int32_t B, int32_t reps, void* stream, double* 
   hipStream_t st = (hipStream_t)stream;
   float* d_opd = nullptr;
   float* d_sl = nullptr;
-  std::array<hipEvent_t, 4> ev{};
+  std::array<hipEvent_t, 6> ev{};
   int status = PWFS_OK;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(st);
@@ -1309,10 +1309,10 @@ int pwfs_autotune(pwfs_plan_t p, int32_t B, int32_t reps, void* stream, double* 
     *row_ms = *col_ms = 1e30;
     for (int r = 0; r < reps && le == hipSuccess; ++r) {
       le = pwfs::launch_measure(a, st, ev.data());
-      if (le == hipSuccess) le = hipEventSynchronize(ev[3]);
+      if (le == hipSuccess) le = hipEventSynchronize(ev[5]);
       float t0 = 0.f, t1 = 0.f;
       if (le == hipSuccess) le = hipEventElapsedTime(&t0, ev[0], ev[1]);
-      if (le == hipSuccess) le = hipEventElapsedTime(&t1, ev[1], ev[3]);
+      if (le == hipSuccess) le = hipEventElapsedTime(&t1, ev[2], ev[5]);
       *row_ms = std::min(*row_ms, (double)t0);
       *col_ms = std::min(*col_ms, (double)t1);
     }

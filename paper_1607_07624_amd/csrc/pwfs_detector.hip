@@ -83,11 +83,10 @@ __global__ __launch_bounds__(256) void detector_kernel(const float* __restrict__
 }
 
 hipError_t launch_detector(const float* intensity, float* pixels, int npix, int B, uint64_t frame0, float gain,
-                           float ron, uint64_t seed, hipStream_t st) {
+                           float ron, uint64_t seed, hipStream_t st, hipEvent_t stop) {
   if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(detector_kernel, dim3((npix + 255) / 256, B), dim3(256), 0, st, intensity, pixels, npix, frame0,
-                     gain, ron, seed);
-  return hipGetLastError();
+  return launch_k(detector_kernel, dim3((npix + 255) / 256, B), dim3(256), 0, st, nullptr, stop, intensity, pixels,
+                  npix, frame0, gain, ron, seed);
 }
 
 }  // namespace pwfs

@@ -219,26 +219,24 @@ __global__ __launch_bounds__(256) void fs_out_kernel(const cpx* __restrict__ W, 
 }
 
 template <int E>
-static hipError_t launch_fs_e(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) {
+static hipError_t launch_fs_e(const MeasureArgs& a, hipStream_t st) {
   constexpr int P = 4 * E, N = 4 * P;
   hipError_t e;
-  hipLaunchKernelGGL(fs_rows_kernel<E>, dim3(P / 16, a.K, a.B), dim3(256), 0, st, a.field, a.fs_rx, a.fs_ry,
-                     a.fs_tw4n, a.fs_twp, a.fs_r2max, a.K, a.fs_Z);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(fs_cols_kernel<E>, dim3(N / 16, a.K, a.B), dim3(256), 0, st, a.fs_Z, a.fs_tw4n, a.fs_twp,
-                     a.fs_twi, a.fs_py, a.fs_r2max, a.K, a.fs_W);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(fs_out_kernel<E>, dim3(2 * P / 16, a.n_chunks, a.B), dim3(256), 0, st, a.fs_W, a.fs_twp,
-                     a.fs_twi, a.K, a.k_chunk, a.n_chunks, a.partial);
-  return hipGetLastError();
+  if ((e = launch_k(fs_rows_kernel<E>, dim3(P / 16, a.K, a.B), dim3(256), 0, st, nullptr, a.tev[1],
+                    (const cpx*)a.field, a.fs_rx, a.fs_ry, a.fs_tw4n, a.fs_twp, a.fs_r2max, a.K, a.fs_Z)) != hipSuccess)
+    return e;
+  if ((e = launch_k(fs_cols_kernel<E>, dim3(N / 16, a.K, a.B), dim3(256), 0, st, a.tev[2], nullptr,
+                    (const cpx*)a.fs_Z, a.fs_tw4n, a.fs_twp, a.fs_twi, a.fs_py, a.fs_r2max, a.K, a.fs_W)) != hipSuccess)
+    return e;
+  return launch_k(fs_out_kernel<E>, dim3(2 * P / 16, a.n_chunks, a.B), dim3(256), 0, st, nullptr, a.tev[3],
+                  (const cpx*)a.fs_W, a.fs_twp, a.fs_twi, a.K, a.k_chunk, a.n_chunks, a.partial);
 }
 
-hipError_t launch_fstop_passes(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) {
+hipError_t launch_fstop_passes(const MeasureArgs& a, hipStream_t st) {
   switch (a.P) {
-    case 32: return launch_fs_e<8>(a, st, ev);
-    case 64: return launch_fs_e<16>(a, st, ev);
-    case 160: return launch_fs_e<40>(a, st, ev);
+    case 32: return launch_fs_e<8>(a, st);
+    case 64: return launch_fs_e<16>(a, st);
+    case 160: return launch_fs_e<40>(a, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -532,9 +532,8 @@ hipError_t launch_field_raw(const float* opd, const float* amp, double kphase, i
 hipError_t launch_field(const MeasureArgs& a, hipStream_t st) {
   const size_t n = (size_t)a.B * a.P * a.P;
   const unsigned fb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(field_kernel, dim3(fb), dim3(256), 0, st, a.opd, a.amp, a.kphase, a.fp32_phase, a.P * a.P, n,
-                     a.field);
-  return hipGetLastError();
+  return launch_k(field_kernel, dim3(fb), dim3(256), 0, st, a.tev[0], nullptr, a.opd, a.amp, a.kphase, a.fp32_phase,
+                  a.P * a.P, n, a.field);
 }
 
 template <int E>
@@ -543,27 +542,20 @@ static hipError_t launch_rows(const MeasureArgs& a, hipStream_t st) {
   hipError_t e = launch_field(a, st);
   if (e != hipSuccess) return e;
   dim3 grid(a.P / 32, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
-  hipLaunchKernelGGL(row_pass_kernel<E>, grid, dim3(256), 0, st, a.field, a.in_a, a.f_a, a.mid, a.outw, a.Rw,
-                     a.n_a, a.a_chunk);
-  return hipGetLastError();
+  return launch_k(row_pass_kernel<E>, grid, dim3(256), 0, st, nullptr, a.tev[1], a.field, a.in_a, a.f_a, a.mid,
+                  a.outw, a.Rw, a.n_a, a.a_chunk);
 }
 
 template <int E>
 static hipError_t launch_cols(const MeasureArgs& a, hipStream_t st) {
   dim3 grid(2 * a.P / 32, a.n_chunks, a.B);
-  if (a.n_bin % 4 == 0)
-    hipLaunchKernelGGL((col_pass_kernel<E, 4>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
-                       a.k_ia, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
-  else if (a.n_bin % 2 == 0)
-    hipLaunchKernelGGL((col_pass_kernel<E, 2>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
-                       a.k_ia, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
-  else
-    hipLaunchKernelGGL((col_pass_kernel<E, 1>), grid, dim3(256), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
-                       a.k_ia, a.mid, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
-  return hipGetLastError();
+  auto* kern = a.n_bin % 4 == 0 ? col_pass_kernel<E, 4> : a.n_bin % 2 == 0 ? col_pass_kernel<E, 2>
+                                                                           : col_pass_kernel<E, 1>;
+  return launch_k(kern, grid, dim3(256), 0, st, a.tev[2], a.tev[3], a.Rw, a.in_b, a.f_b, a.k_order, a.k_ia, a.mid,
+                  a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
 }
 
-hipError_t launch_finish(const MeasureArgs& a, int Sb, hipStream_t st, hipEvent_t* ev);
+hipError_t launch_finish(const MeasureArgs& a, int Sb, hipStream_t st);
 
 // Non-integer detector rebin: each P x P window [B][4][P][P] to S x S pixels
 // of pitch P / S.  Positions in units of 1 / S: pupil pixel y spans
@@ -593,14 +585,14 @@ __global__ __launch_bounds__(256) void rebin_kernel(const float* __restrict__ in
   out[fr * 4 * (size_t)S * S + o] = acc / (float)(S * S);
 }
 
-hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) {
+hipError_t launch_measure(const MeasureArgs& args, hipStream_t st, hipEvent_t* ev) {
+  MeasureArgs a = args;
+  for (int i = 0; i < 6; ++i) a.tev[i] = ev ? ev[i] : nullptr;
   hipError_t e = hipSuccess;
-  if (ev && (e = hipEventRecord(ev[0], st)) != hipSuccess) return e;
   if (a.fs_on) {
     if ((e = launch_field(a, st)) != hipSuccess) return e;
-    if ((e = launch_fstop_passes(a, st, ev)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-    return launch_finish(a, a.P, st, ev);
+    if ((e = launch_fstop_passes(a, st)) != hipSuccess) return e;
+    return launch_finish(a, a.P, st);
   }
   if (a.lines16) {
     e = launch_rows_long(a, st);
@@ -613,7 +605,6 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
     }
   }
   if (e != hipSuccess) return e;
-  if (ev && (e = hipEventRecord(ev[1], st)) != hipSuccess) return e;
   if (a.lines16) {
     e = launch_cols_long(a, st);
   } else {
@@ -625,43 +616,46 @@ hipError_t launch_measure(const MeasureArgs& a, hipStream_t st, hipEvent_t* ev) 
     }
   }
   if (e != hipSuccess) return e;
-  if (ev && (e = hipEventRecord(ev[2], st)) != hipSuccess) return e;
-  return launch_finish(a, a.P / a.n_bin, st, ev);
+  return launch_finish(a, a.P / a.n_bin, st);
 }
 
 // After the passes: chunk sum of the partial images (Sb x Sb per window),
-// optional rebin, detector and slopes.
-hipError_t launch_finish(const MeasureArgs& a, int Sb, hipStream_t st, hipEvent_t* ev) {
+// optional rebin, detector and slopes.  The first kernel takes the finish's
+// start event, the last one its stop event.
+hipError_t launch_finish(const MeasureArgs& a, int Sb, hipStream_t st) {
   hipError_t e = hipSuccess;
   const int S = a.rebin_S > 0 ? a.rebin_S : Sb;
   const int n4ss = 4 * S * S;
+  const int last = a.slopes ? 3 : a.det_on ? 2 : a.rebin_S > 0 ? 1 : 0;
+  auto stop_if = [&](int i) { return i == last ? a.tev[5] : nullptr; };
   // With a detector the noiseless images go to the intensity scratch and the
   // detector writes the pixels that the slopes use.
   float* images = a.det_on ? a.intensity : a.pupils;
   float* reduced = a.rebin_S > 0 ? a.fullres : images;
   if (!a.fs_on && partials_by_column(a.P, a.n_bin)) {
-    if ((e = launch_reduce_cols(a, reduced, st)) != hipSuccess) return e;
+    // (its start event: see launch_reduce_cols)
+    if ((e = launch_reduce_cols(a, reduced, st, stop_if(0))) != hipSuccess) return e;
   } else {
     const int n4bb = 4 * Sb * Sb;
-    hipLaunchKernelGGL(pupil_reduce_kernel, dim3((n4bb + 255) / 256, a.B), dim3(256), 0, st, a.partial,
-                       a.n_chunks, n4bb, 1.0f / (float)a.K, reduced);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_k(pupil_reduce_kernel, dim3((n4bb + 255) / 256, a.B), dim3(256), 0, st, a.tev[4], stop_if(0),
+                      (const float*)a.partial, a.n_chunks, n4bb, 1.0f / (float)a.K, reduced)) != hipSuccess)
+      return e;
   }
   if (a.rebin_S > 0) {
-    hipLaunchKernelGGL(rebin_kernel, dim3((n4ss + 255) / 256, a.B), dim3(256), 0, st, a.fullres, a.P, S, images);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_k(rebin_kernel, dim3((n4ss + 255) / 256, a.B), dim3(256), 0, st, nullptr, stop_if(1),
+                      (const float*)a.fullres, a.P, S, images)) != hipSuccess)
+      return e;
   }
   if (a.det_on) {
-    if ((e = launch_detector(a.intensity, a.pupils, n4ss, a.B, a.frame0, a.det_gain, a.det_ron, a.det_seed, st)) !=
-        hipSuccess)
+    if ((e = launch_detector(a.intensity, a.pupils, n4ss, a.B, a.frame0, a.det_gain, a.det_ron, a.det_seed, st,
+                             stop_if(2))) != hipSuccess)
       return e;
   }
   if (a.slopes) {
-    hipLaunchKernelGGL(slopes_kernel, dim3(a.B), dim3(1024), 0, st, a.pupils, S, a.valid, a.nv, a.sref,
-                       a.norm_mode, a.slopes);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_k(slopes_kernel, dim3(a.B), dim3(1024), 0, st, nullptr, stop_if(3), (const float*)a.pupils, S,
+                      a.valid, a.nv, a.sref, a.norm_mode, a.slopes)) != hipSuccess)
+      return e;
   }
-  if (ev && (e = hipEventRecord(ev[3], st)) != hipSuccess) return e;
   return hipSuccess;
 }
 

@@ -419,17 +419,16 @@ static hipError_t launch_rows16_e(const MeasureArgs& a, hipStream_t st) {
     if (e != hipSuccess) return e;
   }
   dim3 grid(a.P / 8, (a.n_a + a.a_chunk - 1) / a.a_chunk, a.B);
-  hipLaunchKernelGGL((row_pass16_kernel<E, kField>), grid, dim3(256), 0, st, a.field, a.opd, a.amp, a.kphase,
-                     a.fp32_phase, a.in_a, a.f_a, a.mid, a.tw16, a.outw, a.Rw, a.n_a, a.a_chunk);
-  return hipGetLastError();
+  return launch_k(row_pass16_kernel<E, kField>, grid, dim3(256), 0, st, kField ? a.tev[0] : nullptr, a.tev[1],
+                  a.field, a.opd, a.amp, a.kphase, a.fp32_phase, a.in_a, a.f_a, a.mid, a.tw16, a.outw, a.Rw, a.n_a,
+                  a.a_chunk);
 }
 
 template <int E, int CB>
 static hipError_t launch_cols16_e(const MeasureArgs& a, hipStream_t st) {
   dim3 grid(2 * a.P / CB, a.n_chunks, a.B);
-  hipLaunchKernelGGL((col_pass16_kernel<E, CB>), grid, dim3(32 * CB), 0, st, a.Rw, a.in_b, a.f_b, a.k_order,
-                     a.k_ia, a.mid, a.tw16, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
-  return hipGetLastError();
+  return launch_k(col_pass16_kernel<E, CB>, grid, dim3(32 * CB), 0, st, a.tev[2], a.tev[3], a.Rw, a.in_b, a.f_b,
+                  a.k_order, a.k_ia, a.mid, a.tw16, a.outw, a.partial, a.n_a, a.K, a.k_chunk, a.n_chunks, a.n_bin);
 }
 
 hipError_t launch_rows_long(const MeasureArgs& a, hipStream_t st) {
@@ -452,11 +451,11 @@ hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t st) {
 
 bool partials_by_column(int P, int n_bin) { return (P == 128 || P == 480) && 8 % n_bin != 0; }
 
-hipError_t launch_reduce_cols(const MeasureArgs& a, float* out, hipStream_t st) {
+// First kernel of the finish: takes its start event; `stop` when it is also the last.
+hipError_t launch_reduce_cols(const MeasureArgs& a, float* out, hipStream_t st, hipEvent_t stop) {
   const int S = a.P / a.n_bin;
-  hipLaunchKernelGGL(pupil_reduce_cols_kernel, dim3((4 * S * S + 255) / 256, a.B), dim3(256), 0, st, a.partial,
-                     a.n_chunks, a.P, S, a.n_bin, 1.0f / (float)a.K, out);
-  return hipGetLastError();
+  return launch_k(pupil_reduce_cols_kernel, dim3((4 * S * S + 255) / 256, a.B), dim3(256), 0, st, a.tev[4], stop,
+                  (const float*)a.partial, a.n_chunks, a.P, S, a.n_bin, 1.0f / (float)a.K, out);
 }
 
 }  // namespace pwfs

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -58,7 +59,25 @@ struct MeasureArgs {
   const cpx* fs_py;    // [N]     exp(-2 pi i Delta |v_s| / N)
   cpx* fs_Z;           // [B][K][N][P]
   cpx* fs_W;           // [B][K][2P][N]
+  // timing (all NULL unless timed): start and stop of the row segment (field
+  // and row pass), the column segment and the finish (chunk sum to slopes),
+  // bound to the first and last kernel of each (launch_k)
+  hipEvent_t tev[6];
 };
+
+// Kernel launch with optional timing events bound to the kernel itself
+// (hipExtLaunchKernelGGL): `start` takes the kernel's start time and `stop`
+// its end time, so no marker packets are queued between the kernels of a
+// call and the events measure kernel execution only.
+template <typename... KArgs, typename... Args>
+inline hipError_t launch_k(void (*kernel)(KArgs...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t st,
+                           hipEvent_t start, hipEvent_t stop, Args... args) {
+  if (start || stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, st, start, stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, st, args...);
+  return hipGetLastError();
+}
 
 // PSF camera: field at the science wavelength, zero-padded 2-D transform,
 // |.|^2 / (sum A)^2 centred (or accumulated over the frames), Strehl ratios.
@@ -91,12 +110,13 @@ struct ShArgs {
   float* slopes;       // [B][2 nv] or NULL
 };
 
-// ev: NULL, or four events recorded before the row pass, between the passes
-// and after the slopes kernel.
+// ev: NULL, or six events that take the start and end times of the row
+// segment, the column segment and the finish (MeasureArgs::tev).
 hipError_t launch_measure(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
 // The three passes of the field-stop path (pwfs_fstop.hip), after the field;
-// records ev[1] after the row pass when ev is given.
-hipError_t launch_fstop_passes(const MeasureArgs& a, hipStream_t stream, hipEvent_t* ev);
+// its row transforms end the row segment, its column and output passes form
+// the column segment.
+hipError_t launch_fstop_passes(const MeasureArgs& a, hipStream_t stream);
 // Pieces of launch_measure: the pupil field (one frame slice), and the row and
 // column passes of the long-line kernels (P = 128, 480).
 hipError_t launch_field(const MeasureArgs& a, hipStream_t stream);
@@ -109,10 +129,10 @@ hipError_t launch_cols_long(const MeasureArgs& a, hipStream_t stream);
 // Long lines with a binning that does not divide 8 columns: the column pass
 // writes per-column partials [B][n_chunks][2][2P][S], finished here.
 bool partials_by_column(int P, int n_bin);
-hipError_t launch_reduce_cols(const MeasureArgs& a, float* pupils, hipStream_t stream);
+hipError_t launch_reduce_cols(const MeasureArgs& a, float* pupils, hipStream_t stream, hipEvent_t stop);
 hipError_t launch_fill(float* p, size_t n, float v, hipStream_t stream);
 hipError_t launch_detector(const float* intensity, float* pixels, int npix, int B, uint64_t frame0, float gain,
-                           float ron, uint64_t seed, hipStream_t stream);
+                           float ron, uint64_t seed, hipStream_t stream, hipEvent_t stop = nullptr);
 hipError_t launch_recon(const float* R, int M, int ns, const float* s, int B, float alpha, float beta,
                         float* m, hipStream_t stream);
 
