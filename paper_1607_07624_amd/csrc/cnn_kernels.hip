@@ -68,15 +68,18 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int i, int j, float 
 // ---------------------------------------------------------------------------
 // Tiled MFMA GEMM.  Block = 4 waves in a WM x WN arrangement, each wave
 // owning TM x TN blocks of 32 x 32 outputs: a BM x BN tile, BM = 32 WM TM,
-// BN = 32 WN TN.  K advances 32 at a time through two LDS stages (the next
-// stage's global loads are in flight while the current stage is multiplied;
-// one barrier per step).  LDS holds every operand tile as [row][k] with k
-// contiguous and a row pitch of 40 bf16 (80 bytes), so an MFMA operand is
-// one 16-byte read per lane: v_mfma_f32_32x32x16_bf16 takes, in lane l, the
-// 8 consecutive k of row (l mod 32) starting at 8 (l / 32); its 16
-// accumulators of lane l are C(8 (v / 4) + 4 (l / 32) + v mod 4, l mod 32).
+// BN = 32 WN TN.  K advances BK (a multiple of 16; the products use 32) at
+// a time through two LDS stages (the next stage's global loads are in
+// flight while the current stage is multiplied; one barrier per step).
+// LDS holds every operand tile as
+// [row][k] with k contiguous and a row pitch of BK + 8 bf16 (the 8 extra
+// spread the 16-byte reads of eight consecutive rows over all banks), so an
+// MFMA operand is one 16-byte read per lane: v_mfma_f32_32x32x16_bf16
+// takes, in lane l, the 8 consecutive k of row (l mod 32) starting at
+// 8 (l / 32); its 16 accumulators of lane l are
+// C(8 (v / 4) + 4 (l / 32) + v mod 4, l mod 32).
 //
-// Operand views.  A tile of R rows (rows = i for A, j for B) by 32 k comes
+// Operand views.  A tile of R rows (rows = i for A, j for B) by BK k comes
 // from global memory in one of two layouts:
 //  * k-contiguous (stride 1 along k): chunk = 8 k of one row, one 16-byte
 //    load (vw 8), two 8-byte loads (vw 4) or 8 element loads (vw 1);
@@ -86,8 +89,8 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int i, int j, float 
 // vw (16-, 8- or 2-byte groups) is decided on the host from the strides,
 // extents and alignment, uniform per launch.  Elements past the extents are
 // zero; the bias-gradient column (B row N) is 1 in the hi plane.
-constexpr int kBK = 32;
-constexpr int kPitch = 40;
+constexpr int pitch_of(int BK) { return BK + 8; }
+constexpr int kStepK = 32;   // k depth per step of the products
 
 struct OpView {
   const uint16_t* p;
@@ -141,22 +144,25 @@ __device__ __forceinline__ void set_half(Chunk8& c, int r, uint32_t v) {
   c.w[r >> 1] = (c.w[r >> 1] & ~(0xffffu << s)) | (v << s);
 }
 
-// Staged global data of one operand plane for one k step: up to 2 chunks
-// (k-contiguous) or one quad-chunk of 4 loads (row-contiguous) per thread.
+// Staged global data of one operand plane for one k step: up to 4 chunks
+// (k-contiguous) or one quad-chunk of 4 loads (row-contiguous) per thread,
+// which bounds a tile's R rows x BK k at 8192 elements.
 struct Stage {
   Chunk8 c[4];
 };
 
-template <bool KC, int R>
+template <bool KC, int R, int BK>
 __device__ __forceinline__ void op_load(const OpView& v, long lo, int r0, int k0, int K, Stage& s, int tid) {
+  static_assert(R * BK <= 8192, "operand tile too large for the staging registers");
+  constexpr int CPR = BK / 8;   // chunks per row
   const uint16_t* p = v.p + lo;
   if constexpr (KC) {
-    // R rows x 4 chunks; thread t takes chunks t and t + 256
+    // R rows x CPR chunks; thread t takes chunks t, t + 256, ...
 #pragma unroll
-    for (int t = 0; t < (R * 4 + 255) / 256; ++t) {
+    for (int t = 0; t < (R * CPR + 255) / 256; ++t) {
       const int c = tid + 256 * t;
-      if (c < R * 4) {
-        const int row = c >> 2, kk = (c & 3) * 8;
+      if (c < R * CPR) {
+        const int row = c / CPR, kk = (c % CPR) * 8;
         const int gr = r0 + row;
         const bool in = gr < v.rows;
         const int gk = k0 + kk;
@@ -172,8 +178,8 @@ __device__ __forceinline__ void op_load(const OpView& v, long lo, int r0, int k0
       }
     }
   } else {
-    // quad-chunks: (R / 8) row groups x 8 k groups; thread t < R
-    if (tid < R) {
+    // quad-chunks: (R / 8) row groups x (BK / 4) k groups; thread t < R BK / 32
+    if (tid < R * BK / 32) {
       const int rg = tid % (R / 8), kg = tid / (R / 8);
       const int gr = r0 + rg * 8;
 #pragma unroll
@@ -194,34 +200,35 @@ __device__ __forceinline__ void op_load(const OpView& v, long lo, int r0, int k0
   }
 }
 
-template <bool KC, int R>
+template <bool KC, int R, int BK>
 __device__ __forceinline__ void op_store(uint16_t* lds, const Stage& s, int tid) {
+  constexpr int CPR = BK / 8, PITCH = pitch_of(BK);
   if constexpr (KC) {
 #pragma unroll
-    for (int t = 0; t < (R * 4 + 255) / 256; ++t) {
+    for (int t = 0; t < (R * CPR + 255) / 256; ++t) {
       const int c = tid + 256 * t;
-      if (c < R * 4) {
-        const int row = c >> 2, kk = (c & 3) * 8;
-        *reinterpret_cast<uint4*>(lds + row * kPitch + kk) = make_uint4(s.c[t].w[0], s.c[t].w[1], s.c[t].w[2], s.c[t].w[3]);
+      if (c < R * CPR) {
+        const int row = c / CPR, kk = (c % CPR) * 8;
+        *reinterpret_cast<uint4*>(lds + row * PITCH + kk) = make_uint4(s.c[t].w[0], s.c[t].w[1], s.c[t].w[2], s.c[t].w[3]);
       }
     }
   } else {
-    if (tid < R) {
+    if (tid < R * BK / 32) {
       const int rg = tid % (R / 8), kg = tid / (R / 8);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const uint32_t w0 = half_of(s.c[0], r) | (half_of(s.c[1], r) << 16);
         const uint32_t w1 = half_of(s.c[2], r) | (half_of(s.c[3], r) << 16);
-        *reinterpret_cast<uint2*>(lds + (rg * 8 + r) * kPitch + kg * 4) = make_uint2(w0, w1);
+        *reinterpret_cast<uint2*>(lds + (rg * 8 + r) * PITCH + kg * 4) = make_uint2(w0, w1);
       }
     }
   }
 }
 
-template <int WM, int WN, int TM, int TN, bool AKC, bool BKC>
+template <int WM, int WN, int TM, int TN, bool AKC, bool BKC, int BK>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, OpView vb, int kc,
                                                         float* __restrict__ part) {
-  constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN;
+  constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN, kPitch = pitch_of(BK);
   extern __shared__ __align__(16) uint16_t lds[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave / WN, wn = wave % WN;
@@ -248,29 +255,29 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
 
   Stage sa, sal, sb, sbl;
   // prologue
-  op_load<AKC, BM>(va, 0, i0, kbeg, kend, sa, tid);
-  if (alo) op_load<AKC, BM>(va, g.a_lo, i0, kbeg, kend, sal, tid);
-  op_load<BKC, BN>(vb, 0, j0, kbeg, kend, sb, tid);
-  if (blo) op_load<BKC, BN>(vb, g.b_lo, j0, kbeg, kend, sbl, tid);
-  op_store<AKC, BM>(a_hi(st0), sa, tid);
-  if (alo) op_store<AKC, BM>(a_lo(st0), sal, tid);
-  op_store<BKC, BN>(b_hi(st0), sb, tid);
-  if (blo) op_store<BKC, BN>(b_lo(st0), sbl, tid);
+  op_load<AKC, BM, BK>(va, 0, i0, kbeg, kend, sa, tid);
+  if (alo) op_load<AKC, BM, BK>(va, g.a_lo, i0, kbeg, kend, sal, tid);
+  op_load<BKC, BN, BK>(vb, 0, j0, kbeg, kend, sb, tid);
+  if (blo) op_load<BKC, BN, BK>(vb, g.b_lo, j0, kbeg, kend, sbl, tid);
+  op_store<AKC, BM, BK>(a_hi(st0), sa, tid);
+  if (alo) op_store<AKC, BM, BK>(a_lo(st0), sal, tid);
+  op_store<BKC, BN, BK>(b_hi(st0), sb, tid);
+  if (blo) op_store<BKC, BN, BK>(b_lo(st0), sbl, tid);
   __syncthreads();
 
   int it = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += kBK, ++it) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK, ++it) {
     uint16_t* cur = (it & 1) ? st1 : st0;
     uint16_t* nxt = (it & 1) ? st0 : st1;
-    const bool more = k0 + kBK < kend;
+    const bool more = k0 + BK < kend;
     if (more) {
-      op_load<AKC, BM>(va, 0, i0, k0 + kBK, kend, sa, tid);
-      if (alo) op_load<AKC, BM>(va, g.a_lo, i0, k0 + kBK, kend, sal, tid);
-      op_load<BKC, BN>(vb, 0, j0, k0 + kBK, kend, sb, tid);
-      if (blo) op_load<BKC, BN>(vb, g.b_lo, j0, k0 + kBK, kend, sbl, tid);
+      op_load<AKC, BM, BK>(va, 0, i0, k0 + BK, kend, sa, tid);
+      if (alo) op_load<AKC, BM, BK>(va, g.a_lo, i0, k0 + BK, kend, sal, tid);
+      op_load<BKC, BN, BK>(vb, 0, j0, k0 + BK, kend, sb, tid);
+      if (blo) op_load<BKC, BN, BK>(vb, g.b_lo, j0, k0 + BK, kend, sbl, tid);
     }
 #pragma unroll
-    for (int sub = 0; sub < 2; ++sub) {
+    for (int sub = 0; sub < BK / 16; ++sub) {
       const int kof = sub * 16 + 8 * (lane >> 5);
       bf16x8 fa[TM], fb[TN];
 #pragma unroll
@@ -304,10 +311,10 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
       }
     }
     if (more) {
-      op_store<AKC, BM>(a_hi(nxt), sa, tid);
-      if (alo) op_store<AKC, BM>(a_lo(nxt), sal, tid);
-      op_store<BKC, BN>(b_hi(nxt), sb, tid);
-      if (blo) op_store<BKC, BN>(b_lo(nxt), sbl, tid);
+      op_store<AKC, BM, BK>(a_hi(nxt), sa, tid);
+      if (alo) op_store<AKC, BM, BK>(a_lo(nxt), sal, tid);
+      op_store<BKC, BN, BK>(b_hi(nxt), sb, tid);
+      if (blo) op_store<BKC, BN, BK>(b_lo(nxt), sbl, tid);
     }
     __syncthreads();
   }
@@ -733,24 +740,25 @@ static int vec_width(const uint16_t* p, long lo, long other_stride, int extent) 
   return 1;
 }
 
-template <int WM, int WN, int TM, int TN, bool AKC, bool BKC>
+template <int WM, int WN, int TM, int TN, bool AKC, bool BKC, int BK>
 static hipError_t launch_tile(const GemmArgs& g, const OpView& va, const OpView& vb, int splits, int kc, float* part,
                               hipStream_t st) {
   constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN;
   const int Nc = g.N + (g.bias_grad ? 1 : 0);
-  const size_t lds = (size_t)2 * (BM * (g.a_lo ? 2 : 1) + BN * (g.b_lo ? 2 : 1)) * kPitch * sizeof(uint16_t);
-  hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, TM, TN, AKC, BKC>), dim3((Nc + BN - 1) / BN, (g.M + BM - 1) / BM, splits),
-                     dim3(256), lds, st, g, va, vb, kc, splits > 1 ? part : (float*)nullptr);
+  const size_t lds = (size_t)2 * (BM * (g.a_lo ? 2 : 1) + BN * (g.b_lo ? 2 : 1)) * pitch_of(BK) * sizeof(uint16_t);
+  hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, TM, TN, AKC, BKC, BK>),
+                     dim3((Nc + BN - 1) / BN, (g.M + BM - 1) / BM, splits), dim3(256), lds, st, g, va, vb, kc,
+                     splits > 1 ? part : (float*)nullptr);
   return hipGetLastError();
 }
 
-template <int WM, int WN, int TM, int TN>
+template <int WM, int WN, int TM, int TN, int BK>
 static hipError_t launch_layout(const GemmArgs& g, const OpView& va, const OpView& vb, bool akc, bool bkc, int splits,
                                 int kc, float* part, hipStream_t st) {
-  if (akc && bkc) return launch_tile<WM, WN, TM, TN, true, true>(g, va, vb, splits, kc, part, st);
-  if (akc) return launch_tile<WM, WN, TM, TN, true, false>(g, va, vb, splits, kc, part, st);
-  if (bkc) return launch_tile<WM, WN, TM, TN, false, true>(g, va, vb, splits, kc, part, st);
-  return launch_tile<WM, WN, TM, TN, false, false>(g, va, vb, splits, kc, part, st);
+  if (akc && bkc) return launch_tile<WM, WN, TM, TN, true, true, BK>(g, va, vb, splits, kc, part, st);
+  if (akc) return launch_tile<WM, WN, TM, TN, true, false, BK>(g, va, vb, splits, kc, part, st);
+  if (bkc) return launch_tile<WM, WN, TM, TN, false, true, BK>(g, va, vb, splits, kc, part, st);
+  return launch_tile<WM, WN, TM, TN, false, false, BK>(g, va, vb, splits, kc, part, st);
 }
 
 hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t st) {
@@ -775,37 +783,28 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
   OpView vb{g.B, g.sbn, g.sbk, g.N, g.bias_grad ? g.N : -1, 1};
   va.vw = akc ? vec_width(g.A, g.a_lo, g.sam, g.K) : vec_width(g.A, g.a_lo, g.sak, g.M);
   vb.vw = bkc ? vec_width(g.B, g.b_lo, g.sbn, g.K) : vec_width(g.B, g.b_lo, g.sbk, g.N);
-  // Tile: the N extent picks the width; tall products take 128 rows.
-  int tile;   // 0: 128 x 32, 1: 128 x 64, 2: 128 x 128, 3: 64 x 64
-  if (Nc <= 32) tile = 0;
-  else if (Nc <= 64) tile = 1;
-  else if (g.M >= 512 && !(g.a_lo && g.b_lo)) tile = 2;   // (both split: 64 x 64, LDS <= 64 KB)
-  else tile = 3;
+  // Tile and split (measured over the training step's fourteen products at
+  // batch 256): a block's time is mostly the latency of its k steps (~1 us
+  // each), so many small blocks win.  64 x 64 tiles everywhere, except the
+  // narrow first-layer product (32 outputs, K = 36), which takes 128 x 32.
+  // Fewer than 256 tiles leave the GPU short of blocks: split K towards
+  // ~1024 blocks of at least 2 k steps (more splits cost partial traffic and
+  // a longer reduction); partials must fit `part`.  Steps of 64 k were not
+  // faster (a step's time grew with its depth), so steps stay 32 deep.
+  const int bk = kStepK;
+  const int tile = (Nc <= 32 && g.K <= 64) ? 0 : 3;   // 0: 128 x 32, 3: 64 x 64
   const int BM = tile == 3 ? 64 : 128;
-  const int BN = tile == 0 ? 32 : tile == 1 ? 64 : tile == 2 ? 128 : 64;
+  const int BN = tile == 0 ? 32 : 64;
   const long tiles = (long)((Nc + BN - 1) / BN) * ((g.M + BM - 1) / BM);
-  // Split K when the tiles leave the GPU's 256 CUs short of work.  A block's
-  // time is mostly the latency of its k steps, so more, shorter blocks win
-  // while the partials stay cheap to add: a few tiles (long-K weight
-  // gradients) split towards ~1024 blocks of at least 2 k steps, up to 511
-  // tiles towards ~512 blocks of at least 4 steps; partials must fit `part`.
   int splits = 1;
-  if (part && tiles < 512) {
-    const bool few = tiles < 16;
-    const long target = few ? 1024 : 512;
-    const long min_steps = few ? 2 : 4;
-    splits = (int)std::max<long>(1, std::min<long>((target + tiles - 1) / tiles, g.K / (kBK * min_steps)));
+  if (part && tiles < 256) {
+    splits = (int)std::max<long>(1, std::min<long>((1024 + tiles - 1) / tiles, g.K / (bk * 2)));
     while (splits > 1 && (size_t)splits * g.M * Nc > part_elems) --splits;
   }
-  const int kc = ((g.K + splits - 1) / splits + kBK - 1) / kBK * kBK;
+  const int kc = ((g.K + splits - 1) / splits + bk - 1) / bk * bk;
   splits = (g.K + kc - 1) / kc;
-  hipError_t e;
-  switch (tile) {
-    case 0: e = launch_layout<4, 1, 1, 1>(g, va, vb, akc, bkc, splits, kc, part, st); break;
-    case 1: e = launch_layout<2, 2, 2, 1>(g, va, vb, akc, bkc, splits, kc, part, st); break;
-    case 2: e = launch_layout<2, 2, 2, 2>(g, va, vb, akc, bkc, splits, kc, part, st); break;
-    default: e = launch_layout<2, 2, 1, 1>(g, va, vb, akc, bkc, splits, kc, part, st); break;
-  }
+  const hipError_t e = tile == 0 ? launch_layout<4, 1, 1, 1, kStepK>(g, va, vb, akc, bkc, splits, kc, part, st)
+                                  : launch_layout<2, 2, 1, 1, kStepK>(g, va, vb, akc, bkc, splits, kc, part, st);
   if (e != hipSuccess || splits <= 1) return e;
   const size_t MN = (size_t)g.M * Nc;
   if (splits >= 256)
