@@ -83,14 +83,23 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int i, int j, float 
 // from global memory in one of two layouts:
 //  * k-contiguous (stride 1 along k): chunk = 8 k of one row, one 16-byte
 //    load (vw 8), two 8-byte loads (vw 4) or 8 element loads (vw 1);
-//  * row-contiguous (stride 1 along rows): quad-chunk = 8 rows x 4 k, four
-//    loads of 8 rows each, transposed in registers into 8 rows x 4 k and
-//    written as 8-byte LDS stores.
+//  * row-contiguous (stride 1 along rows): chunk = 8 rows of one k, one
+//    16-byte load (or 2 x 8 / 8 x 2 bytes), stored as loaded into an LDS
+//    plane [k][row] (row pitch R + 4); an MFMA fragment then gathers its 8 k
+//    of one row with 2-byte LDS reads.  Every thread takes part in the
+//    staging, as for k-contiguous operands (transposing in registers left it
+//    to one wave and made a k step ~3x slower).
 // vw (16-, 8- or 2-byte groups) is decided on the host from the strides,
 // extents and alignment, uniform per launch.  Elements past the extents are
 // zero; the bias-gradient column (B row N) is 1 in the hi plane.
 constexpr int pitch_of(int BK) { return BK + 8; }
 constexpr int kStepK = 32;   // k depth per step of the products
+// LDS plane of an R-row operand tile, in elements: k-contiguous operands
+// [row][k] with pitch BK + 8 (the 16-byte fragment reads of eight
+// consecutive rows cover all banks); row-contiguous ones [k][row] with pitch
+// R + 4 (8-byte aligned rows; the two half-waves' k, 8 apart, fall on
+// different banks).
+constexpr int plane_elems(bool kc, int R, int BK) { return kc ? R * pitch_of(BK) : BK * (R + 4); }
 
 struct OpView {
   const uint16_t* p;
@@ -136,9 +145,6 @@ __device__ __forceinline__ Chunk8 load8(const uint16_t* q, int e, int lim, int v
   return c;
 }
 
-__device__ __forceinline__ uint32_t half_of(const Chunk8& c, int r) {
-  return (c.w[r >> 1] >> ((r & 1) * 16)) & 0xffffu;
-}
 __device__ __forceinline__ void set_half(Chunk8& c, int r, uint32_t v) {
   const int s = (r & 1) * 16;
   c.w[r >> 1] = (c.w[r >> 1] & ~(0xffffu << s)) | (v << s);
@@ -178,13 +184,14 @@ __device__ __forceinline__ void op_load(const OpView& v, long lo, int r0, int k0
       }
     }
   } else {
-    // quad-chunks: (R / 8) row groups x (BK / 4) k groups; thread t < R BK / 32
-    if (tid < R * BK / 32) {
-      const int rg = tid % (R / 8), kg = tid / (R / 8);
-      const int gr = r0 + rg * 8;
+    // (R / 8) row groups x BK k; unit u = (row group u mod (R / 8), k u / (R / 8)),
+    // thread t takes units t, t + 256, ... (a wave reads whole 128-byte rows)
+    constexpr int RG = R / 8;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int gk = k0 + kg * 4 + t;
+    for (int t = 0; t < (RG * BK + 255) / 256; ++t) {
+      const int u = tid + 256 * t;
+      if (u < RG * BK) {
+        const int gr = r0 + (u % RG) * 8, gk = k0 + u / RG;
         if (gk < K) {
           s.c[t] = load8(p + (long)gk * v.s_k + gr, gr, v.rows, v.vw);
         } else {
@@ -213,22 +220,41 @@ __device__ __forceinline__ void op_store(uint16_t* lds, const Stage& s, int tid)
       }
     }
   } else {
-    if (tid < R * BK / 32) {
-      const int rg = tid % (R / 8), kg = tid / (R / 8);
+    constexpr int RG = R / 8, RP = R + 4;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const uint32_t w0 = half_of(s.c[0], r) | (half_of(s.c[1], r) << 16);
-        const uint32_t w1 = half_of(s.c[2], r) | (half_of(s.c[3], r) << 16);
-        *reinterpret_cast<uint2*>(lds + (rg * 8 + r) * PITCH + kg * 4) = make_uint2(w0, w1);
+    for (int t = 0; t < (RG * BK + 255) / 256; ++t) {
+      const int u = tid + 256 * t;
+      if (u < RG * BK) {
+        uint16_t* q = lds + (u / RG) * RP + (u % RG) * 8;
+        *reinterpret_cast<uint2*>(q) = make_uint2(s.c[t].w[0], s.c[t].w[1]);
+        *reinterpret_cast<uint2*>(q + 4) = make_uint2(s.c[t].w[2], s.c[t].w[3]);
       }
     }
+  }
+}
+
+// MFMA fragment of one lane: the 8 consecutive k from kof of tile row `row`.
+template <bool KC, int R, int BK>
+__device__ __forceinline__ bf16x8 frag(const uint16_t* plane, int row, int kof) {
+  if constexpr (KC) {
+    return *reinterpret_cast<const bf16x8*>(plane + row * pitch_of(BK) + kof);
+  } else {
+    constexpr int RP = R + 4;
+    const uint16_t* q = plane + kof * RP + row;
+    uint32_t w[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) w[h] = (uint32_t)q[(2 * h) * RP] | ((uint32_t)q[(2 * h + 1) * RP] << 16);
+    bf16x8 f;
+    __builtin_memcpy(&f, w, sizeof(f));
+    return f;
   }
 }
 
 template <int WM, int WN, int TM, int TN, bool AKC, bool BKC, int BK>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, OpView vb, int kc,
                                                         float* __restrict__ part) {
-  constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN, kPitch = pitch_of(BK);
+  constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN;
+  constexpr int SA = plane_elems(AKC, BM, BK), SB = plane_elems(BKC, BN, BK);
   extern __shared__ __align__(16) uint16_t lds[];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave / WN, wn = wave % WN;
@@ -236,14 +262,14 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
   const int kbeg = blockIdx.z * kc;
   const int kend = min(g.K, kbeg + kc);
   const bool alo = g.a_lo != 0, blo = g.b_lo != 0;
-  // LDS stage: A_hi [BM], A_lo [BM] (if any), B_hi [BN], B_lo [BN] (if any), rows of kPitch
-  const int stage_rows = BM * (alo ? 2 : 1) + BN * (blo ? 2 : 1);
+  // LDS stage: planes A_hi, A_lo (if any), B_hi, B_lo (if any)
+  const int stage_elems = SA * (alo ? 2 : 1) + SB * (blo ? 2 : 1);
   uint16_t* st0 = lds;
-  uint16_t* st1 = lds + stage_rows * kPitch;
+  uint16_t* st1 = lds + stage_elems;
   auto a_hi = [&](uint16_t* s) { return s; };
-  auto a_lo = [&](uint16_t* s) { return s + BM * kPitch; };
-  auto b_hi = [&](uint16_t* s) { return s + BM * (alo ? 2 : 1) * kPitch; };
-  auto b_lo = [&](uint16_t* s) { return s + (BM * (alo ? 2 : 1) + BN) * kPitch; };
+  auto a_lo = [&](uint16_t* s) { return s + SA; };
+  auto b_hi = [&](uint16_t* s) { return s + SA * (alo ? 2 : 1); };
+  auto b_lo = [&](uint16_t* s) { return s + SA * (alo ? 2 : 1) + SB; };
 
   f32x16 acc[TM][TN];
 #pragma unroll
@@ -282,10 +308,10 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
       bf16x8 fa[TM], fb[TN];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
-        fa[a] = *reinterpret_cast<const bf16x8*>(a_hi(cur) + (wm * TM * 32 + a * 32 + (lane & 31)) * kPitch + kof);
+        fa[a] = frag<AKC, BM, BK>(a_hi(cur), wm * TM * 32 + a * 32 + (lane & 31), kof);
 #pragma unroll
       for (int b = 0; b < TN; ++b)
-        fb[b] = *reinterpret_cast<const bf16x8*>(b_hi(cur) + (wn * TN * 32 + b * 32 + (lane & 31)) * kPitch + kof);
+        fb[b] = frag<BKC, BN, BK>(b_hi(cur), wn * TN * 32 + b * 32 + (lane & 31), kof);
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -294,8 +320,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
       if (alo) {
 #pragma unroll
         for (int a = 0; a < TM; ++a) {
-          const bf16x8 fl =
-              *reinterpret_cast<const bf16x8*>(a_lo(cur) + (wm * TM * 32 + a * 32 + (lane & 31)) * kPitch + kof);
+          const bf16x8 fl = frag<AKC, BM, BK>(a_lo(cur), wm * TM * 32 + a * 32 + (lane & 31), kof);
 #pragma unroll
           for (int b = 0; b < TN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl, fb[b], acc[a][b], 0, 0, 0);
         }
@@ -303,8 +328,7 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
       if (blo) {
 #pragma unroll
         for (int b = 0; b < TN; ++b) {
-          const bf16x8 fl =
-              *reinterpret_cast<const bf16x8*>(b_lo(cur) + (wn * TN * 32 + b * 32 + (lane & 31)) * kPitch + kof);
+          const bf16x8 fl = frag<BKC, BN, BK>(b_lo(cur), wn * TN * 32 + b * 32 + (lane & 31), kof);
 #pragma unroll
           for (int a = 0; a < TM; ++a) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fl, acc[a][b], 0, 0, 0);
         }
@@ -745,7 +769,9 @@ static hipError_t launch_tile(const GemmArgs& g, const OpView& va, const OpView&
                               hipStream_t st) {
   constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN;
   const int Nc = g.N + (g.bias_grad ? 1 : 0);
-  const size_t lds = (size_t)2 * (BM * (g.a_lo ? 2 : 1) + BN * (g.b_lo ? 2 : 1)) * pitch_of(BK) * sizeof(uint16_t);
+  const size_t lds = (size_t)2 *
+                     (plane_elems(AKC, BM, BK) * (g.a_lo ? 2 : 1) + plane_elems(BKC, BN, BK) * (g.b_lo ? 2 : 1)) *
+                     sizeof(uint16_t);
   hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, TM, TN, AKC, BKC, BK>),
                      dim3((Nc + BN - 1) / BN, (g.M + BM - 1) / BM, splits), dim3(256), lds, st, g, va, vb, kc,
                      splits > 1 ? part : (float*)nullptr);
