@@ -59,7 +59,7 @@ struct pwfs_cnn_s {
   // activations as bf16 pairs (lo plane after the hi plane; cols1, the
   // bf16-rounded input's im2col, is one plane) and FP32 work buffers
   uint16_t *cols1 = nullptr, *a1 = nullptr, *cols2 = nullptr, *a2 = nullptr, *cols3 = nullptr,
-           *a3 = nullptr, *h = nullptr, *doutb = nullptr, *dzb = nullptr;
+           *a3 = nullptr, *h = nullptr, *doutb = nullptr, *dzb = nullptr, *dzf = nullptr;
   float *out = nullptr, *gtmp = nullptr, *part = nullptr, *loss = nullptr, *mse_part = nullptr;
   size_t part_elems = 0;
 };
@@ -72,7 +72,7 @@ void free_net(pwfs_cnn_s* n) {
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(n->device);
   void* ptrs[] = {n->w, n->m, n->v, n->g, n->wb, n->cols1, n->a1, n->cols2, n->a2, n->cols3, n->a3,
-                  n->h, n->doutb, n->dzb, n->out, n->gtmp, n->part, n->loss, n->mse_part};
+                  n->h, n->doutb, n->dzb, n->dzf, n->out, n->gtmp, n->part, n->loss, n->mse_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (prev >= 0) (void)hipSetDevice(prev);
@@ -131,6 +131,18 @@ GemmArgs dgrad_args(const uint16_t* dY, const uint16_t* W, int R, int N, int K, 
   return a;
 }
 
+// dX = (dY W) masked by act > 0 (act [R][K], the hi plane of the layer's input
+// activation), as a bf16 pair [R][K] (lo plane R K elements on); dX must not
+// alias dY.
+GemmArgs dgrad_masked_args(const uint16_t* dY, const uint16_t* W, int R, int N, int K, const uint16_t* act,
+                           uint16_t* dX) {
+  GemmArgs a = dgrad_args(dY, W, R, N, K, nullptr);
+  a.ldc = 0;
+  a.Cb = dX; a.ldcb = K; a.cb_lo = (long)R * K;
+  a.mask = act; a.ldm = K;
+  return a;
+}
+
 // Forward pass; the last layer writes out_alpha * net(x) + out_beta * out into
 // `out` (NULL: the internal output buffer, alpha 1, beta 0).
 int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out = nullptr,
@@ -167,13 +179,15 @@ int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B
   // fc2
   CK(pwfs::cnn::gemm(wgrad_args(n->doutb, n->h, true, B, n->nout, n->hidden, G + n->off[8], G + n->off[9]),
                      n->part, P, st));
-  CK(pwfs::cnn::gemm(dgrad_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->gtmp), n->part, P, st));
-  CK(pwfs::cnn::relu_mask(n->gtmp, n->h, (size_t)B * n->hidden, n->dzb, st));
+  // data gradients of the fully connected layers with the ReLU mask of their
+  // input activation applied in the epilogue, out as bf16 pairs
+  CK(pwfs::cnn::gemm(dgrad_masked_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->h, n->dzf), n->part, P,
+                     st));
   // fc1
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->a3, true, B, n->hidden, n->flat, G + n->off[6], G + n->off[7]),
+  CK(pwfs::cnn::gemm(wgrad_args(n->dzf, n->a3, true, B, n->hidden, n->flat, G + n->off[6], G + n->off[7]),
                      n->part, P, st));
-  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[6], B, n->hidden, n->flat, n->gtmp), n->part, P, st));
-  CK(pwfs::cnn::relu_mask(n->gtmp, n->a3, (size_t)B * n->flat, n->dzb, st));
+  CK(pwfs::cnn::gemm(dgrad_masked_args(n->dzf, Wb + n->off[6], B, n->hidden, n->flat, n->a3, n->dzb), n->part, P,
+                     st));
   // conv3
   const int R3 = B * n->S3 * n->S3, R2 = B * n->S2 * n->S2, R1 = B * n->S1 * n->S1;
   CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols3, true, R3, n->c3, n->c2 * 9, G + n->off[4], G + n->off[5], n->c2),
@@ -249,6 +263,7 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
       {(void**)&n->a2, R2 * n->c2 * 2 * 2, "a2 pair"}, {(void**)&n->cols3, R3 * n->c2 * 9 * 2 * 2, "cols3 pair"},
       {(void**)&n->a3, R3 * n->c3 * 2 * 2, "a3 pair"}, {(void**)&n->h, B * n->hidden * 2 * 2, "hidden pair"},
       {(void**)&n->doutb, B * n->nout * 2 * 2, "dout pair"}, {(void**)&n->dzb, dz * 2 * 2, "dz pair"},
+      {(void**)&n->dzf, B * std::max(n->hidden, n->flat) * 2 * 2, "hidden-layer dz pair"},
       {(void**)&n->out, B * n->nout * 4, "out"},
       {(void**)&n->gtmp, gtmp * 4, "data gradients"},
       {(void**)&n->part, n->part_elems * 4, "split-K partials"}, {(void**)&n->loss, 4, "loss"},

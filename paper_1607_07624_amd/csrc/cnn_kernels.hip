@@ -13,8 +13,10 @@
 // the activation operand).  Small products (a few rows) run on a
 // matrix-vector kernel that streams the weights once.  The other kernels
 // are gathers and elementwise passes: im2col, col2im in gather form (each
-// input element sums its own contributions in a fixed order, no atomics),
-// ReLU masks, the MSE loss, Adam and the network-input preparation.
+// input element sums its own contributions in a fixed order, no atomics,
+// with the ReLU mask), the MSE loss, Adam and the network-input preparation.
+// The fully connected layers' data gradients take their ReLU mask in the
+// product's epilogue.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,6 +56,7 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int i, int j, float 
   if (g.bias) x += g.bias[j];
   x *= g.alpha;
   if (g.cperm) j = (j % g.cperm) * 9 + j / g.cperm;   // patch column (tap, c) -> weight column (c, tap)
+  if (g.mask && !bf_pos(g.mask[(long)i * g.ldm + j])) x = 0.f;
   if (g.C && g.beta != 0.f) x = fmaf(g.beta, g.C[(long)i * g.ldc + j], x);
   if (g.relu) x = fmaxf(x, 0.f);
   if (g.C) g.C[(long)i * g.ldc + j] = x;
@@ -62,6 +65,48 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int i, int j, float 
     const uint16_t h = f2bf(x);
     g.Cb[o] = h;
     if (g.cb_lo) g.Cb[o + g.cb_lo] = f2bf(x - bf2f(h));
+  }
+}
+
+// The epilogue of four consecutive outputs (i, j .. j + 3) of one row, in
+// the order of epilogue(), with vector loads and stores; for outputs without
+// the bias-gradient column and the patch-order remap, and 16-byte (FP32) or
+// 8-byte (bf16) aligned rows (checked on the host).
+__device__ __forceinline__ void epilogue4(const GemmArgs& g, int i, int j, float4 s) {
+  float x[4] = {s.x, s.y, s.z, s.w};
+  if (g.bias) {
+    const float4 b = *reinterpret_cast<const float4*>(g.bias + j);
+    x[0] += b.x; x[1] += b.y; x[2] += b.z; x[3] += b.w;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) x[c] *= g.alpha;
+  if (g.mask) {
+    const uint2 m = *reinterpret_cast<const uint2*>(g.mask + (long)i * g.ldm + j);
+    const uint32_t mw[2] = {m.x, m.y};
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (!bf_pos((uint16_t)(mw[c >> 1] >> ((c & 1) * 16)))) x[c] = 0.f;
+  }
+  if (g.C && g.beta != 0.f) {
+    const float4 c0 = *reinterpret_cast<const float4*>(g.C + (long)i * g.ldc + j);
+    x[0] = fmaf(g.beta, c0.x, x[0]); x[1] = fmaf(g.beta, c0.y, x[1]);
+    x[2] = fmaf(g.beta, c0.z, x[2]); x[3] = fmaf(g.beta, c0.w, x[3]);
+  }
+  if (g.relu)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) x[c] = fmaxf(x[c], 0.f);
+  if (g.C) *reinterpret_cast<float4*>(g.C + (long)i * g.ldc + j) = make_float4(x[0], x[1], x[2], x[3]);
+  if (g.Cb) {
+    uint32_t hw[2], lw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint16_t h0 = f2bf(x[2 * h]), h1 = f2bf(x[2 * h + 1]);
+      hw[h] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      lw[h] = (uint32_t)f2bf(x[2 * h] - bf2f(h0)) | ((uint32_t)f2bf(x[2 * h + 1] - bf2f(h1)) << 16);
+    }
+    const long o = (long)i * g.ldcb + j;
+    *reinterpret_cast<uint2*>(g.Cb + o) = make_uint2(hw[0], hw[1]);
+    if (g.cb_lo) *reinterpret_cast<uint2*>(g.Cb + o + g.cb_lo) = make_uint2(lw[0], lw[1]);
   }
 }
 
@@ -362,29 +407,40 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
     }
 }
 
-// Sum of split-K partials, then the epilogue.  Block = EL elements x G split
-// groups (EL G = 256): group q adds splits q, q + G, ... in order, then the G
-// group sums are added in group order (a fixed order overall).  Many splits
-// over few outputs (long-K weight gradients) take G = 16, so that each
-// thread adds only splits / G partials (G = 16 or 64).
-template <int G>
+// Sum of split-K partials, then the epilogue.  Thread = V consecutive
+// outputs (V = 4: one 16-byte load per partial, when M Nc is a multiple of
+// 4 so that every partial slice stays aligned), block = 256 / G threads x G
+// split groups: group q adds splits q, q + G, ... in order, then the G group
+// sums are added in group order (a fixed order overall; each output's
+// component is summed on its own).  Many splits over few outputs (long-K
+// weight gradients) take G = 16 or 64, so that each thread adds only
+// splits / G partials.  VEC: the four outputs are one row's (Nc a multiple
+// of 4) and take the vector epilogue.
+template <int G, int V, bool VEC>
 __global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int splits, const float* __restrict__ part) {
   constexpr int EL = 256 / G;
-  __shared__ float red[G][EL];
+  typedef float vec_t __attribute__((ext_vector_type(V)));
+  __shared__ vec_t red[G][EL];
   const int Nc = g.N + (g.bias_grad ? 1 : 0);
-  const size_t MN = (size_t)g.M * Nc;
+  const size_t MN = (size_t)g.M * Nc, MNV = MN / V;
   const int e = threadIdx.x % EL, q = threadIdx.x / EL;
   const size_t idx = blockIdx.x * (size_t)EL + e;
-  float x = 0.f;
-  if (idx < MN)
-    for (int z = q; z < splits; z += G) x += part[(size_t)z * MN + idx];
+  vec_t x = 0.f;
+  if (idx < MNV)
+    for (int z = q; z < splits; z += G) x += reinterpret_cast<const vec_t*>(part + (size_t)z * MN)[idx];
   red[q][e] = x;
   __syncthreads();
-  if (q == 0 && idx < MN) {
-    float s = red[0][e];
+  if (q == 0 && idx < MNV) {
+    vec_t s = red[0][e];
 #pragma unroll
     for (int t = 1; t < G; ++t) s += red[t][e];
-    epilogue(g, (int)(idx / Nc), (int)(idx % Nc), s);
+    const size_t o = idx * V;
+    if constexpr (VEC) {
+      epilogue4(g, (int)(o / Nc), (int)(o % Nc), make_float4(s[0], s[1], s[2], s[3]));
+    } else {
+#pragma unroll
+      for (int c = 0; c < V; ++c) epilogue(g, (int)((o + c) / Nc), (int)((o + c) % Nc), s[c]);
+    }
   }
 }
 
@@ -603,12 +659,6 @@ __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restric
 }
 
 // dz = (act > 0) * g as a bf16 pair (lo written at dzb + n).
-__global__ __launch_bounds__(256) void relu_mask_kernel(const float* __restrict__ g, const uint16_t* __restrict__ act,
-                                                        size_t n, uint16_t* __restrict__ dzb) {
-  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
-    split_bf(bf_pos(act[i]) ? g[i] : 0.f, dzb, dzb + n, i);
-}
-
 // Position in the bf16 product copy of parameter i: convolution weights
 // [Cout][Cin][3][3] are stored [Cout][3][3][Cin] there (the patch order of
 // im2col), everything else in place.
@@ -833,15 +883,28 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
                                   : launch_layout<2, 2, 1, 1, kStepK>(g, va, vb, akc, bkc, splits, kc, part, st);
   if (e != hipSuccess || splits <= 1) return e;
   const size_t MN = (size_t)g.M * Nc;
-  if (splits >= 256)
-    hipLaunchKernelGGL(gemm_reduce_kernel<64>, dim3((unsigned)((MN + 3) / 4)), dim3(256), 0, st, g, splits,
-                       (const float*)part);
-  else if (splits >= 64)
-    hipLaunchKernelGGL(gemm_reduce_kernel<16>, dim3((unsigned)((MN + 15) / 16)), dim3(256), 0, st, g, splits,
-                       (const float*)part);
-  else
-    hipLaunchKernelGGL(gemm_reduce_kernel<4>, dim3((unsigned)((MN + 63) / 64)), dim3(256), 0, st, g, splits,
-                       (const float*)part);
+  auto al = [](const void* p, uintptr_t b) { return ((uintptr_t)p % b) == 0; };
+  const bool v4 = MN % 4 == 0;
+  const bool vec = v4 && Nc % 4 == 0 && !g.bias_grad && !g.cperm && (!g.C || (al(g.C, 16) && g.ldc % 4 == 0)) &&
+                   (!g.Cb || (al(g.Cb, 8) && g.ldcb % 4 == 0 && g.cb_lo % 4 == 0)) && (!g.bias || al(g.bias, 16)) &&
+                   (!g.mask || (al(g.mask, 8) && g.ldm % 4 == 0));
+  const int G = splits >= 256 ? 64 : splits >= 64 ? 16 : 4;
+  const size_t per_block = (size_t)(256 / G) * (v4 ? 4 : 1);
+  const dim3 grid((unsigned)((MN + per_block - 1) / per_block));
+  auto launch = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, g, splits, (const float*)part); };
+  if (vec) {
+    if (G == 64) launch(gemm_reduce_kernel<64, 4, true>);
+    else if (G == 16) launch(gemm_reduce_kernel<16, 4, true>);
+    else launch(gemm_reduce_kernel<4, 4, true>);
+  } else if (v4) {
+    if (G == 64) launch(gemm_reduce_kernel<64, 4, false>);
+    else if (G == 16) launch(gemm_reduce_kernel<16, 4, false>);
+    else launch(gemm_reduce_kernel<4, 4, false>);
+  } else {
+    if (G == 64) launch(gemm_reduce_kernel<64, 1, false>);
+    else if (G == 16) launch(gemm_reduce_kernel<16, 1, false>);
+    else launch(gemm_reduce_kernel<4, 1, false>);
+  }
   return hipGetLastError();
 }
 
@@ -869,11 +932,6 @@ hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uin
                        dzb);
   else
     hipLaunchKernelGGL(col2im_mask_kernel<1>, dim3(grid_for(pix * C)), dim3(256), 0, st, dcols, B, H, W, C, act, dzb);
-  return hipGetLastError();
-}
-
-hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, uint16_t* dzb, hipStream_t st) {
-  hipLaunchKernelGGL(relu_mask_kernel, dim3(grid_for(n)), dim3(256), 0, st, g, act, n, dzb);
   return hipGetLastError();
 }
 

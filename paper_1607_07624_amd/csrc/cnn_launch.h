@@ -36,6 +36,8 @@ struct GemmArgs {
   long a_lo, b_lo, cb_lo;
   float* bias_grad;
   int cperm;          // > 0: output column j (patch order tap, c) is stored at (j mod cperm) 9 + j / cperm
+  const uint16_t* mask;   // ReLU mask: output (i, j) is zeroed unless mask[i ldm + j] (bf16) > 0; NULL: none
+  long ldm;
 };
 
 // The three convolution weight blocks of the flat parameter vector (offset,
@@ -57,7 +59,6 @@ hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* co
 // (lo plane after the hi plane).
 hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, uint16_t* dzb,
                        hipStream_t st);
-hipError_t relu_mask(const float* g, const uint16_t* act, size_t n, uint16_t* dzb, hipStream_t st);
 // bf16 product copy of the FP32 parameters (convolution weights permuted as in ConvPerm).
 hipError_t weights_bf16(const float* x, size_t n, const ConvPerm& cp, uint16_t* y, hipStream_t st);
 // part: at least mse_partials(n) floats of scratch.
