@@ -561,25 +561,24 @@ __global__ __launch_bounds__(64 * kGemvMaxWaves) void gemv_bf16_kernel(GemmArgs 
 template <int V>
 __global__ __launch_bounds__(256) void im2col_pair_kernel(const uint16_t* __restrict__ act, int B, int H, int W,
                                                           int C, uint16_t* __restrict__ cols) {
-  const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
-  const int G = C / V;                                       // channel groups per tap
-  const size_t K9 = (size_t)C * 9;
-  const size_t rows = (size_t)B * Ho * Wo;
-  const size_t total = rows * 9 * G;
-  const size_t n_in = (size_t)B * H * W * C, n_out = rows * K9;
-  for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
-    const int cg = (int)(idx % G);
-    const size_t t2 = idx / G;
-    const int tap = (int)(t2 % 9);
-    const size_t row = t2 / 9;
-    const int ky = tap / 3, kx = tap - ky * 3;
-    const int b = (int)(row / ((size_t)Ho * Wo));
-    const int rem = (int)(row - (size_t)b * Ho * Wo);
-    const int yo = rem / Wo, xo = rem - yo * Wo;
-    const int y = 2 * yo + ky - 1, x = 2 * xo + kx - 1;
+  // 32-bit index arithmetic (sizes checked on the host): 64-bit divisions
+  // are long emulated sequences that made this gather ALU-bound
+  const uint32_t Ho = (H + 1) / 2, Wo = (W + 1) / 2, HoWo = Ho * Wo;
+  const uint32_t G = C / V;                                  // channel groups per tap
+  const uint32_t K9 = (uint32_t)C * 9;
+  const uint32_t rows = (uint32_t)B * HoWo;
+  const uint32_t total = rows * 9 * G;
+  const uint32_t n_in = (uint32_t)B * H * W * C, n_out = rows * K9;
+  for (uint32_t idx = blockIdx.x * 256u + threadIdx.x; idx < total; idx += gridDim.x * 256u) {
+    const uint32_t t2 = idx / G, cg = idx - t2 * G;
+    const uint32_t row = t2 / 9, tap = t2 - row * 9;
+    const int ky = (int)tap / 3, kx = (int)tap - ky * 3;
+    const uint32_t b = row / HoWo, rem = row - b * HoWo;
+    const uint32_t yo = rem / Wo, xo = rem - yo * Wo;
+    const int y = 2 * (int)yo + ky - 1, x = 2 * (int)xo + kx - 1;
     const bool in = y >= 0 && y < H && x >= 0 && x < W;
-    const size_t src = (((size_t)b * H + y) * W + x) * C + (size_t)cg * V;
-    const size_t dst = row * K9 + (size_t)tap * C + (size_t)cg * V;
+    const uint32_t src = in ? ((b * H + y) * W + x) * C + cg * V : 0u;
+    const uint32_t dst = row * K9 + tap * C + cg * V;
     if constexpr (V == 8) {
       const uint4 z = make_uint4(0u, 0u, 0u, 0u);
       *reinterpret_cast<uint4*>(cols + dst) = in ? *reinterpret_cast<const uint4*>(act + src) : z;
@@ -593,20 +592,18 @@ __global__ __launch_bounds__(256) void im2col_pair_kernel(const uint16_t* __rest
 
 __global__ __launch_bounds__(256) void im2col_f32_kernel(const float* __restrict__ act, int B, int H, int W, int C,
                                                          uint16_t* __restrict__ cols) {
-  const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
-  const size_t K9 = (size_t)C * 9;
-  const size_t total = (size_t)B * Ho * Wo * 9;
-  for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
-    const int tap = (int)(idx % 9);
-    const size_t row = idx / 9;
-    const int ky = tap / 3, kx = tap - ky * 3;
-    const int b = (int)(row / ((size_t)Ho * Wo));
-    const int rem = (int)(row - (size_t)b * Ho * Wo);
-    const int yo = rem / Wo, xo = rem - yo * Wo;
-    const int y = 2 * yo + ky - 1, x = 2 * xo + kx - 1;
+  const uint32_t Ho = (H + 1) / 2, Wo = (W + 1) / 2, HoWo = Ho * Wo;
+  const uint32_t K9 = (uint32_t)C * 9;
+  const uint32_t total = (uint32_t)B * HoWo * 9;
+  for (uint32_t idx = blockIdx.x * 256u + threadIdx.x; idx < total; idx += gridDim.x * 256u) {
+    const uint32_t row = idx / 9, tap = idx - row * 9;
+    const int ky = (int)tap / 3, kx = (int)tap - ky * 3;
+    const uint32_t b = row / HoWo, rem = row - b * HoWo;
+    const uint32_t yo = rem / Wo, xo = rem - yo * Wo;
+    const int y = 2 * (int)yo + ky - 1, x = 2 * (int)xo + kx - 1;
     const bool in = y >= 0 && y < H && x >= 0 && x < W;
-    const float* src = act + (((size_t)b * H + y) * W + x) * C;
-    uint16_t* dst = cols + row * K9 + (size_t)tap * C;
+    const float* src = act + (in ? ((b * H + y) * W + x) * C : 0u);
+    uint16_t* dst = cols + row * K9 + tap * C;
     for (int c = 0; c < C; ++c) dst[c] = in ? f2bf(src[c]) : (uint16_t)0;
   }
 }
@@ -622,16 +619,13 @@ __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restric
                                                           int C, const uint16_t* __restrict__ act,
                                                           uint16_t* __restrict__ dzb) {
   const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
-  const int G = C / V;
-  const size_t n = (size_t)B * H * W * C;
-  const size_t total = (size_t)B * H * W * G;
-  for (size_t idx = blockIdx.x * (size_t)256 + threadIdx.x; idx < total; idx += (size_t)gridDim.x * 256) {
-    const int cg = (int)(idx % G);
-    const size_t pix = idx / G;
-    const int x = (int)(pix % W);
-    const size_t t2 = pix / W;
-    const int y = (int)(t2 % H);
-    const int b = (int)(t2 / H);
+  const uint32_t G = C / V;
+  const uint32_t n = (uint32_t)B * H * W * C;
+  const uint32_t total = (uint32_t)B * H * W * G;
+  for (uint32_t idx = blockIdx.x * 256u + threadIdx.x; idx < total; idx += gridDim.x * 256u) {
+    const uint32_t pix = idx / G, cg = idx - pix * G;
+    const uint32_t t2 = pix / W, b = t2 / H;
+    const int x = (int)(pix - t2 * W), y = (int)(t2 - b * H);
     float s[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) s[v] = 0.f;
@@ -641,8 +635,8 @@ __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restric
       for (int kx = 0; kx < 3; ++kx) {
         const int xx = x + 1 - kx;
         if (xx < 0 || (xx & 1) || (xx >> 1) >= Wo) continue;
-        const float* d = dcols + (((size_t)b * Ho + (yy >> 1)) * Wo + (xx >> 1)) * (size_t)(C * 9) +
-                         (size_t)(ky * 3 + kx) * C + (size_t)cg * V;
+        const float* d = dcols + ((b * Ho + (yy >> 1)) * Wo + (xx >> 1)) * (uint32_t)(C * 9) +
+                         (uint32_t)(ky * 3 + kx) * C + cg * V;
         if constexpr (V == 8) {
           const float4 u = reinterpret_cast<const float4*>(d)[0], w = reinterpret_cast<const float4*>(d)[1];
           s[0] += u.x; s[1] += u.y; s[2] += u.z; s[3] += u.w;
@@ -652,7 +646,7 @@ __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restric
         }
       }
     }
-    const size_t o = pix * C + (size_t)cg * V;
+    const uint32_t o = pix * C + cg * V;
 #pragma unroll
     for (int v = 0; v < V; ++v) split_bf(bf_pos(act[o + v]) ? s[v] : 0.f, dzb, dzb + n, o + v);
   }
@@ -908,8 +902,12 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
   return hipGetLastError();
 }
 
+// The gathers index in 32 bits: every plane must hold fewer than 2^31 elements.
+static bool fits32(size_t n) { return n < ((size_t)1 << 31); }
+
 hipError_t im2col(const uint16_t* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st) {
   const size_t rows = (size_t)B * ((H + 1) / 2) * ((W + 1) / 2);
+  if (!fits32(rows * 9 * C) || !fits32((size_t)B * H * W * C)) return hipErrorInvalidValue;
   if (C % 8 == 0)
     hipLaunchKernelGGL(im2col_pair_kernel<8>, dim3(grid_for(rows * 9 * (C / 8))), dim3(256), 0, st, act, B, H, W, C,
                        cols);
@@ -920,6 +918,7 @@ hipError_t im2col(const uint16_t* act, int B, int H, int W, int C, uint16_t* col
 
 hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* cols, hipStream_t st) {
   const size_t total = (size_t)B * ((H + 1) / 2) * ((W + 1) / 2) * 9;
+  if (!fits32(total * C) || !fits32((size_t)B * H * W * C)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(im2col_f32_kernel, dim3(grid_for(total)), dim3(256), 0, st, act, B, H, W, C, cols);
   return hipGetLastError();
 }
@@ -927,6 +926,7 @@ hipError_t im2col_f32(const float* act, int B, int H, int W, int C, uint16_t* co
 hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uint16_t* act, uint16_t* dzb,
                        hipStream_t st) {
   const size_t pix = (size_t)B * H * W;
+  if (!fits32(pix * C) || !fits32((size_t)B * ((H + 1) / 2) * ((W + 1) / 2) * 9 * C)) return hipErrorInvalidValue;
   if (C % 8 == 0)
     hipLaunchKernelGGL(col2im_mask_kernel<8>, dim3(grid_for(pix * (C / 8))), dim3(256), 0, st, dcols, B, H, W, C, act,
                        dzb);
