@@ -59,9 +59,17 @@ struct pwfs_cnn_s {
   // activations as bf16 pairs (lo plane after the hi plane; cols1, the
   // bf16-rounded input's im2col, is one plane) and FP32 work buffers
   uint16_t *cols1 = nullptr, *a1 = nullptr, *cols2 = nullptr, *a2 = nullptr, *cols3 = nullptr,
-           *a3 = nullptr, *h = nullptr, *doutb = nullptr, *dzb = nullptr, *dzf = nullptr;
-  float *out = nullptr, *gtmp = nullptr, *part = nullptr, *loss = nullptr, *mse_part = nullptr;
+           *a3 = nullptr, *h = nullptr, *doutb = nullptr, *dzf = nullptr;
+  // upstream gradients of the three convolutions' outputs (bf16 pairs), one
+  // buffer per layer so that a layer's weight gradient can still read its
+  // own while the data gradients move on
+  uint16_t *dz3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
+  float *out = nullptr, *gtmp = nullptr, *part = nullptr, *part2 = nullptr, *loss = nullptr, *mse_part = nullptr;
   size_t part_elems = 0;
+  // backward: the weight gradients run on `side` (default priority) beside
+  // the chain of data gradients on the caller's stream; ev fork and join
+  hipStream_t side = nullptr;
+  hipEvent_t ev[6] = {};
 };
 
 namespace {
@@ -71,8 +79,13 @@ void free_net(pwfs_cnn_s* n) {
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(n->device);
+  if (n->side) (void)hipStreamSynchronize(n->side);
+  for (hipEvent_t e : n->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (n->side) (void)hipStreamDestroy(n->side);
   void* ptrs[] = {n->w, n->m, n->v, n->g, n->wb, n->cols1, n->a1, n->cols2, n->a2, n->cols3, n->a3,
-                  n->h, n->doutb, n->dzb, n->dzf, n->out, n->gtmp, n->part, n->loss, n->mse_part};
+                  n->h, n->doutb, n->dzf, n->dz3, n->dz2, n->dz1, n->out, n->gtmp, n->part, n->part2,
+                  n->loss, n->mse_part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (prev >= 0) (void)hipSetDevice(prev);
@@ -171,37 +184,55 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
   return 0;
 }
 
+// Backward pass.  The data gradients form a chain on the caller's stream
+// (each layer's needs the one above); a layer's weight gradient needs only
+// that layer's upstream gradient and its forward input, and nothing reads it
+// before the optimiser, so the weight gradients run on the side stream, each
+// after an event on the chain, and the caller's stream waits for the side
+// stream at the end.  Each product alone leaves most of the GPU idle (a few
+// hundred blocks of a few k steps), so the two streams overlap.
 int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B, float* loss, hipStream_t st) {
   const uint16_t* Wb = n->wb;
   float* G = n->g;
   const size_t P = (size_t)n->part_elems;
+  hipStream_t sd = n->side;
+  auto fork = [&](int e) -> hipError_t {   // side stream continues after everything queued on st so far
+    hipError_t r = hipEventRecord(n->ev[e], st);
+    return r != hipSuccess ? r : hipStreamWaitEvent(sd, n->ev[e], 0);
+  };
+  const int R3 = B * n->S3 * n->S3, R2 = B * n->S2 * n->S2, R1 = B * n->S1 * n->S1;
   CK(pwfs::cnn::mse(n->out, target, weights, B * n->nout, n->nout, n->doutb, loss, n->mse_part, st));
-  // fc2
+  // fc2: weight gradient (side); data gradient with the ReLU mask of h (chain)
+  CK(fork(0));
   CK(pwfs::cnn::gemm(wgrad_args(n->doutb, n->h, true, B, n->nout, n->hidden, G + n->off[8], G + n->off[9]),
-                     n->part, P, st));
-  // data gradients of the fully connected layers with the ReLU mask of their
-  // input activation applied in the epilogue, out as bf16 pairs
+                     n->part2, P, sd));
   CK(pwfs::cnn::gemm(dgrad_masked_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->h, n->dzf), n->part, P,
                      st));
   // fc1
+  CK(fork(1));
   CK(pwfs::cnn::gemm(wgrad_args(n->dzf, n->a3, true, B, n->hidden, n->flat, G + n->off[6], G + n->off[7]),
-                     n->part, P, st));
-  CK(pwfs::cnn::gemm(dgrad_masked_args(n->dzf, Wb + n->off[6], B, n->hidden, n->flat, n->a3, n->dzb), n->part, P,
+                     n->part2, P, sd));
+  CK(pwfs::cnn::gemm(dgrad_masked_args(n->dzf, Wb + n->off[6], B, n->hidden, n->flat, n->a3, n->dz3), n->part, P,
                      st));
   // conv3
-  const int R3 = B * n->S3 * n->S3, R2 = B * n->S2 * n->S2, R1 = B * n->S1 * n->S1;
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols3, true, R3, n->c3, n->c2 * 9, G + n->off[4], G + n->off[5], n->c2),
-                     n->part, P, st));
-  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), n->part, P, st));
-  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S2, n->S2, n->c2, n->a2, n->dzb, st));
+  CK(fork(2));
+  CK(pwfs::cnn::gemm(wgrad_args(n->dz3, n->cols3, true, R3, n->c3, n->c2 * 9, G + n->off[4], G + n->off[5], n->c2),
+                     n->part2, P, sd));
+  CK(pwfs::cnn::gemm(dgrad_args(n->dz3, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), n->part, P, st));
+  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S2, n->S2, n->c2, n->a2, n->dz2, st));
   // conv2
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols2, true, R2, n->c2, n->c1 * 9, G + n->off[2], G + n->off[3], n->c1),
-                     n->part, P, st));
-  CK(pwfs::cnn::gemm(dgrad_args(n->dzb, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, P, st));
-  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dzb, st));
-  // conv1
-  CK(pwfs::cnn::gemm(wgrad_args(n->dzb, n->cols1, false, R1, n->c1, 36, G + n->off[0], G + n->off[1], 4),
-                     n->part, P, st));
+  CK(fork(3));
+  CK(pwfs::cnn::gemm(wgrad_args(n->dz2, n->cols2, true, R2, n->c2, n->c1 * 9, G + n->off[2], G + n->off[3], n->c1),
+                     n->part2, P, sd));
+  CK(pwfs::cnn::gemm(dgrad_args(n->dz2, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, P, st));
+  CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dz1, st));
+  // conv1 (weight gradient only)
+  CK(fork(4));
+  CK(pwfs::cnn::gemm(wgrad_args(n->dz1, n->cols1, false, R1, n->c1, 36, G + n->off[0], G + n->off[1], 4),
+                     n->part2, P, sd));
+  // join
+  CK(hipEventRecord(n->ev[5], sd));
+  CK(hipStreamWaitEvent(st, n->ev[5], 0));
   return 0;
 }
 
@@ -251,7 +282,6 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
   const size_t B = (size_t)n->bm;
   const size_t R1 = B * n->S1 * n->S1, R2 = B * n->S2 * n->S2, R3 = B * n->S3 * n->S3;
   const size_t gtmp = std::max({B * n->hidden, B * n->flat, R3 * n->c2 * 9, R2 * n->c1 * 9});
-  const size_t dz = std::max({B * n->nout, B * n->hidden, B * n->flat, R3 * n->c3, R2 * n->c2, R1 * n->c1});
   n->part_elems = std::max<size_t>({(size_t)4 << 20, (size_t)64 * n->c1 * 36, (size_t)64 * n->c2 * n->c1 * 9,
                                     (size_t)64 * n->c3 * n->c2 * 9});
   struct A { void** p; size_t bytes; const char* what; } al[] = {
@@ -262,11 +292,14 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
       {(void**)&n->a1, R1 * n->c1 * 2 * 2, "a1 pair"}, {(void**)&n->cols2, R2 * n->c1 * 9 * 2 * 2, "cols2 pair"},
       {(void**)&n->a2, R2 * n->c2 * 2 * 2, "a2 pair"}, {(void**)&n->cols3, R3 * n->c2 * 9 * 2 * 2, "cols3 pair"},
       {(void**)&n->a3, R3 * n->c3 * 2 * 2, "a3 pair"}, {(void**)&n->h, B * n->hidden * 2 * 2, "hidden pair"},
-      {(void**)&n->doutb, B * n->nout * 2 * 2, "dout pair"}, {(void**)&n->dzb, dz * 2 * 2, "dz pair"},
-      {(void**)&n->dzf, B * std::max(n->hidden, n->flat) * 2 * 2, "hidden-layer dz pair"},
+      {(void**)&n->doutb, B * n->nout * 2 * 2, "dout pair"},
+      {(void**)&n->dzf, B * n->hidden * 2 * 2, "hidden-layer dz pair"},
+      {(void**)&n->dz3, R3 * n->c3 * 2 * 2, "conv3 dz pair"}, {(void**)&n->dz2, R2 * n->c2 * 2 * 2, "conv2 dz pair"},
+      {(void**)&n->dz1, R1 * n->c1 * 2 * 2, "conv1 dz pair"},
       {(void**)&n->out, B * n->nout * 4, "out"},
       {(void**)&n->gtmp, gtmp * 4, "data gradients"},
-      {(void**)&n->part, n->part_elems * 4, "split-K partials"}, {(void**)&n->loss, 4, "loss"},
+      {(void**)&n->part, n->part_elems * 4, "split-K partials"},
+      {(void**)&n->part2, n->part_elems * 4, "split-K partials (side stream)"}, {(void**)&n->loss, 4, "loss"},
       {(void**)&n->mse_part, pwfs::cnn::mse_partials((int)(B * n->nout)) * 4, "loss partials"},
   };
   for (auto& a : al) {
@@ -277,6 +310,18 @@ int pwfs_cnn_create(const pwfs_cnn_config_t* c, pwfs_cnn_t* out) {
     }
   }
   hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking)) != hipSuccess) {
+    n->side = nullptr;
+    free_net(n);
+    return hip_fail(e, "pwfs_cnn_create (side stream)");
+  }
+  for (hipEvent_t& ev : n->ev) {
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) {
+      ev = nullptr;
+      free_net(n);
+      return hip_fail(e, "pwfs_cnn_create (events)");
+    }
+  }
   if ((e = hipMemset(n->w, 0, n->n_params * 4)) != hipSuccess || (e = hipMemset(n->m, 0, n->n_params * 4)) != hipSuccess ||
       (e = hipMemset(n->v, 0, n->n_params * 4)) != hipSuccess || (e = hipMemset(n->wb, 0, n->n_params * 2)) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess) {
