@@ -38,13 +38,13 @@ PEAK_HBM_GBS = 8000.0
 # modulation chunk).  Valid only for the sources with these hashes (the kernels and the plan's
 # modulation order); reported as null otherwise.
 COUNTER_TRAFFIC = {
-    "sources_sha1": {"pwfs_kernels.hip": "bf725d96f743f1096b8f18a439cc1a734336648c",
+    "sources_sha1": {"pwfs_kernels.hip": "57b9b0cae508d6d627e16137dff991878c3bb183",
                      "pwfs_field.h": "bc1faa09406794b7ad671c337fa21b1f47710d8a",
                      "pwfs_common.h": "3096fe01bd7ba8d5172249619ee3af04487ad813",
                      "pwfs_dft.h": "2311b455e0848ccf3b2b36c948f8cf8f42218515",
-                     "pwfs_api.cpp": "2b001c80741fa12ff0301c96d357c694d2cef3e9"},
+                     "pwfs_api.cpp": "6ea1b5489dff398679f44044805abaa43565d733"},
     "batch": 16,
-    "col_pass_kib": {(3, 2): (81203.9, 9603.5), (3, 4): (81642.4, 4800.0), (3, 6): (81722.1, 3200.0)},
+    "col_pass_kib": {(3, 2): (81209.6, 9602.6), (3, 4): (81629.2, 4800.0), (3, 6): (81709.9, 3200.0)},
 }
 
 
