@@ -101,8 +101,11 @@ typedef struct {
                           /* work); n_pupil must be 32, 64 or 160; fixed work split.       */
 } pwfs_config_t;
 
-/* Build a plan: validates cfg, generates the FP64 tables (tilt ramps,
- * pyramid twiddles), uploads them as FP32, allocates the workspace for
+/* Build a plan (the pyramid object of Sec. 4 with the parameters of Tab. 1
+ * "pyramid", plus the calibration Sec. 4 requires before a run: the
+ * sub-aperture indices and the slope reference of the slope computer, Tab. 1
+ * "slopec" pupdata and sn): validates cfg, generates the FP64 tables (tilt
+ * ramps, pyramid twiddles), uploads them as FP32, allocates the workspace for
  * batch_max frames and measures the reference slopes of a flat wavefront
  * (synchronises the default stream once).  pupil_amp_host: P * P floats,
  * row-major [y][x], or NULL for the circular pupil described above.
@@ -134,7 +137,10 @@ int pwfs_get_reference(pwfs_plan_t plan, float* sref_host);
  * (stream-ordered copy), or with zeros when d_sref is NULL. */
 int pwfs_set_reference(pwfs_plan_t plan, const float* d_sref, void* stream);
 
-/* Modulated pyramid measurement of B frames.
+/* Modulated pyramid measurement of B frames: the chain pyr.in_ef ->
+ * pyr.out_i -> sc.out_slopes of the paper's main file (Sec. 4, Tab. 2), i.e.
+ * the pyramid propagation from wavefront to detector plane that Sec. 6 runs
+ * on the GPU, then the slope computer (Tab. 1 "slopec").
  *   d_opd_nm  device, B * P * P float, [frame][y][x], optical path in nm.
  *   d_pupils  device, B * 4 * S * S float, binned pupil images (mean over
  *             modulation points of |E|^2, pupil-plane pixels summed b x b,
@@ -334,8 +340,10 @@ int pwfs_autotune(pwfs_plan_t plan, int32_t B, int32_t reps, void* stream, doubl
                   double* ms_tuned);
 
 /* Modal reconstruction and integration, m = alpha * R s + beta * m for each
- * of B vectors (an integrator step is alpha = gain, beta = 1; the DM
- * projection opd -= B_KL u is alpha = -1, beta = 1 with R = B_KL).
+ * of B vectors: the modal reconstructor's product with its matrix (Tab. 1
+ * "modalrec", rec.in_slopes -> out_modes in Tab. 2) and the integrator's
+ * update (Tab. 1 "control": alpha = gain, beta = 1); also the DM projection
+ * opd -= B_KL u (alpha = -1, beta = 1 with R = B_KL).
  *   d_R  device, M * n_s float, row-major [mode][slope].
  *   d_s  device, B * n_s float.
  *   d_m  device, B * M float, read (when beta != 0) and written.
