@@ -101,7 +101,9 @@ class ClosedLoop:
     `judge_settle` steps gamma is below `gain_min` (the loop did not close),
     or if gamma falls below `gain_drop` times its best value since then (the
     loop is diverging).  `judged` keeps the (t, gamma) pairs of the last
-    run."""
+    run.  The 2 x (number of probe modes) probe frames are measured as one
+    batch by a second plan of the same geometry (noiseless, the loop plan's
+    valid list); the reference slopes cancel in s+ - s-."""
 
     def __init__(self, plan, modes_dev, R_dev, gain: float, delay: int, net=None,
                  judge_every: int = 10, judge_settle: int = 50, gain_min: float = 0.1,
@@ -134,7 +136,11 @@ class ClosedLoop:
             for j, k in enumerate(self.probe_modes):
                 coef[2 * j, k], coef[2 * j + 1, k] = self.probe_nm, -self.probe_nm
             self.probe_coef = torch.from_numpy(coef).to(dev)
-            self.probe_screen = torch.empty((1, P * P), device=dev)
+            from ._lib import Plan
+            self.probe_plan = Plan(plan.cfg, batch_max=2 * npb, pupil_amp=plan.pupil)
+            if not np.array_equal(self.probe_plan.valid, plan.valid):
+                self.probe_plan.set_valid(plan.valid)
+            self.probe_screen = torch.empty((2 * npb, P * P), device=dev)
             self.probe_s = torch.empty((2 * npb, 2 * plan.n_valid), device=dev)
             self.probe_est = torch.empty((2 * npb, M), device=dev)
 
@@ -142,10 +148,10 @@ class ClosedLoop:
         """Mean push-pull response of the linear reconstructor to the probe
         modes around the residual r_t [1, P*P] (library kernels; host mean)."""
         P = self.P
-        for j in range(self.probe_s.shape[0]):
-            self.probe_screen.copy_(r_t)
-            recon_apply(self.BKL, self.probe_coef[j:j + 1], 1.0, 1.0, self.probe_screen)
-            self.plan.measure_into(self.probe_screen.view(1, P, P), None, self.probe_s[j:j + 1])
+        n = self.probe_screen.shape[0]
+        self.probe_screen.copy_(r_t.expand(n, -1))
+        recon_apply(self.BKL, self.probe_coef, 1.0, 1.0, self.probe_screen)    # r_t +- a B_k, all probes at once
+        self.probe_plan.measure_into(self.probe_screen.view(n, P, P), None, self.probe_s)
         recon_apply(self.R, self.probe_s, 1.0, 0.0, self.probe_est)
         est = self.probe_est.cpu().numpy().astype(np.float64)
         g = [(est[2 * j, k] - est[2 * j + 1, k]) / (2.0 * self.probe_nm) for j, k in enumerate(self.probe_modes)]
