@@ -156,6 +156,34 @@ GemmArgs dgrad_masked_args(const uint16_t* dY, const uint16_t* W, int R, int N, 
   return a;
 }
 
+// Convolutions of the tiled products read their patches straight from the
+// activation (implicit im2col) when its channel count is a multiple of 8 and
+// the product is tall enough for the tiled kernel; otherwise (few frames: the
+// matrix-vector kernel; other channel counts) the patches are gathered first.
+bool implicit_patches(int C, int rows) { return C % 8 == 0 && rows > 512; }
+
+// Forward product of a convolution on implicit patches of act [B][H][W][C]
+// (bf16 pair, lo plane B H W C elements on).
+GemmArgs fwd_conv_args(const uint16_t* act, int H, int W, int C, const uint16_t* Wt, const float* bias, int M, int N,
+                       uint16_t* Cb, int B) {
+  GemmArgs a = fwd_args(act, true, Wt, bias, M, N, 9 * C, true, nullptr, Cb);
+  a.a_lo = (long)B * H * W * C;
+  a.sam = 0;
+  a.conv_op = 1; a.conv_H = H; a.conv_W = W; a.conv_C = C;
+  return a;
+}
+
+// Weight gradient of a convolution with its input patches implicit in act
+// [B][H][W][C] (bf16 pair); dY [R][N] pair as in wgrad_args.
+GemmArgs wgrad_conv_args(const uint16_t* dY, const uint16_t* act, int H, int W, int C, int R, int N, float* dW,
+                         float* db, int B) {
+  GemmArgs a = wgrad_args(dY, act, true, R, N, 9 * C, dW, db, C);
+  a.b_lo = (long)B * H * W * C;
+  a.sbk = 0;
+  a.conv_op = 2; a.conv_H = H; a.conv_W = W; a.conv_C = C;
+  return a;
+}
+
 // Forward pass; the last layer writes out_alpha * net(x) + out_beta * out into
 // `out` (NULL: the internal output buffer, alpha 1, beta 0).
 int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out = nullptr,
@@ -166,12 +194,22 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
   CK(pwfs::cnn::im2col_f32(x, B, n->S, n->S, 4, n->cols1, st));   // input rounded to bf16 on the way
   CK(pwfs::cnn::gemm(fwd_args(n->cols1, false, Wb + n->off[0], W + n->off[1], R1, n->c1, 36, true, nullptr, n->a1),
                      n->part, n->part_elems, st));
-  CK(pwfs::cnn::im2col(n->a1, B, n->S1, n->S1, n->c1, n->cols2, st));
-  CK(pwfs::cnn::gemm(fwd_args(n->cols2, true, Wb + n->off[2], W + n->off[3], R2, n->c2, n->c1 * 9, true, nullptr,
-                              n->a2), n->part, n->part_elems, st));
-  CK(pwfs::cnn::im2col(n->a2, B, n->S2, n->S2, n->c2, n->cols3, st));
-  CK(pwfs::cnn::gemm(fwd_args(n->cols3, true, Wb + n->off[4], W + n->off[5], R3, n->c3, n->c2 * 9, true, nullptr,
-                              n->a3), n->part, n->part_elems, st));
+  if (implicit_patches(n->c1, R2)) {
+    CK(pwfs::cnn::gemm(fwd_conv_args(n->a1, n->S1, n->S1, n->c1, Wb + n->off[2], W + n->off[3], R2, n->c2, n->a2, B),
+                       n->part, n->part_elems, st));
+  } else {
+    CK(pwfs::cnn::im2col(n->a1, B, n->S1, n->S1, n->c1, n->cols2, st));
+    CK(pwfs::cnn::gemm(fwd_args(n->cols2, true, Wb + n->off[2], W + n->off[3], R2, n->c2, n->c1 * 9, true, nullptr,
+                                n->a2), n->part, n->part_elems, st));
+  }
+  if (implicit_patches(n->c2, R3)) {
+    CK(pwfs::cnn::gemm(fwd_conv_args(n->a2, n->S2, n->S2, n->c2, Wb + n->off[4], W + n->off[5], R3, n->c3, n->a3, B),
+                       n->part, n->part_elems, st));
+  } else {
+    CK(pwfs::cnn::im2col(n->a2, B, n->S2, n->S2, n->c2, n->cols3, st));
+    CK(pwfs::cnn::gemm(fwd_args(n->cols3, true, Wb + n->off[4], W + n->off[5], R3, n->c3, n->c2 * 9, true, nullptr,
+                                n->a3), n->part, n->part_elems, st));
+  }
   CK(pwfs::cnn::gemm(fwd_args(n->a3, true, Wb + n->off[6], W + n->off[7], B, n->hidden, n->flat, true, nullptr, n->h),
                      n->part, n->part_elems, st));
   GemmArgs last = fwd_args(n->h, true, Wb + n->off[8], W + n->off[9], B, n->nout, n->hidden, false,
@@ -216,14 +254,22 @@ int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B
                      st));
   // conv3
   CK(fork(2));
-  CK(pwfs::cnn::gemm(wgrad_args(n->dz3, n->cols3, true, R3, n->c3, n->c2 * 9, G + n->off[4], G + n->off[5], n->c2),
-                     n->part2, P, sd));
+  if (n->c2 % 8 == 0)
+    CK(pwfs::cnn::gemm(wgrad_conv_args(n->dz3, n->a2, n->S2, n->S2, n->c2, R3, n->c3, G + n->off[4], G + n->off[5], B),
+                       n->part2, P, sd));
+  else
+    CK(pwfs::cnn::gemm(wgrad_args(n->dz3, n->cols3, true, R3, n->c3, n->c2 * 9, G + n->off[4], G + n->off[5], n->c2),
+                       n->part2, P, sd));
   CK(pwfs::cnn::gemm(dgrad_args(n->dz3, Wb + n->off[4], R3, n->c3, n->c2 * 9, n->gtmp), n->part, P, st));
   CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S2, n->S2, n->c2, n->a2, n->dz2, st));
   // conv2
   CK(fork(3));
-  CK(pwfs::cnn::gemm(wgrad_args(n->dz2, n->cols2, true, R2, n->c2, n->c1 * 9, G + n->off[2], G + n->off[3], n->c1),
-                     n->part2, P, sd));
+  if (n->c1 % 8 == 0)
+    CK(pwfs::cnn::gemm(wgrad_conv_args(n->dz2, n->a1, n->S1, n->S1, n->c1, R2, n->c2, G + n->off[2], G + n->off[3], B),
+                       n->part2, P, sd));
+  else
+    CK(pwfs::cnn::gemm(wgrad_args(n->dz2, n->cols2, true, R2, n->c2, n->c1 * 9, G + n->off[2], G + n->off[3], n->c1),
+                       n->part2, P, sd));
   CK(pwfs::cnn::gemm(dgrad_args(n->dz2, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, P, st));
   CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dz1, st));
   // conv1 (weight gradient only)

@@ -152,7 +152,24 @@ struct OpView {
   int rows;            // extent of rows holding data
   int ones_row;        // a row of ones at this index (hi plane), -1: none
   int vw;              // 8, 4 or 1 elements per load along the contiguous dimension
+  // implicit convolution patches (conv != 0): p is the NHWC activation
+  // [B][H][W][C]; a patch element (pixel (b, yo, xo), column (ky, kx, c)) is
+  // p[b][2 yo + ky - 1][2 xo + kx - 1][c], 0 outside (C a multiple of 8, so
+  // an 8-element chunk is 8 channels of one tap: one 16-byte load)
+  int conv, H, W, C, Wo, HoWo;
 };
+
+// Address of the 8-channel chunk (pixel, column col0) of an implicit patch
+// view, or NULL when the tap falls in the padding.
+__device__ __forceinline__ const uint16_t* patch_chunk(const OpView& v, const uint16_t* p, uint32_t pixel,
+                                                       uint32_t col0) {
+  const uint32_t tap = col0 / (uint32_t)v.C, c0 = col0 - tap * (uint32_t)v.C;
+  const uint32_t b = pixel / (uint32_t)v.HoWo, rem = pixel - b * (uint32_t)v.HoWo;
+  const uint32_t yo = rem / (uint32_t)v.Wo, xo = rem - yo * (uint32_t)v.Wo;
+  const int y = 2 * (int)yo + (int)(tap / 3) - 1, x = 2 * (int)xo + (int)(tap % 3) - 1;
+  if (y < 0 || y >= v.H || x < 0 || x >= v.W) return nullptr;
+  return p + (((size_t)b * v.H + y) * v.W + x) * v.C + c0;
+}
 
 struct Chunk8 { uint32_t w[4]; };
 
@@ -217,7 +234,15 @@ __device__ __forceinline__ void op_load(const OpView& v, long lo, int r0, int k0
         const int gr = r0 + row;
         const bool in = gr < v.rows;
         const int gk = k0 + kk;
-        if (in) {
+        if (v.conv) {
+          const uint16_t* q = (in && gk < K) ? patch_chunk(v, p, (uint32_t)gr, (uint32_t)gk) : nullptr;
+          if (q) {
+            const uint4 x = *reinterpret_cast<const uint4*>(q);
+            s.c[t].w[0] = x.x; s.c[t].w[1] = x.y; s.c[t].w[2] = x.z; s.c[t].w[3] = x.w;
+          } else {
+            s.c[t].w[0] = s.c[t].w[1] = s.c[t].w[2] = s.c[t].w[3] = 0u;
+          }
+        } else if (in) {
           s.c[t] = load8(p + (long)gr * v.s_row + gk, gk, K, v.vw);
         } else {
           s.c[t].w[0] = s.c[t].w[1] = s.c[t].w[2] = s.c[t].w[3] = 0u;
@@ -237,7 +262,15 @@ __device__ __forceinline__ void op_load(const OpView& v, long lo, int r0, int k0
       const int u = tid + 256 * t;
       if (u < RG * BK) {
         const int gr = r0 + (u % RG) * 8, gk = k0 + u / RG;
-        if (gk < K) {
+        if (v.conv) {
+          const uint16_t* q = (gk < K && gr < v.rows) ? patch_chunk(v, p, (uint32_t)gk, (uint32_t)gr) : nullptr;
+          if (q) {
+            const uint4 x = *reinterpret_cast<const uint4*>(q);
+            s.c[t].w[0] = x.x; s.c[t].w[1] = x.y; s.c[t].w[2] = x.z; s.c[t].w[3] = x.w;
+          } else {
+            s.c[t].w[0] = s.c[t].w[1] = s.c[t].w[2] = s.c[t].w[3] = 0u;
+          }
+        } else if (gk < K) {
           s.c[t] = load8(p + (long)gk * v.s_k + gr, gr, v.rows, v.vw);
         } else {
           s.c[t].w[0] = s.c[t].w[1] = s.c[t].w[2] = s.c[t].w[3] = 0u;
@@ -835,7 +868,7 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipErrorInvalidValue;
   // A few rows with both operands contiguous in k (the layers of one or a
   // few frames): the matrix-vector kernel, which streams the weights once.
-  if (!g.bias_grad && g.b_lo == 0 && g.sak == 1 && g.sbk == 1 &&
+  if (!g.bias_grad && g.conv_op == 0 && g.b_lo == 0 && g.sak == 1 && g.sbk == 1 &&
       (g.M <= 16 || (g.M <= 512 && (long)g.N * g.K <= 65536))) {
     if (g.K % 8 == 0 && g.sam % 8 == 0 && g.sbn % 8 == 0 && g.a_lo % 8 == 0 && (uintptr_t)g.A % 16 == 0 &&
         (uintptr_t)g.B % 16 == 0)
@@ -846,13 +879,27 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
   }
   const int Nc = g.N + (g.bias_grad ? 1 : 0);
   // Operand views: A rows = i, B rows = j.
-  const bool akc = g.sak == 1, bkc = g.sbk == 1;
-  if (!akc && g.sam != 1) return hipErrorInvalidValue;
-  if (!bkc && g.sbn != 1) return hipErrorInvalidValue;
-  OpView va{g.A, g.sam, g.sak, g.M, -1, 1};
-  OpView vb{g.B, g.sbn, g.sbk, g.N, g.bias_grad ? g.N : -1, 1};
+  const bool akc = g.conv_op == 1 || (g.conv_op != 2 && g.sak == 1);
+  const bool bkc = g.conv_op != 2 && g.sbk == 1;
+  if (g.conv_op == 0 && !akc && g.sam != 1) return hipErrorInvalidValue;
+  if (g.conv_op == 0 && !bkc && g.sbn != 1) return hipErrorInvalidValue;
+  OpView va{g.A, g.sam, g.sak, g.M, -1, 1, 0, 0, 0, 0, 0, 0};
+  OpView vb{g.B, g.sbn, g.sbk, g.N, g.bias_grad ? g.N : -1, 1, 0, 0, 0, 0, 0, 0};
   va.vw = akc ? vec_width(g.A, g.a_lo, g.sam, g.K) : vec_width(g.A, g.a_lo, g.sak, g.M);
   vb.vw = bkc ? vec_width(g.B, g.b_lo, g.sbn, g.K) : vec_width(g.B, g.b_lo, g.sbk, g.N);
+  if (g.conv_op) {
+    // implicit patches: 16-byte chunks of 8 channels (C a multiple of 8, planes aligned)
+    const uint16_t* act = g.conv_op == 1 ? g.A : g.B;
+    const long lo = g.conv_op == 1 ? g.a_lo : g.b_lo;
+    if (g.conv_C % 8 != 0 || (uintptr_t)act % 16 != 0 || lo % 8 != 0 || g.conv_H < 1 || g.conv_W < 1)
+      return hipErrorInvalidValue;
+    OpView& v = g.conv_op == 1 ? va : vb;
+    v.conv = 1; v.vw = 8;
+    v.H = g.conv_H; v.W = g.conv_W; v.C = g.conv_C;
+    v.Wo = (g.conv_W + 1) / 2; v.HoWo = v.Wo * ((g.conv_H + 1) / 2);
+    if ((g.conv_op == 1 ? g.M : g.K) % v.HoWo != 0 || (g.conv_op == 1 ? g.K : g.N) != 9 * g.conv_C)
+      return hipErrorInvalidValue;
+  }
   // Tile and split (measured over the training step's fourteen products at
   // batch 256): a block's time is mostly the latency of its k steps (~1 us
   // each), so many small blocks win.  64 x 64 tiles everywhere, except the

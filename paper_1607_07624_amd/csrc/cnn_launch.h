@@ -38,6 +38,11 @@ struct GemmArgs {
   int cperm;          // > 0: output column j (patch order tap, c) is stored at (j mod cperm) 9 + j / cperm
   const uint16_t* mask;   // ReLU mask: output (i, j) is zeroed unless mask[i ldm + j] (bf16) > 0; NULL: none
   long ldm;
+  // Implicit patches of a 3x3 stride-2 pad-1 convolution (C a multiple of 8):
+  // conv_op 1: A is the NHWC activation [B][H][W][C] (its lo plane a_lo on)
+  // read as patches A(i = output pixel, k = (ky, kx, c)); conv_op 2: B is that
+  // activation read as B(j = (ky, kx, c), k = output pixel).  0: none.
+  int conv_op, conv_H, conv_W, conv_C;
 };
 
 // The three convolution weight blocks of the flat parameter vector (offset,
