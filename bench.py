@@ -255,6 +255,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--seed", type=int, default=0, help="first screen seed of the benchmark frames")
+    ap.add_argument("--jsonl", type=str, default=None, help="also append the result line (with argv) to this file")
+    ap.add_argument("--calib-dir", type=str, default=None,
+                    help="tagged calibration cache: reuse the reconstructor stored there for this configuration")
     ap.add_argument("--cpu-frames", type=int, default=6)
     ap.add_argument("--cpu-frames-1core", type=int, default=2)
     ap.add_argument("--repeat-frames", type=int, default=2000,
@@ -297,7 +301,7 @@ def main():
     P = cfg.n_pupil
 
     log("inputs")
-    opd_host, r0 = open_loop_batch(cfg, ATMO2, list(range(B)), r0_range=CFG4_R0_RANGE)
+    opd_host, r0 = open_loop_batch(cfg, ATMO2, list(range(args.seed, args.seed + B)), r0_range=CFG4_R0_RANGE)
     opd = torch.from_numpy(opd_host).to(dev)
     plan = pw.Plan(cfg, batch_max=B)
     nv = plan.n_valid
@@ -319,7 +323,13 @@ def main():
         modes = kl_modes(amp, cfg.pixel_m, ATMO2.L0_m, N_KL_MODES)
         M = modes.shape[0]
         modes_dev = torch.from_numpy(modes.astype(np.float32)).to(dev)
-        R, _, sig = calibrate(plan, modes.astype(np.float32), PUSH_PULL_NM, dev)
+        if args.calib_dir:
+            from paper_1607_07624_amd.calib import CalibrationStore, calibrate_cached
+            R, _, sig, hit = calibrate_cached(plan, modes.astype(np.float32), PUSH_PULL_NM,
+                                              CalibrationStore(args.calib_dir), device=dev)
+            log(f"calibration cache {'hit' if hit else 'miss (measured and stored)'} in {args.calib_dir}")
+        else:
+            R, _, sig = calibrate(plan, modes.astype(np.float32), PUSH_PULL_NM, dev)
         log(f"IM condition number {sig[0] / sig[-1]:.1f}")
     if args.random_R:
         R = torch.from_numpy(R_host.astype(np.float32)).to(dev).contiguous()
@@ -725,6 +735,9 @@ def main():
         "schedule": schedule,
     }
     print(json.dumps(out), flush=True)
+    if args.jsonl:
+        with open(args.jsonl, "a") as f:
+            f.write(json.dumps(dict(out, argv=sys.argv[1:], unix_time=round(time.time(), 1))) + "\n")
 
 
 if __name__ == "__main__":
