@@ -119,15 +119,19 @@ class CNN:
                                              self._s()), "pwfs_cnn_forward_acc")
         return out
 
-    def gradients(self, x, target, weights=None):
+    def gradients(self, x, target, weights=None, grads=None, loss=None):
+        """(gradients [n_params], loss [1]); grads / loss: output tensors to
+        write (new ones when None)."""
         t = self._torch
         B = x.shape[0]
         _need(x, t, t.float32, B * self.n_sub * self.n_sub * 4, "x")
         _need(target, t, t.float32, B * self.n_out, "target")
         if weights is not None:
             _need(weights, t, t.float32, B, "weights")
-        g = t.empty(self.n_params, dtype=t.float32, device=x.device)
-        loss = t.empty(1, dtype=t.float32, device=x.device)
+        g = t.empty(self.n_params, dtype=t.float32, device=x.device) if grads is None else grads
+        loss = t.empty(1, dtype=t.float32, device=x.device) if loss is None else loss
+        _need(g, t, t.float32, self.n_params, "grads")
+        _need(loss, t, t.float32, 1, "loss")
         _check(self.lib.pwfs_cnn_gradients(self.handle, _ptr(x), _ptr(target), _ptr(weights), B, _ptr(g),
                                            _ptr(loss), self._s()), "pwfs_cnn_gradients")
         return g, loss

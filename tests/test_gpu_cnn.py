@@ -183,3 +183,37 @@ def test_prepare_matches_oracle():
     x = prepare(torch.from_numpy(pup).cuda(), torch.from_numpy(ref).cuda(), torch.from_numpy(valid).cuda())
     exp = ocnn.network_input(pup, ref, valid)
     assert np.abs(x.cpu().numpy() - exp).max() <= 1e-5 * np.abs(exp).max()
+
+
+def test_gradients_under_graph_capture():
+    """pwfs_cnn_gradients captured in a HIP graph (its backward forks a second
+    stream from the captured one and joins it back): replays with new inputs
+    copied into the captured buffers give the eager call's loss and gradients
+    bit for bit, with eager work between the replays."""
+    net, torch, p, po, x, xb, tgt = _setup(FULL, 16, 21)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda()
+    g_buf = torch.empty(net.n_params, device="cuda")
+    l_buf = torch.empty(1, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        net.gradients(xd, td, grads=g_buf, loss=l_buf)              # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        net.gradients(xd, td, grads=g_buf, loss=l_buf)
+    rng = np.random.default_rng(22)
+    for rep in range(3):
+        x2 = torch.from_numpy(rng.normal(0, 1.0, x.shape).astype(np.float32)).cuda()
+        t2 = torch.from_numpy(rng.normal(0, 1.0, tgt.shape).astype(np.float32)).cuda()
+        ge, le = net.gradients(x2, t2)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 16, device="cuda").sum()              # eager work between replays
+        xd.copy_(x2)
+        td.copy_(t2)
+        graph.replay()
+        torch.cuda.synchronize()
+        same = torch.equal(g_buf, ge) and torch.equal(l_buf.reshape(()), le.reshape(()))
+        say(f"[gpu] cnn gradients graph replay {rep}: equal to eager {same} ({float(junk):.1f})")
+        assert same
+    net.close()
