@@ -88,9 +88,10 @@ int pwfs_cnn_forward_acc(pwfs_cnn_t net, const float* d_x, int32_t B, float alph
 /* Loss and parameter gradients (flat FP32, same order as the parameters)
  * for targets d_target [B][n_out] and per-frame weights d_weights [B] (NULL:
  * all 1); d_loss (1 float) and d_grads may be NULL.
- * The backward pass (also in pwfs_cnn_train_step) runs the weight gradients
- * on a second stream of the network (default priority) beside the chain of
- * data gradients on `stream`, forked from and joined back into `stream` with
+ * The backward pass (also in pwfs_cnn_train_step) runs the loss sum and the
+ * weight gradients of all layers but the first on a second stream of the
+ * network (default priority) beside the chain of data gradients on `stream`
+ * (which ends with the first layer's weight gradient), forked from and joined back into `stream` with
  * events: the call as a whole is ordered after earlier work on `stream` and
  * before later work on it, and a graph capture of `stream` takes in both.
  * Calls on one network must not overlap. */

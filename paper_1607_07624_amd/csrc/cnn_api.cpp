@@ -69,7 +69,7 @@ struct pwfs_cnn_s {
   // backward: the weight gradients run on `side` (default priority) beside
   // the chain of data gradients on the caller's stream; ev fork and join
   hipStream_t side = nullptr;
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[5] = {};
 };
 
 namespace {
@@ -228,7 +228,9 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
 // before the optimiser, so the weight gradients run on the side stream, each
 // after an event on the chain, and the caller's stream waits for the side
 // stream at the end.  Each product alone leaves most of the GPU idle (a few
-// hundred blocks of a few k steps), so the two streams overlap.
+// hundred blocks of a few k steps), so the two streams overlap.  The first
+// layer's weight gradient stays on the chain, which has no other work left
+// by then; the loss sum (read by nothing in the step) goes to the side stream.
 int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B, float* loss, hipStream_t st) {
   const uint16_t* Wb = n->wb;
   float* G = n->g;
@@ -239,9 +241,10 @@ int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B
     return r != hipSuccess ? r : hipStreamWaitEvent(sd, n->ev[e], 0);
   };
   const int R3 = B * n->S3 * n->S3, R2 = B * n->S2 * n->S2, R1 = B * n->S1 * n->S1;
-  CK(pwfs::cnn::mse(n->out, target, weights, B * n->nout, n->nout, n->doutb, loss, n->mse_part, st));
-  // fc2: weight gradient (side); data gradient with the ReLU mask of h (chain)
+  CK(pwfs::cnn::mse(n->out, target, weights, B * n->nout, n->nout, n->doutb, n->mse_part, st));
+  // fc2: weight gradient (side, after the loss sum); data gradient with the ReLU mask of h (chain)
   CK(fork(0));
+  CK(pwfs::cnn::mse_sum(n->mse_part, B * n->nout, loss, sd));
   CK(pwfs::cnn::gemm(wgrad_args(n->doutb, n->h, true, B, n->nout, n->hidden, G + n->off[8], G + n->off[9]),
                      n->part2, P, sd));
   CK(pwfs::cnn::gemm(dgrad_masked_args(n->doutb, Wb + n->off[8], B, n->nout, n->hidden, n->h, n->dzf), n->part, P,
@@ -272,13 +275,12 @@ int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B
                        n->part2, P, sd));
   CK(pwfs::cnn::gemm(dgrad_args(n->dz2, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, P, st));
   CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dz1, st));
-  // conv1 (weight gradient only)
-  CK(fork(4));
+  // conv1: weight gradient only, on the chain
   CK(pwfs::cnn::gemm(wgrad_args(n->dz1, n->cols1, false, R1, n->c1, 36, G + n->off[0], G + n->off[1], 4),
-                     n->part2, P, sd));
+                     n->part, P, st));
   // join
-  CK(hipEventRecord(n->ev[5], sd));
-  CK(hipStreamWaitEvent(st, n->ev[5], 0));
+  CK(hipEventRecord(n->ev[4], sd));
+  CK(hipStreamWaitEvent(st, n->ev[4], 0));
   return 0;
 }
 

@@ -328,9 +328,19 @@ __device__ __forceinline__ bf16x8 frag(const uint16_t* plane, int row, int kof) 
   }
 }
 
+// Output of a wave's 32 x 32 accumulator block through LDS: 32 rows of 36
+// floats (the pitch keeps float4 rows aligned), read back as 4 consecutive
+// columns of one row per lane, so that a row leaves in 16-byte (FP32) or
+// 8-byte (bf16) pieces instead of one element per lane and store.
+constexpr int kEpiPitch = 36;
+__device__ __forceinline__ float f4at(const float4& x, int q) { return q == 0 ? x.x : q == 1 ? x.y : q == 2 ? x.z : x.w; }
+constexpr size_t kEpiLdsBytes = (size_t)4 * 32 * kEpiPitch * sizeof(float);   // four waves
+
+// evec bit 0: epilogue4 may take four regular columns (no patch-order remap,
+// aligned rows); bit 1: the partial rows are 16-byte aligned (Nc a multiple of 4).
 template <int WM, int WN, int TM, int TN, bool AKC, bool BKC, int BK>
 __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, OpView vb, int kc,
-                                                        float* __restrict__ part) {
+                                                        float* __restrict__ part, int evec) {
   constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN;
   constexpr int SA = plane_elems(AKC, BM, BK), SB = plane_elems(BKC, BN, BK);
   extern __shared__ __align__(16) uint16_t lds[];
@@ -421,22 +431,42 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs g, OpView va, O
     __syncthreads();
   }
 
+  // the loop ended with a barrier: the operand stages are free
   const int Nc = g.N + (g.bias_grad ? 1 : 0);
+  float* sc = reinterpret_cast<float*>(lds) + wave * 32 * kEpiPitch;
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
     for (int b = 0; b < TN; ++b) {
-      const int j = j0 + wn * TN * 32 + b * 32 + (lane & 31);
-      if (j >= Nc) continue;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int i = i0 + wm * TM * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-        if (i >= g.M) continue;
-        if (part)
-          part[((size_t)blockIdx.z * g.M + i) * Nc + j] = acc[a][b][v];
-        else
-          epilogue(g, i, j, acc[a][b][v]);
+      for (int v = 0; v < 16; ++v) sc[(8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)) * kEpiPitch + (lane & 31)] = acc[a][b][v];
+      __syncthreads();
+      const int c = (lane & 7) * 4;
+      const int j = j0 + wn * TN * 32 + b * 32 + c;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int r = p * 8 + (lane >> 3);
+        const int i = i0 + wm * TM * 32 + a * 32 + r;
+        if (i >= g.M || j >= Nc) continue;
+        const float4 x = *reinterpret_cast<const float4*>(sc + r * kEpiPitch + c);
+        if (part) {
+          float* o = part + ((size_t)blockIdx.z * g.M + i) * Nc + j;
+          if ((evec & 2) && j + 3 < Nc) {
+            *reinterpret_cast<float4*>(o) = x;
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (j + q < Nc) o[q] = f4at(x, q);
+          }
+        } else if ((evec & 1) && j + 3 < g.N) {
+          epilogue4(g, i, j, x);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (j + q < Nc) epilogue(g, i, j + q, f4at(x, q));
+        }
       }
+      if (a + 1 < TM || b + 1 < TN) __syncthreads();
     }
 }
 
@@ -680,8 +710,27 @@ __global__ __launch_bounds__(256) void col2im_mask_kernel(const float* __restric
       }
     }
     const uint32_t o = pix * C + cg * V;
+    if constexpr (V == 8) {   // 16-byte mask load, 16-byte hi and lo stores (o and n are multiples of 8)
+      const uint4 m = *reinterpret_cast<const uint4*>(act + o);
+      const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+      uint32_t hw[4], lw[4];
 #pragma unroll
-    for (int v = 0; v < V; ++v) split_bf(bf_pos(act[o + v]) ? s[v] : 0.f, dzb, dzb + n, o + v);
+      for (int q = 0; q < 4; ++q) {
+        uint16_t h[2], l[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float x = bf_pos((uint16_t)(mw[q] >> (16 * e))) ? s[2 * q + e] : 0.f;
+          h[e] = f2bf(x);
+          l[e] = f2bf(x - bf2f(h[e]));
+        }
+        hw[q] = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        lw[q] = (uint32_t)l[0] | ((uint32_t)l[1] << 16);
+      }
+      *reinterpret_cast<uint4*>(dzb + o) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+      *reinterpret_cast<uint4*>(dzb + n + o) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    } else {
+      split_bf(bf_pos(act[o]) ? s[0] : 0.f, dzb, dzb + n, o);
+    }
   }
 }
 
@@ -846,12 +895,17 @@ static hipError_t launch_tile(const GemmArgs& g, const OpView& va, const OpView&
                               hipStream_t st) {
   constexpr int BM = 32 * WM * TM, BN = 32 * WN * TN;
   const int Nc = g.N + (g.bias_grad ? 1 : 0);
-  const size_t lds = (size_t)2 *
+  const size_t lds = std::max(kEpiLdsBytes, (size_t)2 *
                      (plane_elems(AKC, BM, BK) * (g.a_lo ? 2 : 1) + plane_elems(BKC, BN, BK) * (g.b_lo ? 2 : 1)) *
-                     sizeof(uint16_t);
+                     sizeof(uint16_t));
+  auto al = [](const void* p, uintptr_t b) { return ((uintptr_t)p % b) == 0; };
+  const bool e4 = !g.cperm && (!g.C || (al(g.C, 16) && g.ldc % 4 == 0)) &&
+                  (!g.Cb || (al(g.Cb, 8) && g.ldcb % 4 == 0 && g.cb_lo % 4 == 0)) && (!g.bias || al(g.bias, 16)) &&
+                  (!g.mask || (al(g.mask, 8) && g.ldm % 4 == 0));
+  const int evec = (e4 ? 1 : 0) | (Nc % 4 == 0 && al(part, 16) ? 2 : 0);
   hipLaunchKernelGGL((gemm_mfma_kernel<WM, WN, TM, TN, AKC, BKC, BK>),
                      dim3((Nc + BN - 1) / BN, (g.M + BM - 1) / BM, splits), dim3(256), lds, st, g, va, vb, kc,
-                     splits > 1 ? part : (float*)nullptr);
+                     splits > 1 ? part : (float*)nullptr, evec);
   return hipGetLastError();
 }
 
@@ -990,12 +1044,14 @@ hipError_t weights_bf16(const float* x, size_t n, const ConvPerm& cp, uint16_t* 
 size_t mse_partials(int n) { return (size_t)(n + kMseBlock - 1) / kMseBlock; }
 
 hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, uint16_t* doutb,
-               float* loss, float* part, hipStream_t st) {
-  const int nb = (int)mse_partials(n);
-  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, pred, target, weights, n, n_out, doutb, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !loss) return e;
-  hipLaunchKernelGGL(mse_sum_kernel, dim3(1), dim3(256), 0, st, (const float*)part, nb, n, loss);
+               float* part, hipStream_t st) {
+  hipLaunchKernelGGL(mse_kernel, dim3((int)mse_partials(n)), dim3(256), 0, st, pred, target, weights, n, n_out, doutb,
+                     part);
+  return hipGetLastError();
+}
+
+hipError_t mse_sum(const float* part, int n, float* loss, hipStream_t st) {
+  hipLaunchKernelGGL(mse_sum_kernel, dim3(1), dim3(256), 0, st, part, (int)mse_partials(n), n, loss);
   return hipGetLastError();
 }
 

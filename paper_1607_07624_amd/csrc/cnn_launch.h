@@ -66,10 +66,13 @@ hipError_t col2im_mask(const float* dcols, int B, int H, int W, int C, const uin
                        hipStream_t st);
 // bf16 product copy of the FP32 parameters (convolution weights permuted as in ConvPerm).
 hipError_t weights_bf16(const float* x, size_t n, const ConvPerm& cp, uint16_t* y, hipStream_t st);
-// part: at least mse_partials(n) floats of scratch.
+// part: at least mse_partials(n) floats of scratch.  mse writes the gradient
+// pair and the per-block partial sums; mse_sum (on any stream ordered after
+// mse) adds the partials in block order into the loss.
 size_t mse_partials(int n);
 hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, uint16_t* doutb,
-               float* loss, float* part, hipStream_t st);
+               float* part, hipStream_t st);
+hipError_t mse_sum(const float* part, int n, float* loss, hipStream_t st);
 hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, const ConvPerm& cp, size_t n, float lr,
                 float b1, float b2, float eps, float c1, float c2, hipStream_t st);
 hipError_t fill0(float* p, size_t n, hipStream_t st);
