@@ -235,21 +235,23 @@ class ClosedLoop:
         return res, hist[d:]
 
     def run_graph(self, opd_seq_dev, residuals_dev=None, steps_per_graph: int = 50):
-        """run() for the linear reconstructor replayed from captured HIP graphs
-        (torch.cuda.CUDAGraph) of `steps_per_graph` steps each: the same
-        library calls in the same order on static buffers, so the same results
-        bit for bit.  A graph advances a window of L steps: the window's
-        inputs are copied in once, its residuals and commands out once, and
-        the delay line is the command window itself (hist_ext[j] = c(t - d)
-        for step t = t0 + j, rows 0..d-1 carried over from the previous
-        window).  A sequence that is not a multiple of L ends with a second,
-        shorter graph on the same buffers.  The graphs and their buffers are
-        kept on the loop object: a later run with the same L replays them
-        without capturing again.  Needs delay >= 1 and a noiseless sensor (a
-        detector's frame counter would be frozen into the graph)."""
+        """run() (from t = 0) replayed from captured HIP graphs
+        (torch.cuda.CUDAGraph) of up to `steps_per_graph` steps each: the
+        same library calls in the same order on static buffers, so the same
+        results bit for bit.  A graph advances a window of n steps: the
+        window's inputs are copied in once, its residuals and commands out
+        once, and the delay line is the command window itself (hist_ext[j] =
+        c(t - d) for step t = t0 + j, rows 0..d-1 carried over from the
+        previous window).  With the learned reconstructor a window ends at
+        each of the judge's steps (t a multiple of judge_every, t = 0 first)
+        and the judge runs between replays as in run(), its probes launched
+        one by one; after a hand-over the linear reconstructor's windows
+        follow.  One graph is captured per (reconstructor, window length),
+        kept on the loop object for later runs with the same steps_per_graph.
+        Afterwards `state` holds the loop's state as after run().  Needs
+        delay >= 1 and a noiseless sensor (a detector's frame counter would
+        be frozen into the graph)."""
         import torch
-        if self.net is not None:
-            raise ValueError("graph replay runs the linear reconstructor only")
         if self.delay < 1:
             raise ValueError("graph replay needs delay >= 1")
         det = getattr(self.plan, "detector", None)
@@ -269,39 +271,69 @@ class ClosedLoop:
             self._graphs = cache
         opd_win, res_win, hist_ext = cache["bufs"]
 
-        def window(n):
+        def window(n, learned):
             for j in range(n):
                 r = res_win[j:j + 1]
                 r.copy_(opd_win[j:j + 1])
                 recon_apply(self.BKL, hist_ext[j:j + 1], -1.0, 1.0, r)          # u(t) = c(t - d)
                 c = hist_ext[j + d:j + d + 1]
                 c.copy_(hist_ext[j + d - 1:j + d])                              # c(t - 1)
-                self.plan.measure_into(r.view(1, P, P), None, self.s)
-                recon_apply(self.R, self.s, self.gain, 1.0, c)                  # c(t) = c(t-1) + g R s(t)
+                if learned:
+                    self.plan.measure_into(r.view(1, P, P), self.pupils, self.s)
+                    recon_apply(self.R, self.s, self.gain, 1.0, c)
+                    self._prepare(self.pupils, self.ref[0], self.valid, self.x)
+                    self.net.forward_acc(self.x, c, self.gain, 1.0)            # c(t) = c(t-1) + g (R s + f(x))
+                else:
+                    self.plan.measure_into(r.view(1, P, P), None, self.s)
+                    recon_apply(self.R, self.s, self.gain, 1.0, c)              # c(t) = c(t-1) + g R s(t)
 
-        def capture(n):
-            side = torch.cuda.Stream(device=dev)
-            side.wait_stream(torch.cuda.current_stream(dev))
-            with torch.cuda.stream(side):
-                window(n)                                                     # warm-up outside the capture
-            torch.cuda.current_stream(dev).wait_stream(side)
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g):
-                window(n)
-            return g
+        def graph(n, learned):
+            key = (learned, n)
+            if key not in cache["graphs"]:
+                carry = hist_ext[:d].clone()                                   # the warm-up overwrites the window
+                side = torch.cuda.Stream(device=dev)
+                side.wait_stream(torch.cuda.current_stream(dev))
+                with torch.cuda.stream(side):
+                    window(n, learned)                                         # warm-up outside the capture
+                torch.cuda.current_stream(dev).wait_stream(side)
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    window(n, learned)
+                hist_ext[:d].copy_(carry)
+                cache["graphs"][key] = g
+            return cache["graphs"][key]
 
-        graphs = cache["graphs"]
-        for n in {L, T % L} - {0}:
-            if n not in graphs:
-                graphs[n] = capture(n)
+        learned = self.net is not None
+        self.judged = []
+        self.fallback_step = None
+        je = self.judge_every
+        if not learned:
+            for n in {L, T % L} - {0}:
+                graph(n, False)
         hist_ext.zero_()
-        for t0 in range(0, T, L):
-            n = min(L, T - t0)
+        t0 = 0
+        while t0 < T:
+            if learned:
+                judge_t = -(-t0 // je) * je                                    # first judge step >= t0
+                n = min(judge_t - t0 + 1, T - t0, L)
+            else:
+                n = min(L, T - t0)
+            g = graph(n, learned)
             opd_win[:n].copy_(opd_seq_dev[t0:t0 + n].reshape(n, -1))
-            graphs[n].replay()
+            g.replay()
+            ta = t0 + n - 1
+            if learned and ta % je == 0 and self._judge(ta, res_win[n - 1:n], hist_ext[n - 1 + d:n + d]):
+                learned = False
+                self.fallback_step = ta
+                hist_ext[n:n + d].zero_()                                      # the delay line still to be read
+                recon_apply(self.R, self.s, self.gain, 1.0, hist_ext[n - 1 + d:n + d])
             res[t0:t0 + n].copy_(res_win[:n])
             hist[t0:t0 + n].copy_(hist_ext[d:d + n])
             hist_ext[:d].copy_(hist_ext[n:n + d].clone())
+            t0 += n
+        self.state = {"t": T, "commands": hist_ext[:d].clone(), "learned": learned,
+                      "fallback_step": -1 if self.fallback_step is None else self.fallback_step,
+                      "judged": list(self.judged)}
         return res, hist
 
 

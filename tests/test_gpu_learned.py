@@ -98,3 +98,53 @@ def test_linear_judge_takes_over_from_a_diverging_network():
         f"after fallback {np.sqrt(np.mean(pc[-50:] ** 2)):.1f}, linear {np.sqrt(np.mean(pl[-50:] ** 2)):.1f} nm")
     assert pc[cl.fallback_step] > 5.0 * pl[cl.fallback_step]
     assert np.sqrt(np.mean(pc[-50:] ** 2)) < 1.5 * np.sqrt(np.mean(pl[-50:] ** 2))
+
+
+@pytest.mark.parametrize("case,L", [("diverging", 50), ("diverging", 7), ("broken", 16), ("random", 10)])
+def test_learned_loop_graph_replay_equals_eager(case, L):
+    """run_graph with the network: windows end at the judge's steps, the judge
+    runs between replays; residuals, commands, the judge's record, the
+    hand-over step and the final state equal run()'s bit for bit (with a
+    hand-over at step 50, at step 0 and none), also when the graph length
+    does not divide the judge's period."""
+    import paper_1607_07624_amd as pw
+    from paper_1607_07624_amd.cnn import CNN, he_init, PARAM_ORDER
+    from paper_1607_07624_amd.loop import ClosedLoop
+    st = _setup()
+    torch = st["torch"]
+    say(f"[gpu] learned graph replay: {case} network, steps per graph {L}")
+    net = CNN(n_sub=CFG2.n_sub, n_out=600, batch_max=4)
+    if case == "broken":
+        net.set_params(torch.full((net.n_params,), float("nan"), device="cuda"))
+    else:
+        p = he_init(net.shapes, 321)
+        if case == "diverging":
+            off = 0
+            for k in PARAM_ORDER:
+                n = int(np.prod(net.shapes[k]))
+                if k in ("fw2", "fb2"):
+                    p[off:off + n] *= 300.0
+                off += n
+        net.set_params(torch.from_numpy(p))
+    plan1 = pw.Plan(CFG2, batch_max=1)
+    modes_dev = torch.from_numpy(st["modes"]).cuda()
+    T = 83
+    seq = torch.from_numpy(frozen_flow_sequence(CFG2, ATMO2, T, seed=5)).cuda()
+    a = ClosedLoop(plan1, modes_dev, st["R"], LOOP_GAIN, LOOP_DELAY, net=net)
+    res_a, c_a = a.run(seq)
+    b = ClosedLoop(plan1, modes_dev, st["R"], LOOP_GAIN, LOOP_DELAY, net=net)
+    for rep in range(2):                                  # the second run replays the kept graphs
+        res_b, c_b = b.run_graph(seq, steps_per_graph=L)
+        torch.cuda.synchronize()
+        say(f"[gpu]   run {rep}: hand-over {a.fallback_step} / {b.fallback_step}, judged {len(a.judged)} / "
+            f"{len(b.judged)}, graphs {sorted(b._graphs['graphs'])}")
+        assert torch.equal(res_a, res_b) and torch.equal(c_a, c_b)
+        assert b.fallback_step == a.fallback_step and [t for t, _ in b.judged] == [t for t, _ in a.judged]
+        assert np.array_equal([g for _, g in b.judged], [g for _, g in a.judged], equal_nan=True)
+        assert b.state["learned"] == a.state["learned"] and b.state["t"] == a.state["t"]
+        assert torch.equal(b.state["commands"], a.state["commands"])
+    if case == "diverging":
+        assert a.fallback_step == a.judge_settle
+    if case == "broken":
+        assert a.fallback_step == 0
+    net.close()
