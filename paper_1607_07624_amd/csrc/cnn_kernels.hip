@@ -959,8 +959,10 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
   // each), so many small blocks win.  64 x 64 tiles everywhere, except the
   // narrow first-layer product (32 outputs, K = 36), which takes 128 x 32.
   // Fewer than 256 tiles leave the GPU short of blocks: split K towards
-  // ~1024 blocks of at least 2 k steps (more splits cost partial traffic and
-  // a longer reduction); partials must fit `part`.  Steps of 64 k were not
+  // ~768 blocks (three per CU) of at least 2 k steps (more splits cost
+  // partial traffic and a longer reduction; against ~1024 blocks a batch-256
+  // training step took 3.4-3.7 % less time at ~768 on two boxes, the same at
+  // ~512, and within 0.5 % of ~768 at ~640 and ~896); partials must fit `part`.  Steps of 64 k were not
   // faster (a step's time grew with its depth), so steps stay 32 deep.
   const int bk = kStepK;
   const int tile = (Nc <= 32 && g.K <= 64) ? 0 : 3;   // 0: 128 x 32, 3: 64 x 64
@@ -969,7 +971,7 @@ hipError_t gemm(const GemmArgs& g, float* part, size_t part_elems, hipStream_t s
   const long tiles = (long)((Nc + BN - 1) / BN) * ((g.M + BM - 1) / BM);
   int splits = 1;
   if (part && tiles < 256) {
-    splits = (int)std::max<long>(1, std::min<long>((1024 + tiles - 1) / tiles, g.K / (bk * 2)));
+    splits = (int)std::max<long>(1, std::min<long>((768 + tiles - 1) / tiles, g.K / (bk * 2)));
     while (splits > 1 && (size_t)splits * g.M * Nc > part_elems) --splits;
   }
   const int kc = ((g.K + splits - 1) / splits + bk - 1) / bk * bk;
