@@ -186,11 +186,38 @@ GemmArgs wgrad_conv_args(const uint16_t* dY, const uint16_t* act, int H, int W, 
 
 // Forward pass; the last layer writes out_alpha * net(x) + out_beta * out into
 // `out` (NULL: the internal output buffer, alpha 1, beta 0).
+// The two fully connected layers, from the third convolution's output pair.
+int run_dense(pwfs_cnn_s* n, int B, hipStream_t st, float* out, float out_alpha, float out_beta) {
+  const float* W = n->w;
+  const uint16_t* Wb = n->wb;
+  CK(pwfs::cnn::gemm(fwd_args(n->a3, true, Wb + n->off[6], W + n->off[7], B, n->hidden, n->flat, true, nullptr, n->h),
+                     n->part, n->part_elems, st));
+  GemmArgs last = fwd_args(n->h, true, Wb + n->off[8], W + n->off[9], B, n->nout, n->hidden, false,
+                           out ? out : n->out, nullptr);
+  if (out) {
+    last.alpha = out_alpha;
+    last.beta = out_beta;
+  }
+  CK(pwfs::cnn::gemm(last, n->part, n->part_elems, st));
+  return 0;
+}
+
+// Forward pass.  A training step keeps every layer's activations for the
+// backward pass; a forward-only call (inference) runs the three
+// convolutions as one block per frame (pwfs::cnn::conv_stack) when the
+// shapes allow it, which keeps only the third convolution's output.
 int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out = nullptr,
-                float out_alpha = 1.f, float out_beta = 0.f) {
+                float out_alpha = 1.f, float out_beta = 0.f, bool inference = false) {
   const float* W = n->w;
   const uint16_t* Wb = n->wb;
   const int R1 = B * n->S1 * n->S1, R2 = B * n->S2 * n->S2, R3 = B * n->S3 * n->S3;
+  const hipError_t cs = inference ? pwfs::cnn::conv_stack(x, B, n->S, Wb + n->off[0], W + n->off[1], n->c1,
+                                                          Wb + n->off[2], W + n->off[3], n->c2, n->a2,
+                                                          (long)R2 * n->c2, Wb + n->off[4], W + n->off[5], n->c3,
+                                                          n->a3, (long)R3 * n->c3, st)
+                                  : hipErrorNotSupported;
+  if (cs != hipSuccess && cs != hipErrorNotSupported) return hip_fail(cs, "cnn convolution stack");
+  if (cs == hipSuccess) return run_dense(n, B, st, out, out_alpha, out_beta);
   CK(pwfs::cnn::im2col_f32(x, B, n->S, n->S, 4, n->cols1, st));   // input rounded to bf16 on the way
   CK(pwfs::cnn::gemm(fwd_args(n->cols1, false, Wb + n->off[0], W + n->off[1], R1, n->c1, 36, true, nullptr, n->a1),
                      n->part, n->part_elems, st));
@@ -210,16 +237,7 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
     CK(pwfs::cnn::gemm(fwd_args(n->cols3, true, Wb + n->off[4], W + n->off[5], R3, n->c3, n->c2 * 9, true, nullptr,
                                 n->a3), n->part, n->part_elems, st));
   }
-  CK(pwfs::cnn::gemm(fwd_args(n->a3, true, Wb + n->off[6], W + n->off[7], B, n->hidden, n->flat, true, nullptr, n->h),
-                     n->part, n->part_elems, st));
-  GemmArgs last = fwd_args(n->h, true, Wb + n->off[8], W + n->off[9], B, n->nout, n->hidden, false,
-                           out ? out : n->out, nullptr);
-  if (out) {
-    last.alpha = out_alpha;
-    last.beta = out_beta;
-  }
-  CK(pwfs::cnn::gemm(last, n->part, n->part_elems, st));
-  return 0;
+  return run_dense(n, B, st, out, out_alpha, out_beta);
 }
 
 // Backward pass.  The data gradients form a chain on the caller's stream
@@ -442,9 +460,7 @@ int pwfs_cnn_forward(pwfs_cnn_t n, const float* d_x, int32_t B, float* d_out, vo
   if (!d_x || !d_out) return fail(PWFS_CNN_ERR_INVALID_ARG, "NULL pointer");
   DevGuard g(n->device);
   hipStream_t st = (hipStream_t)stream;
-  if ((s = run_forward(n, d_x, B, st))) return s;
-  CK(hipMemcpyAsync(d_out, n->out, (size_t)B * n->nout * 4, hipMemcpyDeviceToDevice, st));
-  return 0;
+  return run_forward(n, d_x, B, st, d_out, 1.f, 0.f, true);
 }
 
 int pwfs_cnn_forward_acc(pwfs_cnn_t n, const float* d_x, int32_t B, float alpha, float beta, float* d_out,
@@ -455,7 +471,7 @@ int pwfs_cnn_forward_acc(pwfs_cnn_t n, const float* d_x, int32_t B, float alpha,
   if (!d_x || !d_out) return fail(PWFS_CNN_ERR_INVALID_ARG, "NULL pointer");
   if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(PWFS_CNN_ERR_INVALID_ARG, "alpha/beta not finite");
   DevGuard g(n->device);
-  return run_forward(n, d_x, B, (hipStream_t)stream, d_out, alpha, beta);
+  return run_forward(n, d_x, B, (hipStream_t)stream, d_out, alpha, beta, true);
 }
 
 int pwfs_cnn_gradients(pwfs_cnn_t n, const float* d_x, const float* d_target, const float* d_weights, int32_t B,

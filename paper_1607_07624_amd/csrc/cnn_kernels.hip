@@ -1069,6 +1069,324 @@ hipError_t fill0(float* p, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Convolution stack of forward-only calls on few frames: one block of 8
+// waves per frame instead of a gather and a product per layer.  The frame's
+// input (rounded to bf16) and the first convolution's output pair stay in
+// LDS; the products run on v_mfma_f32_32x32x16_bf16 with the A fragments
+// gathered straight from the LDS activations (implicit patches: 8 channels
+// of one tap per 16-byte read, or two taps of the 4-channel input per pair
+// of 8-byte reads, zero in the padding) and the B fragments read from the
+// bf16 weights in patch order [Cout][3][3][Cin] in global memory.  Same
+// arithmetic as the tiled products (pair operands as two MFMAs, FP32
+// accumulation, bias, ReLU, pair output), in another summation order.
+// A 32 x 32 output tile: rows i = output pixels, columns j = output channels.
+// Weight (B) fragments of this lane's output channel j = 32 tn + lane % 32
+// for the k steps kbeg, kbeg + 16, ... (NS of them; zero past kend and K),
+// loaded once, before the activations they multiply are ready.
+template <bool C4, int NS>
+__device__ __forceinline__ void conv_wfrags(const uint16_t* __restrict__ wt, int K, int tn, int kbeg, int kend,
+                                            int lane, uint32_t (&b)[NS][4]) {
+  const uint16_t* wrow = wt + (size_t)(tn * 32 + (lane & 31)) * K;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int ks = kbeg + 16 * s, kk = ks + 8 * (lane >> 5);
+    b[s][0] = b[s][1] = b[s][2] = b[s][3] = 0u;
+    if constexpr (!C4) {
+      if (ks < kend && kk < K) {
+        const uint4 u = *reinterpret_cast<const uint4*>(wrow + kk);
+        b[s][0] = u.x; b[s][1] = u.y; b[s][2] = u.z; b[s][3] = u.w;
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (ks < kend && kk + 4 * h < K) {
+          const uint2 u = *reinterpret_cast<const uint2*>(wrow + kk + 4 * h);
+          b[s][2 * h] = u.x; b[s][2 * h + 1] = u.y;
+        }
+      }
+    }
+  }
+}
+
+// Activation (A) fragment of output pixel r (valid rv) at k = kk .. kk + 7
+// (patch order: k = (ky 3 + kx) C + c) from the LDS planes.  Branch-free:
+// an address outside the frame is replaced by the plane's start and the
+// loaded words by zero.  C: input channels (a compile-time power of two,
+// or 4 for the network input, whose 8 k span two taps).
+template <int C, bool PAIR>
+__device__ __forceinline__ void conv_afrag(const uint16_t* in_hi, const uint16_t* in_lo, int H, int W, bool rv,
+                                           int yo, int xo, int K, int kk, uint32_t (&a)[4], uint32_t (&al)[4]) {
+  if constexpr (C != 4) {
+    static_assert(C % 8 == 0 && (C & (C - 1)) == 0, "channel count a power of two, at least 8");
+    const int tap = kk / C, c = kk % C;
+    const int ky = tap / 3, kx = tap - ky * 3;
+    const int y = 2 * yo + ky - 1, x = 2 * xo + kx - 1;
+    const bool in = rv && kk < K && y >= 0 && y < H && x >= 0 && x < W;
+    const int off = in ? (y * W + x) * C + c : 0;
+    const uint4 u = *reinterpret_cast<const uint4*>(in_hi + off);
+    a[0] = in ? u.x : 0u; a[1] = in ? u.y : 0u; a[2] = in ? u.z : 0u; a[3] = in ? u.w : 0u;
+    if constexpr (PAIR) {
+      const uint4 q = *reinterpret_cast<const uint4*>(in_lo + off);
+      al[0] = in ? q.x : 0u; al[1] = in ? q.y : 0u; al[2] = in ? q.z : 0u; al[3] = in ? q.w : 0u;
+    } else {
+      al[0] = al[1] = al[2] = al[3] = 0u;
+    }
+  } else {
+    // 4 channels per tap: k = kk .. kk + 7 are taps kk / 4 and kk / 4 + 1
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = kk / 4 + h;
+      const int ky = t / 3, kx = t - ky * 3;
+      const int y = 2 * yo + ky - 1, x = 2 * xo + kx - 1;
+      const bool in = rv && t < 9 && y >= 0 && y < H && x >= 0 && x < W;
+      const uint2 u = *reinterpret_cast<const uint2*>(in_hi + (in ? (y * W + x) * 4 : 0));
+      a[2 * h] = in ? u.x : 0u;
+      a[2 * h + 1] = in ? u.y : 0u;
+    }
+    al[0] = al[1] = al[2] = al[3] = 0u;
+  }
+}
+
+// 32 x 32 output tile (rows i = output pixels 32 tm .., columns = the
+// channels of b) over the k steps of b: activation fragments gathered from
+// LDS in groups of 6 steps, then their products.
+template <int C, bool PAIR, int NS>
+__device__ __forceinline__ f32x16 conv_tile(const uint16_t* in_hi, const uint16_t* in_lo, int H, int W, int Wo,
+                                            int M, int K, int tm, int kbeg, int kend, int lane,
+                                            const uint32_t (&b)[NS][4]) {
+  constexpr int G = 6;
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  const int r = tm * 32 + (lane & 31);
+  const bool rv = r < M;
+  const int yo = rv ? r / Wo : 0, xo = rv ? r - (r / Wo) * Wo : 0;
+#pragma unroll
+  for (int s0 = 0; s0 < NS; s0 += G) {
+    uint32_t a[G][4], al[G][4];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int ks = kbeg + 16 * (s0 + g);
+      if (s0 + g < NS) conv_afrag<C, PAIR>(in_hi, in_lo, H, W, rv && ks < kend, yo, xo, K, ks + 8 * (lane >> 5), a[g], al[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (s0 + g < NS && kbeg + 16 * (s0 + g) < kend) {
+        bf16x8 fa, fb;
+        __builtin_memcpy(&fa, a[g], sizeof(fa));
+        __builtin_memcpy(&fb, b[s0 + g], sizeof(fb));
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc, 0, 0, 0);
+        if constexpr (PAIR) {
+          bf16x8 fl;
+          __builtin_memcpy(&fl, al[g], sizeof(fl));
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl, fb, acc, 0, 0, 0);
+        }
+      }
+    }
+  }
+  return acc;
+}
+
+// Bias, ReLU and the bf16 pair of a tile's outputs (row pitch N; bj: this
+// lane's column's bias).
+__device__ __forceinline__ void conv_tile_out(const f32x16& acc, int tm, int tn, int M, int N, float bj, uint16_t* hi,
+                                              uint16_t* lo, int lane) {
+  const int j = tn * 32 + (lane & 31);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = tm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    if (i < M) {
+      const float x = fmaxf(acc[v] + bj, 0.f);
+      const uint16_t h = f2bf(x);
+      hi[i * N + j] = h;
+      lo[i * N + j] = f2bf(x - bf2f(h));
+    }
+  }
+}
+
+constexpr int kStackThreads = 512;
+constexpr int kStackWaves = kStackThreads / 64;
+constexpr int kStackSteps1 = 3;    // first convolution: K = 36
+constexpr int kStackSteps2 = 18;   // second: K = 9 c1 <= 288
+constexpr int kStackSteps3 = 9;    // third: a wave's share of K = 9 c2
+constexpr int kStackC1 = 32;       // first layer's output channels (the second's input)
+
+// First two convolutions of one frame (block b): x [S][S][4] FP32 -> bf16 in
+// LDS -> conv1 pair in LDS -> conv2 pair to a2 (hi at b M2 c2, lo a2_lo on).
+// A wave keeps one output channel tile per layer (the channel tile counts
+// divide the wave count), so its weight fragments and biases are loaded once,
+// at the start, beside the input.
+__global__ __launch_bounds__(kStackThreads) void conv12_kernel(const float* __restrict__ x, int S,
+                                                              const uint16_t* __restrict__ w1, const float* __restrict__ b1,
+                                                              int c1, const uint16_t* __restrict__ w2,
+                                                              const float* __restrict__ b2, int c2,
+                                                              uint16_t* __restrict__ a2, long a2_lo) {
+  extern __shared__ __align__(16) uint16_t lds[];
+  const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2;
+  const int M1 = S1 * S1, M2 = S2 * S2;
+  const int nx = S * S * 4;
+  uint16_t* xin = lds;
+  uint16_t* a1h = lds + ((nx + 7) & ~7);
+  uint16_t* a1l = a1h + M1 * c1;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const size_t b = blockIdx.x;
+  const int nt1 = c1 / 32, nt2 = c2 / 32;
+  const int tn1 = wave % nt1, tn2 = wave % nt2;
+  uint32_t wf1[kStackSteps1][4], wf2[kStackSteps2][4];
+  conv_wfrags<true, kStackSteps1>(w1, 36, tn1, 0, 36, lane, wf1);
+  conv_wfrags<false, kStackSteps2>(w2, 9 * c1, tn2, 0, 9 * c1, lane, wf2);
+  const float bias1 = b1[tn1 * 32 + (lane & 31)], bias2 = b2[tn2 * 32 + (lane & 31)];
+  {
+    // float4 loads (nx a multiple of 4, x 16-byte aligned), all issued before the conversions
+    constexpr int U = 4;
+    const float4* xf = reinterpret_cast<const float4*>(x + b * (size_t)nx);
+    const int n4 = nx / 4;
+    for (int i0 = tid; i0 < n4; i0 += kStackThreads * U) {
+      float4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kStackThreads;
+        if (i < n4) v[u] = xf[i];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * kStackThreads;
+        if (i < n4)
+          *reinterpret_cast<uint2*>(xin + 4 * i) =
+              make_uint2((uint32_t)f2bf(v[u].x) | ((uint32_t)f2bf(v[u].y) << 16),
+                         (uint32_t)f2bf(v[u].z) | ((uint32_t)f2bf(v[u].w) << 16));
+      }
+    }
+  }
+  __syncthreads();
+  const int tiles1 = (M1 + 31) / 32 * nt1;
+  for (int t = wave; t < tiles1; t += kStackWaves) {
+    const int tm = t / nt1;
+    const f32x16 acc = conv_tile<4, false, kStackSteps1>(xin, nullptr, S, S, S1, M1, 36, tm, 0, 36, lane, wf1);
+    conv_tile_out(acc, tm, tn1, M1, c1, bias1, a1h, a1l, lane);
+  }
+  __syncthreads();
+  const int tiles2 = (M2 + 31) / 32 * nt2;
+  uint16_t* oh = a2 + b * (size_t)M2 * c2;
+  for (int t = wave; t < tiles2; t += kStackWaves) {
+    const int tm = t / nt2;
+    const f32x16 acc = conv_tile<kStackC1, true, kStackSteps2>(a1h, a1l, S1, S1, S2, M2, 9 * kStackC1, tm, 0,
+                                                               9 * kStackC1, lane, wf2);
+    conv_tile_out(acc, tm, tn2, M2, c2, bias2, oh, oh + a2_lo, lane);
+  }
+}
+
+// Third convolution of one frame: a2 pair staged in LDS, K split over the
+// waves that the tiles leave free (partial accumulators added in a fixed
+// order through LDS), output pair to a3 (hi at b M3 c3, lo a3_lo on).
+// Wave w takes tile w mod T and the w / T-th share of the k steps (T tiles,
+// nq = waves / T shares, at most kStackSteps3 steps each).
+__global__ __launch_bounds__(kStackThreads) void conv3_kernel(const uint16_t* __restrict__ a2, long a2_lo, int S2, int c2,
+                                                             const uint16_t* __restrict__ w3,
+                                                             const float* __restrict__ b3, int c3,
+                                                             uint16_t* __restrict__ a3, long a3_lo) {
+  extern __shared__ __align__(16) uint16_t lds[];
+  const int S3 = (S2 + 1) / 2, M2 = S2 * S2, M3 = S3 * S3;
+  const int n2 = M2 * c2;
+  uint16_t* ih = lds;
+  uint16_t* il = lds + n2;
+  float* part = reinterpret_cast<float*>(lds + 2 * ((n2 + 7) & ~7));
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const size_t b = blockIdx.x;
+  const int K = 9 * c2;
+  const int nt3 = c3 / 32, tiles3 = (M3 + 31) / 32 * nt3;
+  const int nq = kStackWaves / tiles3;
+  const int ksteps = (K + 15) / 16, kq = (ksteps + nq - 1) / nq * 16;
+  const int t = wave % tiles3, q = wave / tiles3;
+  const bool active = q < nq;
+  const int tm = t / nt3, tn = t - tm * nt3;
+  const int kb = active ? q * kq : 0, ke = active ? min(K, (q + 1) * kq) : 0;
+  uint32_t wf[kStackSteps3][4];
+  conv_wfrags<false, kStackSteps3>(w3, K, tn, kb, ke, lane, wf);
+  const float bias = b3[tn * 32 + (lane & 31)];
+  {
+    // two words of each plane per thread and pass, all four loads issued first
+    const uint4* sh = reinterpret_cast<const uint4*>(a2 + b * (size_t)n2);
+    const uint4* sl = reinterpret_cast<const uint4*>(a2 + a2_lo + b * (size_t)n2);
+    const int n16 = n2 / 8;
+    for (int i0 = tid; i0 < n16; i0 += 2 * kStackThreads) {
+      const int i1 = min(i0 + kStackThreads, n16 - 1);   // past the end: reload the last word
+      const uint4 h0 = sh[i0], l0 = sl[i0], h1 = sh[i1], l1 = sl[i1];
+      reinterpret_cast<uint4*>(ih)[i0] = h0;
+      reinterpret_cast<uint4*>(il)[i0] = l0;
+      reinterpret_cast<uint4*>(ih)[i1] = h1;
+      reinterpret_cast<uint4*>(il)[i1] = l1;
+    }
+  }
+  __syncthreads();
+  uint16_t* oh = a3 + b * (size_t)M3 * c3;
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  if (active) {
+    if (c2 == 32)
+      acc = conv_tile<32, true, kStackSteps3>(ih, il, S2, S2, S3, M3, K, tm, kb, ke, lane, wf);
+    else
+      acc = conv_tile<64, true, kStackSteps3>(ih, il, S2, S2, S3, M3, K, tm, kb, ke, lane, wf);
+  }
+  if (active && q > 0) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) part[((q * tiles3 + t) * 16 + v) * 64 + lane] = acc[v];
+  }
+  __syncthreads();
+  if (active && q == 0) {
+    for (int qq = 1; qq < nq; ++qq) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] += part[((qq * tiles3 + t) * 16 + v) * 64 + lane];
+    }
+    conv_tile_out(acc, tm, tn, M3, c3, bias, oh, oh + a3_lo, lane);
+  }
+}
+
+static size_t conv12_lds(int S, int c1) {
+  const int S1 = (S + 1) / 2;
+  return ((size_t)((S * S * 4 + 7) & ~7) + (size_t)2 * S1 * S1 * c1) * sizeof(uint16_t);
+}
+static size_t conv3_lds(int S2, int c2, int c3) {
+  const int S3 = (S2 + 1) / 2;
+  const int tiles3 = (S3 * S3 + 31) / 32 * (c3 / 32);
+  const int nq = tiles3 >= 1 && tiles3 <= kStackWaves ? kStackWaves / tiles3 : 1;
+  return (size_t)2 * ((S2 * S2 * c2 + 7) & ~7) * sizeof(uint16_t) + (size_t)nq * tiles3 * 1024 * sizeof(float);
+}
+
+bool conv_stack_fits(int S, int c1, int c2, int c3) {
+  constexpr size_t kMaxLds = 65536;
+  if (S < 2 || c1 < 32 || c2 < 32 || c3 < 32 || c1 % 32 || c2 % 32 || c3 % 32) return false;
+  const int nt1 = c1 / 32, nt2 = c2 / 32;
+  if (kStackWaves % nt1 || kStackWaves % nt2) return false;            // one channel tile per wave
+  if (c1 != kStackC1 || (c2 != 32 && c2 != 64)) return false;          // compile-time input channel counts
+  if ((9 * c1 + 15) / 16 > kStackSteps2) return false;                  // second layer's k steps
+  const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2, S3 = (S2 + 1) / 2;
+  const int tiles3 = (S3 * S3 + 31) / 32 * (c3 / 32);
+  if (tiles3 > kStackWaves) return false;
+  const int nq = kStackWaves / tiles3, ksteps3 = (9 * c2 + 15) / 16;
+  if ((ksteps3 + nq - 1) / nq > kStackSteps3) return false;             // a wave's share of the third layer's
+  return conv12_lds(S, c1) <= kMaxLds && conv3_lds(S2, c2, c3) <= kMaxLds && (size_t)S * S * 4 < ((size_t)1 << 30);
+}
+
+hipError_t conv_stack(const float* x, int B, int S, const uint16_t* w1, const float* b1, int c1, const uint16_t* w2,
+                      const float* b2, int c2, uint16_t* a2, long a2_lo, const uint16_t* w3, const float* b3, int c3,
+                      uint16_t* a3, long a3_lo, hipStream_t st) {
+  auto al = [](const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; };
+  if (B < 1 || B > 65535 || !conv_stack_fits(S, c1, c2, c3) || !al(x, 16) || !al(w1, 8) || !al(w2, 16) || !al(w3, 16) ||
+      !al(a2, 16) || a2_lo % 8 != 0)
+    return hipErrorNotSupported;
+  const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2;
+  hipLaunchKernelGGL(conv12_kernel, dim3(B), dim3(kStackThreads), conv12_lds(S, c1), st, x, S, w1, b1, c1, w2, b2, c2,
+                     a2, a2_lo);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(conv3_kernel, dim3(B), dim3(kStackThreads), conv3_lds(S2, c2, c3), st, (const uint16_t*)a2,
+                     a2_lo, S2, c2, w3, b3, c3, a3, a3_lo);
+  return hipGetLastError();
+}
+
 hipError_t prepare(const float* pupils, const float* ref, const int* valid, int nv, int B, int S, float* x,
                    hipStream_t st) {
   hipLaunchKernelGGL(prepare_kernel, dim3(B), dim3(256), 0, st, pupils, ref, valid, nv, S, x);
