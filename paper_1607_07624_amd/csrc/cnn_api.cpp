@@ -212,9 +212,8 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
   const uint16_t* Wb = n->wb;
   const int R1 = B * n->S1 * n->S1, R2 = B * n->S2 * n->S2, R3 = B * n->S3 * n->S3;
   const hipError_t cs = inference ? pwfs::cnn::conv_stack(x, B, n->S, Wb + n->off[0], W + n->off[1], n->c1,
-                                                          Wb + n->off[2], W + n->off[3], n->c2, n->a2,
-                                                          (long)R2 * n->c2, Wb + n->off[4], W + n->off[5], n->c3,
-                                                          n->a3, (long)R3 * n->c3, st)
+                                                          Wb + n->off[2], W + n->off[3], n->c2, Wb + n->off[4],
+                                                          W + n->off[5], n->c3, n->a3, (long)R3 * n->c3, st)
                                   : hipErrorNotSupported;
   if (cs != hipSuccess && cs != hipErrorNotSupported) return hip_fail(cs, "cnn convolution stack");
   if (cs == hipSuccess) return run_dense(n, B, st, out, out_alpha, out_beta);

@@ -1212,31 +1212,52 @@ constexpr int kStackSteps2 = 18;   // second: K = 9 c1 <= 288
 constexpr int kStackSteps3 = 9;    // third: a wave's share of K = 9 c2
 constexpr int kStackC1 = 32;       // first layer's output channels (the second's input)
 
-// First two convolutions of one frame (block b): x [S][S][4] FP32 -> bf16 in
-// LDS -> conv1 pair in LDS -> conv2 pair to a2 (hi at b M2 c2, lo a2_lo on).
-// A wave keeps one output channel tile per layer (the channel tile counts
-// divide the wave count), so its weight fragments and biases are loaded once,
-// at the start, beside the input.
-__global__ __launch_bounds__(kStackThreads) void conv12_kernel(const float* __restrict__ x, int S,
-                                                              const uint16_t* __restrict__ w1, const float* __restrict__ b1,
-                                                              int c1, const uint16_t* __restrict__ w2,
-                                                              const float* __restrict__ b2, int c2,
-                                                              uint16_t* __restrict__ a2, long a2_lo) {
+// The three convolutions of one frame (block b).  LDS (elements of 16 bits):
+// the input x [S][S][4] rounded to bf16, then the first convolution's
+// output pair; once the second convolution has read them (each wave keeps
+// its one output tile of that layer in registers across a barrier), the
+// second layer's output pair is written at the end of the LDS and the third
+// layer's partial accumulators at its start.  Output: the third layer's pair
+// to a3 (hi at b M3 c3, lo a3_lo on).  A wave keeps one output channel tile
+// per layer (the channel tile counts divide the wave count), so its weight
+// fragments and biases of all three layers are loaded once, beside the input.
+// The third layer's K is split over the waves its tiles leave free: wave w
+// takes tile w mod T3 and the (w / T3)-th share of the k steps, and the
+// shares are added in a fixed order.
+__global__ __launch_bounds__(kStackThreads) void conv_stack_kernel(const float* __restrict__ x, int S,
+                                                                  const uint16_t* __restrict__ w1,
+                                                                  const float* __restrict__ b1, int c1,
+                                                                  const uint16_t* __restrict__ w2,
+                                                                  const float* __restrict__ b2, int c2,
+                                                                  const uint16_t* __restrict__ w3,
+                                                                  const float* __restrict__ b3, int c3,
+                                                                  uint16_t* __restrict__ a3, long a3_lo, int lds_elems) {
   extern __shared__ __align__(16) uint16_t lds[];
-  const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2;
-  const int M1 = S1 * S1, M2 = S2 * S2;
-  const int nx = S * S * 4;
+  const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2, S3 = (S2 + 1) / 2;
+  const int M1 = S1 * S1, M2 = S2 * S2, M3 = S3 * S3;
+  const int nx = S * S * 4, n2 = M2 * c2;
   uint16_t* xin = lds;
   uint16_t* a1h = lds + ((nx + 7) & ~7);
   uint16_t* a1l = a1h + M1 * c1;
+  uint16_t* a2h = lds + (lds_elems - 2 * n2);   // after the second convolution
+  uint16_t* a2l = a2h + n2;
+  float* part = reinterpret_cast<float*>(lds);   // after the second convolution
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const size_t b = blockIdx.x;
-  const int nt1 = c1 / 32, nt2 = c2 / 32;
+  const int nt1 = c1 / 32, nt2 = c2 / 32, nt3 = c3 / 32;
   const int tn1 = wave % nt1, tn2 = wave % nt2;
-  uint32_t wf1[kStackSteps1][4], wf2[kStackSteps2][4];
+  const int K3 = 9 * c2, tiles3 = (M3 + 31) / 32 * nt3, nq = kStackWaves / tiles3;
+  const int kq = ((K3 + 15) / 16 + nq - 1) / nq * 16;
+  const int t3 = wave % tiles3, q3 = wave / tiles3;
+  const bool act3 = q3 < nq;
+  const int tm3 = t3 / nt3, tn3 = t3 - tm3 * nt3;
+  const int kb3 = act3 ? q3 * kq : 0, ke3 = act3 ? min(K3, (q3 + 1) * kq) : 0;
+  uint32_t wf1[kStackSteps1][4], wf2[kStackSteps2][4], wf3[kStackSteps3][4];
   conv_wfrags<true, kStackSteps1>(w1, 36, tn1, 0, 36, lane, wf1);
-  conv_wfrags<false, kStackSteps2>(w2, 9 * c1, tn2, 0, 9 * c1, lane, wf2);
+  conv_wfrags<false, kStackSteps2>(w2, 9 * kStackC1, tn2, 0, 9 * kStackC1, lane, wf2);
+  conv_wfrags<false, kStackSteps3>(w3, K3, tn3, kb3, ke3, lane, wf3);
   const float bias1 = b1[tn1 * 32 + (lane & 31)], bias2 = b2[tn2 * 32 + (lane & 31)];
+  const float bias3 = b3[tn3 * 32 + (lane & 31)];
   {
     // float4 loads (nx a multiple of 4, x 16-byte aligned), all issued before the conversions
     constexpr int U = 4;
@@ -1260,6 +1281,7 @@ __global__ __launch_bounds__(kStackThreads) void conv12_kernel(const float* __re
     }
   }
   __syncthreads();
+  // first convolution -> LDS
   const int tiles1 = (M1 + 31) / 32 * nt1;
   for (int t = wave; t < tiles1; t += kStackWaves) {
     const int tm = t / nt1;
@@ -1267,123 +1289,81 @@ __global__ __launch_bounds__(kStackThreads) void conv12_kernel(const float* __re
     conv_tile_out(acc, tm, tn1, M1, c1, bias1, a1h, a1l, lane);
   }
   __syncthreads();
+  // second convolution: one tile per wave (at most kStackWaves tiles), kept in registers
   const int tiles2 = (M2 + 31) / 32 * nt2;
-  uint16_t* oh = a2 + b * (size_t)M2 * c2;
-  for (int t = wave; t < tiles2; t += kStackWaves) {
-    const int tm = t / nt2;
-    const f32x16 acc = conv_tile<kStackC1, true, kStackSteps2>(a1h, a1l, S1, S1, S2, M2, 9 * kStackC1, tm, 0,
-                                                               9 * kStackC1, lane, wf2);
-    conv_tile_out(acc, tm, tn2, M2, c2, bias2, oh, oh + a2_lo, lane);
-  }
-}
-
-// Third convolution of one frame: a2 pair staged in LDS, K split over the
-// waves that the tiles leave free (partial accumulators added in a fixed
-// order through LDS), output pair to a3 (hi at b M3 c3, lo a3_lo on).
-// Wave w takes tile w mod T and the w / T-th share of the k steps (T tiles,
-// nq = waves / T shares, at most kStackSteps3 steps each).
-__global__ __launch_bounds__(kStackThreads) void conv3_kernel(const uint16_t* __restrict__ a2, long a2_lo, int S2, int c2,
-                                                             const uint16_t* __restrict__ w3,
-                                                             const float* __restrict__ b3, int c3,
-                                                             uint16_t* __restrict__ a3, long a3_lo) {
-  extern __shared__ __align__(16) uint16_t lds[];
-  const int S3 = (S2 + 1) / 2, M2 = S2 * S2, M3 = S3 * S3;
-  const int n2 = M2 * c2;
-  uint16_t* ih = lds;
-  uint16_t* il = lds + n2;
-  float* part = reinterpret_cast<float*>(lds + 2 * ((n2 + 7) & ~7));
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const size_t b = blockIdx.x;
-  const int K = 9 * c2;
-  const int nt3 = c3 / 32, tiles3 = (M3 + 31) / 32 * nt3;
-  const int nq = kStackWaves / tiles3;
-  const int ksteps = (K + 15) / 16, kq = (ksteps + nq - 1) / nq * 16;
-  const int t = wave % tiles3, q = wave / tiles3;
-  const bool active = q < nq;
-  const int tm = t / nt3, tn = t - tm * nt3;
-  const int kb = active ? q * kq : 0, ke = active ? min(K, (q + 1) * kq) : 0;
-  uint32_t wf[kStackSteps3][4];
-  conv_wfrags<false, kStackSteps3>(w3, K, tn, kb, ke, lane, wf);
-  const float bias = b3[tn * 32 + (lane & 31)];
-  {
-    // two words of each plane per thread and pass, all four loads issued first
-    const uint4* sh = reinterpret_cast<const uint4*>(a2 + b * (size_t)n2);
-    const uint4* sl = reinterpret_cast<const uint4*>(a2 + a2_lo + b * (size_t)n2);
-    const int n16 = n2 / 8;
-    for (int i0 = tid; i0 < n16; i0 += 2 * kStackThreads) {
-      const int i1 = min(i0 + kStackThreads, n16 - 1);   // past the end: reload the last word
-      const uint4 h0 = sh[i0], l0 = sl[i0], h1 = sh[i1], l1 = sl[i1];
-      reinterpret_cast<uint4*>(ih)[i0] = h0;
-      reinterpret_cast<uint4*>(il)[i0] = l0;
-      reinterpret_cast<uint4*>(ih)[i1] = h1;
-      reinterpret_cast<uint4*>(il)[i1] = l1;
-    }
-  }
-  __syncthreads();
-  uint16_t* oh = a3 + b * (size_t)M3 * c3;
-  f32x16 acc;
+  const int tm2 = wave / nt2;
+  f32x16 acc2;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  if (active) {
+  for (int v = 0; v < 16; ++v) acc2[v] = 0.f;
+  if (wave < tiles2)
+    acc2 = conv_tile<kStackC1, true, kStackSteps2>(a1h, a1l, S1, S1, S2, M2, 9 * kStackC1, tm2, 0, 9 * kStackC1, lane,
+                                                   wf2);
+  __syncthreads();   // x and the first activation are dead from here
+  if (wave < tiles2) conv_tile_out(acc2, tm2, tn2, M2, c2, bias2, a2h, a2l, lane);
+  __syncthreads();
+  // third convolution: shares of K, partials through LDS, output pair to HBM
+  f32x16 acc3;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc3[v] = 0.f;
+  if (act3) {
     if (c2 == 32)
-      acc = conv_tile<32, true, kStackSteps3>(ih, il, S2, S2, S3, M3, K, tm, kb, ke, lane, wf);
+      acc3 = conv_tile<32, true, kStackSteps3>(a2h, a2l, S2, S2, S3, M3, K3, tm3, kb3, ke3, lane, wf3);
     else
-      acc = conv_tile<64, true, kStackSteps3>(ih, il, S2, S2, S3, M3, K, tm, kb, ke, lane, wf);
+      acc3 = conv_tile<64, true, kStackSteps3>(a2h, a2l, S2, S2, S3, M3, K3, tm3, kb3, ke3, lane, wf3);
   }
-  if (active && q > 0) {
+  if (act3 && q3 > 0) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) part[((q * tiles3 + t) * 16 + v) * 64 + lane] = acc[v];
+    for (int v = 0; v < 16; ++v) part[((q3 * tiles3 + t3) * 16 + v) * 64 + lane] = acc3[v];
   }
   __syncthreads();
-  if (active && q == 0) {
+  if (act3 && q3 == 0) {
     for (int qq = 1; qq < nq; ++qq) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] += part[((qq * tiles3 + t) * 16 + v) * 64 + lane];
+      for (int v = 0; v < 16; ++v) acc3[v] += part[((qq * tiles3 + t3) * 16 + v) * 64 + lane];
     }
-    conv_tile_out(acc, tm, tn, M3, c3, bias, oh, oh + a3_lo, lane);
+    uint16_t* oh = a3 + b * (size_t)M3 * c3;
+    conv_tile_out(acc3, tm3, tn3, M3, c3, bias3, oh, oh + a3_lo, lane);
   }
 }
 
-static size_t conv12_lds(int S, int c1) {
-  const int S1 = (S + 1) / 2;
-  return ((size_t)((S * S * 4 + 7) & ~7) + (size_t)2 * S1 * S1 * c1) * sizeof(uint16_t);
-}
-static size_t conv3_lds(int S2, int c2, int c3) {
-  const int S3 = (S2 + 1) / 2;
+// LDS of the kernel (elements of 16 bits): input and first activation pair,
+// which the second activation pair (at the end) and the third layer's
+// partials (at the start, floats) reuse.
+static int conv_stack_lds_elems(int S, int c1, int c2, int c3) {
+  const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2, S3 = (S2 + 1) / 2;
   const int tiles3 = (S3 * S3 + 31) / 32 * (c3 / 32);
-  const int nq = tiles3 >= 1 && tiles3 <= kStackWaves ? kStackWaves / tiles3 : 1;
-  return (size_t)2 * ((S2 * S2 * c2 + 7) & ~7) * sizeof(uint16_t) + (size_t)nq * tiles3 * 1024 * sizeof(float);
+  const int nq = kStackWaves / tiles3;
+  const int first = ((S * S * 4 + 7) & ~7) + 2 * S1 * S1 * c1;
+  const int later = 2 * nq * tiles3 * 1024 + 2 * S2 * S2 * c2;    // partials (2 elements per float) + second pair
+  return (std::max(first, later) + 7) & ~7;
 }
 
 bool conv_stack_fits(int S, int c1, int c2, int c3) {
-  constexpr size_t kMaxLds = 65536;
-  if (S < 2 || c1 < 32 || c2 < 32 || c3 < 32 || c1 % 32 || c2 % 32 || c3 % 32) return false;
+  constexpr int kMaxLdsElems = 65536 / 2;
+  if (S < 2 || S > 256 || c1 != kStackC1 || (c2 != 32 && c2 != 64) || c3 < 32 || c3 % 32) return false;
   const int nt1 = c1 / 32, nt2 = c2 / 32;
   if (kStackWaves % nt1 || kStackWaves % nt2) return false;            // one channel tile per wave
-  if (c1 != kStackC1 || (c2 != 32 && c2 != 64)) return false;          // compile-time input channel counts
   if ((9 * c1 + 15) / 16 > kStackSteps2) return false;                  // second layer's k steps
   const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2, S3 = (S2 + 1) / 2;
+  if ((S2 * S2 + 31) / 32 * nt2 > kStackWaves) return false;           // second layer: one tile per wave
   const int tiles3 = (S3 * S3 + 31) / 32 * (c3 / 32);
   if (tiles3 > kStackWaves) return false;
   const int nq = kStackWaves / tiles3, ksteps3 = (9 * c2 + 15) / 16;
   if ((ksteps3 + nq - 1) / nq > kStackSteps3) return false;             // a wave's share of the third layer's
-  return conv12_lds(S, c1) <= kMaxLds && conv3_lds(S2, c2, c3) <= kMaxLds && (size_t)S * S * 4 < ((size_t)1 << 30);
+  if (2 * nq * tiles3 * 1024 + 2 * S2 * S2 * c2 > conv_stack_lds_elems(S, c1, c2, c3)) return false;
+  return conv_stack_lds_elems(S, c1, c2, c3) <= kMaxLdsElems;
 }
 
 hipError_t conv_stack(const float* x, int B, int S, const uint16_t* w1, const float* b1, int c1, const uint16_t* w2,
-                      const float* b2, int c2, uint16_t* a2, long a2_lo, const uint16_t* w3, const float* b3, int c3,
-                      uint16_t* a3, long a3_lo, hipStream_t st) {
+                      const float* b2, int c2, const uint16_t* w3, const float* b3, int c3, uint16_t* a3, long a3_lo,
+                      hipStream_t st) {
   auto al = [](const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; };
-  if (B < 1 || B > 65535 || !conv_stack_fits(S, c1, c2, c3) || !al(x, 16) || !al(w1, 8) || !al(w2, 16) || !al(w3, 16) ||
-      !al(a2, 16) || a2_lo % 8 != 0)
+  if (B < 1 || B > 65535 || !conv_stack_fits(S, c1, c2, c3) || !al(x, 16) || !al(w1, 8) || !al(w2, 16) ||
+      !al(w3, 16))
     return hipErrorNotSupported;
-  const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2;
-  hipLaunchKernelGGL(conv12_kernel, dim3(B), dim3(kStackThreads), conv12_lds(S, c1), st, x, S, w1, b1, c1, w2, b2, c2,
-                     a2, a2_lo);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(conv3_kernel, dim3(B), dim3(kStackThreads), conv3_lds(S2, c2, c3), st, (const uint16_t*)a2,
-                     a2_lo, S2, c2, w3, b3, c3, a3, a3_lo);
+  const int le = conv_stack_lds_elems(S, c1, c2, c3);
+  hipLaunchKernelGGL(conv_stack_kernel, dim3(B), dim3(kStackThreads), (size_t)le * sizeof(uint16_t), st, x, S, w1, b1,
+                     c1, w2, b2, c2, w3, b3, c3, a3, a3_lo, le);
   return hipGetLastError();
 }
 

@@ -76,16 +76,17 @@ hipError_t mse_sum(const float* part, int n, float* loss, hipStream_t st);
 hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, const ConvPerm& cp, size_t n, float lr,
                 float b1, float b2, float eps, float c1, float c2, hipStream_t st);
 hipError_t fill0(float* p, size_t n, hipStream_t st);
-// The three convolutions of a forward-only call, one block per frame (few
-// frames): x [B][S][S][4] FP32 -> a2 pair (lo plane a2_lo on) -> a3 pair
-// (lo plane a3_lo on), bf16 weights in patch order.  hipErrorNotSupported
-// (nothing launched) when the shapes are outside the kernel's limits:
-// channel counts multiples of 32, the staged activations within 64 KiB of
-// LDS, a 16-byte aligned input and weights of the second and third layers.
+// The three convolutions of a forward-only call, one block per frame:
+// x [B][S][S][4] FP32 -> a3 pair (lo plane a3_lo on), bf16 weights in patch
+// order.  hipErrorNotSupported (nothing launched) when the shapes are
+// outside the kernel's limits: 32 first-layer and 32 or 64 second-layer
+// channels, a multiple of 32 in the third, the staged activations within
+// 64 KiB of LDS, a 16-byte aligned input and weights of the second and
+// third layers.
 bool conv_stack_fits(int S, int c1, int c2, int c3);
 hipError_t conv_stack(const float* x, int B, int S, const uint16_t* w1, const float* b1, int c1, const uint16_t* w2,
-                      const float* b2, int c2, uint16_t* a2, long a2_lo, const uint16_t* w3, const float* b3, int c3,
-                      uint16_t* a3, long a3_lo, hipStream_t st);
+                      const float* b2, int c2, const uint16_t* w3, const float* b3, int c3, uint16_t* a3, long a3_lo,
+                      hipStream_t st);
 hipError_t prepare(const float* pupils, const float* ref, const int* valid, int nv, int B, int S, float* x,
                    hipStream_t st);
 
