@@ -202,19 +202,24 @@ int run_dense(pwfs_cnn_s* n, int B, hipStream_t st, float* out, float out_alpha,
   return 0;
 }
 
-// Forward pass.  A training step keeps every layer's activations for the
-// backward pass; a forward-only call (inference) runs the three
-// convolutions as one block per frame (pwfs::cnn::conv_stack) when the
-// shapes allow it, which keeps only the third convolution's output.
+// Forward pass: the three convolutions as one block per frame
+// (pwfs::cnn::conv_stack) when the shapes allow it, else a patch gather and
+// a tiled product per layer; a training step keeps every activation its
+// backward pass reads, a forward-only call (inference) only the third
+// convolution's output.
 int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out = nullptr,
                 float out_alpha = 1.f, float out_beta = 0.f, bool inference = false) {
   const float* W = n->w;
   const uint16_t* Wb = n->wb;
   const int R1 = B * n->S1 * n->S1, R2 = B * n->S2 * n->S2, R3 = B * n->S3 * n->S3;
-  const hipError_t cs = inference ? pwfs::cnn::conv_stack(x, B, n->S, Wb + n->off[0], W + n->off[1], n->c1,
-                                                          Wb + n->off[2], W + n->off[3], n->c2, Wb + n->off[4],
-                                                          W + n->off[5], n->c3, n->a3, (long)R3 * n->c3, st)
-                                  : hipErrorNotSupported;
+  // the convolutions as one block per frame; a training step also keeps the
+  // first layer's patches and the first two activation pairs (its backward
+  // pass reads the second and third layers' patches from them)
+  const bool keep = !inference;
+  const hipError_t cs = pwfs::cnn::conv_stack(
+      x, B, n->S, Wb + n->off[0], W + n->off[1], n->c1, Wb + n->off[2], W + n->off[3], n->c2, Wb + n->off[4],
+      W + n->off[5], n->c3, n->a3, (long)R3 * n->c3, st, keep ? n->cols1 : nullptr, keep ? n->a1 : nullptr,
+      (long)R1 * n->c1, keep ? n->a2 : nullptr, (long)R2 * n->c2);
   if (cs != hipSuccess && cs != hipErrorNotSupported) return hip_fail(cs, "cnn convolution stack");
   if (cs == hipSuccess) return run_dense(n, B, st, out, out_alpha, out_beta);
   CK(pwfs::cnn::im2col_f32(x, B, n->S, n->S, 4, n->cols1, st));   // input rounded to bf16 on the way

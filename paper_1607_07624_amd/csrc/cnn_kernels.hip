@@ -1221,6 +1221,9 @@ constexpr int kStackC1 = 32;       // first layer's output channels (the second'
 // to a3 (hi at b M3 c3, lo a3_lo on).  A wave keeps one output channel tile
 // per layer (the channel tile counts divide the wave count), so its weight
 // fragments and biases of all three layers are loaded once, beside the input.
+// A training step also takes the first layer's patches (cols1) and the first
+// and second activation pairs (a1g, a2g) to HBM for its backward pass (NULL:
+// not written).
 // The third layer's K is split over the waves its tiles leave free: wave w
 // takes tile w mod T3 and the (w / T3)-th share of the k steps, and the
 // shares are added in a fixed order.
@@ -1231,7 +1234,10 @@ __global__ __launch_bounds__(kStackThreads) void conv_stack_kernel(const float* 
                                                                   const float* __restrict__ b2, int c2,
                                                                   const uint16_t* __restrict__ w3,
                                                                   const float* __restrict__ b3, int c3,
-                                                                  uint16_t* __restrict__ a3, long a3_lo, int lds_elems) {
+                                                                  uint16_t* __restrict__ a3, long a3_lo, int lds_elems,
+                                                                  uint16_t* __restrict__ cols1,
+                                                                  uint16_t* __restrict__ a1g, long a1_lo,
+                                                                  uint16_t* __restrict__ a2g, long a2_lo) {
   extern __shared__ __align__(16) uint16_t lds[];
   const int S1 = (S + 1) / 2, S2 = (S1 + 1) / 2, S3 = (S2 + 1) / 2;
   const int M1 = S1 * S1, M2 = S2 * S2, M3 = S3 * S3;
@@ -1281,6 +1287,18 @@ __global__ __launch_bounds__(kStackThreads) void conv_stack_kernel(const float* 
     }
   }
   __syncthreads();
+  if (cols1) {
+    // a training step's first-layer patches [M1][9 taps][4] (its weight gradient reads them)
+    uint16_t* cb = cols1 + b * (size_t)M1 * 36;
+    for (int u = tid; u < M1 * 9; u += kStackThreads) {
+      const int r = u / 9, tap = u - r * 9;
+      const int ky = tap / 3, kx = tap - ky * 3, yo = r / S1, xo = r - yo * S1;
+      const int y = 2 * yo + ky - 1, xx = 2 * xo + kx - 1;
+      const bool in = y >= 0 && y < S && xx >= 0 && xx < S;
+      const uint2 v = *reinterpret_cast<const uint2*>(xin + (in ? (y * S + xx) * 4 : 0));
+      *reinterpret_cast<uint2*>(cb + r * 36 + tap * 4) = in ? v : make_uint2(0u, 0u);
+    }
+  }
   // first convolution -> LDS
   const int tiles1 = (M1 + 31) / 32 * nt1;
   for (int t = wave; t < tiles1; t += kStackWaves) {
@@ -1289,6 +1307,16 @@ __global__ __launch_bounds__(kStackThreads) void conv_stack_kernel(const float* 
     conv_tile_out(acc, tm, tn1, M1, c1, bias1, a1h, a1l, lane);
   }
   __syncthreads();
+  if (a1g) {
+    // a training step keeps the first activation pair (16-byte copies, M1 c1 a multiple of 8)
+    const int n16 = M1 * c1 / 8;
+    uint4* dh = reinterpret_cast<uint4*>(a1g + b * (size_t)M1 * c1);
+    uint4* dl = reinterpret_cast<uint4*>(a1g + a1_lo + b * (size_t)M1 * c1);
+    for (int i = tid; i < n16; i += kStackThreads) {
+      dh[i] = reinterpret_cast<const uint4*>(a1h)[i];
+      dl[i] = reinterpret_cast<const uint4*>(a1l)[i];
+    }
+  }
   // second convolution: one tile per wave (at most kStackWaves tiles), kept in registers
   const int tiles2 = (M2 + 31) / 32 * nt2;
   const int tm2 = wave / nt2;
@@ -1301,6 +1329,15 @@ __global__ __launch_bounds__(kStackThreads) void conv_stack_kernel(const float* 
   __syncthreads();   // x and the first activation are dead from here
   if (wave < tiles2) conv_tile_out(acc2, tm2, tn2, M2, c2, bias2, a2h, a2l, lane);
   __syncthreads();
+  if (a2g) {
+    const int n16 = n2 / 8;
+    uint4* dh = reinterpret_cast<uint4*>(a2g + b * (size_t)n2);
+    uint4* dl = reinterpret_cast<uint4*>(a2g + a2_lo + b * (size_t)n2);
+    for (int i = tid; i < n16; i += kStackThreads) {
+      dh[i] = reinterpret_cast<const uint4*>(a2h)[i];
+      dl[i] = reinterpret_cast<const uint4*>(a2l)[i];
+    }
+  }
   // third convolution: shares of K, partials through LDS, output pair to HBM
   f32x16 acc3;
 #pragma unroll
@@ -1356,14 +1393,14 @@ bool conv_stack_fits(int S, int c1, int c2, int c3) {
 
 hipError_t conv_stack(const float* x, int B, int S, const uint16_t* w1, const float* b1, int c1, const uint16_t* w2,
                       const float* b2, int c2, const uint16_t* w3, const float* b3, int c3, uint16_t* a3, long a3_lo,
-                      hipStream_t st) {
+                      hipStream_t st, uint16_t* cols1, uint16_t* a1, long a1_lo, uint16_t* a2, long a2_lo) {
   auto al = [](const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; };
   if (B < 1 || B > 65535 || !conv_stack_fits(S, c1, c2, c3) || !al(x, 16) || !al(w1, 8) || !al(w2, 16) ||
-      !al(w3, 16))
+      !al(w3, 16) || !al(cols1, 8) || !al(a1, 16) || a1_lo % 8 || !al(a2, 16) || a2_lo % 8)
     return hipErrorNotSupported;
   const int le = conv_stack_lds_elems(S, c1, c2, c3);
   hipLaunchKernelGGL(conv_stack_kernel, dim3(B), dim3(kStackThreads), (size_t)le * sizeof(uint16_t), st, x, S, w1, b1,
-                     c1, w2, b2, c2, w3, b3, c3, a3, a3_lo, le);
+                     c1, w2, b2, c2, w3, b3, c3, a3, a3_lo, le, cols1, a1, a1_lo, a2, a2_lo);
   return hipGetLastError();
 }
 

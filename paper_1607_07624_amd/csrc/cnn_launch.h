@@ -84,9 +84,13 @@ hipError_t fill0(float* p, size_t n, hipStream_t st);
 // 64 KiB of LDS, a 16-byte aligned input and weights of the second and
 // third layers.
 bool conv_stack_fits(int S, int c1, int c2, int c3);
+// cols1 [B M1][36], a1 and a2 (pairs, lo planes a1_lo / a2_lo on): the first
+// layer's patches and the first two activation pairs for a training step's
+// backward pass; NULL: not written.
 hipError_t conv_stack(const float* x, int B, int S, const uint16_t* w1, const float* b1, int c1, const uint16_t* w2,
                       const float* b2, int c2, const uint16_t* w3, const float* b3, int c3, uint16_t* a3, long a3_lo,
-                      hipStream_t st);
+                      hipStream_t st, uint16_t* cols1 = nullptr, uint16_t* a1 = nullptr, long a1_lo = 0,
+                      uint16_t* a2 = nullptr, long a2_lo = 0);
 hipError_t prepare(const float* pupils, const float* ref, const int* valid, int nv, int B, int S, float* x,
                    hipStream_t st);
 
