@@ -1176,11 +1176,14 @@ __device__ __forceinline__ f32x16 conv_tile(const uint16_t* in_hi, const uint16_
         bf16x8 fa, fb;
         __builtin_memcpy(&fa, a[g], sizeof(fa));
         __builtin_memcpy(&fb, b[s0 + g], sizeof(fb));
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, fb, acc, 0, 0, 0);
+        // weights as the first operand: the accumulator is the tile transposed
+        // (rows = channels, columns = pixels), so a lane ends up holding four
+        // consecutive channels of one pixel per group of four registers
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fb, fa, acc, 0, 0, 0);
         if constexpr (PAIR) {
           bf16x8 fl;
           __builtin_memcpy(&fl, al[g], sizeof(fl));
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl, fb, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fb, fl, acc, 0, 0, 0);
         }
       }
     }
@@ -1188,20 +1191,36 @@ __device__ __forceinline__ f32x16 conv_tile(const uint16_t* in_hi, const uint16_
   return acc;
 }
 
-// Bias, ReLU and the bf16 pair of a tile's outputs (row pitch N; bj: this
-// lane's column's bias).
-__device__ __forceinline__ void conv_tile_out(const f32x16& acc, int tm, int tn, int M, int N, float bj, uint16_t* hi,
-                                              uint16_t* lo, int lane) {
-  const int j = tn * 32 + (lane & 31);
+// Bias, ReLU and the bf16 pair of a tile's outputs (row pitch N).  Lane l
+// holds pixel 32 tm + l mod 32 and, in registers 4 g .. 4 g + 3, channels
+// 32 tn + 8 g + 4 (l / 32) .. + 3 (bias bq in the same order): one 8-byte
+// store of each plane per group.
+__device__ __forceinline__ void conv_bias4(const float* __restrict__ bias, int tn, int lane, float (&bq)[16]) {
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int i = tm * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-    if (i < M) {
-      const float x = fmaxf(acc[v] + bj, 0.f);
-      const uint16_t h = f2bf(x);
-      hi[i * N + j] = h;
-      lo[i * N + j] = f2bf(x - bf2f(h));
+  for (int g = 0; g < 4; ++g) {
+    const float4 u = *reinterpret_cast<const float4*>(bias + tn * 32 + 8 * g + 4 * (lane >> 5));
+    bq[4 * g] = u.x; bq[4 * g + 1] = u.y; bq[4 * g + 2] = u.z; bq[4 * g + 3] = u.w;
+  }
+}
+
+__device__ __forceinline__ void conv_tile_out(const f32x16& acc, int tm, int tn, int M, int N, const float (&bq)[16],
+                                              uint16_t* hi, uint16_t* lo, int lane) {
+  const int i = tm * 32 + (lane & 31);
+  if (i >= M) return;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    uint32_t hw[2], lw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float x0 = fmaxf(acc[4 * g + 2 * h] + bq[4 * g + 2 * h], 0.f);
+      const float x1 = fmaxf(acc[4 * g + 2 * h + 1] + bq[4 * g + 2 * h + 1], 0.f);
+      const uint16_t h0 = f2bf(x0), h1 = f2bf(x1);
+      hw[h] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      lw[h] = (uint32_t)f2bf(x0 - bf2f(h0)) | ((uint32_t)f2bf(x1 - bf2f(h1)) << 16);
     }
+    const int o = i * N + tn * 32 + 8 * g + 4 * (lane >> 5);
+    *reinterpret_cast<uint2*>(hi + o) = make_uint2(hw[0], hw[1]);
+    *reinterpret_cast<uint2*>(lo + o) = make_uint2(lw[0], lw[1]);
   }
 }
 
@@ -1262,8 +1281,10 @@ __global__ __launch_bounds__(kStackThreads) void conv_stack_kernel(const float* 
   conv_wfrags<true, kStackSteps1>(w1, 36, tn1, 0, 36, lane, wf1);
   conv_wfrags<false, kStackSteps2>(w2, 9 * kStackC1, tn2, 0, 9 * kStackC1, lane, wf2);
   conv_wfrags<false, kStackSteps3>(w3, K3, tn3, kb3, ke3, lane, wf3);
-  const float bias1 = b1[tn1 * 32 + (lane & 31)], bias2 = b2[tn2 * 32 + (lane & 31)];
-  const float bias3 = b3[tn3 * 32 + (lane & 31)];
+  float bias1[16], bias2[16], bias3[16];
+  conv_bias4(b1, tn1, lane, bias1);
+  conv_bias4(b2, tn2, lane, bias2);
+  conv_bias4(b3, tn3, lane, bias3);
   {
     // float4 loads (nx a multiple of 4, x 16-byte aligned), all issued before the conversions
     constexpr int U = 4;
@@ -1396,7 +1417,8 @@ hipError_t conv_stack(const float* x, int B, int S, const uint16_t* w1, const fl
                       hipStream_t st, uint16_t* cols1, uint16_t* a1, long a1_lo, uint16_t* a2, long a2_lo) {
   auto al = [](const void* p, uintptr_t a) { return ((uintptr_t)p % a) == 0; };
   if (B < 1 || B > 65535 || !conv_stack_fits(S, c1, c2, c3) || !al(x, 16) || !al(w1, 8) || !al(w2, 16) ||
-      !al(w3, 16) || !al(cols1, 8) || !al(a1, 16) || a1_lo % 8 || !al(a2, 16) || a2_lo % 8)
+      !al(w3, 16) || !al(b1, 16) || !al(b2, 16) || !al(b3, 16) || !al(a3, 8) || a3_lo % 4 || !al(cols1, 8) ||
+      !al(a1, 16) || a1_lo % 8 || !al(a2, 16) || a2_lo % 8)
     return hipErrorNotSupported;
   const int le = conv_stack_lds_elems(S, c1, c2, c3);
   hipLaunchKernelGGL(conv_stack_kernel, dim3(B), dim3(kStackThreads), (size_t)le * sizeof(uint16_t), st, x, S, w1, b1,
