@@ -144,26 +144,39 @@ class ClosedLoop:
             self.probe_s = torch.empty((2 * npb, 2 * plan.n_valid), device=dev)
             self.probe_est = torch.empty((2 * npb, M), device=dev)
 
-    def optical_gain(self, r_t) -> float:
-        """Mean push-pull response of the linear reconstructor to the probe
-        modes around the residual r_t [1, P*P] (library kernels; host mean)."""
+    def _probe(self, r_t) -> None:
+        """Launch the push-pull probes around the residual r_t [1, P*P] and
+        their reconstruction into probe_est (library kernels)."""
         P = self.P
         n = self.probe_screen.shape[0]
         self.probe_screen.copy_(r_t.expand(n, -1))
         recon_apply(self.BKL, self.probe_coef, 1.0, 1.0, self.probe_screen)    # r_t +- a B_k, all probes at once
         self.probe_plan.measure_into(self.probe_screen.view(n, P, P), None, self.probe_s)
         recon_apply(self.R, self.probe_s, 1.0, 0.0, self.probe_est)
-        est = self.probe_est.cpu().numpy().astype(np.float64)
+
+    def _gain_of(self, est: np.ndarray) -> float:
+        est = est.astype(np.float64)
         g = [(est[2 * j, k] - est[2 * j + 1, k]) / (2.0 * self.probe_nm) for j, k in enumerate(self.probe_modes)]
         return float(np.mean(g))
 
+    def optical_gain(self, r_t) -> float:
+        """Mean push-pull response of the linear reconstructor to the probe
+        modes around the residual r_t [1, P*P] (library kernels; host mean)."""
+        self._probe(r_t)
+        return self._gain_of(self.probe_est.cpu().numpy())
+
     def _judge(self, t: int, r_t, c_next) -> bool:
-        """True when the learned reconstructor must hand over (host logic)."""
-        ok = bool(np.isfinite(c_next.cpu().numpy()).all())
+        """True when the learned reconstructor must hand over (host logic).
+        The probes are launched before the commands are read back, so one
+        transfer (one wait for the device) serves both."""
+        import torch
+        self._probe(r_t)
+        both = torch.cat([c_next.reshape(-1), self.probe_est.reshape(-1)]).cpu().numpy()
+        ok = bool(np.isfinite(both[:c_next.numel()]).all())
         if not ok:
             self.judged.append((t, float("nan")))
             return True
-        gam = self.optical_gain(r_t)
+        gam = self._gain_of(both[c_next.numel():].reshape(self.probe_est.shape))
         self.judged.append((t, gam))
         if t < self.judge_settle:
             return False
