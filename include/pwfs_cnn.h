@@ -101,7 +101,9 @@ int pwfs_cnn_gradients(pwfs_cnn_t net, const float* d_x, const float* d_target, 
 /* One training step (weights as in pwfs_cnn_gradients): forward, MSE loss, backward, Adam update of the FP32
  * master weights (step count incremented), bf16 weight copies refreshed.  The step count and Adam's bias
  * corrections are host state passed to the kernels: a captured graph of this call replays the step count
- * it was captured with.
+ * it was captured with.  The Adam update of every parameter but the first layer's runs on the network's
+ * second stream (once the chain has read those weights for the last time), joined back into `stream`
+ * before the call returns, like the backward pass's weight gradients.
  * d_loss (1 float, may be NULL) receives the loss before the update. */
 int pwfs_cnn_train_step(pwfs_cnn_t net, const float* d_x, const float* d_target, const float* d_weights,
                         int32_t B, float lr, float beta1, float beta2, float eps, float* d_loss, void* stream);

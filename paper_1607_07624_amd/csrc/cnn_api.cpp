@@ -69,7 +69,7 @@ struct pwfs_cnn_s {
   // backward: the weight gradients run on `side` (default priority) beside
   // the chain of data gradients on the caller's stream; ev fork and join
   hipStream_t side = nullptr;
-  hipEvent_t ev[5] = {};
+  hipEvent_t ev[6] = {};
 };
 
 namespace {
@@ -244,6 +244,11 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
   return run_dense(n, B, st, out, out_alpha, out_beta);
 }
 
+// Adam hyper-parameters and bias corrections of one training step.
+struct AdamStep {
+  float lr, b1, b2, eps, c1, c2;
+};
+
 // Backward pass.  The data gradients form a chain on the caller's stream
 // (each layer's needs the one above); a layer's weight gradient needs only
 // that layer's upstream gradient and its forward input, and nothing reads it
@@ -253,7 +258,13 @@ int run_forward(pwfs_cnn_s* n, const float* x, int B, hipStream_t st, float* out
 // hundred blocks of a few k steps), so the two streams overlap.  The first
 // layer's weight gradient stays on the chain, which has no other work left
 // by then; the loss sum (read by nothing in the step) goes to the side stream.
-int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B, float* loss, hipStream_t st) {
+// With opt (a training step), the Adam update of every parameter but the
+// first layer's runs on the side stream after its last weight gradient and
+// after the chain's last read of those weights (the second convolution's
+// data gradient), beside the chain's first-layer weight gradient; the chain
+// then updates the first layer.
+int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B, float* loss, hipStream_t st,
+                 const AdamStep* opt = nullptr) {
   const uint16_t* Wb = n->wb;
   float* G = n->g;
   const size_t P = (size_t)n->part_elems;
@@ -296,10 +307,19 @@ int run_backward(pwfs_cnn_s* n, const float* target, const float* weights, int B
     CK(pwfs::cnn::gemm(wgrad_args(n->dz2, n->cols2, true, R2, n->c2, n->c1 * 9, G + n->off[2], G + n->off[3], n->c1),
                        n->part2, P, sd));
   CK(pwfs::cnn::gemm(dgrad_args(n->dz2, Wb + n->off[2], R2, n->c2, n->c1 * 9, n->gtmp), n->part, P, st));
+  if (opt) {
+    CK(hipEventRecord(n->ev[5], st));   // the chain's last read of the weights past the first layer
+    CK(hipStreamWaitEvent(sd, n->ev[5], 0));
+    CK(pwfs::cnn::adam(n->w, n->g, n->m, n->v, n->wb, n->cperm, n->off[2], n->n_params, opt->lr, opt->b1, opt->b2,
+                       opt->eps, opt->c1, opt->c2, sd));
+  }
   CK(pwfs::cnn::col2im_mask(n->gtmp, B, n->S1, n->S1, n->c1, n->a1, n->dz1, st));
   // conv1: weight gradient only, on the chain
   CK(pwfs::cnn::gemm(wgrad_args(n->dz1, n->cols1, false, R1, n->c1, 36, G + n->off[0], G + n->off[1], 4),
                      n->part, P, st));
+  if (opt)
+    CK(pwfs::cnn::adam(n->w, n->g, n->m, n->v, n->wb, n->cperm, 0, n->off[2], opt->lr, opt->b1, opt->b2, opt->eps,
+                       opt->c1, opt->c2, st));
   // join
   CK(hipEventRecord(n->ev[4], sd));
   CK(hipStreamWaitEvent(st, n->ev[4], 0));
@@ -503,11 +523,11 @@ int pwfs_cnn_train_step(pwfs_cnn_t n, const float* d_x, const float* d_target, c
   DevGuard g(n->device);
   hipStream_t st = (hipStream_t)stream;
   if ((s = run_forward(n, d_x, B, st))) return s;
-  if ((s = run_backward(n, d_target, d_weights, B, d_loss ? d_loss : n->loss, st))) return s;
-  n->step += 1;
-  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)n->step));
-  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)n->step));
-  CK(pwfs::cnn::adam(n->w, n->g, n->m, n->v, n->wb, n->cperm, n->n_params, lr, beta1, beta2, eps, c1, c2, st));
+  const long step = n->step + 1;
+  const AdamStep opt{lr, beta1, beta2, eps, (float)(1.0 - std::pow((double)beta1, (double)step)),
+                     (float)(1.0 - std::pow((double)beta2, (double)step))};
+  if ((s = run_backward(n, d_target, d_weights, B, d_loss ? d_loss : n->loss, st, &opt))) return s;
+  n->step = step;
   return 0;
 }
 

@@ -808,9 +808,9 @@ __global__ __launch_bounds__(256) void mse_sum_kernel(const float* __restrict__ 
 // Adam on the FP32 master weights; refreshes the bf16 copy.
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
                                                    float* __restrict__ v, uint16_t* __restrict__ wb, ConvPerm cp,
-                                                   size_t n, float lr, float b1, float b2, float eps, float c1,
-                                                   float c2) {
-  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+                                                   size_t i0, size_t n, float lr, float b1, float b2, float eps,
+                                                   float c1, float c2) {
+  for (size_t i = i0 + blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
     const float gi = g[i];
     const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
     const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
@@ -1057,9 +1057,11 @@ hipError_t mse_sum(const float* part, int n, float* loss, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, const ConvPerm& cp, size_t n, float lr,
-                float b1, float b2, float eps, float c1, float c2, hipStream_t st) {
-  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, st, w, g, m, v, wb, cp, n, lr, b1, b2, eps, c1, c2);
+hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, const ConvPerm& cp, size_t i0, size_t n,
+                float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t st) {
+  if (i0 >= n) return hipSuccess;
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n - i0)), dim3(256), 0, st, w, g, m, v, wb, cp, i0, n, lr, b1, b2, eps,
+                     c1, c2);
   return hipGetLastError();
 }
 

@@ -73,8 +73,9 @@ size_t mse_partials(int n);
 hipError_t mse(const float* pred, const float* target, const float* weights, int n, int n_out, uint16_t* doutb,
                float* part, hipStream_t st);
 hipError_t mse_sum(const float* part, int n, float* loss, hipStream_t st);
-hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, const ConvPerm& cp, size_t n, float lr,
-                float b1, float b2, float eps, float c1, float c2, hipStream_t st);
+// Adam on the parameters [i0, n) of the flat vector (indices absolute).
+hipError_t adam(float* w, const float* g, float* m, float* v, uint16_t* wb, const ConvPerm& cp, size_t i0, size_t n,
+                float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t st);
 hipError_t fill0(float* p, size_t n, hipStream_t st);
 // The three convolutions of a forward-only call, one block per frame:
 // x [B][S][S][4] FP32 -> a3 pair (lo plane a3_lo on), bf16 weights in patch
