@@ -1072,18 +1072,18 @@ hipError_t fill0(float* p, size_t n, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Convolution stack of forward-only calls on few frames: one block of 8
-// waves per frame instead of a gather and a product per layer.  The frame's
-// input (rounded to bf16) and the first convolution's output pair stay in
-// LDS; the products run on v_mfma_f32_32x32x16_bf16 with the A fragments
-// gathered straight from the LDS activations (implicit patches: 8 channels
-// of one tap per 16-byte read, or two taps of the 4-channel input per pair
-// of 8-byte reads, zero in the padding) and the B fragments read from the
-// bf16 weights in patch order [Cout][3][3][Cin] in global memory.  Same
-// arithmetic as the tiled products (pair operands as two MFMAs, FP32
-// accumulation, bias, ReLU, pair output), in another summation order.
-// A 32 x 32 output tile: rows i = output pixels, columns j = output channels.
-// Weight (B) fragments of this lane's output channel j = 32 tn + lane % 32
+// Convolution stack of a forward pass: one block of 8 waves per frame
+// instead of a gather and a product per layer.  The frame's input (rounded
+// to bf16) and the activations stay in LDS; the products run on
+// v_mfma_f32_32x32x16_bf16 with the activation fragments gathered straight
+// from LDS (implicit patches: 8 channels of one tap per 16-byte read, or two
+// taps of the 4-channel input per pair of 8-byte reads, zero in the padding)
+// and the weight fragments read from the bf16 weights in patch order
+// [Cout][3][3][Cin] in global memory.  Same arithmetic as the tiled products
+// (pair operands as two MFMAs, FP32 accumulation, bias, ReLU, pair output),
+// in another summation order.  A 32 x 32 output tile: 32 output pixels by 32
+// output channels.
+// Weight fragments of this lane's output channel j = 32 tn + lane % 32
 // for the k steps kbeg, kbeg + 16, ... (NS of them; zero past kend and K),
 // loaded once, before the activations they multiply are ready.
 template <bool C4, int NS>
