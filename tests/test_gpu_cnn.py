@@ -20,6 +20,9 @@ frames), also with alpha and beta (the loop's accumulate form).  Forward
 and gradients also run at 256 frames, the timed training batch: the
 products' split-K forms, the implicit patches of the second and third
 convolutions and the two-stream backward as the training step uses them.
+The full network's convolutions run as one block per frame; a network
+with 64 first-layer channels (outside that kernel) checks the tiled
+forward products.
 Adam and input preparation are FP32 elementwise: 1e-5.
 """
 import numpy as np
@@ -32,6 +35,10 @@ pytestmark = pytest.mark.gpu
 
 SMALL = dict(n_sub=9, c1=3, c2=5, c3=4, hidden=37, n_out=11)
 FULL = dict(n_sub=40, c1=32, c2=64, c3=64, hidden=2048, n_out=600)
+# 64 first-layer channels: outside the one-block-per-frame convolution kernel,
+# so the forward pass takes the tiled products (implicit patches of the second
+# and third convolutions from 16 frames on)
+WIDE = dict(n_sub=40, c1=64, c2=64, c3=64, hidden=256, n_out=100)
 FWD_TOL = 1e-4
 GRAD_TOL = 1e-4
 # A ReLU input within ~1e-5 of its layer's spread from zero can land on
@@ -109,11 +116,11 @@ def _setup(cfg, B, seed, relu_margin=None):
     return net, torch, p, po, x, bf16_round(x), tgt
 
 
-FWD_CASES = [(SMALL, 5), (FULL, 1), (FULL, 3), (FULL, 8), (FULL, 16), (FULL, 21), (FULL, 256)]
+FWD_CASES = [(SMALL, 5), (FULL, 1), (FULL, 3), (FULL, 8), (FULL, 16), (FULL, 21), (FULL, 256), (WIDE, 2), (WIDE, 32)]
 
 
 @pytest.mark.parametrize("cfg,B", FWD_CASES, ids=["small-5", "full-1", "full-3", "full-8", "full-16", "full-21",
-                                                  "full-256"])
+                                                  "full-256", "wide-2", "wide-32"])
 def test_forward_matches_oracle(cfg, B):
     net, torch, p, po, x, xb, tgt = _setup(cfg, B, 3)
     out = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
@@ -133,10 +140,12 @@ def test_forward_matches_oracle(cfg, B):
 
 
 @pytest.mark.parametrize("cfg,B,weighted", [(SMALL, 5, False), (FULL, 16, False), (SMALL, 6, True),
-                                            (FULL, 3, True), (FULL, 256, False), (FULL, 256, True)],
-                         ids=["small", "full", "small-weighted", "full-3-weighted", "full-256", "full-256-weighted"])
+                                            (FULL, 3, True), (FULL, 256, False), (FULL, 256, True), (WIDE, 32, False)],
+                         ids=["small", "full", "small-weighted", "full-3-weighted", "full-256", "full-256-weighted",
+                              "wide-32"])
 def test_gradients_match_oracle(cfg, B, weighted):
-    net, torch, p, po, x, xb, tgt = _setup(cfg, B, 5, relu_margin=RELU_MARGIN if B >= 64 else None)
+    many = B >= 64 or cfg is WIDE                       # enough ReLU inputs for one near zero
+    net, torch, p, po, x, xb, tgt = _setup(cfg, B, 5, relu_margin=RELU_MARGIN if many else None)
     w = np.random.default_rng(6).uniform(0.2, 3.0, B).astype(np.float32) if weighted else None
     g, loss = net.gradients(torch.from_numpy(x).cuda(), torch.from_numpy(tgt).cuda(),
                             None if w is None else torch.from_numpy(w).cuda())
